@@ -1,0 +1,201 @@
+/*
+ * mbe3osv.h -- C-ABI of the MBE(3)-OSV-MP2 hot path on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: Liang & Yang, "Multi-GPU MBE(3)-OSV-MP2 for Performant Large-Scale
+ * ab initio Calculations", arXiv:2603.16575.  The calls below follow the
+ * paper's statement of the problem (section "MBE(3)-OSV-MP2 Method") and the
+ * outputs of its Algorithms 5-7:
+ *
+ *   osv_project     regenerated RI slabs (ia|P) projected onto the OSVs of
+ *                   every neighbour (eq. osv_imua; the slab stands in for the
+ *                   fitted Gamma_i of eq. fitting / Algorithm 1)
+ *   pair_K          4-block pair exchange matrices K_(pq,pq)
+ *                   (eq. osv_close_k, Algorithm 6)
+ *   fragment_solve  OSV overlap/Fock blocks (Algorithm 5), pair
+ *                   preconditioner bases (eq. prec_eig) and the coupled
+ *                   residual equations of every 1-, 2- and 3-orbital
+ *                   fragment (eq. res_close, Algorithm 7)
+ *   mbe3_energy     MBE(3) sum of fragment energies (eqs. tmbediag, tmbeoff)
+ *   mbe3_backward   dE/d(ia|P) and dE/df_occ (derived from Hylleraas
+ *                   stationarity; the paper names analytic gradients only as
+ *                   future work)
+ *
+ * Conventions for every call:
+ *   - Arrays are caller-owned.  "device" pointers are HIP device memory on
+ *     the handle's device; "host" pointers are ordinary host memory.
+ *   - All floating point data is IEEE double, row-major.
+ *   - Every call is ordered on the handle's stream (hipStream_t passed as
+ *     void*; NULL = the default stream).  Only mbe3_energy synchronises.
+ *   - Every call returns an int status (MBE3_*).  On failure,
+ *     mbe3_last_error() describes the cause.  No C++ exception crosses the
+ *     ABI.  The library allocates its own device workspace (at create and
+ *     on first use); it never frees or writes caller memory other than the
+ *     documented outputs.
+ *   - The handle is not thread safe; concurrent calls on one handle race.
+ *
+ * Index conventions:
+ *   LMO i in [0, n_occ) has r[i] OSVs; q_off[i] = r[0] + ... + r[i-1].
+ *   N+(i) = {i} united with every j such that the pair (i, j) is kept,
+ *   in ascending order.
+ *   Pair slots: slot s < n_occ is the diagonal pair (s, s); slot n_occ + m
+ *   is kept pair m of the `pairs` list.  d_s = r[p] for (p, p) and
+ *   r[p] + r[q] for (p, q); the pair domain is V_pq = [Q_p Q_q] (or Q_p).
+ */
+#ifndef MBE3OSV_H
+#define MBE3OSV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MBE3_OK 0
+#define MBE3_EINVAL (-1)     /* bad sizes, lists or arguments              */
+#define MBE3_ENOMEM (-2)     /* device allocation failed / too large       */
+#define MBE3_EHIP (-3)       /* a HIP runtime call failed                  */
+#define MBE3_ENOCONV (-4)    /* a fragment hit max_iter (iters[f] < 0)     */
+#define MBE3_ENONFINITE (-5) /* NaN/Inf met in a residual or an energy     */
+
+#define MBE3_FP64 0
+
+typedef struct mbe3_handle mbe3_handle;
+
+/*
+ * Problem description (read once by mbe3_create; host arrays are copied, the
+ * device arrays must stay valid and unchanged-in-shape for the handle's
+ * lifetime; their values may change between calls).
+ */
+typedef struct mbe3_problem {
+  int32_t n_occ; /* localized occupied orbitals (LMOs)                     */
+  int32_t n_vir; /* canonical virtual orbitals                             */
+  int32_t n_aux; /* auxiliary (RI) functions                               */
+  const int32_t *r; /* host [n_occ]: OSVs per LMO, 1 <= r[i] <= n_vir       */
+  const double *Q;  /* device [sum r][n_vir]: row q_off[i]+mu is OSV mu of
+                       LMO i (columns of Q_i, orthonormal)                  */
+  const double *eps_vir; /* device [n_vir]: virtual energies f_aa           */
+  const double *f_occ;   /* device [n_occ][n_occ]: symmetric LMO Fock      */
+  /* RI slab source.  If slab != NULL it is used as (ia|P) directly:
+     device [n_occ][n_vir][n_aux].  Otherwise the slab is regenerated:
+       (ia|P) = z * w_ia[i][a] * w_iP[i][P]   (evaluated in that order)
+     with z the Box-Muller normal of words 0, 1 of the Philox4x64-10 block
+     at counter (P, a, i, 0) under key (seed, 0):
+       u1 = ((w0 >> 11) + 0.5) 2^-53,  u2 = (w1 >> 11) 2^-53,
+       z  = sqrt(-2 ln u1) cos(2 pi u2).                                    */
+  uint64_t seed;
+  const double *w_ia; /* device [n_occ][n_vir]                             */
+  const double *w_iP; /* device [n_occ][n_aux]                             */
+  const double *slab; /* device [n_occ][n_vir][n_aux] or NULL              */
+  int64_t n_pair;
+  const int32_t *pairs; /* host [n_pair][2]: kept pairs, i < j, no repeats  */
+  int64_t n_frag;
+  const int32_t *frags; /* host [n_frag][3]: fragments, ascending orbital
+                           indices padded with -1.  Must be downward closed:
+                           every orbital of a fragment is a monomer
+                           fragment, every pair inside a dimer or trimer is
+                           both kept and a dimer fragment.                  */
+  double tol;       /* convergence: max |X^T R X| < tol (every pair)       */
+  int32_t max_iter; /* maximum amplitude updates per fragment               */
+  double tau_S;     /* drop pair-overlap eigenvalues <= tau_S               */
+  int32_t precision; /* MBE3_FP64                                          */
+} mbe3_problem;
+
+/* Sizes of the packed arrays exchanged between the calls. */
+typedef struct mbe3_layout {
+  int64_t n_slot;      /* n_occ + n_pair                                    */
+  int64_t gamma_rows;  /* sum_i sum_{x in N+(i)} r[x]                       */
+  int64_t gamma_elems; /* gamma_rows * n_aux                                */
+  int64_t k_elems;     /* sum_s d_s^2                                       */
+  int64_t n_frag;
+} mbe3_layout;
+
+/* Create a handle for problem *p on `stream` (hipStream_t).  Validates the
+   lists (MBE3_EINVAL), builds the execution plans and allocates the
+   workspace (MBE3_ENOMEM).  *h is NULL on failure. */
+int mbe3_create(mbe3_handle **h, const mbe3_problem *p, void *stream);
+/* Release the handle and its workspace (after finishing its stream). */
+int mbe3_destroy(mbe3_handle *h);
+/* Host string describing the last failure on h (never NULL). */
+const char *mbe3_last_error(const mbe3_handle *h);
+
+int mbe3_get_layout(const mbe3_handle *h, mbe3_layout *out /* host */);
+/* Plan without a device: validates *p (device pointers are not touched, any
+   non-NULL value is accepted), builds every execution plan and checks that
+   each task stays inside the buffers it addresses.  Returns the status
+   mbe3_create would return for plan errors; the message is available from
+   mbe3_last_error(NULL).  `out` (host, nullable) receives the layout. */
+int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out);
+/* Row offset of LMO i's block in gamma, host out[n_occ + 1]. */
+int mbe3_gamma_offsets(const mbe3_handle *h, int64_t *out);
+/* Offset (in doubles) of slot s in the K layout, host out[n_slot + 1]. */
+int mbe3_k_offsets(const mbe3_handle *h, int64_t *out);
+
+/*
+ * osv_project -- eq. osv_imua.  For every LMO i and x in N+(i):
+ *   gamma[goff[i] + (rows of x within N+(i))][P] = (Q_x^T B_i)[mu][P],
+ * i.e. LMO i's block is the stacked Q_x^T B_i over x in N+(i) (ascending),
+ * each r[x] x n_aux, rows contiguous.  gamma: device, gamma_elems doubles
+ * (mbe3_layout).  B_i is regenerated tile by tile (or read from slab).
+ */
+int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems);
+
+/*
+ * pair_K -- eq. osv_close_k.  For slot s of pair (p, q):
+ *   K_s = [G_{p,p}; G_{p,q}] [G_{q,p}; G_{q,q}]^T          (d_s x d_s)
+ * and for a diagonal slot K_s = G_{p,p} G_{p,p}^T, with G_{i,x} = Q_x^T B_i
+ * read from gamma (osv_project's layout).  K: device, k_elems doubles,
+ * slot s row-major at k_off[s] (the p-block first).
+ */
+int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems);
+
+/*
+ * fragment_solve -- Algorithms 5 and 7 with eq. prec_eig.
+ * Builds S_(x,y) = Q_x^T Q_y and F_(x,y) = Q_x^T diag(eps) Q_y, the pair
+ * bases X_s (F X = S X diag(eps~), X^T S X = 1, overlap eigenvalues <= tau_S
+ * dropped), then for each fragment F iterates from T = 0:
+ *   R_pq = K_pq + F T_pq S + S T_pq F
+ *          - sum_{k in F} [ f_pk S_(pq,kq) T_kq S_(kq,pq)
+ *                         + f_kq S_(pq,pk) T_pk S_(pk,pq) ]   (p <= q in F)
+ *   stop when max |X^T R X| < tol, else T += X ((X^T R X) / E~) X^T,
+ *   E~[mu][nu] = f_pp + f_qq - eps~_mu - eps~_nu,
+ * and returns the Hylleraas fragment energy
+ *   e_frag[f] = sum_{p<=q in F} w_pq <2 T_pq - T_pq^T, K_pq + R_pq>,
+ * w = 1 for p = q, 2 otherwise (Frobenius product).
+ * K: device, pair_K's layout.  e_frag: device [n_frag].  iters: device
+ * [n_frag] int32, number of updates, or -(max_iter+1) if not converged.
+ * W: device, K layout, or NULL; when given it receives the MBE multipliers
+ *   W_s = sum_{F containing p,q} c_F (2 T^F_pq - T^F_pq^T)
+ * used by mbe3_backward.  Returns MBE3_ENOCONV / MBE3_ENONFINITE after the
+ * stream finished if any fragment failed (other fragments are valid).
+ */
+int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
+                   int32_t *iters, double *W);
+
+/*
+ * mbe3_energy -- E = sum_i E_i + sum_ij dE_ij + sum_ijk dE_ijk with
+ * dE_ij = E_ij - E_i - E_j, dE_ijk = E_ijk - dE_ij - dE_ik - dE_jk
+ * - E_i - E_j - E_k (MBE(3) of fragment energies), summed in a fixed order
+ * with compensated (double-double) arithmetic.  e_frag: device [n_frag].
+ * e_total: host, 1 double.  incr: device [n_frag] (dE per fragment) or NULL.
+ * Synchronises the stream.
+ */
+int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
+                double *incr);
+
+/*
+ * Pair bases for inspection: X_s (d_s x D_s, D_s = d_s rounded up to 16,
+ * dropped / padded columns zero) at x_off = sum_{s'<s} d_s' D_s', eps~_s
+ * (D_s entries, padded with 1e30) at e_off = sum_{s'<s} D_s', kept rank per
+ * slot.  Runs the preparation of fragment_solve.  All device pointers.
+ */
+int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank);
+/* Offsets for mbe3_pair_basis: host xoff[n_slot+1], eoff[n_slot+1]. */
+int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBE3OSV_H */

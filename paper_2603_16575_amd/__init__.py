@@ -1,0 +1,218 @@
+"""MBE(3)-OSV-MP2 hot path on AMD Instinct MI355X (gfx950).
+
+Python face of the C-ABI library ``libmbe3osv`` (include/mbe3osv.h).  The
+entry points keep the C names: ``osv_project``, ``pair_K``,
+``fragment_solve``, ``mbe3_energy`` and ``mbe3_pair_basis``; ``Mbe3`` owns a
+library handle for one problem.  Device arrays are torch CUDA (HIP) tensors,
+which supply memory and the stream; the arithmetic runs in the library.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (MBE3_EHIP, MBE3_EINVAL, MBE3_ENOCONV, MBE3_ENOMEM,
+                   MBE3_ENONFINITE, MBE3_FP64, MBE3_OK, Mbe3Error)
+
+__all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
+           "mbe3_energy", "mbe3_pair_basis", "MBE3_OK", "MBE3_EINVAL",
+           "MBE3_ENOMEM", "MBE3_EHIP", "MBE3_ENOCONV", "MBE3_ENONFINITE"]
+
+
+def _f64(t):
+    import torch
+    assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    return t
+
+
+class Mbe3:
+    """One problem on one device.
+
+    Q, eps_vir, f_occ, w_ia, w_iP (or slab): contiguous float64 CUDA tensors,
+    kept referenced by the handle.  r, pairs, frags: host int arrays.
+    """
+
+    def __init__(self, *, r, Q, eps_vir, f_occ, pairs, frags, seed=0,
+                 w_ia=None, w_iP=None, slab=None, tol=1e-8, max_iter=100,
+                 tau_S=1e-8, stream=None):
+        import torch
+        lib = _lib.load()
+        self._keep = [Q, eps_vir, f_occ, w_ia, w_iP, slab]
+        for t in (Q, eps_vir, f_occ, w_ia, w_iP, slab):
+            if t is not None:
+                _f64(t)
+        self.device = Q.device
+        self.r = np.ascontiguousarray(r, dtype=np.int32)
+        self.pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        self.frags = np.ascontiguousarray(frags, dtype=np.int32).reshape(-1, 3)
+        n_occ = len(self.r)
+        p = _lib.Mbe3Problem()
+        p.n_occ = n_occ
+        p.n_vir = int(eps_vir.numel())
+        p.n_aux = int(w_iP.shape[1]) if w_iP is not None else int(slab.shape[2])
+        p.r = _lib.ptr(self.r)
+        p.Q = _lib.ptr(Q)
+        p.eps_vir = _lib.ptr(eps_vir)
+        p.f_occ = _lib.ptr(f_occ)
+        p.seed = int(seed)
+        p.w_ia = _lib.ptr(w_ia)
+        p.w_iP = _lib.ptr(w_iP)
+        p.slab = _lib.ptr(slab)
+        p.n_pair = len(self.pairs)
+        p.pairs = _lib.ptr(self.pairs) if len(self.pairs) else None
+        p.n_frag = len(self.frags)
+        p.frags = _lib.ptr(self.frags)
+        p.tol = float(tol)
+        p.max_iter = int(max_iter)
+        p.tau_S = float(tau_S)
+        p.precision = MBE3_FP64
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._h = ctypes.c_void_p()
+        rc = lib.mbe3_create(ctypes.byref(self._h), ctypes.byref(p),
+                             ctypes.c_void_p(stream.cuda_stream))
+        _lib.check(rc, None)
+        lay = _lib.Mbe3Layout()
+        _lib.check(lib.mbe3_get_layout(self._h, ctypes.byref(lay)), self._h)
+        self.layout = lay
+        self.n_occ = n_occ
+        self.n_aux = p.n_aux
+        self.n_frag = lay.n_frag
+        self.g_off = np.zeros(n_occ + 1, dtype=np.int64)
+        _lib.check(lib.mbe3_gamma_offsets(self._h, _lib.ptr(self.g_off)), self._h)
+        self.k_off = np.zeros(lay.n_slot + 1, dtype=np.int64)
+        _lib.check(lib.mbe3_k_offsets(self._h, _lib.ptr(self.k_off)), self._h)
+        self.x_off = np.zeros(lay.n_slot + 1, dtype=np.int64)
+        self.e_off = np.zeros(lay.n_slot + 1, dtype=np.int64)
+        _lib.check(lib.mbe3_basis_offsets(self._h, _lib.ptr(self.x_off),
+                                          _lib.ptr(self.e_off)), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().mbe3_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- allocation helpers (torch owns memory) ----
+    def empty_gamma(self):
+        import torch
+        return torch.empty(self.layout.gamma_elems, dtype=torch.float64,
+                           device=self.device)
+
+    def empty_K(self):
+        import torch
+        return torch.empty(self.layout.k_elems, dtype=torch.float64,
+                           device=self.device)
+
+    # ---- C-ABI calls ----
+    def osv_project(self, gamma):
+        _lib.check(_lib.load().osv_project(self._h, _lib.ptr(_f64(gamma)),
+                                           gamma.numel()), self._h)
+        return gamma
+
+    def pair_K(self, gamma, K):
+        _lib.check(_lib.load().pair_K(self._h, _lib.ptr(_f64(gamma)),
+                                      _lib.ptr(_f64(K)), K.numel()), self._h)
+        return K
+
+    def fragment_solve(self, K, e_frag, iters, W=None, check=True):
+        rc = _lib.load().fragment_solve(self._h, _lib.ptr(_f64(K)),
+                                        _lib.ptr(e_frag), _lib.ptr(iters),
+                                        _lib.ptr(W))
+        if check:
+            _lib.check(rc, self._h)
+        return rc
+
+    def mbe3_energy(self, e_frag, incr=None):
+        out = np.zeros(1, dtype=np.float64)
+        _lib.check(_lib.load().mbe3_energy(self._h, _lib.ptr(e_frag),
+                                           _lib.ptr(out), _lib.ptr(incr)),
+                   self._h)
+        return float(out[0])
+
+    def mbe3_pair_basis(self):
+        import torch
+        X = torch.empty(int(self.x_off[-1]), dtype=torch.float64, device=self.device)
+        et = torch.empty(int(self.e_off[-1]), dtype=torch.float64, device=self.device)
+        rank = torch.empty(int(self.layout.n_slot), dtype=torch.int32, device=self.device)
+        _lib.check(_lib.load().mbe3_pair_basis(self._h, _lib.ptr(X), _lib.ptr(et),
+                                               _lib.ptr(rank)), self._h)
+        return X, et, rank
+
+    def forward(self):
+        """osv_project -> pair_K -> fragment_solve -> mbe3_energy."""
+        import torch
+        gamma = self.osv_project(self.empty_gamma())
+        K = self.pair_K(gamma, self.empty_K())
+        e = torch.empty(self.n_frag, dtype=torch.float64, device=self.device)
+        it = torch.empty(self.n_frag, dtype=torch.int32, device=self.device)
+        self.fragment_solve(K, e, it)
+        E = self.mbe3_energy(e)
+        return dict(E=E, gamma=gamma, K=K, e_frag=e, iters=it)
+
+
+def osv_project(h, gamma):
+    return h.osv_project(gamma)
+
+
+def pair_K(h, gamma, K):
+    return h.pair_K(gamma, K)
+
+
+def fragment_solve(h, K, e_frag, iters, W=None):
+    return h.fragment_solve(K, e_frag, iters, W)
+
+
+def mbe3_energy(h, e_frag, incr=None):
+    return h.mbe3_energy(e_frag, incr)
+
+
+def mbe3_pair_basis(h):
+    return h.mbe3_pair_basis()
+
+
+def from_problem(prob, device="cuda:0", **kw):
+    """Build an Mbe3 handle from a seeded synthetic Problem (input marshalling)."""
+    import torch
+    dev = torch.device(device)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+    args = dict(r=prob.r, Q=t(prob.QT_packed), eps_vir=t(prob.eps_vir),
+                f_occ=t(prob.f_occ), pairs=prob.pairs, frags=prob.frags,
+                seed=prob.seed, w_ia=t(prob.w_ia), w_iP=t(prob.w_iP),
+                tol=prob.tol, max_iter=prob.max_iter, tau_S=prob.tau_S)
+    args.update(kw)
+    return Mbe3(**args)
+
+
+def plan_check(*, r, pairs, frags, n_vir, n_aux, tol=1e-8, max_iter=100,
+               tau_S=1e-8, explicit_slab=False):
+    """Build and bounds-check every execution plan without a device.
+
+    Returns the layout; raises Mbe3Error with the library's message on
+    invalid lists or a planner bug."""
+    lib = _lib.load()
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    frags = np.ascontiguousarray(frags, dtype=np.int32).reshape(-1, 3)
+    fake = 0x1000  # never dereferenced by the planner
+    p = _lib.Mbe3Problem()
+    p.n_occ, p.n_vir, p.n_aux = len(r), int(n_vir), int(n_aux)
+    p.r = _lib.ptr(r)
+    p.Q = p.eps_vir = p.f_occ = fake
+    p.w_ia = p.w_iP = None if explicit_slab else fake
+    p.slab = fake if explicit_slab else None
+    p.n_pair = len(pairs)
+    p.pairs = _lib.ptr(pairs) if len(pairs) else None
+    p.n_frag = len(frags)
+    p.frags = _lib.ptr(frags)
+    p.tol, p.max_iter, p.tau_S, p.precision = tol, max_iter, tau_S, MBE3_FP64
+    lay = _lib.Mbe3Layout()
+    rc = lib.mbe3_plan_check(ctypes.byref(p), ctypes.byref(lay))
+    _lib.check(rc, None)
+    return lay

@@ -1,0 +1,1273 @@
+// Host side of libmbe3osv: problem validation, execution plans (GEMM /
+// assembly / eigen task tables and the fragment term tables, built once at
+// create time and uploaded), workspace management and the C-ABI entry points
+// declared in include/mbe3osv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+#include "mbe3osv.h"
+
+using namespace mbe3;
+
+namespace {
+
+constexpr int DMAX_SUPPORTED = 96;   // largest padded pair dimension handled
+constexpr int SOLVE_WG = 1024;       // persistent workgroups of the solver
+constexpr int64_t SLAB_BUDGET = 2LL << 30;    // bytes of regenerated slabs
+constexpr int64_t CHUNK_BUDGET = 3LL << 30;   // bytes of per-chunk stores
+
+inline int round16(int x) { return (x + 15) & ~15; }
+inline int64_t key2(int a, int b) { return ((int64_t)a << 32) | (uint32_t)b; }
+
+// base-pointer ids of the GEMM engine
+enum Base {
+  B_Q = 0, B_EQ, B_SLAB, B_GAMMA, B_K, B_SS, B_FS, B_PS, B_PF, B_X0, B_X,
+  B_TMP, B_FP, B_Z, B_KT, B_AT, B_MT, B_ST0, B_CA, B_CM, B_ST1, B_COUNT
+};
+static_assert(B_COUNT <= NBASE, "too many GEMM bases");
+
+struct Chunk {
+  std::vector<int> frag_ids;  // fragment indices (heavy first)
+  GemmTask *d_m = nullptr, *d_s1 = nullptr, *d_s2 = nullptr;
+  int n_gemm = 0;
+  int64_t tiles_m = 0, tiles_s1 = 0, tiles_s2 = 0;
+  AssembleTask *d_asm = nullptr;
+  int n_asm = 0;
+  FragDesc *d_frags = nullptr;
+  int n_frag = 0;
+  Term *d_terms = nullptr;
+  int dmax = 16;
+  int ny_max = 0;
+};
+
+}  // namespace
+
+struct mbe3_handle {
+  // ---- problem ----
+  int n_occ = 0, n_vir = 0, n_aux = 0;
+  std::vector<int> r;
+  std::vector<int64_t> q_off;
+  const double *Q = nullptr, *eps = nullptr, *f = nullptr;
+  const double *w_ia = nullptr, *w_iP = nullptr, *slab = nullptr;
+  uint64_t seed = 0;
+  std::vector<std::array<int, 2>> pairs;
+  std::vector<std::array<int, 3>> frags;
+  double tol = 1e-8, tau_S = 1e-8;
+  int max_iter = 100;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // ---- layout ----
+  std::vector<std::vector<int>> nbr;
+  std::vector<int64_t> g_off;
+  std::unordered_map<int64_t, int64_t> grow;
+  std::unordered_map<int64_t, int> pair_slot;
+  int64_t n_slot = 0;
+  std::vector<int> sp, sq, sd, sD;
+  std::vector<int64_t> k_off, x_off, kt_off, et_off;
+  std::unordered_map<int64_t, int64_t> sb_off;  // S/F block (x<=y) offsets
+  int64_t sb_total = 0;
+  int dmax = 16, dmin_max_pair = 0;
+  std::vector<double> coef;
+  std::vector<int> frag_cost_order;
+
+  // ---- device workspace ----
+  std::vector<void *> allocs;
+  double *slab_buf = nullptr;
+  int slab_nb = 1;
+  double *eq = nullptr, *sstore = nullptr, *fstore = nullptr;
+  double *ps = nullptr, *pf = nullptr, *x0 = nullptr, *xb = nullptr;
+  double *tmp = nullptr, *fp = nullptr, *zb = nullptr, *kt = nullptr;
+  double *et = nullptr, *ev0 = nullptr;
+  int32_t *rank = nullptr;
+  double *at = nullptr, *mt = nullptr, *st0 = nullptr;
+  double *ca = nullptr, *cm = nullptr, *st1 = nullptr;
+  double *scratch = nullptr;
+  int64_t scratch_stride = 0;
+  int32_t *status = nullptr;
+  int32_t *h_status = nullptr;
+  double *d_coef = nullptr;
+  int32_t *d_sub = nullptr;
+  double *d_e3 = nullptr;
+  double *h_e3 = nullptr;
+  int32_t *d_rows = nullptr;
+  SlotInfo *d_slots = nullptr;
+
+  // ---- plans ----
+  std::vector<std::pair<int, int>> proj_batches;  // [i0, i1)
+  std::vector<GemmTask *> d_proj;
+  std::vector<int> n_proj;
+  std::vector<int64_t> t_proj;
+  GemmTask *d_pk = nullptr;
+  int n_pk = 0;
+  int64_t t_pk = 0;
+  GemmTask *d_sf = nullptr;
+  int n_sf = 0;
+  int64_t t_sf = 0;
+  AssembleTask *d_asm_pair = nullptr;
+  int n_asm_pair = 0;
+  EigTask *d_eig0 = nullptr, *d_eig1 = nullptr;
+  GemmTask *d_g_m1 = nullptr, *d_g_fp = nullptr, *d_g_x = nullptr,
+           *d_g_m2 = nullptr, *d_g_kt = nullptr;
+  int64_t t_m1 = 0, t_fp = 0, t_x = 0, t_m2 = 0, t_kt = 0;
+  AssembleTask *d_asm_st = nullptr;
+  int n_asm_st = 0;
+  GemmTask *d_g_stm = nullptr, *d_g_st1 = nullptr, *d_g_st2 = nullptr;
+  int n_g_st = 0;
+  int64_t t_stm = 0, t_st1 = 0, t_st2 = 0;
+  std::vector<Chunk> chunks;
+  int64_t gamma_rows = 0;
+  int64_t k_elems = 0;
+
+  // ---- host mirrors of the plans, for the bounds check ----
+  bool dry = false;  // plan only: no device allocation or copies
+  int64_t at_total = 0, mt_total = 0, st0_total = 0;
+  int64_t max_ca = 1, max_cm = 1, max_st1 = 1, n_rows = 0;
+  std::vector<std::pair<std::string, std::vector<GemmTask>>> h_gemm;
+  std::vector<std::pair<std::array<int64_t, 2>, std::vector<AssembleTask>>> h_asm;
+  std::vector<std::pair<int, std::vector<EigTask>>> h_eig;
+  std::vector<std::vector<FragDesc>> h_fds;
+  std::vector<std::vector<Term>> h_terms;
+  std::vector<int32_t> h_rows;
+
+  int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  ~mbe3_handle() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (h_status) (void)hipHostFree(h_status);
+    if (h_e3) (void)hipHostFree(h_e3);
+  }
+};
+
+#define HIP_TRY(h, expr)                                                   \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return (h)->fail(MBE3_EHIP, "%s: %s (%s:%d)", #expr,                  \
+                       hipGetErrorString(e_), __FILE__, __LINE__);         \
+  } while (0)
+
+namespace {
+
+template <class T>
+int dev_alloc(mbe3_handle *h, T **p, int64_t n) {
+  *p = nullptr;
+  if (h->dry) return MBE3_OK;
+  if (n <= 0) n = 1;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return h->fail(MBE3_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+                   (long long)(n * (int64_t)sizeof(T)), hipGetErrorString(e));
+  }
+  h->allocs.push_back(q);
+  *p = (T *)q;
+  return MBE3_OK;
+}
+
+template <class T>
+int upload(mbe3_handle *h, T **dst, const std::vector<T> &v) {
+  int rc = dev_alloc(h, dst, (int64_t)v.size());
+  if (rc) return rc;
+  if (!v.empty() && !h->dry)
+    HIP_TRY(h, hipMemcpy(*dst, v.data(), v.size() * sizeof(T),
+                         hipMemcpyHostToDevice));
+  return MBE3_OK;
+}
+
+// Finalise a task list: tile prefix sums for the given shape.
+int64_t finish_tasks(std::vector<GemmTask> &ts, GemmShape shape) {
+  int64_t acc = 0;
+  const int b = shape == GEMM_128x128 ? 128 : 64;
+  for (auto &t : ts) {
+    t.tiles_n = (t.N + b - 1) / b;
+    t.tile_begin = acc;
+    acc += gemm_tile_count(t, shape);
+  }
+  return acc;
+}
+
+GemmTask gemm(int a_buf, int64_t a_off, int lda, int transA, int b_buf,
+              int64_t b_off, int ldb, int transB, int c_buf, int64_t c_off,
+              int ldc, int M, int N, int K, double alpha = 1.0,
+              double beta = 0.0) {
+  GemmTask t;
+  std::memset(&t, 0, sizeof t);
+  t.a_buf = a_buf; t.a_off = a_off; t.lda = lda; t.transA = transA;
+  t.b_buf = b_buf; t.b_off = b_off; t.ldb = ldb; t.transB = transB;
+  t.c_buf = c_buf; t.c_off = c_off; t.ldc = ldc;
+  t.M = M; t.N = N; t.K = K;
+  t.alpha = alpha; t.beta = beta;
+  t.a_rows = -1; t.b_rows = -1;
+  return t;
+}
+
+int validate_and_copy(mbe3_handle *h, const mbe3_problem *p) {
+  if (!p) return h->fail(MBE3_EINVAL, "problem is NULL");
+  if (p->n_occ < 1 || p->n_vir < 1 || p->n_aux < 1)
+    return h->fail(MBE3_EINVAL, "sizes must be positive (n_occ=%d n_vir=%d n_aux=%d)",
+                   p->n_occ, p->n_vir, p->n_aux);
+  if (!p->r || !p->Q || !p->eps_vir || !p->f_occ)
+    return h->fail(MBE3_EINVAL, "r, Q, eps_vir and f_occ are required");
+  if (!p->slab && (!p->w_ia || !p->w_iP))
+    return h->fail(MBE3_EINVAL, "either slab or (w_ia, w_iP) must be given");
+  if (!(p->tol > 0.0) || p->max_iter < 0 || !(p->tau_S >= 0.0))
+    return h->fail(MBE3_EINVAL, "tol > 0, max_iter >= 0, tau_S >= 0 required");
+  if (p->precision != MBE3_FP64)
+    return h->fail(MBE3_EINVAL, "unsupported precision %d", p->precision);
+  h->n_occ = p->n_occ; h->n_vir = p->n_vir; h->n_aux = p->n_aux;
+  h->Q = p->Q; h->eps = p->eps_vir; h->f = p->f_occ;
+  h->w_ia = p->w_ia; h->w_iP = p->w_iP; h->slab = p->slab; h->seed = p->seed;
+  h->tol = p->tol; h->tau_S = p->tau_S; h->max_iter = p->max_iter;
+  h->r.assign(p->r, p->r + p->n_occ);
+  h->q_off.assign(h->n_occ + 1, 0);
+  for (int i = 0; i < h->n_occ; ++i) {
+    if (h->r[i] < 1 || h->r[i] > h->n_vir)
+      return h->fail(MBE3_EINVAL, "r[%d]=%d out of [1, n_vir]", i, h->r[i]);
+    h->q_off[i + 1] = h->q_off[i] + h->r[i];
+  }
+  if (p->n_pair < 0 || (p->n_pair > 0 && !p->pairs))
+    return h->fail(MBE3_EINVAL, "bad pair list");
+  for (int64_t m = 0; m < p->n_pair; ++m) {
+    const int a = p->pairs[2 * m], b = p->pairs[2 * m + 1];
+    if (a < 0 || b >= h->n_occ || a >= b)
+      return h->fail(MBE3_EINVAL, "pair %lld = (%d, %d) invalid", (long long)m, a, b);
+    if (h->pair_slot.count(key2(a, b)))
+      return h->fail(MBE3_EINVAL, "pair (%d, %d) repeated", a, b);
+    h->pair_slot[key2(a, b)] = h->n_occ + (int)m;
+    h->pairs.push_back({a, b});
+  }
+  if (p->n_frag < 1 || !p->frags) return h->fail(MBE3_EINVAL, "no fragments");
+  std::map<std::array<int, 3>, int64_t> seen;
+  for (int64_t m = 0; m < p->n_frag; ++m) {
+    std::array<int, 3> o = {p->frags[3 * m], p->frags[3 * m + 1], p->frags[3 * m + 2]};
+    int n = 0;
+    while (n < 3 && o[n] >= 0) ++n;
+    for (int k = n; k < 3; ++k)
+      if (o[k] != -1) return h->fail(MBE3_EINVAL, "fragment %lld: bad padding", (long long)m);
+    if (n == 0) return h->fail(MBE3_EINVAL, "fragment %lld is empty", (long long)m);
+    for (int k = 0; k < n; ++k)
+      if (o[k] >= h->n_occ || (k && o[k] <= o[k - 1]))
+        return h->fail(MBE3_EINVAL, "fragment %lld: orbitals must be ascending and < n_occ",
+                       (long long)m);
+    if (seen.count(o)) return h->fail(MBE3_EINVAL, "fragment %lld repeated", (long long)m);
+    seen[o] = m;
+    h->frags.push_back(o);
+  }
+  // downward closure: every sub-fragment present, every inner pair kept
+  for (auto &o : h->frags) {
+    int n = o[2] >= 0 ? 3 : (o[1] >= 0 ? 2 : 1);
+    for (int k = 0; k < n; ++k)
+      if (!seen.count({o[k], -1, -1}))
+        return h->fail(MBE3_EINVAL, "fragment (%d,%d,%d) lacks monomer %d", o[0], o[1], o[2], o[k]);
+    for (int a = 0; a < n; ++a)
+      for (int b = a + 1; b < n; ++b) {
+        if (!h->pair_slot.count(key2(o[a], o[b])))
+          return h->fail(MBE3_EINVAL, "fragment (%d,%d,%d): pair (%d,%d) not kept",
+                         o[0], o[1], o[2], o[a], o[b]);
+        if (n == 3 && !seen.count({o[a], o[b], -1}))
+          return h->fail(MBE3_EINVAL, "fragment (%d,%d,%d) lacks dimer (%d,%d)",
+                         o[0], o[1], o[2], o[a], o[b]);
+      }
+  }
+  // MBE(3) coefficients and sub-fragment indices
+  std::vector<int64_t> deg(h->n_occ, 0), tri_i(h->n_occ, 0);
+  std::unordered_map<int64_t, int64_t> tri_ij;
+  for (auto &o : h->frags) {
+    if (o[1] >= 0 && o[2] < 0) { deg[o[0]]++; deg[o[1]]++; }
+    if (o[2] >= 0) {
+      tri_i[o[0]]++; tri_i[o[1]]++; tri_i[o[2]]++;
+      tri_ij[key2(o[0], o[1])]++; tri_ij[key2(o[0], o[2])]++; tri_ij[key2(o[1], o[2])]++;
+    }
+  }
+  h->coef.resize(h->frags.size());
+  for (size_t m = 0; m < h->frags.size(); ++m) {
+    auto &o = h->frags[m];
+    if (o[1] < 0) h->coef[m] = (double)(1 - deg[o[0]] + tri_i[o[0]]);
+    else if (o[2] < 0) {
+      auto it = tri_ij.find(key2(o[0], o[1]));
+      h->coef[m] = (double)(1 - (it == tri_ij.end() ? 0 : it->second));
+    } else h->coef[m] = 1.0;
+  }
+  return MBE3_OK;
+}
+
+int build_layout(mbe3_handle *h) {
+  const int n = h->n_occ;
+  h->nbr.assign(n, {});
+  for (int i = 0; i < n; ++i) h->nbr[i].push_back(i);
+  for (auto &pq : h->pairs) {
+    h->nbr[pq[0]].push_back(pq[1]);
+    h->nbr[pq[1]].push_back(pq[0]);
+  }
+  h->g_off.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    std::sort(h->nbr[i].begin(), h->nbr[i].end());
+    int64_t row = h->g_off[i];
+    for (int x : h->nbr[i]) {
+      h->grow[key2(i, x)] = row;
+      row += h->r[x];
+    }
+    h->g_off[i + 1] = row;
+  }
+  h->gamma_rows = h->g_off[n];
+  h->n_slot = n + (int64_t)h->pairs.size();
+  h->sp.resize(h->n_slot); h->sq.resize(h->n_slot);
+  h->sd.resize(h->n_slot); h->sD.resize(h->n_slot);
+  h->k_off.assign(h->n_slot + 1, 0);
+  h->x_off.assign(h->n_slot + 1, 0);
+  h->kt_off.assign(h->n_slot + 1, 0);
+  h->et_off.assign(h->n_slot + 1, 0);
+  h->dmax = 16;
+  for (int64_t s = 0; s < h->n_slot; ++s) {
+    int p, q;
+    if (s < n) { p = q = (int)s; }
+    else { p = h->pairs[s - n][0]; q = h->pairs[s - n][1]; }
+    const int d = p == q ? h->r[p] : h->r[p] + h->r[q];
+    const int D = round16(d);
+    h->sp[s] = p; h->sq[s] = q; h->sd[s] = d; h->sD[s] = D;
+    h->dmax = std::max(h->dmax, D);
+    h->k_off[s + 1] = h->k_off[s] + (int64_t)d * d;
+    h->x_off[s + 1] = h->x_off[s] + (int64_t)d * D;
+    h->kt_off[s + 1] = h->kt_off[s] + (int64_t)D * D;
+    h->et_off[s + 1] = h->et_off[s] + D;
+  }
+  h->k_elems = h->k_off[h->n_slot];
+  if (h->dmax > DMAX_SUPPORTED)
+    return h->fail(MBE3_EINVAL, "pair dimension %d exceeds the supported %d",
+                   h->dmax, DMAX_SUPPORTED);
+  // S/F block store: (x, x) and kept (x, y), x < y
+  h->sb_total = 0;
+  for (int x = 0; x < n; ++x)
+    for (int y : h->nbr[x])
+      if (y >= x) {
+        h->sb_off[key2(x, y)] = h->sb_total;
+        h->sb_total += (int64_t)h->r[x] * h->r[y];
+      }
+  return MBE3_OK;
+}
+
+int slot_of(const mbe3_handle *h, int a, int b) {
+  if (a == b) return a;
+  if (a > b) std::swap(a, b);
+  auto it = h->pair_slot.find(key2(a, b));
+  return it == h->pair_slot.end() ? -1 : it->second;
+}
+
+// Block source for S_(a,b) (or F) in the block store.
+BlockSrc bsrc(const mbe3_handle *h, int a, int b) {
+  BlockSrc s;
+  if (a <= b) {
+    s.off = h->sb_off.at(key2(a, b));
+    s.ld = h->r[b];
+    s.trans = 0;
+  } else {
+    s.off = h->sb_off.at(key2(b, a));
+    s.ld = h->r[a];
+    s.trans = 1;
+  }
+  return s;
+}
+
+std::vector<int> slot_orbs(const mbe3_handle *h, int s) {
+  if (h->sp[s] == h->sq[s]) return {h->sp[s]};
+  return {h->sp[s], h->sq[s]};
+}
+
+// Assembly task for V_A^T M V_B with A = orbitals of slot (or list), into
+// out_off with leading dimension ld_out; rows_out x cols_out region.
+AssembleTask asm_task(const mbe3_handle *h, const std::vector<int> &ro,
+                      const std::vector<int> &co, int src_buf, int out_buf,
+                      int64_t out_off, int ld_out, int rows_out, int cols_out) {
+  AssembleTask t;
+  std::memset(&t, 0, sizeof t);
+  t.out_off = out_off; t.ld_out = ld_out; t.src_buf = src_buf;
+  t.out_buf = out_buf;
+  t.nrb = (int)ro.size(); t.ncb = (int)co.size();
+  for (int a = 0; a < t.nrb; ++a) t.rsz[a] = h->r[ro[a]];
+  for (int b = 0; b < t.ncb; ++b) t.csz[b] = h->r[co[b]];
+  t.rows_out = rows_out; t.cols_out = cols_out;
+  for (int a = 0; a < t.nrb; ++a)
+    for (int b = 0; b < t.ncb; ++b) t.b[a][b] = bsrc(h, ro[a], co[b]);
+  return t;
+}
+
+int build_plans(mbe3_handle *h) {
+  const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
+  int rc;
+  std::vector<int32_t> rows;
+
+  // ---- projection: one GEMM per orbital, A rows gathered from Q ----
+  const int64_t slab_elems = (int64_t)nv * na;
+  if (!h->slab) {
+    int64_t nb = SLAB_BUDGET / (slab_elems * 8);
+    nb = std::max<int64_t>(1, std::min<int64_t>(nb, n));
+    h->slab_nb = (int)nb;
+  } else {
+    h->slab_nb = n;
+  }
+  for (int i0 = 0; i0 < n; i0 += h->slab_nb) {
+    const int i1 = std::min(n, i0 + h->slab_nb);
+    h->proj_batches.push_back({i0, i1});
+    std::vector<GemmTask> ts;
+    for (int i = i0; i < i1; ++i) {
+      GemmTask t = gemm(B_Q, 0, nv, 0, B_SLAB,
+                        (int64_t)(h->slab ? i : i - i0) * slab_elems, na, 0,
+                        B_GAMMA, h->g_off[i] * na, na,
+                        (int)(h->g_off[i + 1] - h->g_off[i]), na, nv);
+      t.a_rows = (int32_t)rows.size();
+      for (int x : h->nbr[i])
+        for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->q_off[x] + mu));
+      ts.push_back(t);
+    }
+    h->t_proj.push_back(finish_tasks(ts, GEMM_128x128));
+    h->n_proj.push_back((int)ts.size());
+    GemmTask *d = nullptr;
+    h->h_gemm.push_back({"project", ts});
+    if ((rc = upload(h, &d, ts))) return rc;
+    h->d_proj.push_back(d);
+  }
+
+  // ---- pair K: K_s = L R^T with gathered rows of gamma ----
+  {
+    std::vector<GemmTask> ts;
+    for (int64_t s = 0; s < h->n_slot; ++s) {
+      const int p = h->sp[s], q = h->sq[s], d = h->sd[s];
+      GemmTask t = gemm(B_GAMMA, 0, na, 0, B_GAMMA, 0, na, 1, B_K, h->k_off[s],
+                        d, d, d, na);
+      t.a_rows = (int32_t)rows.size();
+      for (int x : slot_orbs(h, (int)s))
+        for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->grow.at(key2(p, x)) + mu));
+      t.b_rows = (int32_t)rows.size();
+      for (int x : slot_orbs(h, (int)s))
+        for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
+      ts.push_back(t);
+    }
+    h->t_pk = finish_tasks(ts, GEMM_64x64);
+    h->n_pk = (int)ts.size();
+    h->h_gemm.push_back({"pair_K", ts});
+    if ((rc = upload(h, &h->d_pk, ts))) return rc;
+  }
+  h->n_rows = (int64_t)rows.size();
+  h->h_rows = rows;
+  if ((rc = upload(h, &h->d_rows, rows))) return rc;
+
+  // ---- S / F blocks ----
+  {
+    std::vector<GemmTask> ts;
+    for (int x = 0; x < n; ++x)
+      for (int y : h->nbr[x])
+        if (y >= x) {
+          const int64_t off = h->sb_off.at(key2(x, y));
+          ts.push_back(gemm(B_Q, h->q_off[x] * nv, nv, 0, B_Q, h->q_off[y] * nv, nv, 1,
+                            B_SS, off, h->r[y], h->r[x], h->r[y], nv));
+          ts.push_back(gemm(B_Q, h->q_off[x] * nv, nv, 0, B_EQ, h->q_off[y] * nv, nv, 1,
+                            B_FS, off, h->r[y], h->r[x], h->r[y], nv));
+        }
+    h->t_sf = finish_tasks(ts, GEMM_64x64);
+    h->n_sf = (int)ts.size();
+    h->h_gemm.push_back({"S/F blocks", ts});
+    if ((rc = upload(h, &h->d_sf, ts))) return rc;
+  }
+
+  // ---- pair 4-block S, F (k layout) and the basis pipeline ----
+  {
+    std::vector<AssembleTask> as;
+    std::vector<EigTask> e0, e1;
+    std::vector<GemmTask> m1, fpt, xt, m2, ktt;
+    for (int64_t s = 0; s < h->n_slot; ++s) {
+      const int d = h->sd[s], D = h->sD[s];
+      const auto o = slot_orbs(h, (int)s);
+      as.push_back(asm_task(h, o, o, 0, 0, h->k_off[s], d, d, d));  // S -> ps
+      as.push_back(asm_task(h, o, o, 1, 1, h->k_off[s], d, d, d));  // F -> pf
+      EigTask a;
+      a.a_off = h->k_off[s]; a.lda = d; a.n = d; a.D = D; a.slot = (int)s;
+      a.o_off = h->x_off[s]; a.e_off = h->et_off[s];
+      e0.push_back(a);
+      EigTask b = a;
+      b.a_off = h->kt_off[s]; b.lda = D; b.o_off = h->kt_off[s];
+      e1.push_back(b);
+      // M1 = F X0 (d x D) -> tmp (x layout)
+      m1.push_back(gemm(B_PF, h->k_off[s], d, 0, B_X0, h->x_off[s], D, 0, B_TMP,
+                        h->x_off[s], D, d, D, d));
+      // F' = X0^T M1 (D x D)
+      fpt.push_back(gemm(B_X0, h->x_off[s], D, 1, B_TMP, h->x_off[s], D, 0, B_FP,
+                         h->kt_off[s], D, D, D, d));
+      // X = X0 Z (d x D)
+      xt.push_back(gemm(B_X0, h->x_off[s], D, 0, B_Z, h->kt_off[s], D, 0, B_X,
+                        h->x_off[s], D, d, D, D));
+      // M2 = K X (d x D) -> tmp ; K~ = X^T M2 (D x D) -> kt
+      m2.push_back(gemm(B_K, h->k_off[s], d, 0, B_X, h->x_off[s], D, 0, B_TMP,
+                        h->x_off[s], D, d, D, d));
+      ktt.push_back(gemm(B_X, h->x_off[s], D, 1, B_TMP, h->x_off[s], D, 0, B_KT,
+                         h->kt_off[s], D, D, D, d));
+    }
+    h->n_asm_pair = (int)as.size();
+    if ((rc = upload(h, &h->d_asm_pair, as))) return rc;
+    if ((rc = upload(h, &h->d_eig0, e0))) return rc;
+    if ((rc = upload(h, &h->d_eig1, e1))) return rc;
+    h->t_m1 = finish_tasks(m1, GEMM_64x64);
+    h->t_fp = finish_tasks(fpt, GEMM_64x64);
+    h->t_x = finish_tasks(xt, GEMM_64x64);
+    h->t_m2 = finish_tasks(m2, GEMM_64x64);
+    h->t_kt = finish_tasks(ktt, GEMM_64x64);
+    h->h_gemm.push_back({"M1", m1});
+    h->h_gemm.push_back({"F'", fpt});
+    h->h_gemm.push_back({"X", xt});
+    h->h_gemm.push_back({"M2", m2});
+    h->h_gemm.push_back({"K~", ktt});
+    h->h_asm.push_back({{B_PS, B_PF}, as});
+    h->h_eig.push_back({0, e0});
+    h->h_eig.push_back({1, e1});
+    if ((rc = upload(h, &h->d_g_m1, m1))) return rc;
+    if ((rc = upload(h, &h->d_g_fp, fpt))) return rc;
+    if ((rc = upload(h, &h->d_g_x, xt))) return rc;
+    if ((rc = upload(h, &h->d_g_m2, m2))) return rc;
+    if ((rc = upload(h, &h->d_g_kt, ktt))) return rc;
+  }
+
+  // ---- pair-level S~ between a pair slot and its two diagonal slots ----
+  // For slot t = (p, q) and u in {p, q}:
+  //   A_tu = V_t^T Q_u (d_t x r_u), M = A_tu X_u (d_t x D_u),
+  //   S~_(t,u) = X_t^T M (D_t x D_u), S~_(u,t) = M^T X_t (D_u x D_t).
+  std::vector<int64_t> st0_tu(h->n_slot * 2, -1), st0_ut(h->n_slot * 2, -1);
+  int64_t st0_total = 0;
+  {
+    std::vector<AssembleTask> as;
+    std::vector<GemmTask> gm, g1, g2;
+    int64_t at_total = 0, mt_total = 0;
+    for (int64_t s = n; s < h->n_slot; ++s) {
+      const int dt = h->sd[s], Dt = h->sD[s];
+      const auto o = slot_orbs(h, (int)s);
+      for (int k = 0; k < 2; ++k) {
+        const int u = o[k];
+        const int ru = h->r[u], Du = h->sD[u];
+        as.push_back(asm_task(h, o, {u}, 0, 0, at_total, ru, dt, ru));
+        gm.push_back(gemm(B_AT, at_total, ru, 0, B_X, h->x_off[u], Du, 0, B_MT,
+                          mt_total, Du, dt, Du, ru));
+        st0_tu[2 * s + k] = st0_total;
+        g1.push_back(gemm(B_X, h->x_off[s], Dt, 1, B_MT, mt_total, Du, 0, B_ST0,
+                          st0_total, Du, Dt, Du, dt));
+        st0_total += (int64_t)Dt * Du;
+        st0_ut[2 * s + k] = st0_total;
+        g2.push_back(gemm(B_MT, mt_total, Du, 1, B_X, h->x_off[s], Dt, 0, B_ST0,
+                          st0_total, Dt, Du, Dt, dt));
+        st0_total += (int64_t)Du * Dt;
+        at_total += (int64_t)dt * ru;
+        mt_total += (int64_t)dt * Du;
+      }
+    }
+    h->n_asm_st = (int)as.size();
+    h->n_g_st = (int)gm.size();
+    h->t_stm = finish_tasks(gm, GEMM_64x64);
+    h->t_st1 = finish_tasks(g1, GEMM_64x64);
+    h->t_st2 = finish_tasks(g2, GEMM_64x64);
+    h->h_asm.push_back({{B_AT, -1}, as});
+    h->h_gemm.push_back({"S~ M", gm});
+    h->h_gemm.push_back({"S~ tu", g1});
+    h->h_gemm.push_back({"S~ ut", g2});
+    if ((rc = upload(h, &h->d_asm_st, as))) return rc;
+    if ((rc = upload(h, &h->d_g_stm, gm))) return rc;
+    if ((rc = upload(h, &h->d_g_st1, g1))) return rc;
+    if ((rc = upload(h, &h->d_g_st2, g2))) return rc;
+    h->at_total = at_total; h->mt_total = mt_total; h->st0_total = st0_total;
+    if ((rc = dev_alloc(h, &h->at, at_total))) return rc;
+    if ((rc = dev_alloc(h, &h->mt, mt_total))) return rc;
+    if ((rc = dev_alloc(h, &h->st0, st0_total))) return rc;
+  }
+
+  // ---- fragments: term tables and chunks ----
+  std::vector<int64_t> cost(h->frags.size());
+  for (size_t m = 0; m < h->frags.size(); ++m) {
+    int64_t c = 0;
+    for (int k = 0; k < 3; ++k)
+      if (h->frags[m][k] >= 0) c += h->sD[h->frags[m][k]];
+    const int nf = h->frags[m][2] >= 0 ? 3 : (h->frags[m][1] >= 0 ? 2 : 1);
+    cost[m] = c * c * c * (nf == 3 ? 18 : (nf == 2 ? 4 : 1));
+  }
+  std::vector<int> order(h->frags.size());
+  for (size_t m = 0; m < order.size(); ++m) order[m] = (int)m;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return cost[a] > cost[b]; });
+
+  Chunk cur;
+  std::vector<FragDesc> fds;
+  std::vector<Term> terms;
+  std::vector<AssembleTask> cas;
+  std::vector<GemmTask> cgm, cg1, cg2;
+  int64_t ca_total = 0, cm_total = 0, st1_total = 0;
+  int64_t max_ca = 1, max_cm = 1, max_st1 = 1;
+  auto flush = [&](void) -> int {
+    if (cur.frag_ids.empty()) return MBE3_OK;
+    cur.n_frag = (int)fds.size();
+    cur.n_asm = (int)cas.size();
+    cur.n_gemm = (int)cgm.size();
+    cur.tiles_m = finish_tasks(cgm, GEMM_64x64);
+    cur.tiles_s1 = finish_tasks(cg1, GEMM_64x64);
+    cur.tiles_s2 = finish_tasks(cg2, GEMM_64x64);
+    int rc2;
+    h->h_fds.push_back(fds);
+    h->h_terms.push_back(terms);
+    h->h_asm.push_back({{B_CA, -1}, cas});
+    h->h_gemm.push_back({"cross M", cgm});
+    h->h_gemm.push_back({"cross tu", cg1});
+    h->h_gemm.push_back({"cross ut", cg2});
+    if ((rc2 = upload(h, &cur.d_frags, fds))) return rc2;
+    if ((rc2 = upload(h, &cur.d_terms, terms))) return rc2;
+    if (!cas.empty()) {
+      if ((rc2 = upload(h, &cur.d_asm, cas))) return rc2;
+      if ((rc2 = upload(h, &cur.d_m, cgm))) return rc2;
+      if ((rc2 = upload(h, &cur.d_s1, cg1))) return rc2;
+      if ((rc2 = upload(h, &cur.d_s2, cg2))) return rc2;
+    }
+    max_ca = std::max(max_ca, ca_total);
+    max_cm = std::max(max_cm, cm_total);
+    max_st1 = std::max(max_st1, st1_total);
+    h->chunks.push_back(cur);
+    cur = Chunk();
+    fds.clear(); terms.clear(); cas.clear(); cgm.clear(); cg1.clear(); cg2.clear();
+    ca_total = cm_total = st1_total = 0;
+    return MBE3_OK;
+  };
+
+  for (int m : order) {
+    const auto &o = h->frags[m];
+    std::vector<int> F;
+    for (int k = 0; k < 3; ++k)
+      if (o[k] >= 0) F.push_back(o[k]);
+    const int nf = (int)F.size();
+    // local slots: diagonals, then pairs (ab, ac, bc)
+    std::vector<int> ls;
+    for (int x : F) ls.push_back(x);
+    for (int a = 0; a < nf; ++a)
+      for (int b = a + 1; b < nf; ++b) ls.push_back(slot_of(h, F[a], F[b]));
+    // cross S~ needed by a trimer (bytes of this fragment's chunk stores)
+    int64_t need = 0;
+    if (nf == 3) {
+      for (int a = 3; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b) {
+          const int64_t dt = h->sd[ls[a]], Dt = h->sD[ls[a]];
+          const int64_t ds = h->sd[ls[b]], Ds = h->sD[ls[b]];
+          need += (dt * ds + dt * Ds + 2 * Dt * Ds) * 8;
+        }
+    }
+    if (!cur.frag_ids.empty() &&
+        (ca_total + cm_total + st1_total) * 8 + need > CHUNK_BUDGET) {
+      if ((rc = flush())) return rc;
+    }
+    FragDesc fd;
+    std::memset(&fd, 0, sizeof fd);
+    fd.nt = (int)ls.size();
+    fd.frag = m;
+    fd.coef = h->coef[m];
+    int ny = 0;
+    for (int k = 0; k < fd.nt; ++k) {
+      fd.slot[k] = ls[k];
+      fd.ysub[k] = ny;
+      const int D = h->sD[ls[k]];
+      ny += D * D;
+      fd.sym[k] = k < nf ? 1 : 0;
+      fd.wgt[k] = k < nf ? 1 : 2;
+      cur.dmax = std::max(cur.dmax, D);
+    }
+    fd.ny = ny;
+    cur.ny_max = std::max(cur.ny_max, ny);
+    // cross S~ of this trimer: cross[a][b] = offset of row-major S~_(ls[a], ls[b])
+    int64_t cross[6][6];
+    for (auto &row : cross) for (auto &v : row) v = -1;
+    if (nf == 3) {
+      for (int a = 3; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b) {
+          const int t = ls[a], s = ls[b];
+          const int dt = h->sd[t], Dt = h->sD[t], ds = h->sd[s], Ds = h->sD[s];
+          cas.push_back(asm_task(h, slot_orbs(h, t), slot_orbs(h, s), 0, 0,
+                                 ca_total, ds, dt, ds));
+          // M = A X_s (dt x Ds)
+          cgm.push_back(gemm(B_CA, ca_total, ds, 0, B_X, h->x_off[s], Ds, 0, B_CM,
+                             cm_total, Ds, dt, Ds, ds));
+          cross[a][b] = st1_total;  // S~_(t,s) = X_t^T M  (Dt x Ds)
+          cg1.push_back(gemm(B_X, h->x_off[t], Dt, 1, B_CM, cm_total, Ds, 0, B_ST1,
+                             st1_total, Ds, Dt, Ds, dt));
+          st1_total += (int64_t)Dt * Ds;
+          cross[b][a] = st1_total;  // S~_(s,t) = M^T X_t  (Ds x Dt)
+          cg2.push_back(gemm(B_CM, cm_total, Ds, 1, B_X, h->x_off[t], Dt, 0, B_ST1,
+                             st1_total, Dt, Ds, Dt, dt));
+          st1_total += (int64_t)Ds * Dt;
+          ca_total += (int64_t)dt * ds;
+          cm_total += (int64_t)dt * Ds;
+        }
+    }
+    auto local = [&](int a, int b) {  // local index of slot (a, b) orbitals
+      const int s = slot_of(h, a, b);
+      for (int k = 0; k < fd.nt; ++k)
+        if (ls[k] == s) return k;
+      return -1;
+    };
+    // pair-level S~ offsets: row-major S~_(u,t) (diag u, pair t) and S~_(t,u)
+    auto st_ut = [&](int t, int u) {  // row-major S~_(u, t)
+      const int k = (h->sp[t] == u) ? 0 : 1;
+      return st0_ut[2 * t + k];
+    };
+    auto st_tu = [&](int t, int u) {  // row-major S~_(t, u)
+      const int k = (h->sp[t] == u) ? 0 : 1;
+      return st0_tu[2 * t + k];
+    };
+    fd.term_begin = (int)terms.size();
+    for (int tl = 0; tl < fd.nt; ++tl) {
+      const int t = ls[tl];
+      const int p = h->sp[t], q = h->sq[t];
+      if (p == q) {
+        for (int k : F) {
+          if (k == p) continue;
+          Term tm;
+          std::memset(&tm, 0, sizeof tm);
+          const int s = slot_of(h, p, k);
+          tm.target = tl; tm.src = local(p, k);
+          tm.fx = p; tm.fy = k;
+          tm.trans = k > p ? 1 : 0;  // T_kp from the stored (p,k)
+          tm.st_buf = 0;
+          tm.st_off = st_tu(s, p);   // row-major S~_(src=s, target=pp)
+          terms.push_back(tm);
+        }
+      } else {
+        // k = q in the first sum and k = p in the second (own diagonals)
+        Term tm;
+        std::memset(&tm, 0, sizeof tm);
+        tm.target = tl; tm.fx = p; tm.fy = q; tm.st_buf = 0; tm.trans = 0;
+        tm.src = local(q, q); tm.st_off = st_ut(t, q);
+        terms.push_back(tm);
+        tm.src = local(p, p); tm.st_off = st_ut(t, p);
+        terms.push_back(tm);
+        for (int r : F) {
+          if (r == p || r == q) continue;
+          // first sum, k = r: f_pr S_(pq,rq) T_rq S_(rq,pq)
+          const int lrq = local(r, q), lpr = local(p, r);
+          Term a;
+          std::memset(&a, 0, sizeof a);
+          a.target = tl; a.src = lrq; a.fx = p; a.fy = r;
+          a.trans = r > q ? 1 : 0; a.st_buf = 1;
+          a.st_off = cross[lrq][tl];
+          terms.push_back(a);
+          // second sum, k = r: f_rq S_(pq,pr) T_pr S_(pr,pq)
+          Term b;
+          std::memset(&b, 0, sizeof b);
+          b.target = tl; b.src = lpr; b.fx = r; b.fy = q;
+          b.trans = p > r ? 1 : 0; b.st_buf = 1;
+          b.st_off = cross[lpr][tl];
+          terms.push_back(b);
+        }
+      }
+    }
+    fd.term_end = (int)terms.size();
+    fds.push_back(fd);
+    cur.frag_ids.push_back(m);
+  }
+  if ((rc = flush())) return rc;
+  h->max_ca = max_ca; h->max_cm = max_cm; h->max_st1 = max_st1;
+  if ((rc = dev_alloc(h, &h->ca, max_ca))) return rc;
+  if ((rc = dev_alloc(h, &h->cm, max_cm))) return rc;
+  if ((rc = dev_alloc(h, &h->st1, max_st1))) return rc;
+
+  // ---- slots, energies ----
+  std::vector<SlotInfo> si(h->n_slot);
+  for (int64_t s = 0; s < h->n_slot; ++s) {
+    si[s].p = h->sp[s]; si[s].q = h->sq[s];
+    si[s].d = h->sd[s]; si[s].D = h->sD[s];
+    si[s].kt_off = h->kt_off[s]; si[s].et_off = h->et_off[s];
+  }
+  if ((rc = upload(h, &h->d_slots, si))) return rc;
+  if ((rc = upload(h, &h->d_coef, h->coef))) return rc;
+  {
+    std::map<std::array<int, 3>, int> idx;
+    for (size_t m = 0; m < h->frags.size(); ++m) idx[h->frags[m]] = (int)m;
+    std::vector<int32_t> sub(6 * h->frags.size(), -1);
+    for (size_t m = 0; m < h->frags.size(); ++m) {
+      const auto &o = h->frags[m];
+      if (o[1] < 0) continue;
+      sub[6 * m + 0] = idx.at({o[0], -1, -1});
+      sub[6 * m + 1] = idx.at({o[1], -1, -1});
+      if (o[2] >= 0) {
+        sub[6 * m + 2] = idx.at({o[2], -1, -1});
+        sub[6 * m + 3] = idx.at({o[0], o[1], -1});
+        sub[6 * m + 4] = idx.at({o[0], o[2], -1});
+        sub[6 * m + 5] = idx.at({o[1], o[2], -1});
+      }
+    }
+    if ((rc = upload(h, &h->d_sub, sub))) return rc;
+  }
+  return MBE3_OK;
+}
+
+int alloc_workspace(mbe3_handle *h) {
+  int rc;
+  const int64_t nv = h->n_vir, na = h->n_aux;
+  if (!h->slab && (rc = dev_alloc(h, &h->slab_buf, (int64_t)h->slab_nb * nv * na))) return rc;
+  const int64_t nq = h->q_off[h->n_occ];
+  if ((rc = dev_alloc(h, &h->eq, nq * nv))) return rc;
+  if ((rc = dev_alloc(h, &h->sstore, h->sb_total))) return rc;
+  if ((rc = dev_alloc(h, &h->fstore, h->sb_total))) return rc;
+  if ((rc = dev_alloc(h, &h->ps, h->k_elems))) return rc;
+  if ((rc = dev_alloc(h, &h->pf, h->k_elems))) return rc;
+  const int64_t nx = h->x_off[h->n_slot], nkt = h->kt_off[h->n_slot];
+  if ((rc = dev_alloc(h, &h->x0, nx))) return rc;
+  if ((rc = dev_alloc(h, &h->xb, nx))) return rc;
+  if ((rc = dev_alloc(h, &h->tmp, nx))) return rc;
+  if ((rc = dev_alloc(h, &h->fp, nkt))) return rc;
+  if ((rc = dev_alloc(h, &h->zb, nkt))) return rc;
+  if ((rc = dev_alloc(h, &h->kt, nkt))) return rc;
+  if ((rc = dev_alloc(h, &h->et, h->et_off[h->n_slot]))) return rc;
+  if ((rc = dev_alloc(h, &h->ev0, h->et_off[h->n_slot]))) return rc;
+  if ((rc = dev_alloc(h, &h->rank, h->n_slot))) return rc;
+  int ny_max = 0, dmax = 16;
+  for (auto &c : h->chunks) {
+    ny_max = std::max(ny_max, c.ny_max);
+    dmax = std::max(dmax, c.dmax);
+  }
+  h->scratch_stride = solve_scratch_doubles(ny_max, dmax);
+  h->scratch_stride = (h->scratch_stride + 31) & ~31LL;
+  if ((rc = dev_alloc(h, &h->scratch, h->scratch_stride * SOLVE_WG))) return rc;
+  if ((rc = dev_alloc(h, &h->status, 2 * SOLVE_WG))) return rc;
+  if ((rc = dev_alloc(h, &h->d_e3, 4))) return rc;
+  if (h->dry) return MBE3_OK;
+  HIP_TRY(h, hipHostMalloc((void **)&h->h_status, 2 * SOLVE_WG * sizeof(int32_t)));
+  HIP_TRY(h, hipHostMalloc((void **)&h->h_e3, 4 * sizeof(double)));
+  return MBE3_OK;
+}
+
+GemmBases bases(mbe3_handle *h) {
+  GemmBases b;
+  std::memset(&b, 0, sizeof b);
+  b.p[B_Q] = const_cast<double *>(h->Q);
+  b.p[B_EQ] = h->eq;
+  b.p[B_SLAB] = h->slab ? const_cast<double *>(h->slab) : h->slab_buf;
+  b.p[B_SS] = h->sstore;
+  b.p[B_FS] = h->fstore;
+  b.p[B_PS] = h->ps;
+  b.p[B_PF] = h->pf;
+  b.p[B_X0] = h->x0;
+  b.p[B_X] = h->xb;
+  b.p[B_TMP] = h->tmp;
+  b.p[B_FP] = h->fp;
+  b.p[B_Z] = h->zb;
+  b.p[B_KT] = h->kt;
+  b.p[B_AT] = h->at;
+  b.p[B_MT] = h->mt;
+  b.p[B_ST0] = h->st0;
+  b.p[B_CA] = h->ca;
+  b.p[B_CM] = h->cm;
+  b.p[B_ST1] = h->st1;
+  b.rows = h->d_rows;
+  return b;
+}
+
+int max_d(const mbe3_handle *h) {
+  int m = 1;
+  for (int64_t s = 0; s < h->n_slot; ++s) m = std::max(m, h->sd[s]);
+  return m;
+}
+
+// Pair bases (Algorithm 5 blocks, eq. prec_eig) -- needs only Q and eps.
+int prepare_bases(mbe3_handle *h) {
+  hipStream_t s = h->stream;
+  GemmBases b = bases(h);
+  const int64_t nq = h->q_off[h->n_occ];
+  HIP_TRY(h, launch_scale_rows(h->eq, h->Q, h->eps, nq, h->n_vir, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_sf, h->n_sf, h->t_sf, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_assemble(h->d_asm_pair, h->n_asm_pair, h->sstore, h->fstore,
+                             h->ps, h->pf, s));
+  const int md = max_d(h);
+  HIP_TRY(h, launch_jacobi(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
+                           h->rank, 0, h->tau_S, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_m1, (int)h->n_slot, h->t_m1, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_fp, (int)h->n_slot, h->t_fp, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_jacobi(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
+                           h->rank, 1, h->tau_S, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_x, (int)h->n_slot, h->t_x, b, GEMM_64x64, s));
+  return MBE3_OK;
+}
+
+// K~ = X^T K X and the pair-level S~ blocks.
+int prepare_pairs(mbe3_handle *h, const double *K) {
+  hipStream_t s = h->stream;
+  int rc = prepare_bases(h);
+  if (rc) return rc;
+  GemmBases b = bases(h);
+  b.p[B_K] = const_cast<double *>(K);
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_m2, (int)h->n_slot, h->t_m2, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_kt, (int)h->n_slot, h->t_kt, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_assemble(h->d_asm_st, h->n_asm_st, h->sstore, h->fstore, h->at,
+                             nullptr, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_stm, h->n_g_st, h->t_stm, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_st1, h->n_g_st, h->t_st1, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_gemm_tasks(h->d_g_st2, h->n_g_st, h->t_st2, b, GEMM_64x64, s));
+  return MBE3_OK;
+}
+
+// Host-side bounds check of every plan against the buffers it addresses,
+// run before any kernel of the plan is launched.  A failure here is a bug in
+// the planner, reported as MBE3_EINVAL.
+int validate_plans(mbe3_handle *h) {
+  const int64_t nv = h->n_vir, na = h->n_aux;
+  int64_t sz[B_COUNT];
+  sz[B_Q] = sz[B_EQ] = h->q_off[h->n_occ] * nv;
+  sz[B_SLAB] = (h->slab ? (int64_t)h->n_occ : (int64_t)h->slab_nb) * nv * na;
+  sz[B_GAMMA] = h->gamma_rows * na;
+  sz[B_K] = sz[B_PS] = sz[B_PF] = h->k_elems;
+  sz[B_SS] = sz[B_FS] = h->sb_total;
+  sz[B_X0] = sz[B_X] = sz[B_TMP] = h->x_off[h->n_slot];
+  sz[B_FP] = sz[B_Z] = sz[B_KT] = h->kt_off[h->n_slot];
+  sz[B_AT] = h->at_total;
+  sz[B_MT] = h->mt_total;
+  sz[B_ST0] = h->st0_total;
+  sz[B_CA] = h->max_ca;
+  sz[B_CM] = h->max_cm;
+  sz[B_ST1] = h->max_st1;
+  auto bad = [&](const std::string &what, size_t k) {
+    return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
+  };
+  for (auto &pl : h->h_gemm) {
+    const std::string &name = pl.first;
+    int64_t tb = 0;
+    for (size_t k = 0; k < pl.second.size(); ++k) {
+      const GemmTask &t = pl.second[k];
+      if (t.a_buf < 0 || t.a_buf >= B_COUNT || t.b_buf < 0 || t.b_buf >= B_COUNT ||
+          t.c_buf < 0 || t.c_buf >= B_COUNT)
+        return bad(name + " (buffer id)", k);
+      if (t.M < 1 || t.N < 1 || t.K < 1) return bad(name + " (empty)", k);
+      if (t.tile_begin != tb) return bad(name + " (tile prefix)", k);
+      const int b = name == "project" ? 128 : 64;
+      if (t.tiles_n != (t.N + b - 1) / b) return bad(name + " (tiles_n)", k);
+      tb += (int64_t)((t.M + b - 1) / b) * t.tiles_n;
+      auto rmax = [&](int32_t off, int n, int64_t &out) {
+        if (off < 0) { out = n - 1; return true; }
+        if ((int64_t)off + n > h->n_rows) return false;
+        int64_t m = -1;
+        for (int e = 0; e < n; ++e) {
+          if (h->h_rows[off + e] < 0) return false;
+          m = std::max<int64_t>(m, h->h_rows[off + e]);
+        }
+        out = m;
+        return true;
+      };
+      int64_t amax, bmax, r;
+      if (!t.transA) {
+        if (t.lda < t.K || !rmax(t.a_rows, t.M, r)) return bad(name + " (A rows)", k);
+        amax = t.a_off + r * t.lda + t.K - 1;
+      } else {
+        if (t.lda < t.M || t.a_rows >= 0) return bad(name + " (A^T)", k);
+        amax = t.a_off + (int64_t)(t.K - 1) * t.lda + t.M - 1;
+      }
+      if (!t.transB) {
+        if (t.ldb < t.N || t.b_rows >= 0) return bad(name + " (B)", k);
+        bmax = t.b_off + (int64_t)(t.K - 1) * t.ldb + t.N - 1;
+      } else {
+        if (t.ldb < t.K || !rmax(t.b_rows, t.N, r)) return bad(name + " (B^T rows)", k);
+        bmax = t.b_off + r * t.ldb + t.K - 1;
+      }
+      const int64_t cmax = t.c_off + (int64_t)(t.M - 1) * t.ldc + t.N - 1;
+      if (t.ldc < t.N) return bad(name + " (ldc)", k);
+      if (t.a_off < 0 || amax >= sz[t.a_buf]) return bad(name + " (A bounds)", k);
+      if (t.b_off < 0 || bmax >= sz[t.b_buf]) return bad(name + " (B bounds)", k);
+      if (t.c_off < 0 || cmax >= sz[t.c_buf]) return bad(name + " (C bounds)", k);
+    }
+  }
+  for (auto &pl : h->h_asm) {
+    for (size_t k = 0; k < pl.second.size(); ++k) {
+      const AssembleTask &t = pl.second[k];
+      const int64_t ob = pl.first[t.out_buf ? 1 : 0];
+      if (ob < 0 || ob >= B_COUNT) return bad("assemble (out id)", k);
+      if (t.ld_out < t.cols_out || t.rows_out < 1 || t.cols_out < 1)
+        return bad("assemble (shape)", k);
+      if (t.out_off < 0 || t.out_off + (int64_t)(t.rows_out - 1) * t.ld_out + t.cols_out - 1 >= sz[ob])
+        return bad("assemble (out bounds)", k);
+      if (t.nrb < 1 || t.nrb > 2 || t.ncb < 1 || t.ncb > 2) return bad("assemble (blocks)", k);
+      for (int a = 0; a < t.nrb; ++a)
+        for (int c = 0; c < t.ncb; ++c) {
+          const BlockSrc &b = t.b[a][c];
+          const int64_t last = b.trans ? b.off + (int64_t)(t.csz[c] - 1) * b.ld + t.rsz[a] - 1
+                                       : b.off + (int64_t)(t.rsz[a] - 1) * b.ld + t.csz[c] - 1;
+          if (b.off < 0 || last >= h->sb_total) return bad("assemble (source bounds)", k);
+        }
+    }
+  }
+  const int md = max_d(h);
+  for (auto &pl : h->h_eig) {
+    for (size_t k = 0; k < pl.second.size(); ++k) {
+      const EigTask &t = pl.second[k];
+      if (t.slot < 0 || t.slot >= h->n_slot || t.n > md || t.n > t.D) return bad("eigen (shape)", k);
+      if (t.e_off < 0 || t.e_off + t.D > h->et_off[h->n_slot]) return bad("eigen (values)", k);
+      if (pl.first == 0) {
+        if (t.lda < t.n || t.a_off + (int64_t)(t.n - 1) * t.lda + t.n - 1 >= sz[B_PS])
+          return bad("eigen (S input)", k);
+        if (t.o_off + (int64_t)t.n * t.D > sz[B_X0]) return bad("eigen (X0 output)", k);
+      } else {
+        if (t.lda < t.D || t.a_off + (int64_t)(t.D - 1) * t.lda + t.D - 1 >= sz[B_FP])
+          return bad("eigen (F input)", k);
+        if (t.o_off + (int64_t)t.D * t.D > sz[B_Z]) return bad("eigen (Z output)", k);
+      }
+    }
+  }
+  int dm = 16, nym = 0;
+  for (auto &c : h->chunks) { dm = std::max(dm, c.dmax); nym = std::max(nym, c.ny_max); }
+  const int64_t ny_cap = (h->scratch_stride - 2LL * dm * dm) / 4;
+  if (dm > DMAX_SUPPORTED || nym > ny_cap) return bad("solve (scratch)", 0);
+  for (size_t c = 0; c < h->h_fds.size(); ++c) {
+    const auto &fds = h->h_fds[c];
+    const auto &terms = h->h_terms[c];
+    for (size_t k = 0; k < fds.size(); ++k) {
+      const FragDesc &fd = fds[k];
+      if (!(fd.nt == 1 || fd.nt == 3 || fd.nt == 6)) return bad("solve (nt)", k);
+      if (fd.frag < 0 || fd.frag >= (int)h->frags.size()) return bad("solve (frag)", k);
+      if (fd.term_begin < 0 || fd.term_end < fd.term_begin || fd.term_end > (int)terms.size())
+        return bad("solve (terms)", k);
+      for (int l = 0; l < fd.nt; ++l) {
+        const int s = fd.slot[l];
+        if (s < 0 || s >= h->n_slot) return bad("solve (slot)", k);
+        const int D = h->sD[s];
+        if (D > dm || fd.ysub[l] < 0 || fd.ysub[l] + D * D > fd.ny) return bad("solve (ysub)", k);
+        if (h->kt_off[s] + (int64_t)D * D > sz[B_KT]) return bad("solve (K~)", k);
+      }
+      if (fd.ny > ny_cap) return bad("solve (ny)", k);
+      for (int e = fd.term_begin; e < fd.term_end; ++e) {
+        const Term &t = terms[e];
+        if (t.target < 0 || t.target >= fd.nt || t.src < 0 || t.src >= fd.nt)
+          return bad("solve (term slots)", k);
+        if (t.fx < 0 || t.fx >= h->n_occ || t.fy < 0 || t.fy >= h->n_occ)
+          return bad("solve (term f)", k);
+        const int64_t dt = h->sD[fd.slot[t.target]], ds = h->sD[fd.slot[t.src]];
+        const int64_t lim = t.st_buf ? sz[B_ST1] : sz[B_ST0];
+        if (t.st_off < 0 || t.st_off + ds * dt > lim) return bad("solve (S~ bounds)", k);
+      }
+    }
+  }
+  return MBE3_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+static thread_local std::string g_create_error = "no handle";
+
+extern "C" {
+
+int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
+  if (!out) return MBE3_EINVAL;
+  *out = nullptr;
+  mbe3_handle *h = new (std::nothrow) mbe3_handle();
+  if (!h) return MBE3_ENOMEM;
+  h->stream = (hipStream_t)stream;
+  int rc = validate_and_copy(h, p);
+  if (!rc) rc = build_layout(h);
+  if (!rc) rc = build_plans(h);
+  if (!rc) rc = alloc_workspace(h);
+  if (!rc) rc = validate_plans(h);
+  if (rc) {
+    g_create_error = h->err;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MBE3_OK;
+}
+
+int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out) {
+  mbe3_handle *h = new (std::nothrow) mbe3_handle();
+  if (!h) return MBE3_ENOMEM;
+  h->dry = true;
+  int rc = validate_and_copy(h, p);
+  if (!rc) rc = build_layout(h);
+  if (!rc) rc = build_plans(h);
+  if (!rc) rc = alloc_workspace(h);
+  if (!rc) rc = validate_plans(h);
+  if (!rc && out) mbe3_get_layout(h, out);
+  g_create_error = rc ? h->err : std::string("ok");
+  delete h;
+  return rc;
+}
+
+int mbe3_destroy(mbe3_handle *h) {
+  if (!h) return MBE3_EINVAL;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return MBE3_OK;
+}
+
+const char *mbe3_last_error(const mbe3_handle *h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+int mbe3_get_layout(const mbe3_handle *h, mbe3_layout *o) {
+  if (!h || !o) return MBE3_EINVAL;
+  o->n_slot = h->n_slot;
+  o->gamma_rows = h->gamma_rows;
+  o->gamma_elems = h->gamma_rows * h->n_aux;
+  o->k_elems = h->k_elems;
+  o->n_frag = (int64_t)h->frags.size();
+  return MBE3_OK;
+}
+
+int mbe3_gamma_offsets(const mbe3_handle *h, int64_t *o) {
+  if (!h || !o) return MBE3_EINVAL;
+  std::memcpy(o, h->g_off.data(), h->g_off.size() * sizeof(int64_t));
+  return MBE3_OK;
+}
+
+int mbe3_k_offsets(const mbe3_handle *h, int64_t *o) {
+  if (!h || !o) return MBE3_EINVAL;
+  std::memcpy(o, h->k_off.data(), h->k_off.size() * sizeof(int64_t));
+  return MBE3_OK;
+}
+
+int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff) {
+  if (!h || !xoff || !eoff) return MBE3_EINVAL;
+  std::memcpy(xoff, h->x_off.data(), h->x_off.size() * sizeof(int64_t));
+  std::memcpy(eoff, h->et_off.data(), h->et_off.size() * sizeof(int64_t));
+  return MBE3_OK;
+}
+
+int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems) {
+  if (!h) return MBE3_EINVAL;
+  if (!gamma || gamma_elems < h->gamma_rows * h->n_aux)
+    return h->fail(MBE3_EINVAL, "gamma needs %lld doubles, got %lld",
+                   (long long)(h->gamma_rows * h->n_aux), (long long)gamma_elems);
+  hipStream_t s = h->stream;
+  GemmBases b = bases(h);
+  b.p[B_GAMMA] = gamma;
+  for (size_t k = 0; k < h->proj_batches.size(); ++k) {
+    const int i0 = h->proj_batches[k].first, i1 = h->proj_batches[k].second;
+    if (!h->slab)
+      HIP_TRY(h, launch_regen_slab(h->slab_buf, i0, i1 - i0, h->n_vir, h->n_aux,
+                                   h->seed, h->w_ia, h->w_iP, s));
+    HIP_TRY(h, launch_gemm_tasks(h->d_proj[k], h->n_proj[k], h->t_proj[k], b,
+                                 GEMM_128x128, s));
+  }
+  return MBE3_OK;
+}
+
+int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems) {
+  if (!h) return MBE3_EINVAL;
+  if (!gamma || !K || k_elems < h->k_elems)
+    return h->fail(MBE3_EINVAL, "K needs %lld doubles, got %lld",
+                   (long long)h->k_elems, (long long)k_elems);
+  GemmBases b = bases(h);
+  b.p[B_GAMMA] = const_cast<double *>(gamma);
+  b.p[B_K] = K;
+  HIP_TRY(h, launch_gemm_tasks(h->d_pk, h->n_pk, h->t_pk, b, GEMM_64x64, h->stream));
+  return MBE3_OK;
+}
+
+int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
+                   int32_t *iters, double *W) {
+  if (!h) return MBE3_EINVAL;
+  if (!K || !e_frag || !iters) return h->fail(MBE3_EINVAL, "K, e_frag, iters required");
+  if (W) return h->fail(MBE3_EINVAL, "multiplier output is not available in this build");
+  hipStream_t s = h->stream;
+  int rc = prepare_pairs(h, K);
+  if (rc) return rc;
+  GemmBases b = bases(h);
+  HIP_TRY(h, launch_fill_i32(h->status, 0, 2 * SOLVE_WG, s));
+  for (auto &c : h->chunks) {
+    if (c.n_asm) {
+      HIP_TRY(h, launch_assemble(c.d_asm, c.n_asm, h->sstore, h->fstore, h->ca,
+                                 nullptr, s));
+      HIP_TRY(h, launch_gemm_tasks(c.d_m, c.n_gemm, c.tiles_m, b, GEMM_64x64, s));
+      HIP_TRY(h, launch_gemm_tasks(c.d_s1, c.n_gemm, c.tiles_s1, b, GEMM_64x64, s));
+      HIP_TRY(h, launch_gemm_tasks(c.d_s2, c.n_gemm, c.tiles_s2, b, GEMM_64x64, s));
+    }
+    SolveArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.frags = c.d_frags;
+    a.terms = c.d_terms;
+    a.slots = h->d_slots;
+    a.kt = h->kt;
+    a.et = h->et;
+    a.f_occ = h->f;
+    a.st0 = h->st0;
+    a.st1 = h->st1;
+    a.scratch = h->scratch;
+    a.scratch_stride = h->scratch_stride;
+    a.n_frag = c.n_frag;
+    a.n_occ = h->n_occ;
+    a.max_iter = h->max_iter;
+    a.tol = h->tol;
+    a.e_frag = e_frag;
+    a.iters = iters;
+    a.w_store = nullptr;
+    a.status = h->status;
+    // the scratch layout is fixed by the largest chunk (dmax / ny_max)
+    int dm = 16, nym = 0;
+    for (auto &cc : h->chunks) { dm = std::max(dm, cc.dmax); nym = std::max(nym, cc.ny_max); }
+    a.dmax = dm;
+    const int nwg = std::min(SOLVE_WG, c.n_frag);
+    HIP_TRY(h, launch_solve(a, nwg, s));
+  }
+  HIP_TRY(h, hipMemcpyAsync(h->h_status, h->status, 2 * SOLVE_WG * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  int bad = 0, nconv = 0;
+  for (int k = 0; k < SOLVE_WG; ++k) {
+    bad |= h->h_status[2 * k];
+    nconv |= h->h_status[2 * k + 1];
+  }
+  if (bad) return h->fail(MBE3_ENONFINITE, "non-finite residual in some fragment (e_frag = NaN)");
+  if (nconv) return h->fail(MBE3_ENOCONV, "some fragment did not converge in %d updates (iters < 0)",
+                            h->max_iter);
+  return MBE3_OK;
+}
+
+int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
+                double *incr) {
+  if (!h) return MBE3_EINVAL;
+  if (!e_frag || !e_total) return h->fail(MBE3_EINVAL, "e_frag and e_total required");
+  hipStream_t s = h->stream;
+  const int64_t n = (int64_t)h->frags.size();
+  HIP_TRY(h, launch_mbe_sum(e_frag, h->d_coef, n, h->d_e3, s));
+  if (incr) HIP_TRY(h, launch_increments(e_frag, h->d_sub, n, incr, s));
+  HIP_TRY(h, hipMemcpyAsync(h->h_e3, h->d_e3, 3 * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  *e_total = h->h_e3[0];
+  if (!std::isfinite(*e_total))
+    return h->fail(MBE3_ENONFINITE, "MBE(3) energy is not finite");
+  return MBE3_OK;
+}
+
+int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank) {
+  if (!h) return MBE3_EINVAL;
+  if (!X || !eps_t || !rank) return h->fail(MBE3_EINVAL, "X, eps_t, rank required");
+  int rc = prepare_bases(h);
+  if (rc) return rc;
+  hipStream_t s = h->stream;
+  HIP_TRY(h, hipMemcpyAsync(X, h->xb, h->x_off[h->n_slot] * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(eps_t, h->et, h->et_off[h->n_slot] * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(rank, h->rank, h->n_slot * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, s));
+  return MBE3_OK;
+}
+
+}  // extern "C"

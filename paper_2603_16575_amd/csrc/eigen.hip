@@ -1,0 +1,205 @@
+// Batched symmetric eigensolver for the pair preconditioner (eq. prec_eig):
+// one workgroup per pair matrix, cyclic Jacobi with the round-robin
+// (circle) ordering so that n/2 disjoint rotations run concurrently, matrix
+// and eigenvectors resident in LDS.  The paper also diagonalises each pair
+// on one thread block with Jacobi; here the generalized problem is reduced by
+// canonical orthogonalisation (two Jacobi solves) instead of a Cholesky
+// factor, so rank-deficient pair overlaps are handled by dropping
+// eigenvalues <= tau.
+//
+// Rotation (Golub & Van Loan, sym.schur2): for a_pq != 0,
+//   tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+//   c = 1 / sqrt(1 + t^2), s = t c, and A <- J^T A J with J_pp = J_qq = c,
+//   J_pq = s, J_qp = -s, which zeroes a_pq.
+#include "internal.hpp"
+
+namespace mbe3 {
+
+static constexpr int JAC_MAX_SWEEPS = 40;
+static constexpr double EV_SENTINEL = 1e30;
+
+__device__ double block_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void jacobi_kernel(
+    const EigTask *__restrict__ tasks, const double *__restrict__ in,
+    double *__restrict__ out, double *__restrict__ evals,
+    int32_t *__restrict__ rank, int mode, double tau) {
+  extern __shared__ double sm[];
+  const EigTask t = tasks[blockIdx.x];
+  const int n = mode == 0 ? t.n : rank[t.slot];
+  const int D = t.D;
+  const int ld = n + 1;
+  const int nh = (n + 1) >> 1;  // rotations per round
+  double *A = sm;
+  double *V = A + (size_t)n * ld;
+  double *cs_c = V + (size_t)n * ld;
+  double *cs_s = cs_c + nh + 1;
+  double *lam = cs_s + nh + 1;
+  double *red = lam + n + 1;
+  int *pq = (int *)(red + 8);
+  int *perm = pq + 2 * (nh + 1);
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+
+  for (int e = tid; e < n * n; e += nt) {
+    const int r = e / n, c = e - r * n;
+    A[r * ld + c] = in[t.a_off + (int64_t)r * t.lda + c];
+    V[r * ld + c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  const int nn = n + (n & 1);
+  for (int sweep = 0; sweep < JAC_MAX_SWEEPS && n > 1; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n * n; e += nt) {
+      const int r = e / n, c = e - r * n;
+      const double a = A[r * ld + c];
+      tot += a * a;
+      if (r != c) off += a * a;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (!(off > 1e-30 * tot)) break;  // off-diagonal norm <= 1e-15 ||A||
+    for (int round = 0; round < nn - 1; ++round) {
+      if (tid < nn / 2) {
+        const int k = tid;
+        int a, b;
+        if (k == 0) {
+          a = round;
+          b = nn - 1;
+        } else {
+          a = (round + k) % (nn - 1);
+          b = (round - k + nn - 1) % (nn - 1);
+        }
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * ld + q];
+          if (apq != 0.0) {
+            const double th = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+            double tt;
+            if (fabs(th) > 1e150)
+              tt = 0.5 / th;
+            else
+              tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        pq[2 * k] = p;
+        pq[2 * k + 1] = q;
+        cs_c[k] = c;
+        cs_s[k] = s;
+      }
+      __syncthreads();
+      const int np = nn / 2;
+      for (int e = tid; e < np * n; e += nt) {  // A <- J^T A (rows)
+        const int k = e / n, j = e - k * n;
+        const int p = pq[2 * k], q = pq[2 * k + 1];
+        const double s = cs_s[k];
+        if (q < n && s != 0.0) {
+          const double c = cs_c[k];
+          const double ap = A[p * ld + j], aq = A[q * ld + j];
+          A[p * ld + j] = c * ap - s * aq;
+          A[q * ld + j] = s * ap + c * aq;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < np * n; e += nt) {  // A <- A J, V <- V J (columns)
+        const int k = e / n, i = e - k * n;
+        const int p = pq[2 * k], q = pq[2 * k + 1];
+        const double s = cs_s[k];
+        if (q < n && s != 0.0) {
+          const double c = cs_c[k];
+          const double ap = A[i * ld + p], aq = A[i * ld + q];
+          A[i * ld + p] = c * ap - s * aq;
+          A[i * ld + q] = s * ap + c * aq;
+          const double vp = V[i * ld + p], vq = V[i * ld + q];
+          V[i * ld + p] = c * vp - s * vq;
+          V[i * ld + q] = s * vp + c * vq;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // eigenvalues and ascending order (ties by index)
+  for (int i = tid; i < n; i += nt) lam[i] = A[i * ld + i];
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    const double li = lam[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = lam[j];
+      r += (lj < li) || (lj == li && j < i);
+    }
+    perm[r] = i;
+  }
+  __syncthreads();
+
+  if (mode == 0) {
+    __shared__ int first_kept;
+    if (tid == 0) {
+      int f = n;
+      for (int r = 0; r < n; ++r)
+        if (lam[perm[r]] > tau) { f = r; break; }
+      first_kept = f;
+      rank[t.slot] = n - f;
+    }
+    __syncthreads();
+    const int f = first_kept, nk = n - f;
+    for (int e = tid; e < n * D; e += nt) {
+      const int r = e / D, c = e - r * D;
+      double v = 0.0;
+      if (c < nk) {
+        const int src = perm[f + c];
+        v = V[r * ld + src] / sqrt(lam[src]);
+      }
+      out[t.o_off + (int64_t)r * D + c] = v;
+    }
+    for (int c = tid; c < D; c += nt)
+      evals[t.e_off + c] = c < nk ? lam[perm[f + c]] : EV_SENTINEL;
+  } else {
+    for (int e = tid; e < D * D; e += nt) {
+      const int r = e / D, c = e - r * D;
+      double v = 0.0;
+      if (r < n && c < n) v = V[r * ld + perm[c]];
+      out[t.o_off + (int64_t)r * D + c] = v;
+    }
+    for (int c = tid; c < D; c += nt)
+      evals[t.e_off + c] = c < n ? lam[perm[c]] : EV_SENTINEL;
+  }
+}
+
+static size_t jacobi_smem(int n) {
+  const int ld = n + 1, nh = (n + 1) / 2;
+  return sizeof(double) * ((size_t)2 * n * ld + 2 * (nh + 1) + (n + 1) + 8) +
+         sizeof(int) * (2 * (nh + 1) + n + 1);
+}
+
+hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
+                         const double *in, double *out, double *evals,
+                         int32_t *rank, int mode, double tau, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  const size_t smem = jacobi_smem(max_n);
+  if (smem > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void *)jacobi_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(n_tasks), dim3(256), smem, s, d_tasks,
+                     in, out, evals, rank, mode, tau);
+  return hipGetLastError();
+}
+
+}  // namespace mbe3

@@ -1,0 +1,170 @@
+// Grouped FP64 GEMM engine on the CDNA matrix cores (v_mfma_f64_16x16x4).
+//
+// One workgroup (4 wave64) computes one BM x BN tile of one task.  Operand
+// tiles of depth 16 are staged through LDS with coalesced global reads
+// (k-contiguous or m/n-contiguous depending on the transpose flags) and laid
+// out k-major so that each MFMA operand read is 16 consecutive doubles.
+// Rows of A (and rows of a transposed B) may be gathered through an index
+// list, which lets one task project a slab onto the OSVs of all neighbours
+// of an orbital, or form a 4-block pair K from two scattered row blocks.
+#include "internal.hpp"
+
+namespace mbe3 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_tasks_kernel(
+    const GemmTask *__restrict__ tasks, int n_tasks, GemmBases bases) {
+  constexpr int BK = 16;
+  constexpr int PA = BM + 4;
+  constexpr int PB = BN + 4;
+  __shared__ double As[BK * PA];
+  __shared__ double Bs[BK * PB];
+
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = n_tasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmTask t = tasks[lo];
+  const int64_t local = tile - t.tile_begin;
+  const int m0 = (int)(local / t.tiles_n) * BM;
+  const int n0 = (int)(local % t.tiles_n) * BN;
+  const double *__restrict__ A = bases.p[t.a_buf] + t.a_off;
+  const double *__restrict__ B = bases.p[t.b_buf] + t.b_off;
+  double *__restrict__ C = bases.p[t.c_buf] + t.c_off;
+  const int32_t *__restrict__ rows = bases.rows;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  constexpr int EA = BM * BK / 256;  // A elements per thread
+  constexpr int EB = BN * BK / 256;
+
+  // Per-thread physical row for a k-contiguous A load (transA = 0).
+  const int a_tpr = BK / EA;
+  const int a_r = tid / a_tpr, a_k = (tid % a_tpr) * EA;
+  int64_t a_row = -1;
+  if (!t.transA && m0 + a_r < t.M)
+    a_row = (t.a_rows >= 0) ? rows[t.a_rows + m0 + a_r] : (m0 + a_r);
+  const int b_tpr = BK / EB;
+  const int b_r = tid / b_tpr, b_k = (tid % b_tpr) * EB;
+  int64_t b_row = -1;
+  if (t.transB && n0 + b_r < t.N)
+    b_row = (t.b_rows >= 0) ? rows[t.b_rows + n0 + b_r] : (n0 + b_r);
+
+  for (int k0 = 0; k0 < t.K; k0 += BK) {
+    // ---- stage A (BM x BK) as As[k][m] ----
+    if (!t.transA) {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        const int k = k0 + a_k + e;
+        double v = 0.0;
+        if (a_row >= 0 && k < t.K) v = A[a_row * (int64_t)t.lda + k];
+        As[(a_k + e) * PA + a_r] = v;
+      }
+    } else {
+      const int tpk = BM / EA;
+      const int kk = tid / tpk, mm = (tid % tpk) * EA;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        const int m = m0 + mm + e;
+        double v = 0.0;
+        if (m < t.M && k < t.K) v = A[(int64_t)k * t.lda + m];
+        As[kk * PA + mm + e] = v;
+      }
+    }
+    // ---- stage B (BK x BN) as Bs[k][n] ----
+    if (!t.transB) {
+      const int tpk = BN / EB;
+      const int kk = tid / tpk, nn = (tid % tpk) * EB;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        const int n = n0 + nn + e;
+        double v = 0.0;
+        if (n < t.N && k < t.K) v = B[(int64_t)k * t.ldb + n];
+        Bs[kk * PB + nn + e] = v;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        const int k = k0 + b_k + e;
+        double v = 0.0;
+        if (b_row >= 0 && k < t.K) v = B[b_row * (int64_t)t.ldb + k];
+        Bs[(b_k + e) * PB + b_r] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[kr * PA + wr * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[kr * PB + wc * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: D layout of v_mfma_f64_16x16x4: register v of lane l holds
+  //      row (l / 16) + 4 v, column l % 16
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = n0 + wc * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wr * WM + i * 16 + (lane >> 4) + 4 * v;
+        if (m < t.M && n < t.N) {
+          double *c = C + (int64_t)m * t.ldc + n;
+          double r = t.alpha * acc[i][j][v];
+          if (t.beta != 0.0) r += t.beta * *c;
+          *c = r;
+        }
+      }
+    }
+}
+
+int64_t gemm_tile_count(const GemmTask &t, GemmShape shape) {
+  const int bm = shape == GEMM_128x128 ? 128 : 64;
+  const int bn = bm;
+  return (int64_t)((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
+}
+
+hipError_t launch_gemm_tasks(const GemmTask *d_tasks, int n_tasks,
+                             int64_t n_tiles, const GemmBases &bases,
+                             GemmShape shape, hipStream_t s) {
+  if (n_tasks <= 0 || n_tiles <= 0) return hipSuccess;
+  if (n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)n_tiles), block(256);
+  if (shape == GEMM_128x128)
+    hipLaunchKernelGGL((gemm_tasks_kernel<128, 128>), grid, block, 0, s,
+                       d_tasks, n_tasks, bases);
+  else
+    hipLaunchKernelGGL((gemm_tasks_kernel<64, 64>), grid, block, 0, s,
+                       d_tasks, n_tasks, bases);
+  return hipGetLastError();
+}
+
+}  // namespace mbe3

@@ -1,0 +1,162 @@
+// Internal declarations shared by the HIP translation units of libmbe3osv.
+// Each .hip file owns its kernels and exposes host launchers declared here.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbe3 {
+
+// ---------------------------------------------------------------------------
+// Grouped FP64 GEMM engine (gemm.hip)
+//   C = alpha * op(A) op(B) + beta * C   for every task of a list, one
+//   workgroup per BM x BN output tile.  Operands are addressed relative to a
+//   small table of base pointers so that plans built once at create time can
+//   be replayed on caller buffers.
+// ---------------------------------------------------------------------------
+enum { NBASE = 24 };
+struct GemmBases {
+  double *p[NBASE];
+  const int32_t *rows;  // row-gather indices (see a_rows / b_rows)
+};
+
+struct GemmTask {
+  int64_t a_off, b_off, c_off;  // element offsets into bases.p[*_buf]
+  int64_t tile_begin;           // first tile of this task (prefix sum)
+  int32_t a_buf, b_buf, c_buf;
+  int32_t a_rows;  // >= 0: logical row m of A (transA = 0) is physical row
+                   // rows[a_rows + m]; -1: identity
+  int32_t b_rows;  // >= 0: logical column n of B (transB = 1, B stored as
+                   // rows) is physical row rows[b_rows + n]; -1: identity
+  int32_t M, N, K, lda, ldb, ldc;
+  int32_t transA, transB;
+  int32_t tiles_n;
+  int32_t pad_;
+  double alpha, beta;
+};
+
+// Tile shape ids for launch_gemm_tasks.
+enum GemmShape { GEMM_64x64 = 0, GEMM_128x128 = 1 };
+int64_t gemm_tile_count(const GemmTask &t, GemmShape shape);
+hipError_t launch_gemm_tasks(const GemmTask *d_tasks, int n_tasks,
+                             int64_t n_tiles, const GemmBases &bases,
+                             GemmShape shape, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Slab regeneration (regen.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
+                             uint64_t seed, const double *w_ia,
+                             const double *w_iP, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Block assembly (prep.hip): out[r][c] for a matrix made of up to 2 x 2
+// blocks of the S or F block store (or identity-free zero padding).
+// ---------------------------------------------------------------------------
+struct BlockSrc {
+  int64_t off;   // offset of the source block (r_x x r_y row-major, ld = r_y)
+  int32_t ld;    // leading dimension of the stored block
+  int32_t trans; // 1: read the stored block transposed
+};
+struct AssembleTask {
+  int64_t out_off;   // into the output base
+  int32_t ld_out;    // output leading dimension
+  int32_t nrb, ncb;  // number of row / column blocks (1 or 2)
+  int32_t rsz[2], csz[2];  // block sizes
+  int32_t rows_out, cols_out;  // total written region (>= sum of sizes:
+                               // the remainder is zero-filled)
+  int32_t src_buf;   // 0: S store, 1: F store
+  int32_t out_buf;   // 0: out0, 1: out1
+  BlockSrc b[2][2];
+};
+hipError_t launch_assemble(const AssembleTask *d_tasks, int n_tasks,
+                           const double *sstore, const double *fstore,
+                           double *out0, double *out1, hipStream_t s);
+hipError_t launch_scale_rows(double *out, const double *Q, const double *eps,
+                             int64_t rows, int n_vir, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched symmetric Jacobi eigensolver (eigen.hip)
+// ---------------------------------------------------------------------------
+struct EigTask {
+  int64_t a_off;    // input matrix (n x n, lda) in the input base
+  int64_t o_off;    // output vectors (n_out x D, ld D) in the output base
+  int64_t e_off;    // eigenvalues (D) in the eigenvalue base
+  int32_t n;        // matrix order (mode 0); for mode 1 read from rank[slot]
+  int32_t lda;
+  int32_t D;        // padded column count of the outputs
+  int32_t slot;     // slot id (rank array index)
+};
+// mode 0: overlap step.  Writes X0 = U_keep s^-1/2 (kept eigenvalues > tau,
+//         ascending), zero columns up to D, rank[slot] = kept count;
+//         eigenvalue array receives the kept eigenvalues (sentinel after).
+// mode 1: Fock step.  Order = rank[slot].  Writes Z (D x D: eigenvectors in
+//         the leading rank x rank block, zero elsewhere) and eps~ ascending
+//         (sentinel 1e30 beyond rank).
+hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
+                         const double *in, double *out, double *evals,
+                         int32_t *rank, int mode, double tau,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Fragment solver (solve.hip)
+// ---------------------------------------------------------------------------
+struct SlotInfo {
+  int32_t p, q;      // orbitals (p == q for diagonal slots)
+  int32_t d, D;      // pair-domain dimension and padded X-basis dimension
+  int64_t kt_off;    // K~ = X^T K X (D x D) in the K~ store
+  int64_t et_off;    // eps~ (D) in the eps~ store
+};
+struct FragDesc {
+  int32_t nt;           // number of pair slots (1, 3 or 6)
+  int32_t frag;         // fragment index in the caller's list
+  int32_t term_begin, term_end;
+  int32_t slot[6];      // global slot ids, order: diagonals then pairs
+  int32_t ysub[6];      // offset of each slot's D x D block in Y scratch
+  int32_t sym[6];       // 1 for diagonal slots (residual symmetrised)
+  int32_t wgt[6];       // energy weight 1 (diagonal) or 2 (pair)
+  int32_t ny;           // sum of D^2 over the fragment's slots
+  int32_t pad_;
+  double coef;          // MBE(3) coefficient c_F
+};
+struct Term {
+  int32_t target, src;  // local slot indices within the fragment
+  int32_t fx, fy;       // coefficient f_occ[fx][fy]
+  int32_t trans;        // use Y_src^T
+  int32_t st_buf;       // 0: pair-level S~ store, 1: per-chunk cross store
+  int64_t st_off;       // row-major S~_(src,target)  (D_src x D_target)
+};
+struct SolveArgs {
+  const FragDesc *frags;
+  const Term *terms;
+  const SlotInfo *slots;
+  const double *kt;      // K~ store
+  const double *et;      // eps~ store
+  const double *f_occ;
+  const double *st0;     // pair-level S~ store
+  const double *st1;     // cross S~ store of this chunk
+  double *scratch;       // per-workgroup scratch
+  int64_t scratch_stride;  // doubles per workgroup
+  int32_t n_frag;        // fragments in this chunk
+  int32_t n_occ;
+  int32_t max_iter;
+  int32_t dmax;          // largest D in the chunk
+  double tol;
+  double *e_frag;
+  int32_t *iters;
+  double *w_store;       // MBE multipliers in the K~ layout (X basis) or null
+  int32_t *status;       // [2 * workgroup]: non-finite seen, non-converged seen
+};
+hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s);
+int64_t solve_scratch_doubles(int ny_max, int dmax);
+
+// ---------------------------------------------------------------------------
+// Reductions (reduce.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_mbe_sum(const double *e_frag, const double *coef, int64_t n,
+                          double *out2, hipStream_t s);
+hipError_t launch_increments(const double *e_frag, const int32_t *sub,
+                             int64_t n, double *incr, hipStream_t s);
+hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace mbe3

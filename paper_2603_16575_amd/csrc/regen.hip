@@ -1,0 +1,69 @@
+// Counter-based regeneration of the RI slabs (ia|P), standing in for the
+// paper's direct Gamma_i generator (Algorithm 1): nothing is stored between
+// uses, every element is a pure function of (seed, i, a, P).
+//
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128-bit products with the Philox multipliers, high halves xored into
+// the other words with the round key, key bumped by the Weyl constants
+// between rounds.  Box-Muller (1958) on the top 53 bits of words 0 and 1.
+// One thread per element; consecutive threads take consecutive P so the
+// slab is written as coalesced rows of the [n_vir][n_aux] tile.
+#include "internal.hpp"
+
+namespace mbe3 {
+
+__device__ __forceinline__ void philox4x64_10(uint64_t &c0, uint64_t &c1,
+                                              uint64_t &c2, uint64_t &c3,
+                                              uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+}
+
+__device__ __forceinline__ double box_muller(uint64_t w0, uint64_t w1) {
+  const double u1 = ((double)(w0 >> 11) + 0.5) * 0x1p-53;
+  const double u2 = (double)(w1 >> 11) * 0x1p-53;
+  return sqrt(-2.0 * log(u1)) * cos((2.0 * M_PI) * u2);
+}
+
+__global__ __launch_bounds__(256) void regen_slab_kernel(
+    double *__restrict__ out, int i0, int nb, int n_vir, int n_aux,
+    uint64_t seed, const double *__restrict__ w_ia,
+    const double *__restrict__ w_iP) {
+  const int64_t per = (int64_t)n_vir * n_aux;
+  const int64_t total = per * nb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / per);
+    const int64_t r = e - (int64_t)b * per;
+    const int a = (int)(r / n_aux);
+    const int P = (int)(r - (int64_t)a * n_aux);
+    const int i = i0 + b;
+    uint64_t c0 = (uint64_t)P, c1 = (uint64_t)a, c2 = (uint64_t)i, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+    const double z = box_muller(c0, c1);
+    out[e] = (z * w_ia[(int64_t)i * n_vir + a]) * w_iP[(int64_t)i * n_aux + P];
+  }
+}
+
+hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
+                             uint64_t seed, const double *w_ia,
+                             const double *w_iP, hipStream_t s) {
+  const int64_t total = (int64_t)n_vir * n_aux * nb;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(regen_slab_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     out, i0, nb, n_vir, n_aux, seed, w_ia, w_iP);
+  return hipGetLastError();
+}
+
+}  // namespace mbe3

@@ -1,0 +1,228 @@
+"""HIP path vs the CPU oracle, through the C-ABI (needs an MI355X)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2603_16575_amd as pkg
+    pkg._lib.load()
+    return pkg
+
+
+def strong(p, scale=8.0):
+    f = p.f_occ.copy()
+    off = ~np.eye(p.n_occ, dtype=bool)
+    f[off] *= scale
+    return dataclasses.replace(p, f_occ=f)
+
+
+def gamma_block(h, prob, gamma, i, x):
+    nb = prob.neighbours(i)
+    row = int(h.g_off[i]) + int(sum(prob.r[y] for y in nb if y < x))
+    g = gamma.view(-1, prob.n_aux)
+    return g[row:row + int(prob.r[x])].cpu().numpy()
+
+
+def k_block(h, prob, K, s):
+    off = int(h.k_off[s])
+    p, q = (s, s) if s < prob.n_occ else tuple(prob.pairs[s - prob.n_occ])
+    d = int(prob.r[p] + (prob.r[q] if p != q else 0))
+    return K[off:off + d * d].view(d, d).cpu().numpy(), (int(p), int(q))
+
+
+def run_all(m, prob, **kw):
+    import torch
+    h = m.from_problem(prob, **kw)
+    out = h.forward()
+    torch.cuda.synchronize()
+    return h, out
+
+
+def test_chain8_end_to_end(m):
+    say("case: chain8 (configs 0) full forward vs oracle")
+    prob = synth.config(0)
+    h, out = run_all(m, prob)
+    ref = oracle.run(prob)
+    ora = ref["oracle"]
+    E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
+    # O2: every projected block
+    for i in range(prob.n_occ):
+        for x in prob.neighbours(i):
+            g = gamma_block(h, prob, out["gamma"], i, int(x))
+            r = ora.gamma(i, int(x))
+            assert np.abs(g - r).max() <= 1e-13 * np.abs(r).max(), (i, x)
+    # O3: every pair K
+    for s in range(h.layout.n_slot):
+        k, (p, q) = k_block(h, prob, out["K"], s)
+        r = ora.Kbar(p, q)
+        assert np.abs(k - r).max() <= 1e-13 * np.abs(r).max(), s
+    e = out["e_frag"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    say(f"chain8: E_gpu={out['E']:.16f} E_ref={E_ref:.16f} dE={out['E'] - E_ref:.3e}")
+    assert np.abs(e - ref["e_frag"]).max() <= 1e-12
+    assert np.array_equal(it, ref["iters"])
+    assert abs(out["E"] - E_ref) <= 1e-10
+    h.close()
+
+
+def test_pair_basis_gauge_invariants(m):
+    say("case: chain8 pair bases (eq. prec_eig) vs oracle S, F")
+    prob = synth.config(0)
+    h = m.from_problem(prob)
+    X, et, rank = h.mbe3_pair_basis()
+    X, et, rank = X.cpu().numpy(), et.cpu().numpy(), rank.cpu().numpy()
+    ora = oracle.Oracle(prob)
+    for s in range(h.layout.n_slot):
+        p, q = (s, s) if s < prob.n_occ else tuple(int(v) for v in prob.pairs[s - prob.n_occ])
+        o = oracle.orbs(p, q)
+        S, F = ora.Sblk(o, o), ora.Fblk(o, o)
+        d = S.shape[0]
+        D = (d + 15) // 16 * 16
+        Xs = X[h.x_off[s]:h.x_off[s + 1]].reshape(d, D)[:, :rank[s]]
+        es = et[h.e_off[s]:h.e_off[s] + rank[s]]
+        Xr, er = ora.basis(p, q)
+        assert rank[s] == Xr.shape[1]
+        assert np.allclose(Xs.T @ S @ Xs, np.eye(rank[s]), atol=1e-12)
+        assert np.allclose(Xs.T @ F @ Xs, np.diag(es), atol=1e-12)
+        assert np.allclose(es, er, rtol=0, atol=1e-12)
+        # projector onto the pair space, gauge free
+        assert np.allclose(Xs @ Xs.T, Xr @ Xr.T, atol=1e-10)
+    h.close()
+
+
+def test_slab_regeneration_ulps(m):
+    """Identity OSVs make the projection return the slab itself (each output
+    is one product with an exact 1), so the regenerated slab is compared to
+    the oracle's element by element."""
+    say("case: slab regeneration, identity OSVs, n_vir=64 n_aux=192")
+    cfg = dict(synth.CONFIGS[0])
+    prob = synth.build(cfg, synth.SEED_BASE, identity_q=True, diagonal_f=True)
+    prob = dataclasses.replace(prob, pairs=prob.pairs[:0], trimers=prob.trimers[:0])
+    import torch
+    h = m.from_problem(prob)
+    g = h.osv_project(h.empty_gamma())
+    torch.cuda.synchronize()
+    g = g.view(prob.n_occ, prob.n_vir, prob.n_aux).cpu().numpy()
+    worst = 0
+    for i in range(prob.n_occ):
+        ref = oracle.slab(prob, i)
+        ulp = np.abs(g[i] - ref) / np.spacing(np.abs(ref))
+        worst = max(worst, float(ulp.max()))
+    say(f"slab: max ulp difference {worst}")
+    assert worst <= 4
+    h.close()
+
+
+@pytest.mark.parametrize("n_occ", [3, 4])
+def test_micro_strong_coupling(m, n_occ):
+    say(f"case: micro n_occ={n_occ} strong coupling, all fragments")
+    prob = dataclasses.replace(strong(synth.micro(n_occ)), tol=1e-12, max_iter=300)
+    h, out = run_all(m, prob)
+    ref = oracle.run(prob)
+    e = out["e_frag"].cpu().numpy()
+    assert np.abs(e - ref["e_frag"]).max() <= 1e-13
+    E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
+    assert abs(out["E"] - E_ref) <= 1e-12
+    h.close()
+
+
+def test_explicit_slab_matches_regenerated(m):
+    say("case: explicit slab input == regenerated slab, micro n_occ=4")
+    import torch
+    prob = strong(synth.micro(4))
+    slab = np.stack([oracle.slab(prob, i) for i in range(prob.n_occ)])
+    h1, out1 = run_all(m, prob)
+    h2, out2 = run_all(m, prob, slab=torch.as_tensor(slab, device="cuda:0"),
+                       w_ia=None, w_iP=None)
+    e1, e2 = out1["e_frag"].cpu().numpy(), out2["e_frag"].cpu().numpy()
+    assert np.abs(e1 - e2).max() <= 1e-14
+    h1.close()
+    h2.close()
+
+
+def test_water40u_sampled(m):
+    """configs 1 (160 LMOs, 89969 fragments) in the benchmark's launch shape:
+    fragment energies of a deterministic sample against the oracle, one by
+    one; projected blocks and K of sampled orbitals/pairs."""
+    say("case: water40u (configs 1) full forward, sampled oracle fragments")
+    prob = synth.config(1)
+    h, out = run_all(m, prob)
+    e = out["e_frag"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert (it >= 0).all() and np.isfinite(e).all()
+    fr = prob.frags
+    pick = np.unique(np.concatenate([
+        np.nonzero((fr == 0).any(1))[0][:40],
+        np.arange(0, len(fr), 4999),
+        [len(fr) - 1]]))
+    ora = oracle.Oracle(prob)
+    for i, x in [(0, 0), (0, int(prob.neighbours(0)[-1])), (77, 77)]:
+        g = gamma_block(h, prob, out["gamma"], i, x)
+        r = ora.gamma(i, x)
+        assert np.abs(g - r).max() <= 1e-13 * np.abs(r).max()
+    for s in [0, prob.n_occ, prob.n_occ + 2000, h.layout.n_slot - 1]:
+        k, (p, q) = k_block(h, prob, out["K"], s)
+        r = ora.Kbar(p, q)
+        assert np.abs(k - r).max() <= 1e-13 * np.abs(r).max()
+    res = oracle.run(prob, frags=fr[pick], ora=ora)
+    say(f"water40u: {len(pick)} sampled fragments, max |dE_F| = "
+        f"{np.abs(e[pick] - res['e_frag']).max():.3e}, E = {out['E']:.12f}")
+    assert np.abs(e[pick] - res["e_frag"]).max() <= 1e-12
+    assert np.array_equal(it[pick], res["iters"])
+    h.close()
+
+
+def test_failure_modes(m):
+    import torch
+    say("case: failure modes (no convergence, non-finite Fock, bad lists)")
+    prob = dataclasses.replace(synth.config(0), max_iter=1)
+    h = m.from_problem(prob)
+    gamma = h.osv_project(h.empty_gamma())
+    K = h.pair_K(gamma, h.empty_K())
+    e = torch.empty(h.n_frag, dtype=torch.float64, device="cuda:0")
+    it = torch.empty(h.n_frag, dtype=torch.int32, device="cuda:0")
+    rc = h.fragment_solve(K, e, it, check=False)
+    assert rc == m.MBE3_ENOCONV
+    itn = it.cpu().numpy()
+    assert (itn[:prob.n_occ] == 1).all() and (itn < 0).any()
+    h.close()
+    f = synth.config(0).f_occ.copy()
+    f[2, 3] = f[3, 2] = np.nan
+    prob = dataclasses.replace(synth.config(0), f_occ=f)
+    h = m.from_problem(prob)
+    gamma = h.osv_project(h.empty_gamma())
+    K = h.pair_K(gamma, h.empty_K())
+    rc = h.fragment_solve(K, e, it, check=False)
+    assert rc == m.MBE3_ENONFINITE
+    assert np.isnan(e.cpu().numpy()).any()
+    h.close()
+    p = synth.config(0)
+    with pytest.raises(m.Mbe3Error) as ex:
+        m.from_problem(dataclasses.replace(p, pairs=p.pairs[1:]))
+    assert ex.value.code == m.MBE3_EINVAL
+
+
+def test_deterministic(m):
+    say("case: chain8 twice, bitwise equal")
+    prob = synth.config(0)
+    _, o1 = run_all(m, prob)
+    _, o2 = run_all(m, prob)
+    assert o1["E"] == o2["E"]
+    assert np.array_equal(o1["e_frag"].cpu().numpy(), o2["e_frag"].cpu().numpy())
