@@ -61,6 +61,17 @@ extern "C" {
 
 #define MBE3_FP64 0
 
+/* Phases reported by mbe3_get_timing. */
+#define MBE3_PHASE_REGEN 0   /* slab regeneration (osv_project)             */
+#define MBE3_PHASE_PROJECT 1 /* projection GEMMs (osv_project)              */
+#define MBE3_PHASE_PAIR_K 2  /* pair_K                                      */
+#define MBE3_PHASE_BASES 3   /* S/F blocks, pair eigensolves, X             */
+#define MBE3_PHASE_PAIRS 4   /* K~ = X^T K X, pair-level S~                  */
+#define MBE3_PHASE_CROSS 5   /* per-trimer S~ between pair domains          */
+#define MBE3_PHASE_SOLVE 6   /* fragment residual iterations                */
+#define MBE3_PHASE_ENERGY 7  /* MBE(3) sum                                  */
+#define MBE3_NPHASE 8
+
 typedef struct mbe3_handle mbe3_handle;
 
 /*
@@ -191,6 +202,16 @@ int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
  * slot.  Runs the preparation of fragment_solve.  All device pointers.
  */
 int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank);
+/*
+ * Kernel timing: mbe3_set_timing(h, 1) synchronises the stream, clears the
+ * accumulators and from then on brackets every phase's launches with HIP
+ * events on the handle's stream.  mbe3_get_timing synchronises and writes
+ * the accumulated milliseconds per phase (host ms[MBE3_NPHASE]) and the
+ * number of timed regions (host launches[MBE3_NPHASE], nullable).
+ */
+int mbe3_set_timing(mbe3_handle *h, int enable);
+int mbe3_get_timing(mbe3_handle *h, double *ms, int64_t *launches);
+
 /* Offsets for mbe3_pair_basis: host xoff[n_slot+1], eoff[n_slot+1]. */
 int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
 

@@ -145,6 +145,16 @@ class Mbe3:
                                                _lib.ptr(rank)), self._h)
         return X, et, rank
 
+    def set_timing(self, enable=True):
+        _lib.check(_lib.load().mbe3_set_timing(self._h, int(bool(enable))), self._h)
+
+    def get_timing(self):
+        """{phase: (ms, regions)} accumulated since set_timing."""
+        ms = np.zeros(len(_lib.PHASES), dtype=np.float64)
+        n = np.zeros(len(_lib.PHASES), dtype=np.int64)
+        _lib.check(_lib.load().mbe3_get_timing(self._h, _lib.ptr(ms), _lib.ptr(n)), self._h)
+        return {ph: (float(ms[k]), int(n[k])) for k, ph in enumerate(_lib.PHASES)}
+
     def forward(self):
         """osv_project -> pair_K -> fragment_solve -> mbe3_energy."""
         import torch

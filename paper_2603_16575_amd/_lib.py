@@ -25,8 +25,11 @@ EXPORTS = [
     "mbe3_create", "mbe3_destroy", "mbe3_last_error", "mbe3_get_layout",
     "mbe3_gamma_offsets", "mbe3_k_offsets", "mbe3_basis_offsets",
     "osv_project", "pair_K", "fragment_solve", "mbe3_energy",
-    "mbe3_pair_basis", "mbe3_plan_check",
+    "mbe3_pair_basis", "mbe3_plan_check", "mbe3_set_timing",
+    "mbe3_get_timing",
 ]
+PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
+          "energy"]
 
 
 class Mbe3Problem(ctypes.Structure):
@@ -83,6 +86,8 @@ def load():
         "mbe3_energy": [vp, vp, vp, vp],
         "mbe3_pair_basis": [vp, vp, vp, vp],
         "mbe3_plan_check": [ctypes.POINTER(Mbe3Problem), ctypes.POINTER(Mbe3Layout)],
+        "mbe3_set_timing": [vp, ctypes.c_int],
+        "mbe3_get_timing": [vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

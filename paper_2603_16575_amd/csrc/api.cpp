@@ -131,6 +131,15 @@ struct mbe3_handle {
   int64_t gamma_rows = 0;
   int64_t k_elems = 0;
 
+  // ---- per-phase event timing (mbe3_set_timing) ----
+  bool timing = false;
+  struct Region { int phase; hipEvent_t a, b; };
+  std::vector<Region> regions;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_next = 0;
+  double phase_ms[MBE3_NPHASE] = {0};
+  int64_t phase_n[MBE3_NPHASE] = {0};
+
   // ---- host mirrors of the plans, for the bounds check ----
   bool dry = false;  // plan only: no device allocation or copies
   int64_t at_total = 0, mt_total = 0, st0_total = 0;
@@ -152,6 +161,7 @@ struct mbe3_handle {
     return code;
   }
   ~mbe3_handle() {
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
     if (h_status) (void)hipHostFree(h_status);
     if (h_e3) (void)hipHostFree(h_e3);
@@ -167,6 +177,31 @@ struct mbe3_handle {
   } while (0)
 
 namespace {
+
+// Event pair around a group of launches of one phase (only when timing).
+hipEvent_t next_event(mbe3_handle *h) {
+  if (h->event_next == h->event_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->event_pool.push_back(e);
+  }
+  return h->event_pool[h->event_next++];
+}
+struct PhaseScope {
+  mbe3_handle *h;
+  int phase;
+  hipEvent_t a = nullptr;
+  PhaseScope(mbe3_handle *hh, int ph) : h(hh), phase(ph) {
+    if (h->timing && (a = next_event(h))) (void)hipEventRecord(a, h->stream);
+  }
+  ~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = next_event(h);
+    if (!b) return;
+    (void)hipEventRecord(b, h->stream);
+    h->regions.push_back({phase, a, b});
+  }
+};
 
 template <class T>
 int dev_alloc(mbe3_handle *h, T **p, int64_t n) {
@@ -888,6 +923,7 @@ int max_d(const mbe3_handle *h) {
 
 // Pair bases (Algorithm 5 blocks, eq. prec_eig) -- needs only Q and eps.
 int prepare_bases(mbe3_handle *h) {
+  PhaseScope ps_(h, MBE3_PHASE_BASES);
   hipStream_t s = h->stream;
   GemmBases b = bases(h);
   const int64_t nq = h->q_off[h->n_occ];
@@ -911,6 +947,7 @@ int prepare_pairs(mbe3_handle *h, const double *K) {
   hipStream_t s = h->stream;
   int rc = prepare_bases(h);
   if (rc) return rc;
+  PhaseScope ps_(h, MBE3_PHASE_PAIRS);
   GemmBases b = bases(h);
   b.p[B_K] = const_cast<double *>(K);
   HIP_TRY(h, launch_gemm_tasks(h->d_g_m2, (int)h->n_slot, h->t_m2, b, GEMM_64x64, s));
@@ -1158,9 +1195,12 @@ int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems) {
   b.p[B_GAMMA] = gamma;
   for (size_t k = 0; k < h->proj_batches.size(); ++k) {
     const int i0 = h->proj_batches[k].first, i1 = h->proj_batches[k].second;
-    if (!h->slab)
+    if (!h->slab) {
+      PhaseScope ps_(h, MBE3_PHASE_REGEN);
       HIP_TRY(h, launch_regen_slab(h->slab_buf, i0, i1 - i0, h->n_vir, h->n_aux,
                                    h->seed, h->w_ia, h->w_iP, s));
+    }
+    PhaseScope ps_(h, MBE3_PHASE_PROJECT);
     HIP_TRY(h, launch_gemm_tasks(h->d_proj[k], h->n_proj[k], h->t_proj[k], b,
                                  GEMM_128x128, s));
   }
@@ -1175,6 +1215,7 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems) {
   GemmBases b = bases(h);
   b.p[B_GAMMA] = const_cast<double *>(gamma);
   b.p[B_K] = K;
+  PhaseScope ps_(h, MBE3_PHASE_PAIR_K);
   HIP_TRY(h, launch_gemm_tasks(h->d_pk, h->n_pk, h->t_pk, b, GEMM_64x64, h->stream));
   return MBE3_OK;
 }
@@ -1191,6 +1232,7 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
   HIP_TRY(h, launch_fill_i32(h->status, 0, 2 * SOLVE_WG, s));
   for (auto &c : h->chunks) {
     if (c.n_asm) {
+      PhaseScope ps_(h, MBE3_PHASE_CROSS);
       HIP_TRY(h, launch_assemble(c.d_asm, c.n_asm, h->sstore, h->fstore, h->ca,
                                  nullptr, s));
       HIP_TRY(h, launch_gemm_tasks(c.d_m, c.n_gemm, c.tiles_m, b, GEMM_64x64, s));
@@ -1222,6 +1264,7 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
     for (auto &cc : h->chunks) { dm = std::max(dm, cc.dmax); nym = std::max(nym, cc.ny_max); }
     a.dmax = dm;
     const int nwg = std::min(SOLVE_WG, c.n_frag);
+    PhaseScope ps_(h, MBE3_PHASE_SOLVE);
     HIP_TRY(h, launch_solve(a, nwg, s));
   }
   HIP_TRY(h, hipMemcpyAsync(h->h_status, h->status, 2 * SOLVE_WG * sizeof(int32_t),
@@ -1244,14 +1287,45 @@ int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
   if (!e_frag || !e_total) return h->fail(MBE3_EINVAL, "e_frag and e_total required");
   hipStream_t s = h->stream;
   const int64_t n = (int64_t)h->frags.size();
-  HIP_TRY(h, launch_mbe_sum(e_frag, h->d_coef, n, h->d_e3, s));
-  if (incr) HIP_TRY(h, launch_increments(e_frag, h->d_sub, n, incr, s));
+  {
+    PhaseScope ps_(h, MBE3_PHASE_ENERGY);
+    HIP_TRY(h, launch_mbe_sum(e_frag, h->d_coef, n, h->d_e3, s));
+    if (incr) HIP_TRY(h, launch_increments(e_frag, h->d_sub, n, incr, s));
+  }
   HIP_TRY(h, hipMemcpyAsync(h->h_e3, h->d_e3, 3 * sizeof(double),
                             hipMemcpyDeviceToHost, s));
   HIP_TRY(h, hipStreamSynchronize(s));
   *e_total = h->h_e3[0];
   if (!std::isfinite(*e_total))
     return h->fail(MBE3_ENONFINITE, "MBE(3) energy is not finite");
+  return MBE3_OK;
+}
+
+int mbe3_set_timing(mbe3_handle *h, int enable) {
+  if (!h) return MBE3_EINVAL;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->timing = enable != 0;
+  h->regions.clear();
+  h->event_next = 0;
+  for (int k = 0; k < MBE3_NPHASE; ++k) { h->phase_ms[k] = 0.0; h->phase_n[k] = 0; }
+  return MBE3_OK;
+}
+
+int mbe3_get_timing(mbe3_handle *h, double *ms, int64_t *launches) {
+  if (!h || !ms) return MBE3_EINVAL;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (auto &r : h->regions) {
+    float t = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&t, r.a, r.b));
+    h->phase_ms[r.phase] += t;
+    h->phase_n[r.phase] += 1;
+  }
+  h->regions.clear();
+  h->event_next = 0;
+  for (int k = 0; k < MBE3_NPHASE; ++k) {
+    ms[k] = h->phase_ms[k];
+    if (launches) launches[k] = h->phase_n[k];
+  }
   return MBE3_OK;
 }
 
