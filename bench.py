@@ -54,13 +54,14 @@ def fragment_dims(prob):
 
 def solve_flops(prob, iters):
     """Algorithmic FP64 FLOPs of the residual iterations: per sweep and term
-    2 d_t d_s^2 (S~ Y) + 2 d_t^2 d_s (Z S~^T); iters + 1 sweeps per fragment
-    (the last one only evaluates the converged residual and energy)."""
+    2 d_t d_s^2 (S~ Y) + 2 d_t^2 d_s (Z S~^T).  A fragment with `iters`
+    updates evaluates iters + 1 residuals; the first (T = 0, R~ = K~) needs no
+    product, so `iters` sweeps carry the products."""
     dims = fragment_dims(prob)
     tot = 0.0
     for terms, it in zip(dims, iters):
         per = sum(2.0 * dt * ds * (ds + dt) for dt, ds in terms)
-        tot += per * (int(it) + 1)
+        tot += per * int(it)
     return tot
 
 

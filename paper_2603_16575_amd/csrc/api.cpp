@@ -1263,7 +1263,10 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
     int dm = 16, nym = 0;
     for (auto &cc : h->chunks) { dm = std::max(dm, cc.dmax); nym = std::max(nym, cc.ny_max); }
     a.dmax = dm;
-    const int nwg = std::min(SOLVE_WG, c.n_frag);
+    // persistent grid: as many workgroups as fit on the 256 CUs at once
+    const int per_cu = (int)std::max<size_t>(
+        1, std::min<size_t>(4, (160 * 1024) / (solve_lds_bytes(dm) + 2048)));
+    const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu);
     PhaseScope ps_(h, MBE3_PHASE_SOLVE);
     HIP_TRY(h, launch_solve(a, nwg, s));
   }

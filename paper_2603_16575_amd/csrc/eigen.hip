@@ -1,7 +1,9 @@
 // Batched symmetric eigensolver for the pair preconditioner (eq. prec_eig):
 // one workgroup per pair matrix, cyclic Jacobi with the round-robin
 // (circle) ordering so that n/2 disjoint rotations run concurrently, matrix
-// and eigenvectors resident in LDS.  The paper also diagonalises each pair
+// and eigenvectors resident in LDS.  A round is two phases: the rotations,
+// then J^T A J applied as independent 2x2 blocks J_k1^T A_(k1,k2) J_k2 (upper
+// blocks only, mirrored) together with V <- V J.  The paper also diagonalises each pair
 // on one thread block with Jacobi; here the generalized problem is reduced by
 // canonical orthogonalisation (two Jacobi solves) instead of a Cholesky
 // factor, so rank-deficient pair overlaps are handled by dropping
@@ -59,19 +61,22 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
   __syncthreads();
 
   const int nn = n + (n & 1);
+  const int np = nn / 2;              // rotations per round
+  const int nblk = np * (np + 1) / 2; // 2x2 blocks (k1 <= k2) of A
   for (int sweep = 0; sweep < JAC_MAX_SWEEPS && n > 1; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += nt) {
       const int r = e / n, c = e - r * n;
-      const double a = A[r * ld + c];
-      tot += a * a;
-      if (r != c) off += a * a;
+      const double v = A[r * ld + c];
+      tot += v * v;
+      if (r != c) off += v * v;
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red);
     if (!(off > 1e-30 * tot)) break;  // off-diagonal norm <= 1e-15 ||A||
     for (int round = 0; round < nn - 1; ++round) {
-      if (tid < nn / 2) {
+      // phase 1: the round's np disjoint rotations (circle ordering)
+      if (tid < np) {
         const int k = tid;
         int a, b;
         if (k == 0) {
@@ -102,28 +107,46 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
         cs_s[k] = s;
       }
       __syncthreads();
-      const int np = nn / 2;
-      for (int e = tid; e < np * n; e += nt) {  // A <- J^T A (rows)
-        const int k = e / n, j = e - k * n;
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double s = cs_s[k];
-        if (q < n && s != 0.0) {
-          const double c = cs_c[k];
-          const double ap = A[p * ld + j], aq = A[q * ld + j];
-          A[p * ld + j] = c * ap - s * aq;
-          A[q * ld + j] = s * ap + c * aq;
+      // phase 2: A <- J^T A J as independent 2x2 blocks, V <- V J
+      for (int e = tid; e < nblk; e += nt) {
+        int k2 = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (k2 * (k2 + 1) / 2 > e) --k2;
+        while ((k2 + 1) * (k2 + 2) / 2 <= e) ++k2;
+        const int k1 = e - k2 * (k2 + 1) / 2;  // k1 <= k2
+        const double s1 = cs_s[k1], s2 = cs_s[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const double c1 = cs_c[k1], c2 = cs_c[k2];
+        const int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1];
+        const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+        const bool h1 = q1 < n, h2 = q2 < n;  // second index exists
+        const double b00 = A[p1 * ld + p2];
+        const double b01 = h2 ? A[p1 * ld + q2] : 0.0;
+        const double b10 = h1 ? A[q1 * ld + p2] : 0.0;
+        const double b11 = (h1 && h2) ? A[q1 * ld + q2] : 0.0;
+        // T = J1^T B (rows), B' = T J2 (columns)
+        const double t00 = c1 * b00 - s1 * b10, t01 = c1 * b01 - s1 * b11;
+        const double t10 = s1 * b00 + c1 * b10, t11 = s1 * b01 + c1 * b11;
+        double n00 = c2 * t00 - s2 * t01, n01 = s2 * t00 + c2 * t01;
+        double n10 = c2 * t10 - s2 * t11, n11 = s2 * t10 + c2 * t11;
+        if (k1 == k2) { n01 = 0.0; n10 = 0.0; }  // rotated pair: zeroed
+        A[p1 * ld + p2] = n00;
+        if (h2) A[p1 * ld + q2] = n01;
+        if (h1) A[q1 * ld + p2] = n10;
+        if (h1 && h2) A[q1 * ld + q2] = n11;
+        if (k1 != k2) {  // mirror into the lower block
+          A[p2 * ld + p1] = n00;
+          if (h2) A[q2 * ld + p1] = n01;
+          if (h1) A[p2 * ld + q1] = n10;
+          if (h1 && h2) A[q2 * ld + q1] = n11;
         }
       }
-      __syncthreads();
-      for (int e = tid; e < np * n; e += nt) {  // A <- A J, V <- V J (columns)
+      for (int e = tid; e < np * n; e += nt) {
         const int k = e / n, i = e - k * n;
-        const int p = pq[2 * k], q = pq[2 * k + 1];
         const double s = cs_s[k];
+        const int q = pq[2 * k + 1];
         if (q < n && s != 0.0) {
+          const int p = pq[2 * k];
           const double c = cs_c[k];
-          const double ap = A[i * ld + p], aq = A[i * ld + q];
-          A[i * ld + p] = c * ap - s * aq;
-          A[i * ld + q] = s * ap + c * aq;
           const double vp = V[i * ld + p], vq = V[i * ld + q];
           V[i * ld + p] = c * vp - s * vq;
           V[i * ld + q] = s * vp + c * vq;

@@ -148,6 +148,7 @@ struct SolveArgs {
 };
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s);
 int64_t solve_scratch_doubles(int ny_max, int dmax);
+size_t solve_lds_bytes(int dmax);
 
 // ---------------------------------------------------------------------------
 // Reductions (reduce.hip)

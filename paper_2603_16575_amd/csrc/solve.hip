@@ -16,21 +16,39 @@
 //   E_F = sum_t w_t <2 Y_t - Y_t^T, K~_t + R~_t>
 // is accumulated in the same pass.
 //
-// Products run on v_mfma_f64_16x16x4 with operands read straight from the
-// (L2-resident) per-workgroup scratch and the S~ stores; all pair blocks are
-// zero padded to multiples of 16, so no tile needs masking.
+// Data flow of one term on the FP64 matrix cores (v_mfma_f64_16x16x4), with
+// S~ stored as S~_(s,t) = S~'^T (D_s x D_t, row-major):
+//   pass 1: each wave owns whole 16-row blocks ib of R~_t and accumulates
+//      W = Z^T = (Y_s^(T))^T S~'^T over 16-row panels m of Y_s^(T) and S~;
+//   pass 2: the MFMA output layout (register v of lane l holds row l/16 + 4v,
+//      column l%16) is exactly the A-operand layout of the second product for
+//      the four k-steps kb*16 + 4v, so Z never leaves the registers and
+//      R~_t[ib, :] += Z[ib, :] S~'^T reads the S~ resident in LDS.
+// Panels go global -> registers (prefetched one step ahead) -> LDS: the
+// term's S~ panels land in a resident D_s x D_t block reused by pass 2 (which
+// then needs no barrier and hides the next term's first load), the Y^(T)
+// rows in two alternating 16-row buffers.  LDS per workgroup is
+// D_max^2 + 32 D_max doubles, so two fragments share a CU.  A diagonal pair's
+// mirror terms f S~ Y S~^T and its transpose are formed once and symmetrised
+// through LDS.
+// Sweep 0 has T = 0, so R~ = K~ needs no product.  All pair blocks are zero
+// padded to multiples of 16: no tile is masked.
 #include "internal.hpp"
 
 namespace mbe3 {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int MAXT>
-__global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) {
+// MAXNT: largest number of 16-blocks per pair dimension (dmax / 16).
+template <int MAXNT>
+__global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
+  extern __shared__ double lds[];
+  constexpr int MAXRB = (MAXNT + 3) / 4;  // row blocks per wave
   __shared__ double red_d[8];
   __shared__ int red_i[8];
   const int tid = threadIdx.x;
@@ -38,23 +56,23 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) {
   const int wave = tid >> 6;
   const int l16 = lane & 15;
   const int lq = lane >> 4;
+  // LDS: the term's whole S~ (D_s x D_t) stays resident for both passes; the
+  // Y^(T) rows stream through two 16-row buffers.
+  double *const Sl = lds;
+  double *const yb0 = lds + (int64_t)a.dmax * a.dmax;
+  double *const yb1 = yb0 + 16 * a.dmax;
 
   double *scr = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int64_t ny_cap = (a.scratch_stride - 2LL * a.dmax * a.dmax) / 4;
   double *const Y0 = scr;
   double *const YT0 = scr + 2 * ny_cap;
-  double *Z = scr + 4 * ny_cap;
-  double *ACC = Z + (int64_t)a.dmax * a.dmax;
+
+  d2 pf[MAXNT];  // next panel: S~ rows then Y^(T) rows
 
   for (int fi = blockIdx.x; fi < a.n_frag; fi += gridDim.x) {
     const FragDesc *__restrict__ fdp = a.frags + fi;
-    const int f_nt = fdp->nt, f_ny = fdp->ny, f_frag = fdp->frag;
+    const int f_nt = fdp->nt, f_frag = fdp->frag;
     const int f_tb = fdp->term_begin, f_te = fdp->term_end;
-    for (int e = tid; e < f_ny; e += 256) {
-      Y0[e] = 0.0;
-      YT0[e] = 0.0;
-    }
-    __syncthreads();
     int cur = 0;
     for (int it = 0;; ++it) {
       double mres = 0.0, epart = 0.0;
@@ -63,76 +81,136 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) {
       double *const YTcb = YT0 + (cur ? ny_cap : 0);
       double *const Ynb = Y0 + (cur ? 0 : ny_cap);
       double *const YTnb = YT0 + (cur ? 0 : ny_cap);
+
+      // ---- panel pipeline: step (ti, m) = rows 16m.. of S~ and of Y^(T) ----
+      int p_ti = f_tb, p_m = 0;  // step held in pf
+      int p_n1 = 0, p_n2 = 0;
+#define MBE3_LOAD_PANEL()                                                      \
+  do {                                                                         \
+    const Term tm_ = a.terms[p_ti];                                            \
+    const int dt_ = a.slots[fdp->slot[tm_.target]].D;                          \
+    const int ds_ = a.slots[fdp->slot[tm_.src]].D;                             \
+    const d2 *st_ = reinterpret_cast<const d2 *>(                              \
+        (tm_.st_buf ? a.st1 : a.st0) + tm_.st_off + (int64_t)16 * p_m * dt_);  \
+    const d2 *y_ = reinterpret_cast<const d2 *>(                               \
+        (tm_.trans ? YTcb : Ycb) + fdp->ysub[tm_.src] + (int64_t)16 * p_m * ds_); \
+    p_n1 = 8 * dt_;                                                            \
+    p_n2 = 8 * ds_;                                                            \
+    _Pragma("unroll") for (int u = 0; u < MAXNT; ++u) {                        \
+      const int e = tid + 256 * u;                                             \
+      if (e < p_n1) pf[u] = st_[e];                                            \
+      else if (e - p_n1 < p_n2) pf[u] = y_[e - p_n1];                          \
+    }                                                                          \
+  } while (0)
+#define MBE3_ADVANCE()                                                         \
+  do {                                                                         \
+    const int ds_ = a.slots[fdp->slot[a.terms[p_ti].src]].D;                   \
+    if (++p_m >= (ds_ >> 4)) { p_m = 0; ++p_ti; }                              \
+  } while (0)
+
+      if (it > 0 && f_tb < f_te) MBE3_LOAD_PANEL();
+
       for (int tl = 0; tl < f_nt; ++tl) {
         const SlotInfo sl = a.slots[fdp->slot[tl]];
         const int Dt = sl.D;
         const int nT = Dt >> 4;
-        const int ntile = nT * nT;
-        d4 acc[MAXT];
+        d4 acc[MAXRB][MAXNT];
 #pragma unroll
-        for (int u = 0; u < MAXT; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int rb = 0; rb < MAXRB; ++rb)
+#pragma unroll
+          for (int jb = 0; jb < MAXNT; ++jb) acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
 
-        for (int ti = f_tb; ti < f_te; ++ti) {
-          const Term tm = a.terms[ti];
-          if (tm.target != tl) continue;
-          const double coef = a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
-          const int Ds = a.slots[fdp->slot[tm.src]].D;
-          const double *__restrict__ Ys =
-              (tm.trans ? YTcb : Ycb) + fdp->ysub[tm.src];
-          const double *__restrict__ ST = (tm.st_buf ? a.st1 : a.st0) + tm.st_off;
-          // Z = coef * S~'(Dt x Ds) . Ys^(T) (Ds x Ds), S~'[i][k] = ST[k*Dt+i];
-          // stored column-major Z[j*Dt + i].
-          const int nS = Ds >> 4;
-          const int nZ = nT * nS;
-          for (int zt = wave; zt < nZ; zt += 4) {
-            const int zi = zt % nT, zj = zt / nT;
-            d4 z = d4{0.0, 0.0, 0.0, 0.0};
-            const double *ap = ST + zi * 16 + l16;
-            const double *bp = Ys + zj * 16 + l16;
-            for (int k0 = 0; k0 < Ds; k0 += 4) {
-              const int k = k0 + lq;
-              z = mfma_f64(ap[(int64_t)k * Dt], bp[(int64_t)k * Ds], z);
-            }
-            // D layout: register v of lane l is row l/16 + 4v, column l%16
-            double *zp = Z + (int64_t)(zj * 16 + l16) * Dt + zi * 16 + lq;
+        if (it > 0) {
+          for (int ti = f_tb; ti < f_te; ++ti) {
+            const Term tm = a.terms[ti];
+            if (tm.target != tl) continue;
+            const double coef = a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
+            const int Ds = a.slots[fdp->slot[tm.src]].D;
+            const int nS = Ds >> 4;
+            d4 W[MAXRB][MAXNT];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) zp[4 * v] = coef * z[v];
-          }
-          __syncthreads();
-          // acc += Z (Dt x Ds) . S~'^T (Ds x Dt), S~'^T[k][j] = ST[k*Dt+j]
+            for (int rb = 0; rb < MAXRB; ++rb)
 #pragma unroll
-          for (int u = 0; u < MAXT; ++u) {
-            const int tt = wave + 4 * u;
-            if (tt < ntile) {
-              const int ri = tt / nT, rj = tt - ri * nT;
-              const double *ap = Z + ri * 16 + l16;
-              const double *bp = ST + rj * 16 + l16;
-              d4 c = acc[u];
-              for (int k0 = 0; k0 < Ds; k0 += 4) {
-                const int k = k0 + lq;
-                c = mfma_f64(ap[(int64_t)k * Dt], bp[(int64_t)k * Dt], c);
+              for (int kb = 0; kb < MAXNT; ++kb) W[rb][kb] = d4{0.0, 0.0, 0.0, 0.0};
+            __syncthreads();  // the previous term's S~ is no longer read
+            // pass 1: W(kb, ib) += Y^(T)[m, kb] (x) S~'^T[m, ib] over panels
+            for (int mp = 0; mp < nS; ++mp) {
+              double *const yb = (mp & 1) ? yb1 : yb0;
+              {
+                d2 *s_ = reinterpret_cast<d2 *>(Sl + 16 * mp * Dt);
+                d2 *y_ = reinterpret_cast<d2 *>(yb);
+#pragma unroll
+                for (int u = 0; u < MAXNT; ++u) {
+                  const int e = tid + 256 * u;
+                  if (e < p_n1) s_[e] = pf[u];
+                  else if (e - p_n1 < p_n2) y_[e - p_n1] = pf[u];
+                }
               }
-              acc[u] = c;
+              MBE3_ADVANCE();
+              // the next panel streams in under the products; the last
+              // panel of a term prefetches the next term's first one
+              if (p_ti < f_te) MBE3_LOAD_PANEL();
+              __syncthreads();
+              const double *STp = Sl + 16 * mp * Dt;
+#pragma unroll
+              for (int mm = 0; mm < 4; ++mm) {
+                const int ml = 4 * mm + lq;
+#pragma unroll
+                for (int rb = 0; rb < MAXRB; ++rb) {
+                  const int ib = wave + 4 * rb;
+                  if (ib < nT) {
+                    const double bv = STp[ml * Dt + ib * 16 + l16];
+#pragma unroll
+                    for (int kb = 0; kb < MAXNT; ++kb)
+                      if (kb < nS)
+                        W[rb][kb] = mfma_f64(yb[ml * Ds + kb * 16 + l16], bv, W[rb][kb]);
+                  }
+                }
+              }
+            }
+            // pass 2: acc[ib, jb] += coef Z[ib, k] S~'^T[k, jb] from LDS
+#pragma unroll
+            for (int kp = 0; kp < MAXNT; ++kp) {
+              if (kp < nS) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  const double *brow = Sl + (kp * 16 + 4 * v + lq) * Dt + l16;
+#pragma unroll
+                  for (int rb = 0; rb < MAXRB; ++rb) {
+                    const int ib = wave + 4 * rb;
+                    if (ib < nT) {
+                      const double av = coef * W[rb][kp][v];
+#pragma unroll
+                      for (int jb = 0; jb < MAXNT; ++jb)
+                        if (jb < nT) acc[rb][jb] = mfma_f64(av, brow[jb * 16], acc[rb][jb]);
+                    }
+                  }
+                }
+              }
             }
           }
-          __syncthreads();
         }
 
         const int sym = fdp->sym[tl];
-        if (sym) {
+        if (sym) {  // diagonal pair: R~ gets acc + acc^T (mirror terms)
+          __syncthreads();  // S~ of the last term is no longer read
 #pragma unroll
-          for (int u = 0; u < MAXT; ++u) {
-            const int tt = wave + 4 * u;
-            if (tt < ntile) {
-              const int ri = tt / nT, rj = tt - ri * nT;
+          for (int rb = 0; rb < MAXRB; ++rb) {
+            const int ib = wave + 4 * rb;
+            if (ib < nT) {
 #pragma unroll
-              for (int v = 0; v < 4; ++v)
-                ACC[(int64_t)(ri * 16 + lq + 4 * v) * Dt + rj * 16 + l16] = acc[u][v];
+              for (int jb = 0; jb < MAXNT; ++jb)
+                if (jb < nT) {
+#pragma unroll
+                  for (int v = 0; v < 4; ++v)
+                    Sl[(ib * 16 + lq + 4 * v) * Dt + jb * 16 + l16] = acc[rb][jb][v];
+                }
             }
           }
           __syncthreads();
         }
 
+        // ---- residual, energy, update for the owned rows of target tl ----
         const int ysub = fdp->ysub[tl];
         const double *Yc = Ycb + ysub;
         const double *YTc = YTcb + ysub;
@@ -144,34 +222,39 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) {
                            a.f_occ[(int64_t)sl.q * a.n_occ + sl.q];
         const double w = (double)fdp->wgt[tl];
 #pragma unroll
-        for (int u = 0; u < MAXT; ++u) {
-          const int tt = wave + 4 * u;
-          if (tt < ntile) {
-            const int ri = tt / nT, rj = tt - ri * nT;
-            const int j = rj * 16 + l16;
-            const double ej = et[j];
+        for (int rb = 0; rb < MAXRB; ++rb) {
+          const int ib = wave + 4 * rb;
+          if (ib < nT) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int i = ri * 16 + lq + 4 * v;
-              double s = acc[u][v];
-              if (sym) s += ACC[(int64_t)j * Dt + i];
-              const int64_t ij = (int64_t)i * Dt + j;
-              const double y = Yc[ij];
-              const double yt = YTc[ij];
-              const double den = fpq - et[i] - ej;
-              const double r = Kt[ij] - den * y - s;
-              const double ar = fabs(r);
-              if (!(ar <= 1e300)) bad = 1;
-              mres = fmax(mres, ar);
-              epart += w * (2.0 * y - yt) * (Kt[ij] + r);
-              const double yn = y + r / den;
-              Yn[ij] = yn;
-              YTn[(int64_t)j * Dt + i] = yn;
+            for (int jb = 0; jb < MAXNT; ++jb) {
+              if (jb < nT) {
+                const int j = jb * 16 + l16;
+                const double ej = et[j];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  const int i = ib * 16 + lq + 4 * v;
+                  const int64_t ij = (int64_t)i * Dt + j;
+                  const double y = it > 0 ? Yc[ij] : 0.0;
+                  const double yt = it > 0 ? YTc[ij] : 0.0;
+                  const double kij = Kt[ij];
+                  const double den = fpq - et[i] - ej;
+                  const double sacc = sym ? acc[rb][jb][v] + Sl[j * Dt + i] : acc[rb][jb][v];
+                  const double r = kij - den * y - sacc;
+                  const double ar = fabs(r);
+                  if (!(ar <= 1e300)) bad = 1;
+                  mres = fmax(mres, ar);
+                  epart += w * (2.0 * y - yt) * (kij + r);
+                  const double yn = y + r / den;
+                  Yn[ij] = yn;
+                  YTn[(int64_t)j * Dt + i] = yn;
+                }
+              }
             }
           }
         }
-        if (sym) __syncthreads();  // ACC is reused by the next target
       }
+#undef MBE3_ADVANCE
+#undef MBE3_LOAD_PANEL
 
       // block reductions (fixed order: deterministic)
       for (int o = 32; o > 0; o >>= 1) {
@@ -184,7 +267,7 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) {
         red_d[4 + wave] = epart;
         red_i[wave] = bad;
       }
-      __syncthreads();
+      __syncthreads();  // also orders this sweep's Y writes before the next
       const double M = fmax(fmax(red_d[0], red_d[1]), fmax(red_d[2], red_d[3]));
       const double E = (red_d[4] + red_d[5]) + (red_d[6] + red_d[7]);
       const int B = red_i[0] | red_i[1] | red_i[2] | red_i[3];
@@ -202,7 +285,6 @@ __global__ __launch_bounds__(256) void solve_kernel(SolveArgs a) {
       }
       cur ^= 1;
     }
-    __syncthreads();
   }
 }
 
@@ -210,26 +292,33 @@ int64_t solve_scratch_doubles(int ny_max, int dmax) {
   return 4LL * ny_max + 2LL * dmax * dmax;
 }
 
+size_t solve_lds_bytes(int dmax) {
+  return (size_t)(dmax * dmax + 32 * dmax) * sizeof(double);
+}
+
+template <int NT>
+static hipError_t launch_nt(const SolveArgs &a, int n_wg, hipStream_t s) {
+  const size_t smem = solve_lds_bytes(a.dmax);
+  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(solve_kernel<NT>, dim3(n_wg), dim3(256), smem, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s) {
   if (a.n_frag <= 0) return hipSuccess;
-  const int nt = a.dmax / 16;
-  const int tiles = (nt * nt + 3) / 4;
-  dim3 grid(n_wg), block(256);
-  if (tiles <= 1)
-    hipLaunchKernelGGL(solve_kernel<1>, grid, block, 0, s, a);
-  else if (tiles <= 4)
-    hipLaunchKernelGGL(solve_kernel<4>, grid, block, 0, s, a);
-  else if (tiles <= 7)
-    hipLaunchKernelGGL(solve_kernel<7>, grid, block, 0, s, a);
-  else if (tiles <= 9)
-    hipLaunchKernelGGL(solve_kernel<9>, grid, block, 0, s, a);
-  else if (tiles <= 16)
-    hipLaunchKernelGGL(solve_kernel<16>, grid, block, 0, s, a);
-  else if (tiles <= 25)
-    hipLaunchKernelGGL(solve_kernel<25>, grid, block, 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (solve_lds_bytes(a.dmax) > 150 * 1024) return hipErrorInvalidValue;
+  switch (a.dmax / 16) {
+    case 1:
+    case 2: return launch_nt<2>(a, n_wg, s);
+    case 3: return launch_nt<3>(a, n_wg, s);
+    case 4: return launch_nt<4>(a, n_wg, s);
+    case 5: return launch_nt<5>(a, n_wg, s);
+    case 6: return launch_nt<6>(a, n_wg, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace mbe3
