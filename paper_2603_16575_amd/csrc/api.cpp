@@ -92,6 +92,7 @@ struct mbe3_handle {
   double *tmp = nullptr, *fp = nullptr, *zb = nullptr, *kt = nullptr;
   double *et = nullptr, *ev0 = nullptr;
   int32_t *rank = nullptr;
+  int32_t *sflag = nullptr;  // per slot: overlap not safely positive definite
   double *at = nullptr, *mt = nullptr, *st0 = nullptr;
   double *ca = nullptr, *cm = nullptr, *st1 = nullptr;
   double *scratch = nullptr;
@@ -873,6 +874,7 @@ int alloc_workspace(mbe3_handle *h) {
   if ((rc = dev_alloc(h, &h->et, h->et_off[h->n_slot]))) return rc;
   if ((rc = dev_alloc(h, &h->ev0, h->et_off[h->n_slot]))) return rc;
   if ((rc = dev_alloc(h, &h->rank, h->n_slot))) return rc;
+  if ((rc = dev_alloc(h, &h->sflag, h->n_slot))) return rc;
   int ny_max = 0, dmax = 16;
   for (auto &c : h->chunks) {
     ny_max = std::max(ny_max, c.ny_max);
@@ -932,12 +934,14 @@ int prepare_bases(mbe3_handle *h) {
   HIP_TRY(h, launch_assemble(h->d_asm_pair, h->n_asm_pair, h->sstore, h->fstore,
                              h->ps, h->pf, s));
   const int md = max_d(h);
+  HIP_TRY(h, launch_cholesky(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
+                             h->rank, h->sflag, h->tau_S, s));
   HIP_TRY(h, launch_jacobi(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
-                           h->rank, 0, h->tau_S, s));
+                           h->rank, 0, h->tau_S, h->sflag, s));
   HIP_TRY(h, launch_gemm_tasks(h->d_g_m1, (int)h->n_slot, h->t_m1, b, GEMM_64x64, s));
   HIP_TRY(h, launch_gemm_tasks(h->d_g_fp, (int)h->n_slot, h->t_fp, b, GEMM_64x64, s));
   HIP_TRY(h, launch_jacobi(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
-                           h->rank, 1, h->tau_S, s));
+                           h->rank, 1, h->tau_S, nullptr, s));
   HIP_TRY(h, launch_gemm_tasks(h->d_g_x, (int)h->n_slot, h->t_x, b, GEMM_64x64, s));
   return MBE3_OK;
 }

@@ -35,9 +35,11 @@ __device__ double block_sum(double v, double *red) {
 __global__ __launch_bounds__(256) void jacobi_kernel(
     const EigTask *__restrict__ tasks, const double *__restrict__ in,
     double *__restrict__ out, double *__restrict__ evals,
-    int32_t *__restrict__ rank, int mode, double tau) {
+    int32_t *__restrict__ rank, int mode, double tau,
+    const int32_t *__restrict__ only_flagged) {
   extern __shared__ double sm[];
   const EigTask t = tasks[blockIdx.x];
+  if (only_flagged && only_flagged[t.slot] == 0) return;
   const int n = mode == 0 ? t.n : rank[t.slot];
   const int D = t.D;
   const int ld = n + 1;
@@ -204,6 +206,94 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
   }
 }
 
+// Overlap step by Cholesky: S = L L^T in LDS (right-looking, one column per
+// step), then L^{-1} column by column (forward substitution, one column per
+// thread) and X0 = L^{-T}, which satisfies X0^T S X0 = 1 with the full rank.
+// A pivot <= tau (S not safely positive definite) sets flag[slot] and leaves
+// the slot to the canonical-orthogonalisation Jacobi launch that follows.
+__global__ __launch_bounds__(256) void cholesky_kernel(
+    const EigTask *__restrict__ tasks, const double *__restrict__ in,
+    double *__restrict__ out, double *__restrict__ evals,
+    int32_t *__restrict__ rank, int32_t *__restrict__ flag, double tau) {
+  extern __shared__ double sm[];
+  __shared__ int failed;
+  const EigTask t = tasks[blockIdx.x];
+  const int n = t.n, D = t.D, ld = n + 1;
+  double *L = sm;             // n x ld, lower triangle
+  double *Li = sm + n * ld;   // n x ld, L^{-1} (lower triangle)
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < n * n; e += nt) {
+    const int r = e / n, c = e - r * n;
+    L[r * ld + c] = c <= r ? in[t.a_off + (int64_t)r * t.lda + c] : 0.0;
+  }
+  if (tid == 0) failed = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = L[k * ld + k];
+    if (!(piv > tau)) {  // uniform: every thread reads the same value
+      if (tid == 0) failed = 1;
+      break;
+    }
+    const double lkk = sqrt(piv);
+    const double inv = 1.0 / lkk;
+    for (int i = k + 1 + tid; i < n; i += nt) L[i * ld + k] *= inv;
+    __syncthreads();
+    if (tid == 0) L[k * ld + k] = lkk;
+    const int m = n - k - 1;  // trailing order
+    const int ntri = m * (m + 1) / 2;
+    for (int e = tid; e < ntri; e += nt) {
+      int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (ii * (ii + 1) / 2 > e) --ii;
+      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      const int jj = e - ii * (ii + 1) / 2;  // jj <= ii
+      const int i = k + 1 + ii, j = k + 1 + jj;
+      L[i * ld + j] -= L[i * ld + k] * L[j * ld + k];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (failed) {
+    if (tid == 0) flag[t.slot] = 1;
+    return;
+  }
+  // L^{-1}: thread c solves L x = e_c for column c (rows >= c)
+  for (int c = tid; c < n; c += nt) {
+    for (int i = 0; i < c; ++i) Li[i * ld + c] = 0.0;
+    for (int i = c; i < n; ++i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int m2 = c; m2 < i; ++m2) acc -= L[i * ld + m2] * Li[m2 * ld + c];
+      Li[i * ld + c] = acc / L[i * ld + i];
+    }
+  }
+  __syncthreads();
+  // X0 = L^{-T}: X0[r][c] = Li[c][r]
+  for (int e = tid; e < n * D; e += nt) {
+    const int r = e / D, c = e - r * D;
+    out[t.o_off + (int64_t)r * D + c] = c < n ? Li[c * ld + r] : 0.0;
+  }
+  for (int c = tid; c < D; c += nt) evals[t.e_off + c] = c < n ? 1.0 : EV_SENTINEL;
+  if (tid == 0) {
+    rank[t.slot] = n;
+    flag[t.slot] = 0;
+  }
+}
+
+hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
+                           const double *in, double *out, double *evals,
+                           int32_t *rank, int32_t *flag, double tau,
+                           hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  const size_t smem = sizeof(double) * (size_t)2 * max_n * (max_n + 1);
+  if (smem > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void *)cholesky_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cholesky_kernel, dim3(n_tasks), dim3(256), smem, s, d_tasks,
+                     in, out, evals, rank, flag, tau);
+  return hipGetLastError();
+}
+
 static size_t jacobi_smem(int n) {
   const int ld = n + 1, nh = (n + 1) / 2;
   return sizeof(double) * ((size_t)2 * n * ld + 2 * (nh + 1) + (n + 1) + 8) +
@@ -212,7 +302,8 @@ static size_t jacobi_smem(int n) {
 
 hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
                          const double *in, double *out, double *evals,
-                         int32_t *rank, int mode, double tau, hipStream_t s) {
+                         int32_t *rank, int mode, double tau,
+                         const int32_t *only_flagged, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
   const size_t smem = jacobi_smem(max_n);
   if (smem > 160 * 1024) return hipErrorInvalidValue;
@@ -221,7 +312,7 @@ hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
                                      (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(jacobi_kernel, dim3(n_tasks), dim3(256), smem, s, d_tasks,
-                     in, out, evals, rank, mode, tau);
+                     in, out, evals, rank, mode, tau, only_flagged);
   return hipGetLastError();
 }
 

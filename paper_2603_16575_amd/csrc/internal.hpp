@@ -95,7 +95,14 @@ struct EigTask {
 hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
                          const double *in, double *out, double *evals,
                          int32_t *rank, int mode, double tau,
-                         hipStream_t s);
+                         const int32_t *only_flagged, hipStream_t s);
+// Overlap step by Cholesky (X0 = L^-T, full rank).  Slots whose pivots drop
+// to <= tau get flag[slot] = 1 and are redone by launch_jacobi(mode 0,
+// only_flagged = flag).
+hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
+                           const double *in, double *out, double *evals,
+                           int32_t *rank, int32_t *flag, double tau,
+                           hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Fragment solver (solve.hip)
