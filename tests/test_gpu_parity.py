@@ -226,3 +226,27 @@ def test_deterministic(m):
     _, o2 = run_all(m, prob)
     assert o1["E"] == o2["E"]
     assert np.array_equal(o1["e_frag"].cpu().numpy(), o2["e_frag"].cpu().numpy())
+
+
+def test_water40u_total_vs_golden(m):
+    """Full configuration 1: E against the oracle's full run (written by
+    tests/golden/make_golden.py, oracle only), |dE| <= 1e-10 Eh; the update
+    count histogram and every 1000th fragment energy as well."""
+    import json
+    import os
+    say("case: water40u (configs 1) total energy vs golden oracle run")
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "water40u_oracle.json")))
+    prob = synth.config(1)
+    h, out = run_all(m, prob)
+    E_ref = float(g["E_total"])
+    say(f"water40u: E_gpu={out['E']:.13f} E_oracle={E_ref:.13f} "
+        f"dE={out['E'] - E_ref:.3e}")
+    assert abs(out["E"] - E_ref) <= 1e-10
+    it = out["iters"].cpu().numpy()
+    assert np.bincount(it).tolist() == g["iters_hist"]
+    e = out["e_frag"].cpu().numpy()
+    idx = np.array(g["sample_index"])
+    ref = np.array([float(x) for x in g["sample_e_frag"]])
+    assert np.abs(e[idx] - ref).max() <= 1e-12
+    h.close()
