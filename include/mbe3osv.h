@@ -70,7 +70,13 @@ extern "C" {
 #define MBE3_PHASE_CROSS 5   /* per-trimer S~ between pair domains          */
 #define MBE3_PHASE_SOLVE 6   /* fragment residual iterations                */
 #define MBE3_PHASE_ENERGY 7  /* MBE(3) sum                                  */
-#define MBE3_NPHASE 8
+#define MBE3_PHASE_GRAD 8    /* multipliers and dE/df (fragment_solve, W)   */
+#define MBE3_PHASE_BACKWARD 9 /* mbe3_backward                              */
+#define MBE3_NPHASE 10
+
+/* Output selector of mbe3_backward. */
+#define MBE3_GRAD_SLAB 0  /* dE/d(ia|P), [n_occ][n_vir][n_aux]               */
+#define MBE3_GRAD_GAMMA 1 /* dE/dG, osv_project's layout                     */
 
 typedef struct mbe3_handle mbe3_handle;
 
@@ -178,11 +184,46 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems);
  * [n_frag] int32, number of updates, or -(max_iter+1) if not converged.
  * W: device, K layout, or NULL; when given it receives the MBE multipliers
  *   W_s = sum_{F containing p,q} c_F (2 T^F_pq - T^F_pq^T)
- * used by mbe3_backward.  Returns MBE3_ENOCONV / MBE3_ENONFINITE after the
- * stream finished if any fragment failed (other fragments are valid).
+ * (c_F: the fragment's coefficient in the MBE(3) sum of mbe3_energy, i.e.
+ * E = sum_F c_F e_frag[F]) at the converged amplitudes, and the handle
+ * records dE/df_occ for mbe3_backward.  The first call with W plans and
+ * allocates the gradient workspace (about one Y block per fragment and
+ * chunk, one gamma-sized buffer).  Returns MBE3_ENOCONV / MBE3_ENONFINITE
+ * after the stream finished if any fragment failed (other fragments are
+ * valid; W is then not).
  */
 int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
                    int32_t *iters, double *W);
+
+/*
+ * mbe3_backward -- gradient of the MBE(3) energy through pair_K and
+ * osv_project.  Because every fragment energy is a Hylleraas functional at
+ * a stationary point of its amplitudes, its derivative with respect to K or
+ * f_occ is the explicit one at the converged amplitudes:
+ *   dE/dK_s = 4 W_s (pairs), 2 W_s (diagonal slots)  with W from
+ *   fragment_solve; K_s = L R^T (pair_K) gives dL = G R and dR = G^T L, so
+ *   dE/dB_i = 4 sum_{q in N+(i)} V_iq W_iq V_iq^T B_q  (W_qi = W_iq^T in
+ *   the swapped basis, W_ii symmetrised), and
+ *   dE/df_xy = -sum_F c_F [ sum_q <T~_xq, S_(xq,yq) T_yq S_(yq,xq)>
+ *                         + sum_p <T~_py, S_(py,px) T_px S_(px,py)> ]
+ *   over ordered pairs of F, T~ = 2T - T^T, returned symmetrised.
+ * dE: scale applied to every output (the upstream derivative).
+ * gamma: device, osv_project's output for the same slabs.  W: device, K
+ *   layout (fragment_solve's multipliers, or any d_s x d_s blocks G_s / 4
+ *   for pairs and G_s / 2 for diagonal slots to back-propagate dE/dK = G).
+ * mode MBE3_GRAD_SLAB: out = dE dE/dB, device [n_occ][n_vir][n_aux];
+ *   MBE3_GRAD_GAMMA: out = dE dE/dG (G_{i,x} = Q_x^T B_i), gamma layout.
+ *   out_elems: doubles available at out.
+ * dEdF: device [n_occ][n_occ] or NULL: dE (g + g^T) / 2 from the last
+ *   fragment_solve that received W (MBE3_EINVAL if there was none).
+ * probe: host double or NULL: receives <out_G, G> with out_G = dE dE/dG
+ *   (summed in double-double).  E is homogeneous of degree 4 in the slabs,
+ *   so at exact convergence this is 4 E dE; the difference is of the order
+ *   of the residual left at tol.  Synchronises the stream.
+ */
+int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
+                  const double *W, int mode, double *out, int64_t out_elems,
+                  double *dEdF, double *probe);
 
 /*
  * mbe3_energy -- E = sum_i E_i + sum_ij dE_ij + sum_ijk dE_ijk with

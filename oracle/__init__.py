@@ -24,10 +24,11 @@ occupied Fock matrix, the amplitude form of the expansion, invariance under
 OSV rotations, homogeneity and the Euler identity, and central finite
 differences.
 """
-from .mbe3 import (Oracle, gradient, energy, mbe3_coefficients, mbe3_energy,
-                   orbs, run, slab, swap_blocks)
+from .mbe3 import (Oracle, gradient, energy, fragment_gradient,
+                   mbe3_coefficients, mbe3_energy, orbs, run, slab, swap_blocks)
 from .philox import box_muller, philox4x64_10
 
-__all__ = ["Oracle", "gradient", "energy", "mbe3_coefficients", "mbe3_energy",
+__all__ = ["Oracle", "gradient", "energy", "fragment_gradient",
+           "mbe3_coefficients", "mbe3_energy",
            "orbs", "run", "slab", "swap_blocks", "box_muller",
            "philox4x64_10"]

@@ -377,17 +377,47 @@ def energy(prob, workers: int = 1, ora: Optional[Oracle] = None) -> float:
 # --------------------------------------------------------------------------
 # O8: gradient through Hylleraas stationarity
 # --------------------------------------------------------------------------
+def fragment_gradient(ora: Oracle, frag: Sequence[int], T: dict):
+    """Explicit derivatives of one fragment's Hylleraas energy at its
+    converged amplitudes T (stored p <= q), the unit the MBE sums:
+      Tt[(p, q)] = 2 T_pq - T_pq^T                      (multiplier share)
+      g[x, y]    = dE_F/df_xy
+                 = -[ sum_q <T~_xq, S_(xq,yq) T_yq S_(yq,xq)>
+                    + sum_p <T~_py, S_(py,px) T_px S_(px,py)> ]
+    with p, q, x, y over the fragment's orbitals (ordered pairs), i.e. the
+    f-dependent terms of eq. res_close inside the functional.
+    """
+    o = sorted(int(x) for x in frag if x >= 0)
+    Tt = {t: 2.0 * v - v.T for t, v in T.items()}
+    g = np.zeros((ora.prob.n_occ, ora.prob.n_occ))
+    for x in o:
+        for y in o:
+            acc = 0.0
+            for q in o:
+                Sa = ora.Sblk(orbs(x, q), orbs(y, q))
+                Txq = ora.get_T(T, x, q)
+                acc += np.sum((2.0 * Txq - Txq.T)
+                              * (Sa @ ora.get_T(T, y, q) @ Sa.T))
+            for p in o:
+                Sb = ora.Sblk(orbs(p, y), orbs(p, x))
+                Tpy = ora.get_T(T, p, y)
+                acc += np.sum((2.0 * Tpy - Tpy.T)
+                              * (Sb @ ora.get_T(T, p, x) @ Sb.T))
+            g[x, y] = -acc
+    return Tt, g
+
+
 def gradient(prob, workers: int = 1, ora: Optional[Oracle] = None):
     """dE/dB_i (dict of [n_vir, n_aux]) and dE/df (symmetric [n_occ, n_occ]).
 
     Each fragment energy is stationary in its amplitudes, so its derivative
     with respect to K or f is the explicit derivative of the Hylleraas
-    functional at the converged amplitudes:
+    functional at the converged amplitudes (fragment_gradient), summed with
+    the MBE(3) coefficients:
       W_pq = sum_{F containing p,q} c_F (2 T^F_pq - T^F_pq^T)
       dE/dB_i = 4 sum_{q in N+(i)} V_iq W_iq V_iq^T B_q
-      dE/df_xy = -sum_F c_F [ sum_q <T~_xq, S_(xq,yq) T_yq S_(yq,xq)>
-                            + sum_p <T~_py, S_(py,px) T_px S_(px,py)> ]
-    (ordered pairs over F).  The symmetric gradient (g + g^T)/2 is returned.
+      dE/df = sum_F c_F g_F
+    The symmetric gradient (g + g^T)/2 is returned.
     """
     frags = prob.frags
     out = run(prob, frags, workers=workers, keep_T=True, ora=ora)
@@ -396,24 +426,10 @@ def gradient(prob, workers: int = 1, ora: Optional[Oracle] = None):
     W: Dict[Tuple[int, int], np.ndarray] = {}
     g = np.zeros((prob.n_occ, prob.n_occ))
     for f, cF, T in zip(frags, c, out["T"]):
-        o = sorted(int(x) for x in f if x >= 0)
-        for t, Tt in T.items():
-            tt = 2.0 * Tt - Tt.T
-            W[t] = W.get(t, 0.0) + cF * tt
-        for x in o:
-            for y in o:
-                acc = 0.0
-                for q in o:
-                    Sa = ora.Sblk(orbs(x, q), orbs(y, q))
-                    Txq = ora.get_T(T, x, q)
-                    acc += np.sum((2.0 * Txq - Txq.T)
-                                  * (Sa @ ora.get_T(T, y, q) @ Sa.T))
-                for p in o:
-                    Sb = ora.Sblk(orbs(p, y), orbs(p, x))
-                    Tpy = ora.get_T(T, p, y)
-                    acc += np.sum((2.0 * Tpy - Tpy.T)
-                                  * (Sb @ ora.get_T(T, p, x) @ Sb.T))
-                g[x, y] -= cF * acc
+        Tt, gF = fragment_gradient(ora, f, T)
+        for t, v in Tt.items():
+            W[t] = W.get(t, 0.0) + cF * v
+        g += cF * gF
     dB = {}
     for i in range(prob.n_occ):
         acc = np.zeros((prob.n_vir, prob.n_aux))

@@ -2,9 +2,11 @@
 
 Python face of the C-ABI library ``libmbe3osv`` (include/mbe3osv.h).  The
 entry points keep the C names: ``osv_project``, ``pair_K``,
-``fragment_solve``, ``mbe3_energy`` and ``mbe3_pair_basis``; ``Mbe3`` owns a
-library handle for one problem.  Device arrays are torch CUDA (HIP) tensors,
-which supply memory and the stream; the arithmetic runs in the library.
+``fragment_solve``, ``mbe3_energy``, ``mbe3_backward`` and
+``mbe3_pair_basis``; ``Mbe3`` owns a library handle for one problem.  Device
+arrays are torch CUDA (HIP) tensors, which supply memory and the stream; the
+arithmetic runs in the library.  ``energy_fn`` exposes the energy as a
+differentiable torch function of the slab and the occupied Fock matrix.
 """
 import ctypes
 
@@ -12,11 +14,14 @@ import numpy as np
 
 from . import _lib
 from ._lib import (MBE3_EHIP, MBE3_EINVAL, MBE3_ENOCONV, MBE3_ENOMEM,
-                   MBE3_ENONFINITE, MBE3_FP64, MBE3_OK, Mbe3Error)
+                   MBE3_ENONFINITE, MBE3_FP64, MBE3_GRAD_GAMMA, MBE3_GRAD_SLAB,
+                   MBE3_OK, Mbe3Error)
 
 __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
-           "mbe3_energy", "mbe3_pair_basis", "MBE3_OK", "MBE3_EINVAL",
-           "MBE3_ENOMEM", "MBE3_EHIP", "MBE3_ENOCONV", "MBE3_ENONFINITE"]
+           "mbe3_energy", "mbe3_backward", "mbe3_pair_basis", "energy_fn",
+           "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
+           "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
+           "MBE3_GRAD_GAMMA"]
 
 
 def _f64(t):
@@ -38,6 +43,7 @@ class Mbe3:
         import torch
         lib = _lib.load()
         self._keep = [Q, eps_vir, f_occ, w_ia, w_iP, slab]
+        self.f_occ, self.slab = f_occ, slab
         for t in (Q, eps_vir, f_occ, w_ia, w_iP, slab):
             if t is not None:
                 _f64(t)
@@ -77,6 +83,7 @@ class Mbe3:
         _lib.check(lib.mbe3_get_layout(self._h, ctypes.byref(lay)), self._h)
         self.layout = lay
         self.n_occ = n_occ
+        self.n_vir = p.n_vir
         self.n_aux = p.n_aux
         self.n_frag = lay.n_frag
         self.g_off = np.zeros(n_occ + 1, dtype=np.int64)
@@ -136,6 +143,25 @@ class Mbe3:
                    self._h)
         return float(out[0])
 
+    def mbe3_backward(self, gamma, W, dE=1.0, mode=MBE3_GRAD_SLAB, out=None,
+                      dEdF=None, probe=False):
+        """dE * dE/d(slab) (mode MBE3_GRAD_SLAB, [n_occ, n_vir, n_aux]) or
+        dE * dE/dGamma (MBE3_GRAD_GAMMA, gamma layout) into ``out``, and
+        dE * dE/df_occ into ``dEdF`` when given.  Returns (out, probe) with
+        probe = <dE dE/dGamma, Gamma> (host float) if requested."""
+        import torch
+        if out is None:
+            shape = ((self.n_occ, self.n_vir, self.n_aux) if mode == MBE3_GRAD_SLAB
+                     else (int(self.layout.gamma_elems),))
+            out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        pr = np.zeros(1, dtype=np.float64)
+        _lib.check(_lib.load().mbe3_backward(
+            self._h, float(dE), _lib.ptr(_f64(gamma)), _lib.ptr(_f64(W)),
+            int(mode), _lib.ptr(_f64(out)), out.numel(),
+            _lib.ptr(None if dEdF is None else _f64(dEdF)),
+            _lib.ptr(pr) if probe else None), self._h)
+        return out, (float(pr[0]) if probe else None)
+
     def mbe3_pair_basis(self):
         import torch
         X = torch.empty(int(self.x_off[-1]), dtype=torch.float64, device=self.device)
@@ -155,16 +181,61 @@ class Mbe3:
         _lib.check(_lib.load().mbe3_get_timing(self._h, _lib.ptr(ms), _lib.ptr(n)), self._h)
         return {ph: (float(ms[k]), int(n[k])) for k, ph in enumerate(_lib.PHASES)}
 
-    def forward(self):
-        """osv_project -> pair_K -> fragment_solve -> mbe3_energy."""
+    def forward(self, grad=False):
+        """osv_project -> pair_K -> fragment_solve -> mbe3_energy; with
+        grad=True fragment_solve also returns the multipliers W."""
         import torch
         gamma = self.osv_project(self.empty_gamma())
         K = self.pair_K(gamma, self.empty_K())
         e = torch.empty(self.n_frag, dtype=torch.float64, device=self.device)
         it = torch.empty(self.n_frag, dtype=torch.int32, device=self.device)
-        self.fragment_solve(K, e, it)
+        W = self.empty_K() if grad else None
+        self.fragment_solve(K, e, it, W)
         E = self.mbe3_energy(e)
-        return dict(E=E, gamma=gamma, K=K, e_frag=e, iters=it)
+        return dict(E=E, gamma=gamma, K=K, e_frag=e, iters=it, W=W)
+
+
+def _energy_function():
+    import torch
+
+    class _Mbe3Energy(torch.autograd.Function):
+        """E(slab, f_occ) with the library's forward and backward."""
+
+        @staticmethod
+        def forward(ctx, h, slab, f_occ):
+            if h.slab is None or slab.data_ptr() != h.slab.data_ptr() or \
+                    f_occ.data_ptr() != h.f_occ.data_ptr():
+                raise ValueError("energy_fn: slab and f_occ must be the tensors "
+                                 "the handle was created with")
+            out = h.forward(grad=True)
+            ctx.h = h
+            ctx.saved = (out["gamma"], out["W"])
+            return torch.tensor(out["E"], dtype=torch.float64, device=slab.device)
+
+        @staticmethod
+        def backward(ctx, gE):
+            h = ctx.h
+            gamma, W = ctx.saved
+            dE = float(gE)
+            dF = torch.empty((h.n_occ, h.n_occ), dtype=torch.float64, device=h.device)
+            dB, _ = h.mbe3_backward(gamma, W, dE=dE, mode=MBE3_GRAD_SLAB, dEdF=dF)
+            return None, dB, dF
+
+    return _Mbe3Energy
+
+
+_ENERGY_FN = None
+
+
+def energy_fn(h, slab, f_occ):
+    """Differentiable MBE(3)-OSV-MP2 energy (0-d float64 tensor) of the
+    handle's problem.  ``slab`` ([n_occ, n_vir, n_aux]) and ``f_occ`` must be
+    the tensors the handle was created with (the library reads them in
+    place); their gradients come from mbe3_backward."""
+    global _ENERGY_FN
+    if _ENERGY_FN is None:
+        _ENERGY_FN = _energy_function()
+    return _ENERGY_FN.apply(h, slab, f_occ)
 
 
 def osv_project(h, gamma):
@@ -181,6 +252,11 @@ def fragment_solve(h, K, e_frag, iters, W=None):
 
 def mbe3_energy(h, e_frag, incr=None):
     return h.mbe3_energy(e_frag, incr)
+
+
+def mbe3_backward(h, gamma, W, dE=1.0, mode=MBE3_GRAD_SLAB, out=None,
+                  dEdF=None, probe=False):
+    return h.mbe3_backward(gamma, W, dE, mode, out, dEdF, probe)
 
 
 def mbe3_pair_basis(h):

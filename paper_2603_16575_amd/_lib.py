@@ -20,16 +20,18 @@ MBE3_EHIP = -3
 MBE3_ENOCONV = -4
 MBE3_ENONFINITE = -5
 MBE3_FP64 = 0
+MBE3_GRAD_SLAB = 0
+MBE3_GRAD_GAMMA = 1
 
 EXPORTS = [
     "mbe3_create", "mbe3_destroy", "mbe3_last_error", "mbe3_get_layout",
     "mbe3_gamma_offsets", "mbe3_k_offsets", "mbe3_basis_offsets",
     "osv_project", "pair_K", "fragment_solve", "mbe3_energy",
     "mbe3_pair_basis", "mbe3_plan_check", "mbe3_set_timing",
-    "mbe3_get_timing",
+    "mbe3_get_timing", "mbe3_backward",
 ]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
-          "energy"]
+          "energy", "grad", "backward"]
 
 
 class Mbe3Problem(ctypes.Structure):
@@ -88,6 +90,8 @@ def load():
         "mbe3_plan_check": [ctypes.POINTER(Mbe3Problem), ctypes.POINTER(Mbe3Layout)],
         "mbe3_set_timing": [vp, ctypes.c_int],
         "mbe3_get_timing": [vp, vp, vp],
+        "mbe3_backward": [vp, ctypes.c_double, vp, vp, ctypes.c_int, vp, i64,
+                          vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

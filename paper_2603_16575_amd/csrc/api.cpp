@@ -34,7 +34,8 @@ inline int64_t key2(int a, int b) { return ((int64_t)a << 32) | (uint32_t)b; }
 // base-pointer ids of the GEMM engine
 enum Base {
   B_Q = 0, B_EQ, B_SLAB, B_GAMMA, B_K, B_SS, B_FS, B_PS, B_PF, B_X0, B_X,
-  B_TMP, B_FP, B_Z, B_KT, B_AT, B_MT, B_ST0, B_CA, B_CM, B_ST1, B_COUNT
+  B_TMP, B_FP, B_Z, B_KT, B_AT, B_MT, B_ST0, B_CA, B_CM, B_ST1,
+  B_WT, B_W, B_GA, B_DG, B_DB, B_COUNT
 };
 static_assert(B_COUNT <= NBASE, "too many GEMM bases");
 
@@ -50,6 +51,15 @@ struct Chunk {
   Term *d_terms = nullptr;
   int dmax = 16;
   int ny_max = 0;
+  int64_t ny_total = 0;  // converged Y blocks of the chunk (gradient mode)
+  int n_terms = 0;
+  // gradient reductions of this chunk (planned on first use)
+  WSlot *d_ws = nullptr;
+  WEntry *d_we = nullptr;
+  int n_ws = 0;
+  GDest *d_gd = nullptr;
+  GEntry *d_ge = nullptr;
+  int n_gd = 0;
 };
 
 }  // namespace
@@ -132,6 +142,23 @@ struct mbe3_handle {
   int64_t gamma_rows = 0;
   int64_t k_elems = 0;
 
+  // ---- gradient (planned on first use) ----
+  bool grad_planned = false;
+  bool grad_ready = false;   // W and dE/df of the last fragment_solve are valid
+  double *wt = nullptr;      // W~ per slot (K~ layout)
+  double *yfin = nullptr, *gterm = nullptr, *gdiag = nullptr;
+  double *graw = nullptr;    // unsymmetrised dE/df
+  double *ga = nullptr, *dg = nullptr;
+  double *dot_part = nullptr, *d_probe = nullptr, *h_probe = nullptr;
+  int64_t yfin_max = 1, gterm_max = 1, gdiag_max = 1, ga_total = 1;
+  GemmTask *d_g_wm = nullptr, *d_g_ww = nullptr, *d_g_dg = nullptr,
+           *d_g_up = nullptr;
+  int64_t t_wm = 0, t_ww = 0, t_dg = 0, t_up = 0;
+  int n_dg = 0;
+  GASeg *d_ga = nullptr;
+  int n_ga = 0;
+  int32_t *d_grows = nullptr;
+
   // ---- per-phase event timing (mbe3_set_timing) ----
   bool timing = false;
   struct Region { int phase; hipEvent_t a, b; };
@@ -166,6 +193,7 @@ struct mbe3_handle {
     for (void *p : allocs) (void)hipFree(p);
     if (h_status) (void)hipHostFree(h_status);
     if (h_e3) (void)hipHostFree(h_e3);
+    if (h_probe) (void)hipHostFree(h_probe);
   }
 };
 
@@ -656,6 +684,7 @@ int build_plans(mbe3_handle *h) {
   auto flush = [&](void) -> int {
     if (cur.frag_ids.empty()) return MBE3_OK;
     cur.n_frag = (int)fds.size();
+    cur.n_terms = (int)terms.size();
     cur.n_asm = (int)cas.size();
     cur.n_gemm = (int)cgm.size();
     cur.tiles_m = finish_tasks(cgm, GEMM_64x64);
@@ -727,6 +756,8 @@ int build_plans(mbe3_handle *h) {
       cur.dmax = std::max(cur.dmax, D);
     }
     fd.ny = ny;
+    fd.yout = cur.ny_total;
+    cur.ny_total += ny;
     cur.ny_max = std::max(cur.ny_max, ny);
     // cross S~ of this trimer: cross[a][b] = offset of row-major S~_(ls[a], ls[b])
     int64_t cross[6][6];
@@ -913,6 +944,9 @@ GemmBases bases(mbe3_handle *h) {
   b.p[B_CA] = h->ca;
   b.p[B_CM] = h->cm;
   b.p[B_ST1] = h->st1;
+  b.p[B_WT] = h->wt;
+  b.p[B_GA] = h->ga;
+  b.p[B_DG] = h->dg;
   b.rows = h->d_rows;
   return b;
 }
@@ -964,73 +998,94 @@ int prepare_pairs(mbe3_handle *h, const double *K) {
   return MBE3_OK;
 }
 
-// Host-side bounds check of every plan against the buffers it addresses,
-// run before any kernel of the plan is launched.  A failure here is a bug in
-// the planner, reported as MBE3_EINVAL.
-int validate_plans(mbe3_handle *h) {
+// Bounds of one GEMM task list against the buffer sizes sz[] (in doubles)
+// and the row-gather table it uses.
+int check_gemm_list(mbe3_handle *h, const std::string &name,
+                    const std::vector<GemmTask> &ts, const int64_t *sz,
+                    const std::vector<int32_t> &rows, int tile) {
+  auto bad = [&](const std::string &what, size_t k) {
+    return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
+  };
+  const int64_t n_rows = (int64_t)rows.size();
+  int64_t tb = 0;
+  for (size_t k = 0; k < ts.size(); ++k) {
+    const GemmTask &t = ts[k];
+    if (t.a_buf < 0 || t.a_buf >= B_COUNT || t.b_buf < 0 || t.b_buf >= B_COUNT ||
+        t.c_buf < 0 || t.c_buf >= B_COUNT)
+      return bad(name + " (buffer id)", k);
+    if (t.M < 1 || t.N < 1 || t.K < 1) return bad(name + " (empty)", k);
+    if (t.tile_begin != tb) return bad(name + " (tile prefix)", k);
+    if (t.tiles_n != (t.N + tile - 1) / tile) return bad(name + " (tiles_n)", k);
+    tb += (int64_t)((t.M + tile - 1) / tile) * t.tiles_n;
+    auto rmax = [&](int32_t off, int n, int64_t &out) {
+      if (off < 0) { out = n - 1; return true; }
+      if ((int64_t)off + n > n_rows) return false;
+      int64_t m = -1;
+      for (int e = 0; e < n; ++e) {
+        if (rows[off + e] < 0) return false;
+        m = std::max<int64_t>(m, rows[off + e]);
+      }
+      out = m;
+      return true;
+    };
+    int64_t amax, bmax, r;
+    if (!t.transA) {
+      if (t.lda < t.K || !rmax(t.a_rows, t.M, r)) return bad(name + " (A rows)", k);
+      amax = t.a_off + r * t.lda + t.K - 1;
+    } else {
+      if (t.lda < t.M || !rmax(t.a_rows, t.K, r)) return bad(name + " (A^T rows)", k);
+      amax = t.a_off + r * t.lda + t.M - 1;
+    }
+    if (!t.transB) {
+      if (t.ldb < t.N || !rmax(t.b_rows, t.K, r)) return bad(name + " (B rows)", k);
+      bmax = t.b_off + r * t.ldb + t.N - 1;
+    } else {
+      if (t.ldb < t.K || !rmax(t.b_rows, t.N, r)) return bad(name + " (B^T rows)", k);
+      bmax = t.b_off + r * t.ldb + t.K - 1;
+    }
+    const int64_t cmax = t.c_off + (int64_t)(t.M - 1) * t.ldc + t.N - 1;
+    if (t.ldc < t.N) return bad(name + " (ldc)", k);
+    if (t.a_off < 0 || amax >= sz[t.a_buf]) return bad(name + " (A bounds)", k);
+    if (t.b_off < 0 || bmax >= sz[t.b_buf]) return bad(name + " (B bounds)", k);
+    if (t.c_off < 0 || cmax >= sz[t.c_buf]) return bad(name + " (C bounds)", k);
+  }
+  return MBE3_OK;
+}
+
+// Sizes (doubles) of every GEMM base; caller buffers at their required size.
+void base_sizes(const mbe3_handle *h, int64_t *sz) {
   const int64_t nv = h->n_vir, na = h->n_aux;
-  int64_t sz[B_COUNT];
+  for (int k = 0; k < B_COUNT; ++k) sz[k] = 0;
   sz[B_Q] = sz[B_EQ] = h->q_off[h->n_occ] * nv;
   sz[B_SLAB] = (h->slab ? (int64_t)h->n_occ : (int64_t)h->slab_nb) * nv * na;
-  sz[B_GAMMA] = h->gamma_rows * na;
-  sz[B_K] = sz[B_PS] = sz[B_PF] = h->k_elems;
+  sz[B_GAMMA] = sz[B_DG] = h->gamma_rows * na;
+  sz[B_K] = sz[B_PS] = sz[B_PF] = sz[B_W] = h->k_elems;
   sz[B_SS] = sz[B_FS] = h->sb_total;
   sz[B_X0] = sz[B_X] = sz[B_TMP] = h->x_off[h->n_slot];
-  sz[B_FP] = sz[B_Z] = sz[B_KT] = h->kt_off[h->n_slot];
+  sz[B_FP] = sz[B_Z] = sz[B_KT] = sz[B_WT] = h->kt_off[h->n_slot];
   sz[B_AT] = h->at_total;
   sz[B_MT] = h->mt_total;
   sz[B_ST0] = h->st0_total;
   sz[B_CA] = h->max_ca;
   sz[B_CM] = h->max_cm;
   sz[B_ST1] = h->max_st1;
+  sz[B_GA] = h->ga_total;
+  sz[B_DB] = (int64_t)h->n_occ * nv * na;
+}
+
+// Host-side bounds check of every plan against the buffers it addresses,
+// run before any kernel of the plan is launched.  A failure here is a bug in
+// the planner, reported as MBE3_EINVAL.
+int validate_plans(mbe3_handle *h) {
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
   auto bad = [&](const std::string &what, size_t k) {
     return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
   };
   for (auto &pl : h->h_gemm) {
-    const std::string &name = pl.first;
-    int64_t tb = 0;
-    for (size_t k = 0; k < pl.second.size(); ++k) {
-      const GemmTask &t = pl.second[k];
-      if (t.a_buf < 0 || t.a_buf >= B_COUNT || t.b_buf < 0 || t.b_buf >= B_COUNT ||
-          t.c_buf < 0 || t.c_buf >= B_COUNT)
-        return bad(name + " (buffer id)", k);
-      if (t.M < 1 || t.N < 1 || t.K < 1) return bad(name + " (empty)", k);
-      if (t.tile_begin != tb) return bad(name + " (tile prefix)", k);
-      const int b = name == "project" ? 128 : 64;
-      if (t.tiles_n != (t.N + b - 1) / b) return bad(name + " (tiles_n)", k);
-      tb += (int64_t)((t.M + b - 1) / b) * t.tiles_n;
-      auto rmax = [&](int32_t off, int n, int64_t &out) {
-        if (off < 0) { out = n - 1; return true; }
-        if ((int64_t)off + n > h->n_rows) return false;
-        int64_t m = -1;
-        for (int e = 0; e < n; ++e) {
-          if (h->h_rows[off + e] < 0) return false;
-          m = std::max<int64_t>(m, h->h_rows[off + e]);
-        }
-        out = m;
-        return true;
-      };
-      int64_t amax, bmax, r;
-      if (!t.transA) {
-        if (t.lda < t.K || !rmax(t.a_rows, t.M, r)) return bad(name + " (A rows)", k);
-        amax = t.a_off + r * t.lda + t.K - 1;
-      } else {
-        if (t.lda < t.M || t.a_rows >= 0) return bad(name + " (A^T)", k);
-        amax = t.a_off + (int64_t)(t.K - 1) * t.lda + t.M - 1;
-      }
-      if (!t.transB) {
-        if (t.ldb < t.N || t.b_rows >= 0) return bad(name + " (B)", k);
-        bmax = t.b_off + (int64_t)(t.K - 1) * t.ldb + t.N - 1;
-      } else {
-        if (t.ldb < t.K || !rmax(t.b_rows, t.N, r)) return bad(name + " (B^T rows)", k);
-        bmax = t.b_off + r * t.ldb + t.K - 1;
-      }
-      const int64_t cmax = t.c_off + (int64_t)(t.M - 1) * t.ldc + t.N - 1;
-      if (t.ldc < t.N) return bad(name + " (ldc)", k);
-      if (t.a_off < 0 || amax >= sz[t.a_buf]) return bad(name + " (A bounds)", k);
-      if (t.b_off < 0 || bmax >= sz[t.b_buf]) return bad(name + " (B bounds)", k);
-      if (t.c_off < 0 || cmax >= sz[t.c_buf]) return bad(name + " (C bounds)", k);
-    }
+    const int rc = check_gemm_list(h, pl.first, pl.second, sz, h->h_rows,
+                                   pl.first == "project" ? 128 : 64);
+    if (rc) return rc;
   }
   for (auto &pl : h->h_asm) {
     for (size_t k = 0; k < pl.second.size(); ++k) {
@@ -1104,6 +1159,227 @@ int validate_plans(mbe3_handle *h) {
   return MBE3_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Gradient plans (built on the first call that asks for multipliers).
+//   per chunk: W~ entries grouped by slot and f-gradient entries grouped by
+//              destination f_xy, both in fragment order (deterministic);
+//   W_s = X_s W~_s X_s^T for every slot;
+//   dGamma~_{i,x} = GA_{i,x} [gathered Gamma~ rows], one product per
+//              destination block, GA the concatenated multiplier segments;
+//   dE/dB_i = sum_x Q_x dGamma~_{i,x} (gathered Q rows, transposed).
+// ---------------------------------------------------------------------------
+int build_grad_plans(mbe3_handle *h) {
+  if (h->grad_planned) return MBE3_OK;
+  const int n = h->n_occ, na = h->n_aux, nv = h->n_vir;
+  int rc;
+  auto bad = [&](const char *what, size_t k) {
+    return h->fail(MBE3_EINVAL, "internal plan check failed: gradient %s %zu", what, k);
+  };
+  int64_t ymax = 1, tmax = 1, gmax = 1;
+  for (size_t c = 0; c < h->chunks.size(); ++c) {
+    Chunk &ch = h->chunks[c];
+    const auto &fds = h->h_fds[c];
+    const auto &terms = h->h_terms[c];
+    ymax = std::max(ymax, ch.ny_total);
+    tmax = std::max<int64_t>(tmax, ch.n_terms);
+    gmax = std::max<int64_t>(gmax, 6LL * ch.n_frag);
+    std::map<int, std::vector<WEntry>> bs;
+    std::map<int, std::vector<GEntry>> gs;
+    for (size_t k = 0; k < fds.size(); ++k) {
+      const FragDesc &fd = fds[k];
+      for (int l = 0; l < fd.nt; ++l) {
+        const int sl = fd.slot[l];
+        const int64_t D = h->sD[sl];
+        if (fd.yout < 0 || fd.yout + fd.ysub[l] + D * D > ch.ny_total) return bad("Y store", k);
+        bs[sl].push_back({fd.yout + fd.ysub[l], fd.coef});
+      }
+      for (int e = fd.term_begin; e < fd.term_end; ++e) {
+        const Term &t = terms[e];
+        gs[t.fx * n + t.fy].push_back({-fd.coef * fd.wgt[t.target], 0, e});
+      }
+      // f_pp and f_qq inside E~ (both f_pp for a diagonal slot)
+      for (int l = 0; l < fd.nt; ++l) {
+        const int sl = fd.slot[l];
+        const double sc = -fd.coef * fd.wgt[l];
+        gs[h->sp[sl] * n + h->sp[sl]].push_back({sc, 1, (int32_t)(6 * k + l)});
+        gs[h->sq[sl] * n + h->sq[sl]].push_back({sc, 1, (int32_t)(6 * k + l)});
+      }
+    }
+    std::vector<WSlot> ws;
+    std::vector<WEntry> we;
+    for (auto &kv : bs) {
+      WSlot w;
+      std::memset(&w, 0, sizeof w);
+      w.wt_off = h->kt_off[kv.first];
+      w.D = h->sD[kv.first];
+      w.e_begin = (int32_t)we.size();
+      we.insert(we.end(), kv.second.begin(), kv.second.end());
+      w.e_end = (int32_t)we.size();
+      ws.push_back(w);
+    }
+    std::vector<GDest> gd;
+    std::vector<GEntry> ge;
+    for (auto &kv : gs) {
+      GDest d;
+      std::memset(&d, 0, sizeof d);
+      d.dst = kv.first;
+      d.e_begin = (int32_t)ge.size();
+      for (const GEntry &e : kv.second) {
+        if (e.kind == 0 ? (e.idx < 0 || e.idx >= ch.n_terms)
+                        : (e.idx < 0 || e.idx >= 6 * ch.n_frag))
+          return bad("f entry", ge.size());
+        ge.push_back(e);
+      }
+      d.e_end = (int32_t)ge.size();
+      if (d.dst < 0 || d.dst >= n * n) return bad("f destination", gd.size());
+      gd.push_back(d);
+    }
+    ch.n_ws = (int)ws.size();
+    ch.n_gd = (int)gd.size();
+    if ((rc = upload(h, &ch.d_ws, ws))) return rc;
+    if ((rc = upload(h, &ch.d_we, we))) return rc;
+    if ((rc = upload(h, &ch.d_gd, gd))) return rc;
+    if ((rc = upload(h, &ch.d_ge, ge))) return rc;
+  }
+  h->yfin_max = ymax;
+  h->gterm_max = tmax;
+  h->gdiag_max = gmax;
+
+  std::vector<std::pair<std::string, std::vector<GemmTask>>> lists;
+  // ---- W_s = X_s W~_s X_s^T ----
+  {
+    std::vector<GemmTask> wm, ww;
+    for (int64_t s = 0; s < h->n_slot; ++s) {
+      const int d = h->sd[s], D = h->sD[s];
+      wm.push_back(gemm(B_X, h->x_off[s], D, 0, B_WT, h->kt_off[s], D, 0, B_TMP,
+                        h->x_off[s], D, d, D, D));
+      ww.push_back(gemm(B_TMP, h->x_off[s], D, 0, B_X, h->x_off[s], D, 1, B_W,
+                        h->k_off[s], d, d, d, D));
+    }
+    h->t_wm = finish_tasks(wm, GEMM_64x64);
+    h->t_ww = finish_tasks(ww, GEMM_64x64);
+    if ((rc = upload(h, &h->d_g_wm, wm))) return rc;
+    if ((rc = upload(h, &h->d_g_ww, ww))) return rc;
+    lists.push_back({"W left", wm});
+    lists.push_back({"W right", ww});
+  }
+  // ---- dGamma~ per destination block (i, x) ----
+  std::vector<int32_t> rows;
+  std::vector<GASeg> segs;
+  std::vector<GemmTask> dg, up;
+  int64_t ga_total = 0;
+  auto grows = [&](int i, int x) {  // rows of Gamma~_{i,x}
+    const int64_t g0 = h->grow.at(key2(i, x));
+    for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)g0 + mu);
+  };
+  for (int i = 0; i < n; ++i) {
+    for (int x : h->nbr[i]) {
+      const int rx = h->r[x];
+      // segments of this destination: (slot, rc0, mode, scale, right factor)
+      struct Seg { int s, rc0, mode; double scale; int ra, xa, rb, xb; };
+      std::vector<Seg> sl;
+      auto add_pair = [&](int a, int b) {  // contribution through slot (a, b)
+        const int s = slot_of(h, a, b);
+        const int p = h->sp[s], q = h->sq[s];
+        const int rc0 = (x == i) ? (i == p ? 0 : h->r[p]) : (i == p ? h->r[p] : 0);
+        if (i == p)  // dL = G R, R = [Gamma~_{q,p}; Gamma~_{q,q}]
+          sl.push_back({s, rc0, 0, 4.0, q, p, q, q});
+        else         // dR = G^T L, L = [Gamma~_{p,p}; Gamma~_{p,q}]
+          sl.push_back({s, rc0, 1, 4.0, p, p, p, q});
+      };
+      if (x == i) {
+        sl.push_back({i, 0, 2, 2.0, i, i, -1, -1});  // K_ii = G~ G~^T
+        for (int q : h->nbr[i])
+          if (q != i) add_pair(i, q);
+      } else {
+        add_pair(i, x);
+      }
+      const int32_t brow = (int32_t)rows.size();
+      const size_t seg0 = segs.size();
+      int ktot = 0;
+      for (const Seg &g : sl) {
+        const int d = h->sd[g.s];
+        GASeg a;
+        std::memset(&a, 0, sizeof a);
+        a.w_off = h->k_off[g.s];
+        a.w_ld = d;
+        a.ga_off = ga_total;
+        a.rc0 = g.rc0;
+        a.k0 = ktot;
+        a.rows = rx;
+        a.kseg = d;
+        a.mode = g.mode;
+        a.scale = g.scale;
+        segs.push_back(a);
+        grows(g.ra, g.xa);
+        if (g.rb >= 0) grows(g.rb, g.xb);
+        ktot += d;
+      }
+      for (size_t k = seg0; k < segs.size(); ++k) segs[k].ga_ld = ktot;
+      if ((int)rows.size() - brow != ktot) return bad("gather rows", (size_t)i);
+      GemmTask t = gemm(B_GA, ga_total, ktot, 0, B_GAMMA, 0, na, 0, B_DG,
+                        h->grow.at(key2(i, x)) * na, na, rx, na, ktot);
+      t.b_rows = brow;
+      dg.push_back(t);
+      ga_total += (int64_t)rx * ktot;
+    }
+    // dE/dB_i = [Q_x ...] dGamma~_i
+    GemmTask t = gemm(B_Q, 0, nv, 1, B_DG, h->g_off[i] * na, na, 0, B_DB,
+                      (int64_t)i * nv * na, na, nv, na,
+                      (int)(h->g_off[i + 1] - h->g_off[i]));
+    t.a_rows = (int32_t)rows.size();
+    for (int x : h->nbr[i])
+      for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->q_off[x] + mu));
+    up.push_back(t);
+  }
+  h->ga_total = std::max<int64_t>(1, ga_total);
+  h->t_dg = finish_tasks(dg, GEMM_64x64);
+  h->n_dg = (int)dg.size();
+  h->t_up = finish_tasks(up, GEMM_128x128);
+  h->n_ga = (int)segs.size();
+  if ((rc = upload(h, &h->d_g_dg, dg))) return rc;
+  if ((rc = upload(h, &h->d_g_up, up))) return rc;
+  if ((rc = upload(h, &h->d_ga, segs))) return rc;
+  if ((rc = upload(h, &h->d_grows, rows))) return rc;
+
+  // ---- bounds ----
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  for (auto &pl : lists)
+    if ((rc = check_gemm_list(h, pl.first, pl.second, sz, h->h_rows, 64))) return rc;
+  if ((rc = check_gemm_list(h, "dGamma", dg, sz, rows, 64))) return rc;
+  if ((rc = check_gemm_list(h, "unproject", up, sz, rows, 128))) return rc;
+  for (size_t k = 0; k < segs.size(); ++k) {
+    const GASeg &a = segs[k];
+    if (a.rows < 1 || a.kseg < 1 || a.k0 + a.kseg > a.ga_ld) return bad("segment shape", k);
+    if (a.ga_off + (int64_t)(a.rows - 1) * a.ga_ld + a.k0 + a.kseg > h->ga_total)
+      return bad("segment output", k);
+    int64_t last;
+    if (a.mode == 0) last = (int64_t)(a.rc0 + a.rows - 1) * a.w_ld + a.kseg - 1;
+    else if (a.mode == 1) last = (int64_t)(a.kseg - 1) * a.w_ld + a.rc0 + a.rows - 1;
+    else {
+      if (a.rc0 != 0 || a.rows != a.kseg) return bad("segment symmetric", k);
+      last = (int64_t)(a.kseg - 1) * a.w_ld + a.kseg - 1;
+    }
+    if (a.rc0 + a.rows > a.w_ld || a.w_off + last >= h->k_elems) return bad("segment input", k);
+  }
+
+  // ---- buffers ----
+  if ((rc = dev_alloc(h, &h->wt, h->kt_off[h->n_slot]))) return rc;
+  if ((rc = dev_alloc(h, &h->yfin, ymax))) return rc;
+  if ((rc = dev_alloc(h, &h->gterm, tmax))) return rc;
+  if ((rc = dev_alloc(h, &h->gdiag, gmax))) return rc;
+  if ((rc = dev_alloc(h, &h->graw, (int64_t)n * n))) return rc;
+  if ((rc = dev_alloc(h, &h->ga, h->ga_total))) return rc;
+  if ((rc = dev_alloc(h, &h->dg, h->gamma_rows * na))) return rc;
+  if ((rc = dev_alloc(h, &h->dot_part, 2LL * dot_partials()))) return rc;
+  if ((rc = dev_alloc(h, &h->d_probe, 1))) return rc;
+  if (!h->dry)
+    HIP_TRY(h, hipHostMalloc((void **)&h->h_probe, sizeof(double)));
+  h->grad_planned = true;
+  return MBE3_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1142,6 +1418,7 @@ int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out) {
   if (!rc) rc = build_plans(h);
   if (!rc) rc = alloc_workspace(h);
   if (!rc) rc = validate_plans(h);
+  if (!rc) rc = build_grad_plans(h);
   if (!rc && out) mbe3_get_layout(h, out);
   g_create_error = rc ? h->err : std::string("ok");
   delete h;
@@ -1228,12 +1505,18 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
                    int32_t *iters, double *W) {
   if (!h) return MBE3_EINVAL;
   if (!K || !e_frag || !iters) return h->fail(MBE3_EINVAL, "K, e_frag, iters required");
-  if (W) return h->fail(MBE3_EINVAL, "multiplier output is not available in this build");
   hipStream_t s = h->stream;
-  int rc = prepare_pairs(h, K);
-  if (rc) return rc;
+  h->grad_ready = false;
+  int rc;
+  if (W && (rc = build_grad_plans(h))) return rc;
+  if ((rc = prepare_pairs(h, K))) return rc;
   GemmBases b = bases(h);
   HIP_TRY(h, launch_fill_i32(h->status, 0, 2 * SOLVE_WG, s));
+  if (W) {
+    PhaseScope ps_(h, MBE3_PHASE_GRAD);
+    HIP_TRY(h, launch_fill(h->wt, 0.0, h->kt_off[h->n_slot], s));
+    HIP_TRY(h, launch_fill(h->graw, 0.0, (int64_t)h->n_occ * h->n_occ, s));
+  }
   for (auto &c : h->chunks) {
     if (c.n_asm) {
       PhaseScope ps_(h, MBE3_PHASE_CROSS);
@@ -1261,8 +1544,12 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
     a.tol = h->tol;
     a.e_frag = e_frag;
     a.iters = iters;
-    a.w_store = nullptr;
     a.status = h->status;
+    if (W) {
+      a.yfin = h->yfin;
+      a.gterm = h->gterm;
+      a.gdiag = h->gdiag;
+    }
     // the scratch layout is fixed by the largest chunk (dmax / ny_max)
     int dm = 16, nym = 0;
     for (auto &cc : h->chunks) { dm = std::max(dm, cc.dmax); nym = std::max(nym, cc.ny_max); }
@@ -1271,8 +1558,23 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
     const int per_cu = (int)std::max<size_t>(
         1, std::min<size_t>(4, (160 * 1024) / (solve_lds_bytes(dm) + 2048)));
     const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu);
-    PhaseScope ps_(h, MBE3_PHASE_SOLVE);
-    HIP_TRY(h, launch_solve(a, nwg, s));
+    {
+      PhaseScope ps_(h, MBE3_PHASE_SOLVE);
+      HIP_TRY(h, launch_solve(a, nwg, s));
+    }
+    if (W) {
+      // this chunk's share of W~ and dE/df (its Y store is reused next)
+      PhaseScope ps_(h, MBE3_PHASE_GRAD);
+      HIP_TRY(h, launch_wtilde(c.d_ws, c.n_ws, c.d_we, h->yfin, h->wt, s));
+      HIP_TRY(h, launch_fgrad(c.d_gd, c.n_gd, c.d_ge, h->gterm, h->gdiag,
+                              h->graw, s));
+    }
+  }
+  if (W) {
+    PhaseScope ps_(h, MBE3_PHASE_GRAD);
+    b.p[B_W] = W;
+    HIP_TRY(h, launch_gemm_tasks(h->d_g_wm, (int)h->n_slot, h->t_wm, b, GEMM_64x64, s));
+    HIP_TRY(h, launch_gemm_tasks(h->d_g_ww, (int)h->n_slot, h->t_ww, b, GEMM_64x64, s));
   }
   HIP_TRY(h, hipMemcpyAsync(h->h_status, h->status, 2 * SOLVE_WG * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
@@ -1285,6 +1587,53 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
   if (bad) return h->fail(MBE3_ENONFINITE, "non-finite residual in some fragment (e_frag = NaN)");
   if (nconv) return h->fail(MBE3_ENOCONV, "some fragment did not converge in %d updates (iters < 0)",
                             h->max_iter);
+  h->grad_ready = W != nullptr;
+  return MBE3_OK;
+}
+
+int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
+                  const double *W, int mode, double *out, int64_t out_elems,
+                  double *dEdF, double *probe) {
+  if (!h) return MBE3_EINVAL;
+  if (!gamma || !W || !out) return h->fail(MBE3_EINVAL, "gamma, W and out required");
+  if (mode != MBE3_GRAD_SLAB && mode != MBE3_GRAD_GAMMA)
+    return h->fail(MBE3_EINVAL, "unknown gradient mode %d", mode);
+  if (!std::isfinite(dE)) return h->fail(MBE3_EINVAL, "dE is not finite");
+  const int64_t na = h->n_aux;
+  const int64_t need = mode == MBE3_GRAD_SLAB ? (int64_t)h->n_occ * h->n_vir * na
+                                              : h->gamma_rows * na;
+  if (out_elems < need)
+    return h->fail(MBE3_EINVAL, "out needs %lld doubles, got %lld", (long long)need,
+                   (long long)out_elems);
+  if (dEdF && !h->grad_ready)
+    return h->fail(MBE3_EINVAL, "dE/df needs a preceding successful fragment_solve with W");
+  int rc = build_grad_plans(h);
+  if (rc) return rc;
+  hipStream_t s = h->stream;
+  double *dgam = mode == MBE3_GRAD_GAMMA ? out : h->dg;
+  {
+    PhaseScope ps_(h, MBE3_PHASE_BACKWARD);
+    GemmBases b = bases(h);
+    b.rows = h->d_grows;
+    b.p[B_GAMMA] = const_cast<double *>(gamma);
+    b.p[B_W] = const_cast<double *>(W);
+    b.p[B_DG] = dgam;
+    b.p[B_DB] = out;
+    HIP_TRY(h, launch_ga(h->d_ga, h->n_ga, W, dE, h->ga, s));
+    HIP_TRY(h, launch_gemm_tasks(h->d_g_dg, h->n_dg, h->t_dg, b, GEMM_64x64, s));
+    if (mode == MBE3_GRAD_SLAB)
+      HIP_TRY(h, launch_gemm_tasks(h->d_g_up, h->n_occ, h->t_up, b, GEMM_128x128, s));
+    if (dEdF) HIP_TRY(h, launch_fsym(h->graw, h->n_occ, dE, dEdF, s));
+    if (probe)
+      HIP_TRY(h, launch_dot(dgam, gamma, h->gamma_rows * na, 1.0, h->dot_part,
+                            h->d_probe, s));
+  }
+  if (probe) {
+    HIP_TRY(h, hipMemcpyAsync(h->h_probe, h->d_probe, sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    *probe = *h->h_probe;
+  }
   return MBE3_OK;
 }
 

@@ -4,9 +4,12 @@
 // tiles of depth 16 are staged through LDS with coalesced global reads
 // (k-contiguous or m/n-contiguous depending on the transpose flags) and laid
 // out k-major so that each MFMA operand read is 16 consecutive doubles.
-// Rows of A (and rows of a transposed B) may be gathered through an index
-// list, which lets one task project a slab onto the OSVs of all neighbours
-// of an orbital, or form a 4-block pair K from two scattered row blocks.
+// Stored rows of either operand may be gathered through an index list (rows
+// of A = M index when A is not transposed, K index when it is; rows of B = K
+// index when B is not transposed, N index when it is), which lets one task
+// project a slab onto the OSVs of all neighbours of an orbital, form a
+// 4-block pair K from two scattered row blocks, or contract gradient blocks
+// of many pairs in one K-concatenated product.
 #include "internal.hpp"
 
 namespace mbe3 {
@@ -79,11 +82,12 @@ __global__ __launch_bounds__(256) void gemm_tasks_kernel(
       const int tpk = BM / EA;
       const int kk = tid / tpk, mm = (tid % tpk) * EA;
       const int k = k0 + kk;
+      const int64_t krow = k < t.K ? (t.a_rows >= 0 ? rows[t.a_rows + k] : k) : 0;
 #pragma unroll
       for (int e = 0; e < EA; ++e) {
         const int m = m0 + mm + e;
         double v = 0.0;
-        if (m < t.M && k < t.K) v = A[(int64_t)k * t.lda + m];
+        if (m < t.M && k < t.K) v = A[krow * t.lda + m];
         As[kk * PA + mm + e] = v;
       }
     }
@@ -92,11 +96,12 @@ __global__ __launch_bounds__(256) void gemm_tasks_kernel(
       const int tpk = BN / EB;
       const int kk = tid / tpk, nn = (tid % tpk) * EB;
       const int k = k0 + kk;
+      const int64_t krow = k < t.K ? (t.b_rows >= 0 ? rows[t.b_rows + k] : k) : 0;
 #pragma unroll
       for (int e = 0; e < EB; ++e) {
         const int n = n0 + nn + e;
         double v = 0.0;
-        if (n < t.N && k < t.K) v = B[(int64_t)k * t.ldb + n];
+        if (n < t.N && k < t.K) v = B[krow * t.ldb + n];
         Bs[kk * PB + nn + e] = v;
       }
     } else {

@@ -13,7 +13,7 @@ namespace mbe3 {
 //   small table of base pointers so that plans built once at create time can
 //   be replayed on caller buffers.
 // ---------------------------------------------------------------------------
-enum { NBASE = 24 };
+enum { NBASE = 32 };
 struct GemmBases {
   double *p[NBASE];
   const int32_t *rows;  // row-gather indices (see a_rows / b_rows)
@@ -23,10 +23,10 @@ struct GemmTask {
   int64_t a_off, b_off, c_off;  // element offsets into bases.p[*_buf]
   int64_t tile_begin;           // first tile of this task (prefix sum)
   int32_t a_buf, b_buf, c_buf;
-  int32_t a_rows;  // >= 0: logical row m of A (transA = 0) is physical row
-                   // rows[a_rows + m]; -1: identity
-  int32_t b_rows;  // >= 0: logical column n of B (transB = 1, B stored as
-                   // rows) is physical row rows[b_rows + n]; -1: identity
+  int32_t a_rows;  // >= 0: stored row r of A is physical row rows[a_rows + r]
+                   // (r = m for transA = 0, r = k for transA = 1); -1: identity
+  int32_t b_rows;  // >= 0: stored row r of B is physical row rows[b_rows + r]
+                   // (r = k for transB = 0, r = n for transB = 1); -1: identity
   int32_t M, N, K, lda, ldb, ldc;
   int32_t transA, transB;
   int32_t tiles_n;
@@ -124,6 +124,7 @@ struct FragDesc {
   int32_t ny;           // sum of D^2 over the fragment's slots
   int32_t pad_;
   double coef;          // MBE(3) coefficient c_F
+  int64_t yout;         // offset of the converged Y blocks in the chunk store
 };
 struct Term {
   int32_t target, src;  // local slot indices within the fragment
@@ -150,12 +151,64 @@ struct SolveArgs {
   double tol;
   double *e_frag;
   int32_t *iters;
-  double *w_store;       // MBE multipliers in the K~ layout (X basis) or null
   int32_t *status;       // [2 * workgroup]: non-finite seen, non-converged seen
+  // gradient mode (all null otherwise): converged Y blocks per fragment
+  // (at FragDesc::yout), per-term contractions <Y~_t, S~ Y_s^(T) S~^T>
+  // (<Y_t + Y_t^T, .> for diagonal targets) indexed by term, and per-target
+  // <Y~_t, Y_t> at 6 * fragment + target.
+  double *yfin;
+  double *gterm;
+  double *gdiag;
 };
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s);
 int64_t solve_scratch_doubles(int ny_max, int dmax);
 size_t solve_lds_bytes(int dmax);
+
+// ---------------------------------------------------------------------------
+// Backward (backward.hip)
+// ---------------------------------------------------------------------------
+// W~ of one slot (D x D at wt_off) += sum of its entries [e_begin, e_end).
+struct WSlot {
+  int64_t wt_off;
+  int32_t D, e_begin, e_end, pad_;
+};
+struct WEntry {
+  int64_t yoff;  // converged Y block (D x D) in the chunk's Y store
+  double coef;   // c_F
+};
+hipError_t launch_wtilde(const WSlot *slots, int n_slots, const WEntry *ents,
+                         const double *yfin, double *wt, hipStream_t s);
+// g[dst] += sum of scale * (kind ? gdiag[idx] : gterm[idx]) over the entries.
+struct GDest {
+  int32_t dst, e_begin, e_end, pad_;
+};
+struct GEntry {
+  double scale;
+  int32_t kind, idx;
+};
+hipError_t launch_fgrad(const GDest *dests, int n, const GEntry *ents,
+                        const double *gterm, const double *gdiag, double *g,
+                        hipStream_t s);
+// One segment of the concatenated multiplier block of a dGamma destination:
+// ga[ga_off + r * ga_ld + k0 + k] = mult * scale * src(r, k), r < rows,
+// k < kseg,
+//   mode 0: W[rc0 + r][k], mode 1: W[k][rc0 + r], mode 2: W[r][k] + W[k][r]
+// with W the d x d multiplier block at w_off (leading dimension w_ld).
+struct GASeg {
+  int64_t w_off, ga_off;
+  int32_t w_ld, ga_ld, rc0, k0, rows, kseg, mode, pad_;
+  double scale;
+};
+hipError_t launch_ga(const GASeg *segs, int n, const double *W, double mult,
+                     double *ga, hipStream_t s);
+// out[0] = scale * <x, y> in double-double arithmetic, fixed order; part
+// holds 2 * dot_partials() doubles.
+hipError_t launch_dot(const double *x, const double *y, int64_t n, double scale,
+                      double *part, double *out, hipStream_t s);
+int dot_partials();
+// out = scale (g + g^T) / 2 for an n x n matrix.
+hipError_t launch_fsym(const double *g, int n, double scale, double *out,
+                       hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Reductions (reduce.hip)

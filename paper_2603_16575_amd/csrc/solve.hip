@@ -44,8 +44,77 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Workgroup sum in a fixed order (wave shuffles, then the four waves).
+__device__ __forceinline__ double wg_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+// One term's products accumulated into acc (see the data flow above): pass 1
+// streams the S~ and Y^(T) row panels into LDS and forms W = Z^T in
+// registers, pass 2 reads the S~ resident in LDS.  Expects the panel
+// pipeline state (pf, p_*), Dt/nT, Ds/nS, acc and the LDS pointers in scope.
+#define MBE3_TERM_PRODUCTS(COEF)                                               \
+  do {                                                                         \
+    d4 W[MAXRB][MAXNT];                                                        \
+    _Pragma("unroll") for (int rb = 0; rb < MAXRB; ++rb)                       \
+      _Pragma("unroll") for (int kb = 0; kb < MAXNT; ++kb)                     \
+        W[rb][kb] = d4{0.0, 0.0, 0.0, 0.0};                                    \
+    __syncthreads(); /* the previous term's S~ is no longer read */            \
+    for (int mp = 0; mp < nS; ++mp) {                                          \
+      double *const yb = (mp & 1) ? yb1 : yb0;                                 \
+      {                                                                        \
+        d2 *s_ = reinterpret_cast<d2 *>(Sl + 16 * mp * Dt);                    \
+        d2 *y_ = reinterpret_cast<d2 *>(yb);                                   \
+        _Pragma("unroll") for (int u = 0; u < MAXNT; ++u) {                    \
+          const int e = tid + 256 * u;                                         \
+          if (e < p_n1) s_[e] = pf[u];                                         \
+          else if (e - p_n1 < p_n2) y_[e - p_n1] = pf[u];                      \
+        }                                                                      \
+      }                                                                        \
+      /* the next panel streams in under the products; a term's last panel   \
+         prefetches the next term's first one */                              \
+      MBE3_ADVANCE();                                                          \
+      if (p_ti < f_te) MBE3_LOAD_PANEL();                                      \
+      __syncthreads();                                                         \
+      const double *STp = Sl + 16 * mp * Dt;                                   \
+      _Pragma("unroll") for (int mm = 0; mm < 4; ++mm) {                       \
+        const int ml = 4 * mm + lq;                                            \
+        _Pragma("unroll") for (int rb = 0; rb < MAXRB; ++rb) {                 \
+          const int ib = wave + 4 * rb;                                        \
+          if (ib < nT) {                                                       \
+            const double bv = STp[ml * Dt + ib * 16 + l16];                    \
+            _Pragma("unroll") for (int kb = 0; kb < MAXNT; ++kb)               \
+              if (kb < nS)                                                     \
+                W[rb][kb] = mfma_f64(yb[ml * Ds + kb * 16 + l16], bv, W[rb][kb]); \
+          }                                                                    \
+        }                                                                      \
+      }                                                                        \
+    }                                                                          \
+    _Pragma("unroll") for (int kp = 0; kp < MAXNT; ++kp) {                     \
+      if (kp < nS) {                                                           \
+        _Pragma("unroll") for (int v = 0; v < 4; ++v) {                        \
+          const double *brow = Sl + (kp * 16 + 4 * v + lq) * Dt + l16;         \
+          _Pragma("unroll") for (int rb = 0; rb < MAXRB; ++rb) {               \
+            const int ib = wave + 4 * rb;                                      \
+            if (ib < nT) {                                                     \
+              const double av = (COEF) * W[rb][kp][v];                         \
+              _Pragma("unroll") for (int jb = 0; jb < MAXNT; ++jb)             \
+                if (jb < nT) acc[rb][jb] = mfma_f64(av, brow[jb * 16], acc[rb][jb]); \
+            }                                                                  \
+          }                                                                    \
+        }                                                                      \
+      }                                                                        \
+    }                                                                          \
+  } while (0)
+
 // MAXNT: largest number of 16-blocks per pair dimension (dmax / 16).
-template <int MAXNT>
+// GRAD: also run the gradient pass after convergence.
+template <int MAXNT, bool GRAD>
 __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
   extern __shared__ double lds[];
   constexpr int MAXRB = (MAXNT + 3) / 4;  // row blocks per wave
@@ -127,67 +196,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             const double coef = a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
             const int Ds = a.slots[fdp->slot[tm.src]].D;
             const int nS = Ds >> 4;
-            d4 W[MAXRB][MAXNT];
-#pragma unroll
-            for (int rb = 0; rb < MAXRB; ++rb)
-#pragma unroll
-              for (int kb = 0; kb < MAXNT; ++kb) W[rb][kb] = d4{0.0, 0.0, 0.0, 0.0};
-            __syncthreads();  // the previous term's S~ is no longer read
-            // pass 1: W(kb, ib) += Y^(T)[m, kb] (x) S~'^T[m, ib] over panels
-            for (int mp = 0; mp < nS; ++mp) {
-              double *const yb = (mp & 1) ? yb1 : yb0;
-              {
-                d2 *s_ = reinterpret_cast<d2 *>(Sl + 16 * mp * Dt);
-                d2 *y_ = reinterpret_cast<d2 *>(yb);
-#pragma unroll
-                for (int u = 0; u < MAXNT; ++u) {
-                  const int e = tid + 256 * u;
-                  if (e < p_n1) s_[e] = pf[u];
-                  else if (e - p_n1 < p_n2) y_[e - p_n1] = pf[u];
-                }
-              }
-              MBE3_ADVANCE();
-              // the next panel streams in under the products; the last
-              // panel of a term prefetches the next term's first one
-              if (p_ti < f_te) MBE3_LOAD_PANEL();
-              __syncthreads();
-              const double *STp = Sl + 16 * mp * Dt;
-#pragma unroll
-              for (int mm = 0; mm < 4; ++mm) {
-                const int ml = 4 * mm + lq;
-#pragma unroll
-                for (int rb = 0; rb < MAXRB; ++rb) {
-                  const int ib = wave + 4 * rb;
-                  if (ib < nT) {
-                    const double bv = STp[ml * Dt + ib * 16 + l16];
-#pragma unroll
-                    for (int kb = 0; kb < MAXNT; ++kb)
-                      if (kb < nS)
-                        W[rb][kb] = mfma_f64(yb[ml * Ds + kb * 16 + l16], bv, W[rb][kb]);
-                  }
-                }
-              }
-            }
-            // pass 2: acc[ib, jb] += coef Z[ib, k] S~'^T[k, jb] from LDS
-#pragma unroll
-            for (int kp = 0; kp < MAXNT; ++kp) {
-              if (kp < nS) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                  const double *brow = Sl + (kp * 16 + 4 * v + lq) * Dt + l16;
-#pragma unroll
-                  for (int rb = 0; rb < MAXRB; ++rb) {
-                    const int ib = wave + 4 * rb;
-                    if (ib < nT) {
-                      const double av = coef * W[rb][kp][v];
-#pragma unroll
-                      for (int jb = 0; jb < MAXNT; ++jb)
-                        if (jb < nT) acc[rb][jb] = mfma_f64(av, brow[jb * 16], acc[rb][jb]);
-                    }
-                  }
-                }
-              }
-            }
+            MBE3_TERM_PRODUCTS(coef);
           }
         }
 
@@ -253,9 +262,6 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           }
         }
       }
-#undef MBE3_ADVANCE
-#undef MBE3_LOAD_PANEL
-
       // block reductions (fixed order: deterministic)
       for (int o = 32; o > 0; o >>= 1) {
         mres = fmax(mres, __shfl_xor(mres, o));
@@ -281,12 +287,79 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           if (B) st[0] = 1;
           if (!conv && !B) st[1] = 1;
         }
+        if (GRAD && conv && !B) {
+          // ---- gradient pass at the converged amplitudes ----
+          // Y blocks for the multipliers W, then each term's product with
+          // coefficient 1 contracted with Y~ = 2Y - Y^T (Y + Y^T for a
+          // diagonal target, whose mirror terms are folded), and <Y~, Y>
+          // per target for the f_pp, f_qq inside E~.
+          if (it == 0) {
+            // converged at T = 0 (K~ below the threshold): all zero
+            for (int e = tid; e < fdp->ny; e += 256) a.yfin[fdp->yout + e] = 0.0;
+            for (int ti = f_tb + tid; ti < f_te; ti += 256) a.gterm[ti] = 0.0;
+            if (tid < f_nt) a.gdiag[6 * fi + tid] = 0.0;
+            break;
+          }
+          for (int e = tid; e < fdp->ny; e += 256) a.yfin[fdp->yout + e] = Ycb[e];
+          p_ti = f_tb;
+          p_m = 0;
+          if (f_tb < f_te) MBE3_LOAD_PANEL();
+          for (int tl = 0; tl < f_nt; ++tl) {
+            const SlotInfo sl = a.slots[fdp->slot[tl]];
+            const int Dt = sl.D;
+            const int nT = Dt >> 4;
+            const int sym = fdp->sym[tl];
+            const double *Yc = Ycb + fdp->ysub[tl];
+            const double *YTc = YTcb + fdp->ysub[tl];
+            d4 acc[MAXRB][MAXNT];
+            for (int ti = f_tb; ti < f_te; ++ti) {
+              const Term tm = a.terms[ti];
+              if (tm.target != tl) continue;
+              const int Ds = a.slots[fdp->slot[tm.src]].D;
+              const int nS = Ds >> 4;
+#pragma unroll
+              for (int rb = 0; rb < MAXRB; ++rb)
+#pragma unroll
+                for (int jb = 0; jb < MAXNT; ++jb) acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
+              MBE3_TERM_PRODUCTS(1.0);
+              double part = 0.0;
+#pragma unroll
+              for (int rb = 0; rb < MAXRB; ++rb) {
+                const int ib = wave + 4 * rb;
+                if (ib < nT) {
+#pragma unroll
+                  for (int jb = 0; jb < MAXNT; ++jb)
+                    if (jb < nT) {
+#pragma unroll
+                      for (int v = 0; v < 4; ++v) {
+                        const int64_t ij = (int64_t)(ib * 16 + lq + 4 * v) * Dt + jb * 16 + l16;
+                        const double wy = sym ? Yc[ij] + YTc[ij] : 2.0 * Yc[ij] - YTc[ij];
+                        part += wy * acc[rb][jb][v];
+                      }
+                    }
+                }
+              }
+              const double tot = wg_sum(part, red_d);
+              if (tid == 0) a.gterm[ti] = tot;
+            }
+            double part = 0.0;
+            for (int e = tid; e < Dt * Dt; e += 256) {
+              const double y = Yc[e];
+              part += (2.0 * y - YTc[e]) * y;
+            }
+            const double tot = wg_sum(part, red_d);
+            if (tid == 0) a.gdiag[6 * fi + tl] = tot;
+          }
+        }
         break;
       }
       cur ^= 1;
     }
   }
 }
+#undef MBE3_ADVANCE
+#undef MBE3_LOAD_PANEL
+#undef MBE3_TERM_PRODUCTS
 
 int64_t solve_scratch_doubles(int ny_max, int dmax) {
   return 4LL * ny_max + 2LL * dmax * dmax;
@@ -296,15 +369,20 @@ size_t solve_lds_bytes(int dmax) {
   return (size_t)(dmax * dmax + 32 * dmax) * sizeof(double);
 }
 
-template <int NT>
-static hipError_t launch_nt(const SolveArgs &a, int n_wg, hipStream_t s) {
+template <int NT, bool GRAD>
+static hipError_t launch_nt_g(const SolveArgs &a, int n_wg, hipStream_t s) {
   const size_t smem = solve_lds_bytes(a.dmax);
-  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT>,
+  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT, GRAD>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(solve_kernel<NT>, dim3(n_wg), dim3(256), smem, s, a);
+  hipLaunchKernelGGL((solve_kernel<NT, GRAD>), dim3(n_wg), dim3(256), smem, s, a);
   return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t launch_nt(const SolveArgs &a, int n_wg, hipStream_t s) {
+  return a.yfin ? launch_nt_g<NT, true>(a, n_wg, s) : launch_nt_g<NT, false>(a, n_wg, s);
 }
 
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s) {
