@@ -2,14 +2,17 @@
 
 One step = the whole hot path on one batch of seeded synthetic input:
 osv_project (slab regeneration + OSV projection) -> pair_K -> fragment_solve
-(pair bases, coupling blocks, residual iterations of every fragment) ->
-mbe3_energy.  Inputs (Q, eps, f, slab weights, lists) are resident in HBM
-before the timed region.  Prints ONE JSON line on stdout; progress goes to
-stderr.
+(pair bases, coupling blocks, residual iterations of every fragment, and the
+MBE multipliers W with dE/df_occ) -> mbe3_energy -> mbe3_backward (dense
+dE/d(ia|P) and dE/df_occ).  Inputs (Q, eps, f, slab weights, lists) are
+resident in HBM before the timed region.  The same K steps without the
+backward are timed afterwards and reported as "forward_only".  Prints ONE
+JSON line on stdout; progress goes to stderr.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -52,24 +55,43 @@ def fragment_dims(prob):
     return out
 
 
-def solve_flops(prob, iters):
+def solve_flops(prob, iters, grad=False):
     """Algorithmic FP64 FLOPs of the residual iterations: per sweep and term
     2 d_t d_s^2 (S~ Y) + 2 d_t^2 d_s (Z S~^T).  A fragment with `iters`
     updates evaluates iters + 1 residuals; the first (T = 0, R~ = K~) needs no
-    product, so `iters` sweeps carry the products."""
+    product, so `iters` sweeps carry the products.  With the gradient the
+    converged amplitudes go through the products once more (dE/df)."""
     dims = fragment_dims(prob)
     tot = 0.0
     for terms, it in zip(dims, iters):
         per = sum(2.0 * dt * ds * (ds + dt) for dt, ds in terms)
-        tot += per * int(it)
+        tot += per * (int(it) + (1 if grad and int(it) > 0 else 0))
     return tot
 
 
+def traffic_from_profile(kernel_file, launches_per_step):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    (sha256 of the .hip file); None otherwise."""
+    path = os.path.join(ROOT, "profiles", "solve_water40u_traffic.json")
+    src = os.path.join(ROOT, "paper_2603_16575_amd", "csrc", kernel_file)
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def cpu_baseline(prob, budget_workers):
-    """Oracle throughput on the host: a stratified sample on the first 16
-    orbitals (their slabs + projections, the K / bases of the pairs among
-    them, then every fragment among them by class), each stage on a pool of
-    worker processes, extrapolated by count to the whole workload."""
+    """Oracle throughput on the host for the same step (forward + gradient):
+    a stratified sample on the first 16 orbitals (their slabs + projections,
+    the K / bases of the pairs among them, every fragment among them by
+    class with its gradient contributions, then the dE/dB assembly of the
+    sampled orbitals), each stage on a pool of worker processes,
+    extrapolated by count to the whole workload."""
     import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     import oracle
@@ -112,31 +134,70 @@ def cpu_baseline(prob, budget_workers):
             ora._basis[t] = bas
         n_slot = prob.n_occ + len(prob.pairs)
         TB = tB * n_slot / len(slots)
-        # stage C: fragment solves by class
+        # stage C: fragment solves by class, with the fragment's gradient terms
         size = (sel >= 0).sum(1)
         TC = 0.0
         counts = {}
         all_size = (prob.frags >= 0).sum(1)
+        Wacc = {}
+
+        def solve_grad(f):
+            r = ora.solve_fragment(f, prob.tol, prob.max_iter)
+            Tt, g = oracle.fragment_gradient(ora, f, r["T"])
+            return Tt
+        om._POOL_ORACLE = solve_grad
         for c in (1, 2, 3):
             fr = sel[size == c]
             if len(fr) == 0:
                 continue
             t0 = time.perf_counter()
-            om.run(prob, frags=fr, workers=W, ora=ora)
+            with ctx.Pool(W) as pool:
+                outs = pool.map(_call_pool_fn, list(fr))
             dt = time.perf_counter() - t0
+            for Tt in outs:
+                for t, v in Tt.items():
+                    Wacc[t] = Wacc.get(t, 0.0) + v
             counts[c] = len(fr)
             TC += dt * int((all_size == c).sum()) / len(fr)
+
+        # stage D: dE/dB_i = 4 sum_q V_iq W_iq V_iq^T B_q for the sampled i,
+        # with V_iq^T B_q taken from the stage-A projections (multipliers and
+        # projections outside the sample: zero blocks of full size)
+        def G(a, x):
+            return ora._gamma.get((a, x), np.zeros((prob.r[x], prob.n_aux)))
+
+        def unproject(i):
+            acc = np.zeros((prob.n_vir, prob.n_aux))
+            for q in prob.neighbours(i):
+                q = int(q)
+                if q == i:
+                    Wm = Wacc.get((i, i), np.zeros((prob.r[i], prob.r[i])))
+                    acc += 4.0 * ora.Q[i] @ (Wm @ G(i, i))
+                else:
+                    d = prob.r[i] + prob.r[q]
+                    Wm = Wacc.get((min(i, q), max(i, q)), np.zeros((d, d)))
+                    V = np.concatenate([ora.Q[i], ora.Q[q]], 1)
+                    acc += 4.0 * V @ (Wm @ np.vstack([G(q, i), G(q, q)]))
+            return float(acc[0, 0])
+        om._POOL_ORACLE = unproject
+        t0 = time.perf_counter()
+        with ctx.Pool(W) as pool:
+            pool.map(_call_pool_fn, orbs)
+        tD = time.perf_counter() - t0
+        TD = tD * int(np.ceil(prob.n_occ / len(orbs)))
     om._POOL_ORACLE = None
-    T = TA + TB + TC
+    T = TA + TB + TC + TD
     return dict(value=prob.n_frag / T, unit="fragments/s", cores=W, kind="oracle",
                 sample=(f"orbitals 0-{n_s - 1}: {n_s} slabs+projections, "
                         f"{len(slots)} pair K+bases, fragments among them "
                         f"(monomers {counts.get(1, 0)}, dimers {counts.get(2, 0)}, "
-                        f"trimers {counts.get(3, 0)}); each stage on {W} worker "
-                        f"processes (1 BLAS thread each), extrapolated by count "
-                        f"to all {prob.n_frag} fragments"),
+                        f"trimers {counts.get(3, 0)}) solved with their gradient "
+                        f"terms, dE/dB of the {n_s} orbitals; each stage on {W} "
+                        f"worker processes (1 BLAS thread each), extrapolated by "
+                        f"count to all {prob.n_frag} fragments"),
                 stage_seconds=dict(slab_projection=TA, pair_k_bases=TB,
-                                   fragment_solves=TC))
+                                   fragment_solves_with_gradient=TC,
+                                   dEdB_assembly=TD))
 
 
 def _call_pool_fn(x):
@@ -152,6 +213,9 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 1 GiB device copy (a reference kernel "
+                         "of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus "
@@ -171,16 +235,28 @@ def main():
         f"pairs={len(prob.pairs)} trimers={len(prob.trimers)} fragments={prob.n_frag}")
     h = m.from_problem(prob, device="cuda:0")
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     gamma = h.empty_gamma()
     K = h.empty_K()
+    W = h.empty_K()
     e = torch.empty(h.n_frag, dtype=torch.float64, device=dev)
     it = torch.empty(h.n_frag, dtype=torch.int32, device=dev)
+    dB = torch.empty((prob.n_occ, prob.n_vir, prob.n_aux), dtype=torch.float64, device=dev)
+    dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device=dev)
 
-    def step():
+    def step(backward=True):
         h.osv_project(gamma)
         h.pair_K(gamma, K)
-        h.fragment_solve(K, e, it)
-        return h.mbe3_energy(e)
+        h.fragment_solve(K, e, it, W if backward else None)
+        E = h.mbe3_energy(e)
+        if backward:
+            h.mbe3_backward(gamma, W, 1.0, m.MBE3_GRAD_SLAB, out=dB, dEdF=dF)
+        return E
 
     for w in range(args.warmup):
         E = step()
@@ -197,14 +273,30 @@ def main():
     ms_step = (t1 - t0) * 1000.0 / args.steps
     value = prob.n_frag / (ms_step / 1000.0)
     log(f"bench: {args.steps} steps, {ms_step:.2f} ms/step, {value:.1f} fragments/s, E={E:.12f}")
+    gnorm = float(torch.linalg.vector_norm(dB))
+    # the same steps without the backward
+    step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        E_f = step(False)
+    torch.cuda.synchronize()
+    ms_fwd = (time.perf_counter() - t0) * 1000.0 / args.steps
+    log(f"bench: forward only {ms_fwd:.2f} ms/step, {prob.n_frag / (ms_fwd / 1e3):.1f} fragments/s")
 
     iters = it.cpu().numpy()
     n_aux, n_vir = prob.n_aux, prob.n_vir
+    d2 = np.diff(h.k_off).astype(np.float64)   # d_s^2 per slot
+    sum_diag, sum_pair = float(d2[:prob.n_occ].sum()), float(d2[prob.n_occ:].sum())
     work = {
         "regen": ("alu", float(prob.n_occ) * n_vir * n_aux),
         "project": ("mfma", 2.0 * n_vir * n_aux * float(h.layout.gamma_rows)),
-        "pair_K": ("mfma", 2.0 * n_aux * float((np.diff(h.k_off)).sum())),
-        "solve": ("mfma", solve_flops(prob, iters)),
+        "pair_K": ("mfma", 2.0 * n_aux * (sum_diag + sum_pair)),
+        "solve": ("mfma", solve_flops(prob, iters, grad=True)),
+        # dGamma: every pair block feeds four destination blocks, every
+        # diagonal one; then the un-projection (projection-shaped)
+        "backward": ("mfma", 2.0 * n_aux * (2.0 * sum_pair + sum_diag)
+                     + 2.0 * n_vir * n_aux * float(h.layout.gamma_rows)),
     }
     phases = {}
     for name, (ms, n) in ph.items():
@@ -224,9 +316,12 @@ def main():
     if dom in ("project", "pair_K", "solve"):
         per_launch = work[dom][1] / max(1, ph[dom][1] // args.steps)
         ach = per_launch / (ms_dom * 1e-3) / 1e12
+        traffic = None
+        if dom == "solve":
+            traffic = traffic_from_profile("solve.hip", ph[dom][1] // args.steps)
         roofline = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3),
                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None}
+                    "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic}
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a host sample ...")
@@ -250,8 +345,13 @@ def main():
                                f"n_vir={n_vir}, n_aux={n_aux}, r={prob.r.min()}-{prob.r.max()}, "
                                f"cutoff 6, {len(prob.pairs)} pairs, {len(prob.trimers)} trimers, "
                                f"{prob.n_frag} fragments, tol {prob.tol:g}",
+                   "step": "forward + backward (dE/d(ia|P), dE/df_occ)",
                    "precision": "fp64", "E_total": E,
+                   "grad_norm_dB": gnorm,
                    "iters_hist": np.bincount(np.maximum(iters, 0)).tolist()},
+        "forward_only": {"ms_per_step": round(ms_fwd, 3),
+                         "fragments_per_s": round(prob.n_frag / (ms_fwd / 1e3), 2),
+                         "E_total": E_f},
         "roofline": roofline,
         "phases": phases,
         "cpu_baseline": cpu,

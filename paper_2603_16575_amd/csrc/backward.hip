@@ -14,19 +14,17 @@
 
 namespace mbe3 {
 
-// W~_slot += sum_entries c (2 Y - Y^T), one workgroup per slot.
+// W~_slot += sum_entries c Y~ (Y~ = 2Y - Y^T stored by the solver), one
+// workgroup per slot; entries in fragment order.
 __global__ __launch_bounds__(256) void wtilde_kernel(
     const WSlot *__restrict__ slots, const WEntry *__restrict__ ents,
     const double *__restrict__ yfin, double *__restrict__ wt) {
   const WSlot sl = slots[blockIdx.x];
-  const int D = sl.D;
-  for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
-    const int i = e / D, j = e - i * D;
+  const int n = sl.D * sl.D;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
     double acc = wt[sl.wt_off + e];
-    for (int k = sl.e_begin; k < sl.e_end; ++k) {
-      const double *y = yfin + ents[k].yoff;
-      acc += ents[k].coef * (2.0 * y[i * D + j] - y[j * D + i]);
-    }
+    for (int k = sl.e_begin; k < sl.e_end; ++k)
+      acc += ents[k].coef * yfin[ents[k].yoff + e];
     wt[sl.wt_off + e] = acc;
   }
 }
@@ -39,21 +37,24 @@ hipError_t launch_wtilde(const WSlot *slots, int n_slots, const WEntry *ents,
   return hipGetLastError();
 }
 
-// g[dst] += sum_entries scale * (term or target scalar), one thread per dst.
-__global__ void fgrad_kernel(const GDest *__restrict__ dests, int n,
-                             const GEntry *__restrict__ ents,
-                             const double *__restrict__ gterm,
-                             const double *__restrict__ gdiag,
-                             double *__restrict__ g) {
-  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < n;
-       d += gridDim.x * blockDim.x) {
+// g[dst] += sum_entries scale * (term or target scalar): one wave per
+// destination; lane l sums entries l, l + 64, ... and a fixed xor tree
+// combines the lanes (deterministic).
+__global__ __launch_bounds__(256) void fgrad_kernel(
+    const GDest *__restrict__ dests, int n, const GEntry *__restrict__ ents,
+    const double *__restrict__ gterm, const double *__restrict__ gdiag,
+    double *__restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  for (int d = blockIdx.x * wpb + (threadIdx.x >> 6); d < n; d += gridDim.x * wpb) {
     const GDest gd = dests[d];
-    double acc = g[gd.dst];
-    for (int k = gd.e_begin; k < gd.e_end; ++k) {
+    double acc = 0.0;
+    for (int k = gd.e_begin + lane; k < gd.e_end; k += 64) {
       const GEntry e = ents[k];
       acc += e.scale * (e.kind ? gdiag[e.idx] : gterm[e.idx]);
     }
-    g[gd.dst] = acc;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) g[gd.dst] += acc;
   }
 }
 
@@ -61,7 +62,7 @@ hipError_t launch_fgrad(const GDest *dests, int n, const GEntry *ents,
                         const double *gterm, const double *gdiag, double *g,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  int blocks = (n + 255) / 256;
+  int blocks = (n + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fgrad_kernel, dim3(blocks), dim3(256), 0, s, dests, n, ents,
                      gterm, gdiag, g);

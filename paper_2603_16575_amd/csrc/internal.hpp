@@ -152,8 +152,8 @@ struct SolveArgs {
   double *e_frag;
   int32_t *iters;
   int32_t *status;       // [2 * workgroup]: non-finite seen, non-converged seen
-  // gradient mode (all null otherwise): converged Y blocks per fragment
-  // (at FragDesc::yout), per-term contractions <Y~_t, S~ Y_s^(T) S~^T>
+  // gradient mode (all null otherwise): Y~ = 2Y - Y^T of the converged
+  // blocks per fragment (at FragDesc::yout), per-term contractions <Y~_t, S~ Y_s^(T) S~^T>
   // (<Y_t + Y_t^T, .> for diagonal targets) indexed by term, and per-target
   // <Y~_t, Y_t> at 6 * fragment + target.
   double *yfin;
@@ -173,12 +173,13 @@ struct WSlot {
   int32_t D, e_begin, e_end, pad_;
 };
 struct WEntry {
-  int64_t yoff;  // converged Y block (D x D) in the chunk's Y store
+  int64_t yoff;  // converged Y~ = 2Y - Y^T block (D x D) in the chunk's store
   double coef;   // c_F
 };
 hipError_t launch_wtilde(const WSlot *slots, int n_slots, const WEntry *ents,
                          const double *yfin, double *wt, hipStream_t s);
-// g[dst] += sum of scale * (kind ? gdiag[idx] : gterm[idx]) over the entries.
+// g[dst] += sum of scale * (kind ? gdiag[idx] : gterm[idx]) over the entries
+// (one wave per destination, lane-strided partial sums, fixed shuffle tree).
 struct GDest {
   int32_t dst, e_begin, e_end, pad_;
 };

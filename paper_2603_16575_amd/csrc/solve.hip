@@ -143,6 +143,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     const int f_nt = fdp->nt, f_frag = fdp->frag;
     const int f_tb = fdp->term_begin, f_te = fdp->term_end;
     int cur = 0;
+    bool gpass = false;  // GRAD: the extra pass at the converged amplitudes
     for (int it = 0;; ++it) {
       double mres = 0.0, epart = 0.0;
       int bad = 0;
@@ -193,11 +194,48 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           for (int ti = f_tb; ti < f_te; ++ti) {
             const Term tm = a.terms[ti];
             if (tm.target != tl) continue;
-            const double coef = a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
+            const double coef =
+                (GRAD && gpass) ? 1.0 : a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
             const int Ds = a.slots[fdp->slot[tm.src]].D;
             const int nS = Ds >> 4;
             MBE3_TERM_PRODUCTS(coef);
+            if (GRAD && gpass) {
+              // this term's product alone, contracted with Y~ = 2Y - Y^T
+              // (Y + Y^T for a diagonal target, whose mirror term is folded)
+              const int sy = fdp->sym[tl];
+              const double *Yc = Ycb + fdp->ysub[tl];
+              const double *YTc = YTcb + fdp->ysub[tl];
+              double part = 0.0;
+#pragma unroll
+              for (int rb = 0; rb < MAXRB; ++rb) {
+                const int ib = wave + 4 * rb;
+#pragma unroll
+                for (int jb = 0; jb < MAXNT; ++jb) {
+                  if (ib < nT && jb < nT) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                      const int64_t ij = (int64_t)(ib * 16 + lq + 4 * v) * Dt + jb * 16 + l16;
+                      const double wy = sy ? Yc[ij] + YTc[ij] : 2.0 * Yc[ij] - YTc[ij];
+                      part += wy * acc[rb][jb][v];
+                    }
+                  }
+                  acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
+                }
+              }
+              const double tot = wg_sum(part, red_d);
+              if (tid == 0) a.gterm[ti] = tot;
+            }
           }
+        }
+        if (GRAD && gpass) {
+          // <Y~, Y> of the target, for the f_pp and f_qq inside E~
+          const double *Yc = Ycb + fdp->ysub[tl];
+          const double *YTc = YTcb + fdp->ysub[tl];
+          double part = 0.0;
+          for (int e = tid; e < Dt * Dt; e += 256) part += (2.0 * Yc[e] - YTc[e]) * Yc[e];
+          const double tot = wg_sum(part, red_d);
+          if (tid == 0) a.gdiag[6 * fi + tl] = tot;
+          continue;
         }
 
         const int sym = fdp->sym[tl];
@@ -262,6 +300,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           }
         }
       }
+      if (GRAD && gpass) break;
       // block reductions (fixed order: deterministic)
       for (int o = 32; o > 0; o >>= 1) {
         mres = fmax(mres, __shfl_xor(mres, o));
@@ -288,11 +327,6 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           if (!conv && !B) st[1] = 1;
         }
         if (GRAD && conv && !B) {
-          // ---- gradient pass at the converged amplitudes ----
-          // Y blocks for the multipliers W, then each term's product with
-          // coefficient 1 contracted with Y~ = 2Y - Y^T (Y + Y^T for a
-          // diagonal target, whose mirror terms are folded), and <Y~, Y>
-          // per target for the f_pp, f_qq inside E~.
           if (it == 0) {
             // converged at T = 0 (K~ below the threshold): all zero
             for (int e = tid; e < fdp->ny; e += 256) a.yfin[fdp->yout + e] = 0.0;
@@ -300,56 +334,12 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             if (tid < f_nt) a.gdiag[6 * fi + tid] = 0.0;
             break;
           }
-          for (int e = tid; e < fdp->ny; e += 256) a.yfin[fdp->yout + e] = Ycb[e];
-          p_ti = f_tb;
-          p_m = 0;
-          if (f_tb < f_te) MBE3_LOAD_PANEL();
-          for (int tl = 0; tl < f_nt; ++tl) {
-            const SlotInfo sl = a.slots[fdp->slot[tl]];
-            const int Dt = sl.D;
-            const int nT = Dt >> 4;
-            const int sym = fdp->sym[tl];
-            const double *Yc = Ycb + fdp->ysub[tl];
-            const double *YTc = YTcb + fdp->ysub[tl];
-            d4 acc[MAXRB][MAXNT];
-            for (int ti = f_tb; ti < f_te; ++ti) {
-              const Term tm = a.terms[ti];
-              if (tm.target != tl) continue;
-              const int Ds = a.slots[fdp->slot[tm.src]].D;
-              const int nS = Ds >> 4;
-#pragma unroll
-              for (int rb = 0; rb < MAXRB; ++rb)
-#pragma unroll
-                for (int jb = 0; jb < MAXNT; ++jb) acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
-              MBE3_TERM_PRODUCTS(1.0);
-              double part = 0.0;
-#pragma unroll
-              for (int rb = 0; rb < MAXRB; ++rb) {
-                const int ib = wave + 4 * rb;
-                if (ib < nT) {
-#pragma unroll
-                  for (int jb = 0; jb < MAXNT; ++jb)
-                    if (jb < nT) {
-#pragma unroll
-                      for (int v = 0; v < 4; ++v) {
-                        const int64_t ij = (int64_t)(ib * 16 + lq + 4 * v) * Dt + jb * 16 + l16;
-                        const double wy = sym ? Yc[ij] + YTc[ij] : 2.0 * Yc[ij] - YTc[ij];
-                        part += wy * acc[rb][jb][v];
-                      }
-                    }
-                }
-              }
-              const double tot = wg_sum(part, red_d);
-              if (tid == 0) a.gterm[ti] = tot;
-            }
-            double part = 0.0;
-            for (int e = tid; e < Dt * Dt; e += 256) {
-              const double y = Yc[e];
-              part += (2.0 * y - YTc[e]) * y;
-            }
-            const double tot = wg_sum(part, red_d);
-            if (tid == 0) a.gdiag[6 * fi + tl] = tot;
-          }
+          // Y~ = 2Y - Y^T for the multipliers W, then one more pass over the
+          // same amplitudes with unit coefficients for dE/df
+          for (int e = tid; e < fdp->ny; e += 256)
+            a.yfin[fdp->yout + e] = 2.0 * Ycb[e] - YTcb[e];
+          gpass = true;
+          continue;
         }
         break;
       }
