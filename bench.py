@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0
 METRIC = "MBE(3) fragments solved/s + MFMA % of peak; mixed vs FP64 at |ΔE|≤1e-6 Eh"
 
@@ -200,6 +201,67 @@ def cpu_baseline(prob, budget_workers):
                                    dEdB_assembly=TD))
 
 
+def mixed_run(m, prob, args, dev, E64, e64, h64):
+    """The same forward + backward steps with osv_project and pair_K in the
+    split-precision form (MBE3_MIXED_BF16); energy deviations against the
+    FP64 run of this process."""
+    import torch
+    h = m.from_problem(prob, device=str(dev), precision=m.MBE3_MIXED_BF16)
+    gamma, K, W = h.empty_gamma(), h.empty_K(), h.empty_K()
+    e = torch.empty(h.n_frag, dtype=torch.float64, device=dev)
+    it = torch.empty(h.n_frag, dtype=torch.int32, device=dev)
+    dB = torch.empty((prob.n_occ, prob.n_vir, prob.n_aux), dtype=torch.float64, device=dev)
+    dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device=dev)
+
+    def step():
+        h.osv_project(gamma)
+        h.pair_K(gamma, K)
+        h.fragment_solve(K, e, it, W)
+        E = h.mbe3_energy(e)
+        h.mbe3_backward(gamma, W, 1.0, m.MBE3_GRAD_SLAB, out=dB, dEdF=dF)
+        return E
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    ph = h.get_timing()
+    h.set_timing(False)
+    d = np.abs(e.cpu().numpy() - e64)
+    ldk_vir = (prob.n_vir + 7) // 8 * 8
+    ldk_aux = (prob.n_aux + 7) // 8 * 8
+    rows = float(h.layout.gamma_rows)
+    d2 = float(np.diff(h.k_off).sum())
+    proj_ms = ph["project"][0] / args.steps
+    pk_ms = ph["pair_K"][0] / args.steps
+    out = {
+        "ms_per_step": round(ms, 3),
+        "fragments_per_s": round(prob.n_frag / (ms / 1e3), 2),
+        "speedup_vs_fp64": None,
+        "E_total": E,
+        "abs_dE_total_vs_fp64": abs(E - E64),
+        "max_abs_dE_fragment_vs_fp64": float(d.max()),
+        "mean_abs_dE_fragment_vs_fp64": float(d.mean()),
+        "budget_abs_dE_total": 1e-6,
+        "project": {"ms_per_step": round(proj_ms, 4),
+                    "tflops_fp64_equivalent": round(2.0 * prob.n_vir * prob.n_aux * rows / (proj_ms * 1e-3) / 1e12, 2),
+                    "frac_bf16_peak_issued": round(6 * 2.0 * ldk_vir * prob.n_aux * rows / (proj_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)},
+        "pair_K": {"ms_per_step": round(pk_ms, 4),
+                   "tflops_fp64_equivalent": round(2.0 * prob.n_aux * d2 / (pk_ms * 1e-3) / 1e12, 2),
+                   "frac_bf16_peak_issued": round(6 * 2.0 * ldk_aux * d2 / (pk_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)},
+        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph.items()},
+    }
+    log(f"bench: mixed bf16 {ms:.2f} ms/step, |dE| vs fp64 {abs(E - E64):.3e}, "
+        f"max |dE_F| {d.max():.3e}")
+    h.close()
+    return out
+
+
 def _call_pool_fn(x):
     from oracle import mbe3 as om
     return om._POOL_ORACLE(x)
@@ -213,6 +275,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the split-precision (bf16) comparison run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device copy (a reference kernel "
                          "of known traffic for counter calibration)")
@@ -274,6 +338,8 @@ def main():
     value = prob.n_frag / (ms_step / 1000.0)
     log(f"bench: {args.steps} steps, {ms_step:.2f} ms/step, {value:.1f} fragments/s, E={E:.12f}")
     gnorm = float(torch.linalg.vector_norm(dB))
+    e64 = e.cpu().numpy().copy()
+    E64 = E
     # the same steps without the backward
     step(False)
     torch.cuda.synchronize()
@@ -322,6 +388,9 @@ def main():
         roofline = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3),
                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic}
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_run(m, prob, args, dev, E64, e64, h)
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a host sample ...")
@@ -355,7 +424,10 @@ def main():
         "roofline": roofline,
         "phases": phases,
         "cpu_baseline": cpu,
+        "mixed_bf16": mixed,
     }
+    if mixed is not None:
+        mixed["speedup_vs_fp64"] = round(ms_step / mixed["ms_per_step"], 4)
     print(json.dumps(out), flush=True)
     h.close()
 

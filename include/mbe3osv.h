@@ -59,7 +59,16 @@ extern "C" {
 #define MBE3_ENOCONV (-4)    /* a fragment hit max_iter (iters[f] < 0)     */
 #define MBE3_ENONFINITE (-5) /* NaN/Inf met in a residual or an energy     */
 
+/* Arithmetic of osv_project and pair_K (everything else is FP64 always). */
 #define MBE3_FP64 0
+/* Split precision: every FP64 operand of the two products is carried as
+   three bf16 pieces x = h + m + l (h = bf16(x), m = bf16(x - h),
+   l = bf16(x - h - m)); the six cross products with piece orders summing to
+   at most 2 run on bf16 matrix cores with FP32 accumulation, and the results
+   are stored in FP64.  Per product the relative error is about 2^-24 of
+   sum |a_k b_k| plus the FP32 accumulation error; the energy error this
+   causes is reported by the tests and the benchmark against MBE3_FP64. */
+#define MBE3_MIXED_BF16 1
 
 /* Phases reported by mbe3_get_timing. */
 #define MBE3_PHASE_REGEN 0   /* slab regeneration (osv_project)             */
@@ -116,7 +125,7 @@ typedef struct mbe3_problem {
   double tol;       /* convergence: max |X^T R X| < tol (every pair)       */
   int32_t max_iter; /* maximum amplitude updates per fragment               */
   double tau_S;     /* drop pair-overlap eigenvalues <= tau_S               */
-  int32_t precision; /* MBE3_FP64                                          */
+  int32_t precision; /* MBE3_FP64 or MBE3_MIXED_BF16                       */
 } mbe3_problem;
 
 /* Sizes of the packed arrays exchanged between the calls. */

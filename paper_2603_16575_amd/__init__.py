@@ -15,13 +15,13 @@ import numpy as np
 from . import _lib
 from ._lib import (MBE3_EHIP, MBE3_EINVAL, MBE3_ENOCONV, MBE3_ENOMEM,
                    MBE3_ENONFINITE, MBE3_FP64, MBE3_GRAD_GAMMA, MBE3_GRAD_SLAB,
-                   MBE3_OK, Mbe3Error)
+                   MBE3_MIXED_BF16, MBE3_OK, Mbe3Error)
 
 __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
            "mbe3_energy", "mbe3_backward", "mbe3_pair_basis", "energy_fn",
            "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
            "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
-           "MBE3_GRAD_GAMMA"]
+           "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16"]
 
 
 def _f64(t):
@@ -35,11 +35,12 @@ class Mbe3:
 
     Q, eps_vir, f_occ, w_ia, w_iP (or slab): contiguous float64 CUDA tensors,
     kept referenced by the handle.  r, pairs, frags: host int arrays.
+    precision: MBE3_FP64 or MBE3_MIXED_BF16 (osv_project and pair_K only).
     """
 
     def __init__(self, *, r, Q, eps_vir, f_occ, pairs, frags, seed=0,
                  w_ia=None, w_iP=None, slab=None, tol=1e-8, max_iter=100,
-                 tau_S=1e-8, stream=None):
+                 tau_S=1e-8, stream=None, precision=MBE3_FP64):
         import torch
         lib = _lib.load()
         self._keep = [Q, eps_vir, f_occ, w_ia, w_iP, slab]
@@ -71,7 +72,8 @@ class Mbe3:
         p.tol = float(tol)
         p.max_iter = int(max_iter)
         p.tau_S = float(tau_S)
-        p.precision = MBE3_FP64
+        p.precision = int(precision)
+        self.precision = int(precision)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -277,7 +279,7 @@ def from_problem(prob, device="cuda:0", **kw):
 
 
 def plan_check(*, r, pairs, frags, n_vir, n_aux, tol=1e-8, max_iter=100,
-               tau_S=1e-8, explicit_slab=False):
+               tau_S=1e-8, explicit_slab=False, precision=MBE3_FP64):
     """Build and bounds-check every execution plan without a device.
 
     Returns the layout; raises Mbe3Error with the library's message on
@@ -297,7 +299,7 @@ def plan_check(*, r, pairs, frags, n_vir, n_aux, tol=1e-8, max_iter=100,
     p.pairs = _lib.ptr(pairs) if len(pairs) else None
     p.n_frag = len(frags)
     p.frags = _lib.ptr(frags)
-    p.tol, p.max_iter, p.tau_S, p.precision = tol, max_iter, tau_S, MBE3_FP64
+    p.tol, p.max_iter, p.tau_S, p.precision = tol, max_iter, tau_S, int(precision)
     lay = _lib.Mbe3Layout()
     rc = lib.mbe3_plan_check(ctypes.byref(p), ctypes.byref(lay))
     _lib.check(rc, None)

@@ -76,6 +76,8 @@ struct mbe3_handle {
   std::vector<std::array<int, 3>> frags;
   double tol = 1e-8, tau_S = 1e-8;
   int max_iter = 100;
+  int precision = MBE3_FP64;
+  int ldk_vir = 0, ldk_aux = 0;  // padded row pitch of split planes
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -141,6 +143,17 @@ struct mbe3_handle {
   std::vector<Chunk> chunks;
   int64_t gamma_rows = 0;
   int64_t k_elems = 0;
+
+  // ---- split-precision projection / pair_K (MBE3_MIXED_BF16) ----
+  uint16_t *qplanes = nullptr, *splanes = nullptr, *gplanes = nullptr;
+  int64_t q_ps = 0, s_ps = 0, g_ps = 0;  // plane strides (elements)
+  std::vector<MixedTask *> d_mproj;
+  std::vector<int64_t> t_mproj;
+  MixedTask *d_mpk = nullptr;
+  int64_t t_mpk = 0;
+  int32_t *d_mrows = nullptr;
+  std::vector<std::pair<std::string, std::vector<MixedTask>>> h_mixed;
+  std::vector<int32_t> h_mrows;
 
   // ---- gradient (planned on first use) ----
   bool grad_planned = false;
@@ -297,8 +310,11 @@ int validate_and_copy(mbe3_handle *h, const mbe3_problem *p) {
     return h->fail(MBE3_EINVAL, "either slab or (w_ia, w_iP) must be given");
   if (!(p->tol > 0.0) || p->max_iter < 0 || !(p->tau_S >= 0.0))
     return h->fail(MBE3_EINVAL, "tol > 0, max_iter >= 0, tau_S >= 0 required");
-  if (p->precision != MBE3_FP64)
+  if (p->precision != MBE3_FP64 && p->precision != MBE3_MIXED_BF16)
     return h->fail(MBE3_EINVAL, "unsupported precision %d", p->precision);
+  h->precision = p->precision;
+  h->ldk_vir = (p->n_vir + 7) & ~7;
+  h->ldk_aux = (p->n_aux + 7) & ~7;
   h->n_occ = p->n_occ; h->n_vir = p->n_vir; h->n_aux = p->n_aux;
   h->Q = p->Q; h->eps = p->eps_vir; h->f = p->f_occ;
   h->w_ia = p->w_ia; h->w_iP = p->w_iP; h->slab = p->slab; h->seed = p->seed;
@@ -483,7 +499,11 @@ int build_plans(mbe3_handle *h) {
 
   // ---- projection: one GEMM per orbital, A rows gathered from Q ----
   const int64_t slab_elems = (int64_t)nv * na;
-  if (!h->slab) {
+  const bool mixed = h->precision == MBE3_MIXED_BF16;
+  if (mixed) {  // three bf16 planes per slab element
+    int64_t nb = SLAB_BUDGET / ((int64_t)na * h->ldk_vir * 6);
+    h->slab_nb = (int)std::max<int64_t>(1, std::min<int64_t>(nb, n));
+  } else if (!h->slab) {
     int64_t nb = SLAB_BUDGET / (slab_elems * 8);
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, n));
     h->slab_nb = (int)nb;
@@ -535,6 +555,69 @@ int build_plans(mbe3_handle *h) {
   h->n_rows = (int64_t)rows.size();
   h->h_rows = rows;
   if ((rc = upload(h, &h->d_rows, rows))) return rc;
+
+  // ---- split-precision variants of the two products ----
+  if (mixed) {
+    std::vector<int32_t> mr;
+    const int lv = h->ldk_vir, la = h->ldk_aux;
+    auto finish = [](std::vector<MixedTask> &ts, MixedShape sh) {
+      int64_t acc = 0;
+      for (auto &t : ts) {
+        t.tiles_n = (t.N + mixed_tile_n(sh) - 1) / mixed_tile_n(sh);
+        t.tile_begin = acc;
+        acc += mixed_tile_count(t, sh);
+      }
+      return acc;
+    };
+    for (auto &bt : h->proj_batches) {
+      std::vector<MixedTask> ts;
+      for (int i = bt.first; i < bt.second; ++i) {
+        MixedTask t;
+        std::memset(&t, 0, sizeof t);
+        t.a_off = 0;
+        t.a_rows = (int32_t)mr.size();
+        for (int x : h->nbr[i])
+          for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->q_off[x] + mu));
+        t.b_off = (int64_t)(i - bt.first) * na * lv;
+        t.b_rows = -1;
+        t.c_off = h->g_off[i] * na;
+        t.M = (int)(h->g_off[i + 1] - h->g_off[i]);
+        t.N = na;
+        t.K = lv;
+        t.lda = lv; t.ldb = lv; t.ldc = na;
+        ts.push_back(t);
+      }
+      h->t_mproj.push_back(finish(ts, MIXED_64x128));
+      MixedTask *d = nullptr;
+      if ((rc = upload(h, &d, ts))) return rc;
+      h->d_mproj.push_back(d);
+      h->h_mixed.push_back({"project (split)", ts});
+    }
+    std::vector<MixedTask> ts;
+    for (int64_t sl = 0; sl < h->n_slot; ++sl) {
+      const int p = h->sp[sl], q = h->sq[sl], d = h->sd[sl];
+      MixedTask t;
+      std::memset(&t, 0, sizeof t);
+      t.a_rows = (int32_t)mr.size();
+      for (int x : slot_orbs(h, (int)sl))
+        for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->grow.at(key2(p, x)) + mu));
+      t.b_rows = (int32_t)mr.size();
+      for (int x : slot_orbs(h, (int)sl))
+        for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
+      t.c_off = h->k_off[sl];
+      t.M = d; t.N = d; t.K = la;
+      t.lda = la; t.ldb = la; t.ldc = d;
+      ts.push_back(t);
+    }
+    h->t_mpk = finish(ts, MIXED_32x64);
+    if ((rc = upload(h, &h->d_mpk, ts))) return rc;
+    h->h_mixed.push_back({"pair_K (split)", ts});
+    h->h_mrows = mr;
+    if ((rc = upload(h, &h->d_mrows, mr))) return rc;
+    h->q_ps = h->q_off[n] * lv;
+    h->s_ps = (int64_t)h->slab_nb * na * lv;
+    h->g_ps = h->gamma_rows * la;
+  }
 
   // ---- S / F blocks ----
   {
@@ -888,7 +971,14 @@ int build_plans(mbe3_handle *h) {
 int alloc_workspace(mbe3_handle *h) {
   int rc;
   const int64_t nv = h->n_vir, na = h->n_aux;
-  if (!h->slab && (rc = dev_alloc(h, &h->slab_buf, (int64_t)h->slab_nb * nv * na))) return rc;
+  if (h->precision == MBE3_MIXED_BF16) {
+    if ((rc = dev_alloc(h, &h->qplanes, 3 * h->q_ps))) return rc;
+    if ((rc = dev_alloc(h, &h->splanes, 3 * h->s_ps))) return rc;
+    if ((rc = dev_alloc(h, &h->gplanes, 3 * h->g_ps))) return rc;
+  } else if (!h->slab &&
+             (rc = dev_alloc(h, &h->slab_buf, (int64_t)h->slab_nb * nv * na))) {
+    return rc;
+  }
   const int64_t nq = h->q_off[h->n_occ];
   if ((rc = dev_alloc(h, &h->eq, nq * nv))) return rc;
   if ((rc = dev_alloc(h, &h->sstore, h->sb_total))) return rc;
@@ -1076,9 +1166,59 @@ void base_sizes(const mbe3_handle *h, int64_t *sz) {
 // Host-side bounds check of every plan against the buffers it addresses,
 // run before any kernel of the plan is launched.  A failure here is a bug in
 // the planner, reported as MBE3_EINVAL.
+// Bounds of a split-precision task list: A rows inside a plane of a_ps
+// elements, B rows inside b_ps, C inside c_size; 16-byte aligned operands.
+int check_mixed_list(mbe3_handle *h, const std::string &name,
+                     const std::vector<MixedTask> &ts, int64_t a_ps,
+                     int64_t b_ps, int64_t c_size, MixedShape shape) {
+  auto bad = [&](const std::string &what, size_t k) {
+    return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
+  };
+  const std::vector<int32_t> &rows = h->h_mrows;
+  int64_t tb = 0;
+  for (size_t k = 0; k < ts.size(); ++k) {
+    const MixedTask &t = ts[k];
+    if (t.M < 1 || t.N < 1 || t.K < 1) return bad(name + " (empty)", k);
+    if (t.K % 8 || t.lda % 8 || t.ldb % 8 || t.a_off % 8 || t.b_off % 8 ||
+        t.lda < t.K || t.ldb < t.K || t.ldc < t.N)
+      return bad(name + " (alignment)", k);
+    if (t.tile_begin != tb) return bad(name + " (tile prefix)", k);
+    tb += mixed_tile_count(t, shape);
+    auto rmax = [&](int32_t off, int n, int64_t &out) {
+      if (off < 0) { out = n - 1; return true; }
+      if ((int64_t)off + n > (int64_t)rows.size()) return false;
+      int64_t m = -1;
+      for (int e = 0; e < n; ++e) {
+        if (rows[off + e] < 0) return false;
+        m = std::max<int64_t>(m, rows[off + e]);
+      }
+      out = m;
+      return true;
+    };
+    int64_t ra, rb;
+    if (!rmax(t.a_rows, t.M, ra) || t.a_off + ra * t.lda + t.K > a_ps)
+      return bad(name + " (A bounds)", k);
+    if (!rmax(t.b_rows, t.N, rb) || t.b_off + rb * t.ldb + t.K > b_ps)
+      return bad(name + " (B bounds)", k);
+    if (t.c_off < 0 || t.c_off + (int64_t)(t.M - 1) * t.ldc + t.N > c_size)
+      return bad(name + " (C bounds)", k);
+  }
+  return MBE3_OK;
+}
+
 int validate_plans(mbe3_handle *h) {
   int64_t sz[B_COUNT];
   base_sizes(h, sz);
+  if (h->precision == MBE3_MIXED_BF16) {
+    for (auto &pl : h->h_mixed) {
+      const bool proj = pl.first[0] == 'p' && pl.first[1] == 'r';
+      const int rc = proj ? check_mixed_list(h, pl.first, pl.second, h->q_ps, h->s_ps,
+                                             h->gamma_rows * h->n_aux, MIXED_64x128)
+                          : check_mixed_list(h, pl.first, pl.second, h->g_ps, h->g_ps,
+                                             h->k_elems, MIXED_32x64);
+      if (rc) return rc;
+    }
+  }
   auto bad = [&](const std::string &what, size_t k) {
     return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
   };
@@ -1472,6 +1612,27 @@ int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems) {
     return h->fail(MBE3_EINVAL, "gamma needs %lld doubles, got %lld",
                    (long long)(h->gamma_rows * h->n_aux), (long long)gamma_elems);
   hipStream_t s = h->stream;
+  if (h->precision == MBE3_MIXED_BF16) {
+    {
+      PhaseScope ps_(h, MBE3_PHASE_REGEN);
+      HIP_TRY(h, launch_split_rows(h->Q, h->q_off[h->n_occ], h->n_vir, h->n_vir,
+                                   h->qplanes, h->q_ps, h->ldk_vir, s));
+    }
+    for (size_t k = 0; k < h->proj_batches.size(); ++k) {
+      const int i0 = h->proj_batches[k].first, i1 = h->proj_batches[k].second;
+      {
+        PhaseScope ps_(h, MBE3_PHASE_REGEN);
+        HIP_TRY(h, launch_regen_split(h->splanes, h->s_ps, i0, i1 - i0, h->n_vir,
+                                      h->n_aux, h->ldk_vir, h->seed, h->w_ia,
+                                      h->w_iP, h->slab, s));
+      }
+      PhaseScope ps_(h, MBE3_PHASE_PROJECT);
+      HIP_TRY(h, launch_gemm_mixed(h->d_mproj[k], i1 - i0, h->t_mproj[k], h->qplanes,
+                                   h->q_ps, h->splanes, h->s_ps, gamma, h->d_mrows,
+                                   MIXED_64x128, s));
+    }
+    return MBE3_OK;
+  }
   GemmBases b = bases(h);
   b.p[B_GAMMA] = gamma;
   for (size_t k = 0; k < h->proj_batches.size(); ++k) {
@@ -1493,10 +1654,18 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems) {
   if (!gamma || !K || k_elems < h->k_elems)
     return h->fail(MBE3_EINVAL, "K needs %lld doubles, got %lld",
                    (long long)h->k_elems, (long long)k_elems);
+  PhaseScope ps_(h, MBE3_PHASE_PAIR_K);
+  if (h->precision == MBE3_MIXED_BF16) {
+    HIP_TRY(h, launch_split_rows(gamma, h->gamma_rows, h->n_aux, h->n_aux, h->gplanes,
+                                 h->g_ps, h->ldk_aux, h->stream));
+    HIP_TRY(h, launch_gemm_mixed(h->d_mpk, (int)h->n_slot, h->t_mpk, h->gplanes, h->g_ps,
+                                 h->gplanes, h->g_ps, K, h->d_mrows, MIXED_32x64,
+                                 h->stream));
+    return MBE3_OK;
+  }
   GemmBases b = bases(h);
   b.p[B_GAMMA] = const_cast<double *>(gamma);
   b.p[B_K] = K;
-  PhaseScope ps_(h, MBE3_PHASE_PAIR_K);
   HIP_TRY(h, launch_gemm_tasks(h->d_pk, h->n_pk, h->t_pk, b, GEMM_64x64, h->stream));
   return MBE3_OK;
 }

@@ -48,6 +48,39 @@ hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia,
                              const double *w_iP, hipStream_t s);
 
+// Split-precision operands (regen.hip): three bf16 planes (bit patterns),
+// plane stride ps elements, rows padded with zeros to ldk (a multiple of 8).
+hipError_t launch_regen_split(uint16_t *planes, int64_t ps, int i0, int nb,
+                              int n_vir, int n_aux, int ldk, uint64_t seed,
+                              const double *w_ia, const double *w_iP,
+                              const double *slab, hipStream_t s);
+hipError_t launch_split_rows(const double *x, int64_t rows, int cols, int64_t ld,
+                             uint16_t *planes, int64_t ps, int ldk,
+                             hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Split-precision grouped GEMM (gemm_mixed.hip): C = A B^T in FP64 storage
+// from three-piece bf16 operands, six cross products (pieces p + q <= 2) on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  A rows and B rows are
+// K-contiguous (row pitch lda / ldb, multiples of 8), optionally gathered.
+// ---------------------------------------------------------------------------
+struct MixedTask {
+  int64_t a_off, b_off, c_off;  // element offsets (A/B in plane 0, C)
+  int64_t tile_begin;
+  int32_t a_rows, b_rows;       // gather offsets into the row table, or -1
+  int32_t M, N, K, lda, ldb, ldc;
+  int32_t tiles_n, pad_;
+};
+enum MixedShape { MIXED_32x64 = 0, MIXED_64x128 = 1 };
+int64_t mixed_tile_count(const MixedTask &t, MixedShape shape);
+int mixed_tile_m(MixedShape shape);
+int mixed_tile_n(MixedShape shape);
+hipError_t launch_gemm_mixed(const MixedTask *d_tasks, int n_tasks,
+                             int64_t n_tiles, const uint16_t *A, int64_t a_ps,
+                             const uint16_t *B, int64_t b_ps, double *C,
+                             const int32_t *rows, MixedShape shape,
+                             hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Block assembly (prep.hip): out[r][c] for a matrix made of up to 2 x 2
 // blocks of the S or F block store (or identity-free zero padding).

@@ -54,6 +54,105 @@ __global__ __launch_bounds__(256) void regen_slab_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split-precision operands.  x = h + m + l with h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m), the remainders formed in FP64 (exact): 24 significant
+// bits, |x - h - m - l| <= 2^-24 |x| up to the tail rounding.  Pieces are
+// stored as three planes of bf16 bit patterns, rows padded with zeros to ldk.
+// ---------------------------------------------------------------------------
+// Round to the nearest bf16, ties to even: FP64 -> FP32 (nearest even) and
+// FP32 -> bf16 on the bit pattern.  The pieces only need to be close, but
+// unbiased rounding keeps their tails unbiased too.
+__device__ __forceinline__ uint16_t bf16_bits(double x) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, (float)x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ double bf16_value(uint16_t u) {
+  return (double)(float)__builtin_bit_cast(__bf16, u);
+}
+__device__ __forceinline__ void split3(double x, uint16_t *dst, int64_t ps) {
+  const uint16_t h = bf16_bits(x);
+  const double r1 = x - bf16_value(h);
+  const uint16_t m = bf16_bits(r1);
+  const double r2 = r1 - bf16_value(m);
+  dst[0] = h;
+  dst[ps] = m;
+  dst[2 * ps] = bf16_bits(r2);
+}
+
+// Slabs of LMOs i0 .. i0 + nb - 1 regenerated straight into split planes in
+// the transposed layout [b][P][a] (a fastest, row pitch ldk >= n_vir, zero
+// padded), the K-contiguous operand of the projection.  With an explicit
+// slab (device [n_occ][n_vir][n_aux]) its values are split instead.
+__global__ __launch_bounds__(256) void regen_split_kernel(
+    uint16_t *__restrict__ planes, int64_t ps, int i0, int nb, int n_vir,
+    int n_aux, int ldk, uint64_t seed, const double *__restrict__ w_ia,
+    const double *__restrict__ w_iP, const double *__restrict__ slab) {
+  const int64_t per = (int64_t)n_aux * ldk;
+  const int64_t total = per * nb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / per);
+    const int64_t r = e - (int64_t)b * per;
+    const int P = (int)(r / ldk);
+    const int a = (int)(r - (int64_t)P * ldk);
+    const int i = i0 + b;
+    double x = 0.0;
+    if (a < n_vir) {
+      if (slab) {
+        x = slab[((int64_t)i * n_vir + a) * n_aux + P];
+      } else {
+        uint64_t c0 = (uint64_t)P, c1 = (uint64_t)a, c2 = (uint64_t)i, c3 = 0;
+        philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+        const double z = box_muller(c0, c1);
+        x = (z * w_ia[(int64_t)i * n_vir + a]) * w_iP[(int64_t)i * n_aux + P];
+      }
+    }
+    split3(x, planes + e, ps);
+  }
+}
+
+// Rows of a row-major FP64 matrix (rows x cols, leading dimension ld) into
+// split planes with row pitch ldk >= cols (zero padded).
+__global__ __launch_bounds__(256) void split_rows_kernel(
+    const double *__restrict__ x, int64_t rows, int cols, int64_t ld,
+    uint16_t *__restrict__ planes, int64_t ps, int ldk) {
+  const int64_t total = rows * ldk;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rw = e / ldk;
+    const int c = (int)(e - rw * ldk);
+    split3(c < cols ? x[rw * ld + c] : 0.0, planes + e, ps);
+  }
+}
+
+static int64_t grid_for(int64_t total) {
+  int64_t blocks = (total + 255) / 256;
+  return blocks > 65536 ? 65536 : blocks;
+}
+
+hipError_t launch_regen_split(uint16_t *planes, int64_t ps, int i0, int nb,
+                              int n_vir, int n_aux, int ldk, uint64_t seed,
+                              const double *w_ia, const double *w_iP,
+                              const double *slab, hipStream_t s) {
+  const int64_t total = (int64_t)n_aux * ldk * nb;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(regen_split_kernel, dim3((unsigned)grid_for(total)), dim3(256),
+                     0, s, planes, ps, i0, nb, n_vir, n_aux, ldk, seed, w_ia,
+                     w_iP, slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_rows(const double *x, int64_t rows, int cols, int64_t ld,
+                             uint16_t *planes, int64_t ps, int ldk,
+                             hipStream_t s) {
+  const int64_t total = rows * ldk;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)grid_for(total)), dim3(256),
+                     0, s, x, rows, cols, ld, planes, ps, ldk);
+  return hipGetLastError();
+}
+
 hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia,
                              const double *w_iP, hipStream_t s) {

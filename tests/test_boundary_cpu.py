@@ -35,10 +35,12 @@ def test_header_symbols_exported(pkg):
 
 
 @pytest.mark.parametrize("k", [0, 1])
-def test_plan_check_configs(pkg, k):
+@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16"])
+def test_plan_check_configs(pkg, k, precision):
     p = synth.config(k)
+    prec = pkg.MBE3_FP64 if precision == "fp64" else pkg.MBE3_MIXED_BF16
     lay = pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
-                         n_aux=p.n_aux)
+                         n_aux=p.n_aux, precision=prec)
     rows = sum(int(p.r[p.neighbours(i)].sum()) for i in range(p.n_occ))
     assert lay.gamma_rows == rows
     assert lay.n_frag == p.n_frag
@@ -50,6 +52,18 @@ def test_plan_check_micro_explicit_slab(pkg):
     p = synth.micro(4)
     pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
                    n_aux=p.n_aux, explicit_slab=True)
+    # split planes pad rows to a multiple of 8: odd sizes plan as well
+    pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir + 3,
+                   n_aux=p.n_aux + 5, explicit_slab=True,
+                   precision=pkg.MBE3_MIXED_BF16)
+
+
+def test_plan_check_rejects_unknown_precision(pkg):
+    p = synth.micro(3)
+    with pytest.raises(pkg.Mbe3Error) as ex:
+        pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
+                       n_aux=p.n_aux, precision=7)
+    assert ex.value.code == pkg.MBE3_EINVAL
 
 
 def test_plan_check_rejects_bad_lists(pkg):

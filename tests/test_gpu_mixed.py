@@ -1,0 +1,156 @@
+"""Split-precision (MBE3_MIXED_BF16) projection and pair_K against the FP64
+oracle, through the C-ABI (needs an MI355X).
+
+Error model of one product c = sum_k a_k b_k in the mixed form: each operand
+carries 24 significant bits (three bf16 pieces), the dropped cross products
+are below 3 * 2^-24 of |a_k b_k|, and the FP32 accumulation of K terms adds at
+most K * 2^-24 of sum |a_k b_k| (worst case, one rounding per step).  The
+tests bound |c_mixed - c| by (K + 8) * 2^-24 * sum_k |a_k| |b_k| element by
+element and require the typical error (RMS over elements, relative to the
+same scale) to be far below it."""
+import dataclasses
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2603_16575_amd as pkg
+    pkg._lib.load()
+    return pkg
+
+
+def gamma_rows_of(h, prob, gamma, i):
+    g = gamma.view(-1, prob.n_aux)
+    return g[int(h.g_off[i]):int(h.g_off[i + 1])].cpu().numpy()
+
+
+def check_products(m, prob):
+    import torch
+    h = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    gamma = h.osv_project(h.empty_gamma())
+    torch.cuda.synchronize()
+    ora = oracle.Oracle(prob)
+    eps = 2.0 ** -24
+    worst = 0.0
+    rms = []
+    for i in range(prob.n_occ):
+        nb = [int(x) for x in prob.neighbours(i)]
+        Qn = np.concatenate([ora.Q[x] for x in nb], 1)        # n_vir x rows
+        B = ora.B(i)
+        ref = Qn.T @ B
+        scale = np.abs(Qn).T @ np.abs(B)
+        err = np.abs(gamma_rows_of(h, prob, gamma, i) - ref)
+        worst = max(worst, float((err / scale).max()))
+        rms.append(float(np.sqrt(np.mean((err / scale) ** 2))))
+    bound = (prob.n_vir + 8) * eps
+    say(f"projection: worst err/scale {worst:.3e}, rms {max(rms):.3e}, bound {bound:.3e}")
+    assert worst <= bound
+    assert max(rms) <= 8 * eps
+    # pair_K from the oracle's own FP64 projection (isolates the K product)
+    g64 = np.zeros(int(h.layout.gamma_elems))
+    gv = g64.reshape(-1, prob.n_aux)
+    for i in range(prob.n_occ):
+        nb = [int(x) for x in prob.neighbours(i)]
+        gv[int(h.g_off[i]):int(h.g_off[i + 1])] = np.concatenate([ora.gamma(i, x) for x in nb], 0)
+    K = h.pair_K(torch.as_tensor(g64, device="cuda:0"), h.empty_K())
+    torch.cuda.synchronize()
+    Kn = K.cpu().numpy()
+    worst_k = 0.0
+    for s in range(h.layout.n_slot):
+        p, q = (s, s) if s < prob.n_occ else tuple(int(v) for v in prob.pairs[s - prob.n_occ])
+        o = oracle.orbs(p, q)
+        L = np.concatenate([ora.gamma(p, x) for x in o], 0)
+        R = np.concatenate([ora.gamma(q, x) for x in o], 0)
+        d = L.shape[0]
+        got = Kn[h.k_off[s]:h.k_off[s] + d * d].reshape(d, d)
+        scale = np.abs(L) @ np.abs(R).T
+        worst_k = max(worst_k, float((np.abs(got - L @ R.T) / scale).max()))
+    bound_k = (prob.n_aux + 8) * eps
+    say(f"pair_K: worst err/scale {worst_k:.3e}, bound {bound_k:.3e}")
+    assert worst_k <= bound_k
+    h.close()
+
+
+def test_mixed_products_chain8(m):
+    say("case: chain8 (configs 0) split-precision projection and pair_K vs oracle")
+    check_products(m, synth.config(0))
+
+
+def test_mixed_products_padded_sizes(m):
+    """n_vir, n_aux not multiples of 8: zero-padded plane rows."""
+    say("case: micro n_occ=4, n_vir=21, n_aux=35, split-precision products vs oracle")
+    check_products(m, synth.micro(4, n_vir=21, n_aux=35))
+
+
+def test_mixed_explicit_slab_equals_regenerated(m):
+    import torch
+    say("case: micro n_occ=4 mixed, explicit slab == regenerated")
+    prob = synth.micro(4)
+    slab = np.stack([oracle.slab(prob, i) for i in range(prob.n_occ)])
+    h1 = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    h2 = m.from_problem(prob, precision=m.MBE3_MIXED_BF16,
+                        slab=torch.as_tensor(slab, device="cuda:0"), w_ia=None, w_iP=None)
+    g1 = h1.osv_project(h1.empty_gamma())
+    g2 = h2.osv_project(h2.empty_gamma())
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    h1.close()
+    h2.close()
+
+
+def test_mixed_energy_micro(m):
+    say("case: micro n_occ=4 mixed precision energy vs oracle")
+    prob = dataclasses.replace(synth.micro(4), tol=1e-12, max_iter=300)
+    h = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    out = h.forward()
+    ref = oracle.run(prob)
+    E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
+    say(f"micro mixed: dE = {out['E'] - E_ref:.3e} (E = {E_ref:.6f})")
+    assert abs(out["E"] - E_ref) <= 1e-7 * abs(E_ref)
+    h.close()
+
+
+def test_mixed_energy_water40u(m):
+    """configs 1 in the benchmark's launch shape: the mixed total energy
+    against the oracle's full run (|dE| <= 1e-6 Eh, the budget of the mixed
+    form), and per-fragment deviations from the FP64 GPU path."""
+    import torch
+    say("case: water40u (configs 1) mixed precision vs golden oracle and FP64 path")
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "water40u_oracle.json")))
+    E_ref = float(g["E_total"])
+    prob = synth.config(1)
+    hm = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    om = hm.forward()
+    E_m = om["E"]
+    em = om["e_frag"].cpu().numpy()
+    hm.close()
+    del om, hm
+    torch.cuda.empty_cache()
+    hf = m.from_problem(prob)
+    of = hf.forward()
+    ef = of["e_frag"].cpu().numpy()
+    hf.close()
+    d = np.abs(em - ef)
+    say(f"water40u mixed: E = {E_m:.12f}, |E - E_oracle| = {abs(E_m - E_ref):.3e}, "
+        f"max |dE_F| vs FP64 = {d.max():.3e}, mean {d.mean():.3e}")
+    assert abs(E_m - E_ref) <= 1e-6
+    assert d.max() <= 1e-7
