@@ -35,21 +35,23 @@ STREAM_SLAB = 0
 # --------------------------------------------------------------------------
 # O1: regenerated slab (stand-in for the direct Gamma_i generator, Alg. 1)
 # --------------------------------------------------------------------------
-def slab(prob, i: int) -> np.ndarray:
+def slab(prob, i: int, cols=None) -> np.ndarray:
     """B_i[a,P] = z(seed,i,a,P) * w_ia[i,a] * w_iP[i,P] (in that order).
 
     z is the Box-Muller normal of words 0 and 1 of the Philox4x64-10 block at
     counter (P, a, i, 0) under key (seed, 0).  The product is evaluated left to
-    right.  Plays the role of the fitted Gamma_i of eq. fitting.
+    right.  Plays the role of the fitted Gamma_i of eq. fitting.  ``cols``
+    (optional) restricts P to a list of auxiliary indices.
     """
-    nv, na = prob.n_vir, prob.n_aux
-    ctr = np.zeros((nv, na, 4), dtype=np.uint64)
-    ctr[..., 0] = np.arange(na, dtype=np.uint64)[None, :]
+    nv = prob.n_vir
+    P = np.arange(prob.n_aux) if cols is None else np.asarray(cols)
+    ctr = np.zeros((nv, len(P), 4), dtype=np.uint64)
+    ctr[..., 0] = P.astype(np.uint64)[None, :]
     ctr[..., 1] = np.arange(nv, dtype=np.uint64)[:, None]
     ctr[..., 2] = np.uint64(i)
     w = philox4x64_10(ctr, (prob.seed, STREAM_SLAB))
     z = box_muller(w[..., 0], w[..., 1])
-    return (z * prob.w_ia[i][:, None]) * prob.w_iP[i][None, :]
+    return (z * prob.w_ia[i][:, None]) * prob.w_iP[i][P][None, :]
 
 
 def orbs(p: int, q: int) -> Tuple[int, ...]:

@@ -23,10 +23,10 @@ using namespace mbe3;
 
 namespace {
 
-constexpr int DMAX_SUPPORTED = 96;   // largest padded pair dimension handled
+constexpr int DMAX_SUPPORTED = 160;  // largest padded pair dimension handled
 constexpr int SOLVE_WG = 1024;       // persistent workgroups of the solver
 constexpr int64_t SLAB_BUDGET = 2LL << 30;    // bytes of regenerated slabs
-constexpr int64_t CHUNK_BUDGET = 3LL << 30;   // bytes of per-chunk stores
+constexpr int64_t CHUNK_BUDGET = 12LL << 30;  // bytes of per-chunk stores
 
 inline int round16(int x) { return (x + 15) & ~15; }
 inline int64_t key2(int a, int b) { return ((int64_t)a << 32) | (uint32_t)b; }
@@ -105,6 +105,8 @@ struct mbe3_handle {
   double *et = nullptr, *ev0 = nullptr;
   int32_t *rank = nullptr;
   int32_t *sflag = nullptr;  // per slot: overlap not safely positive definite
+  double *eig_ws = nullptr;  // eigensolver workspace for orders beyond LDS
+  int64_t eig_ws_doubles = 0;
   double *at = nullptr, *mt = nullptr, *st0 = nullptr;
   double *ca = nullptr, *cm = nullptr, *st1 = nullptr;
   double *scratch = nullptr;
@@ -968,6 +970,8 @@ int build_plans(mbe3_handle *h) {
   return MBE3_OK;
 }
 
+int max_d(const mbe3_handle *h);
+
 int alloc_workspace(mbe3_handle *h) {
   int rc;
   const int64_t nv = h->n_vir, na = h->n_aux;
@@ -996,6 +1000,15 @@ int alloc_workspace(mbe3_handle *h) {
   if ((rc = dev_alloc(h, &h->ev0, h->et_off[h->n_slot]))) return rc;
   if ((rc = dev_alloc(h, &h->rank, h->n_slot))) return rc;
   if ((rc = dev_alloc(h, &h->sflag, h->n_slot))) return rc;
+  {
+    const int md = max_d(h), nl = eig_lds_max_order();
+    if (md > nl) {
+      int64_t n_large = 0;
+      for (int64_t sl = 0; sl < h->n_slot; ++sl) n_large += h->sd[sl] > nl;
+      h->eig_ws_doubles = std::min<int64_t>(n_large, 1024) * eig_workspace_doubles(md);
+      if ((rc = dev_alloc(h, &h->eig_ws, h->eig_ws_doubles))) return rc;
+    }
+  }
   int ny_max = 0, dmax = 16;
   for (auto &c : h->chunks) {
     ny_max = std::max(ny_max, c.ny_max);
@@ -1059,13 +1072,16 @@ int prepare_bases(mbe3_handle *h) {
                              h->ps, h->pf, s));
   const int md = max_d(h);
   HIP_TRY(h, launch_cholesky(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
-                             h->rank, h->sflag, h->tau_S, s));
+                             h->rank, h->sflag, h->tau_S, h->eig_ws,
+                             h->eig_ws_doubles, s));
   HIP_TRY(h, launch_jacobi(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
-                           h->rank, 0, h->tau_S, h->sflag, s));
+                           h->rank, 0, h->tau_S, h->sflag, h->eig_ws,
+                           h->eig_ws_doubles, s));
   HIP_TRY(h, launch_gemm_tasks(h->d_g_m1, (int)h->n_slot, h->t_m1, b, GEMM_64x64, s));
   HIP_TRY(h, launch_gemm_tasks(h->d_g_fp, (int)h->n_slot, h->t_fp, b, GEMM_64x64, s));
   HIP_TRY(h, launch_jacobi(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
-                           h->rank, 1, h->tau_S, nullptr, s));
+                           h->rank, 1, h->tau_S, nullptr, h->eig_ws,
+                           h->eig_ws_doubles, s));
   HIP_TRY(h, launch_gemm_tasks(h->d_g_x, (int)h->n_slot, h->t_x, b, GEMM_64x64, s));
   return MBE3_OK;
 }
@@ -1719,17 +1735,20 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
       a.gterm = h->gterm;
       a.gdiag = h->gdiag;
     }
-    // the scratch layout is fixed by the largest chunk (dmax / ny_max)
-    int dm = 16, nym = 0;
-    for (auto &cc : h->chunks) { dm = std::max(dm, cc.dmax); nym = std::max(nym, cc.ny_max); }
-    a.dmax = dm;
-    // persistent grid: as many workgroups as fit on the 256 CUs at once
-    const int per_cu = (int)std::max<size_t>(
-        1, std::min<size_t>(4, (160 * 1024) / (solve_lds_bytes(dm) + 2048)));
-    const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu);
-    {
+    // the chunk's largest pair dimension picks the kernel and its LDS
+    // layout; the scratch stride is the handle's (sized for the largest)
+    a.dmax = c.dmax;
+    if (c.dmax <= SOLVE_LDS_DMAX) {
+      // persistent grid: as many workgroups as fit on the 256 CUs at once
+      const int per_cu = (int)std::max<size_t>(
+          1, std::min<size_t>(4, (160 * 1024) / (solve_lds_bytes(c.dmax) + 2048)));
+      const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu);
       PhaseScope ps_(h, MBE3_PHASE_SOLVE);
       HIP_TRY(h, launch_solve(a, nwg, s));
+    } else {
+      const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256);
+      PhaseScope ps_(h, MBE3_PHASE_SOLVE);
+      HIP_TRY(h, launch_solve_wide(a, nwg, s));
     }
     if (W) {
       // this chunk's share of W~ and dE/df (its Y store is reused next)

@@ -9,10 +9,17 @@
 // factor, so rank-deficient pair overlaps are handled by dropping
 // eigenvalues <= tau.
 //
+// Workspace: matrix, vectors and the small per-round arrays live in LDS when
+// they fit (n up to ~96); larger pair domains run a second launch with the
+// same code on a per-workgroup slice of global memory (L2 resident), the
+// workgroups looping over their share of the tasks.
+//
 // Rotation (Golub & Van Loan, sym.schur2): for a_pq != 0,
 //   tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 //   c = 1 / sqrt(1 + t^2), s = t c, and A <- J^T A J with J_pp = J_qq = c,
 //   J_pq = s, J_qp = -s, which zeroes a_pq.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mbe3 {
@@ -33,13 +40,17 @@ __device__ double block_sum(double v, double *red) {
 }
 
 __global__ __launch_bounds__(256) void jacobi_kernel(
-    const EigTask *__restrict__ tasks, const double *__restrict__ in,
+    const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
     double *__restrict__ out, double *__restrict__ evals,
     int32_t *__restrict__ rank, int mode, double tau,
-    const int32_t *__restrict__ only_flagged) {
-  extern __shared__ double sm[];
-  const EigTask t = tasks[blockIdx.x];
-  if (only_flagged && only_flagged[t.slot] == 0) return;
+    const int32_t *__restrict__ only_flagged, int n_lo, int n_hi, double *gws,
+    int64_t gstride) {
+  extern __shared__ double sm_dyn[];
+  double *const sm = gws ? gws + (int64_t)blockIdx.x * gstride : sm_dyn;
+  for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+  const EigTask t = tasks[ti];
+  if (t.n < n_lo || t.n > n_hi) continue;  // the other launch's task
+  if (only_flagged && only_flagged[t.slot] == 0) continue;
   const int n = mode == 0 ? t.n : rank[t.slot];
   const int D = t.D;
   const int ld = n + 1;
@@ -204,6 +215,8 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
     for (int c = tid; c < D; c += nt)
       evals[t.e_off + c] = c < n ? lam[perm[c]] : EV_SENTINEL;
   }
+  __syncthreads();  // the workspace is reused by the next task
+  }
 }
 
 // Overlap step by Cholesky: S = L L^T in LDS (right-looking, one column per
@@ -212,12 +225,16 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
 // A pivot <= tau (S not safely positive definite) sets flag[slot] and leaves
 // the slot to the canonical-orthogonalisation Jacobi launch that follows.
 __global__ __launch_bounds__(256) void cholesky_kernel(
-    const EigTask *__restrict__ tasks, const double *__restrict__ in,
+    const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
     double *__restrict__ out, double *__restrict__ evals,
-    int32_t *__restrict__ rank, int32_t *__restrict__ flag, double tau) {
-  extern __shared__ double sm[];
+    int32_t *__restrict__ rank, int32_t *__restrict__ flag, double tau, int n_lo,
+    int n_hi, double *gws, int64_t gstride) {
+  extern __shared__ double sm_dyn[];
+  double *const sm = gws ? gws + (int64_t)blockIdx.x * gstride : sm_dyn;
   __shared__ int failed;
-  const EigTask t = tasks[blockIdx.x];
+  for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+  const EigTask t = tasks[ti];
+  if (t.n < n_lo || t.n > n_hi) continue;  // the other launch's task
   const int n = t.n, D = t.D, ld = n + 1;
   double *L = sm;             // n x ld, lower triangle
   double *Li = sm + n * ld;   // n x ld, L^{-1} (lower triangle)
@@ -254,7 +271,8 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
   __syncthreads();
   if (failed) {
     if (tid == 0) flag[t.slot] = 1;
-    return;
+    __syncthreads();
+    continue;
   }
   // L^{-1}: thread c solves L x = e_c for column c (rows >= c)
   for (int c = tid; c < n; c += nt) {
@@ -276,23 +294,11 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
     rank[t.slot] = n;
     flag[t.slot] = 0;
   }
+  __syncthreads();  // the workspace is reused by the next task
+  }
 }
 
-hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
-                           const double *in, double *out, double *evals,
-                           int32_t *rank, int32_t *flag, double tau,
-                           hipStream_t s) {
-  if (n_tasks <= 0) return hipSuccess;
-  const size_t smem = sizeof(double) * (size_t)2 * max_n * (max_n + 1);
-  if (smem > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void *)cholesky_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cholesky_kernel, dim3(n_tasks), dim3(256), smem, s, d_tasks,
-                     in, out, evals, rank, flag, tau);
-  return hipGetLastError();
-}
+static size_t cholesky_smem(int n) { return sizeof(double) * (size_t)2 * n * (n + 1); }
 
 static size_t jacobi_smem(int n) {
   const int ld = n + 1, nh = (n + 1) / 2;
@@ -300,20 +306,73 @@ static size_t jacobi_smem(int n) {
          sizeof(int) * (2 * (nh + 1) + n + 1);
 }
 
+static constexpr size_t EIG_LDS = 160 * 1024;
+
+// Largest order whose workspace fits in LDS.
+static int lds_order(size_t (*bytes)(int)) {
+  int n = 1;
+  while (bytes(n + 1) <= EIG_LDS) ++n;
+  return n;
+}
+
+int64_t eig_workspace_doubles(int max_n) {
+  const size_t b = std::max(jacobi_smem(max_n), cholesky_smem(max_n));
+  return (int64_t)((b + 255) / 256 * 256 / sizeof(double));
+}
+int eig_lds_max_order() { return std::min(lds_order(jacobi_smem), lds_order(cholesky_smem)); }
+
+// Launch the LDS variant for tasks of order <= the LDS limit and, if needed,
+// the global-workspace variant (grid bounded by the workspace) for the rest.
+template <class Launch>
+static hipError_t two_launches(int n_tasks, int max_n, size_t (*bytes)(int),
+                               double *gws, int64_t gws_doubles, Launch launch) {
+  const int nl = lds_order(bytes);
+  const int hi = std::min(max_n, nl);
+  hipError_t e = launch(n_tasks, 0, hi, nullptr, (int64_t)0, bytes(hi));
+  if (e != hipSuccess || max_n <= nl) return e;
+  const int64_t stride = eig_workspace_doubles(max_n);
+  if (!gws || gws_doubles < stride) return hipErrorInvalidValue;
+  const int grid = (int)std::min<int64_t>(n_tasks, gws_doubles / stride);
+  return launch(grid, nl + 1, max_n, gws, stride, (size_t)0);
+}
+
+hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
+                           const double *in, double *out, double *evals,
+                           int32_t *rank, int32_t *flag, double tau, double *gws,
+                           int64_t gws_doubles, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  return two_launches(n_tasks, max_n, cholesky_smem, gws, gws_doubles,
+                      [&](int grid, int lo, int hi, double *ws, int64_t stride,
+                          size_t smem) -> hipError_t {
+                        hipError_t e = hipFuncSetAttribute(
+                            (const void *)cholesky_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+                        if (e != hipSuccess) return e;
+                        hipLaunchKernelGGL(cholesky_kernel, dim3(grid), dim3(256), smem,
+                                           s, d_tasks, n_tasks, in, out, evals, rank,
+                                           flag, tau, lo, hi, ws, stride);
+                        return hipGetLastError();
+                      });
+}
+
 hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
                          const double *in, double *out, double *evals,
                          int32_t *rank, int mode, double tau,
-                         const int32_t *only_flagged, hipStream_t s) {
+                         const int32_t *only_flagged, double *gws,
+                         int64_t gws_doubles, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
-  const size_t smem = jacobi_smem(max_n);
-  if (smem > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void *)jacobi_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(n_tasks), dim3(256), smem, s, d_tasks,
-                     in, out, evals, rank, mode, tau, only_flagged);
-  return hipGetLastError();
+  return two_launches(n_tasks, max_n, jacobi_smem, gws, gws_doubles,
+                      [&](int grid, int lo, int hi, double *ws, int64_t stride,
+                          size_t smem) -> hipError_t {
+                        hipError_t e = hipFuncSetAttribute(
+                            (const void *)jacobi_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+                        if (e != hipSuccess) return e;
+                        hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), smem, s,
+                                           d_tasks, n_tasks, in, out, evals, rank, mode,
+                                           tau, only_flagged, lo, hi, ws, stride);
+                        return hipGetLastError();
+                      });
 }
 
 }  // namespace mbe3

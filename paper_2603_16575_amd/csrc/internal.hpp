@@ -125,17 +125,22 @@ struct EigTask {
 // mode 1: Fock step.  Order = rank[slot].  Writes Z (D x D: eigenvectors in
 //         the leading rank x rank block, zero elsewhere) and eps~ ascending
 //         (sentinel 1e30 beyond rank).
+// Tasks of order above eig_lds_max_order() run on a global workspace of
+// gws_doubles (>= eig_workspace_doubles(max_n); one slice per workgroup).
 hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
                          const double *in, double *out, double *evals,
                          int32_t *rank, int mode, double tau,
-                         const int32_t *only_flagged, hipStream_t s);
+                         const int32_t *only_flagged, double *gws,
+                         int64_t gws_doubles, hipStream_t s);
 // Overlap step by Cholesky (X0 = L^-T, full rank).  Slots whose pivots drop
 // to <= tau get flag[slot] = 1 and are redone by launch_jacobi(mode 0,
 // only_flagged = flag).
 hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
                            const double *in, double *out, double *evals,
-                           int32_t *rank, int32_t *flag, double tau,
-                           hipStream_t s);
+                           int32_t *rank, int32_t *flag, double tau, double *gws,
+                           int64_t gws_doubles, hipStream_t s);
+int64_t eig_workspace_doubles(int max_n);
+int eig_lds_max_order();
 
 // ---------------------------------------------------------------------------
 // Fragment solver (solve.hip)
@@ -194,6 +199,12 @@ struct SolveArgs {
   double *gdiag;
 };
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s);
+// Variant for 96 < dmax <= 160 (solve_wide.hip): one wave per 16-row block,
+// panels streamed for both products, per-workgroup term sums in the scratch
+// (which must hold 4 ny + 2 dmax^2 doubles, as solve_scratch_doubles gives).
+hipError_t launch_solve_wide(const SolveArgs &a, int n_wg, hipStream_t s);
+size_t solve_wide_lds_bytes(int dmax);
+constexpr int SOLVE_LDS_DMAX = 96;  // largest dmax of the LDS-resident solver
 int64_t solve_scratch_doubles(int ny_max, int dmax);
 size_t solve_lds_bytes(int dmax);
 

@@ -48,6 +48,17 @@ def test_plan_check_configs(pkg, k, precision):
     assert lay.k_elems == int((d.astype(np.int64) ** 2).sum())
 
 
+@pytest.mark.parametrize("k", [2, 4])
+def test_plan_check_large_configs(pkg, k):
+    """Configurations 2 (470k fragments, D <= 128) and 4 (D <= 160) plan and
+    pass every bounds check, both precisions."""
+    p = synth.config(k)
+    for prec in (pkg.MBE3_FP64, pkg.MBE3_MIXED_BF16):
+        lay = pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
+                             n_aux=p.n_aux, precision=prec)
+        assert lay.n_frag == p.n_frag
+
+
 def test_plan_check_micro_explicit_slab(pkg):
     p = synth.micro(4)
     pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
