@@ -56,24 +56,27 @@ def fragment_dims(prob):
     return out
 
 
-def solve_flops(prob, iters, grad=False):
+def solve_flops(prob, iters, grad=False, warm=True):
     """Algorithmic FP64 FLOPs of the residual iterations: per sweep and term
     2 d_t d_s^2 (S~ Y) + 2 d_t^2 d_s (Z S~^T).  A fragment with `iters`
-    updates evaluates iters + 1 residuals; the first (T = 0, R~ = K~) needs no
-    product, so `iters` sweeps carry the products.  With the gradient the
+    updates evaluates iters + 1 residuals; from T = 0 the first (R~ = K~)
+    needs no product, so `iters` sweeps carry the products; a warm-started
+    trimer's first residual has them too (iters + 1).  With the gradient the
     converged amplitudes go through the products once more (dE/df)."""
     dims = fragment_dims(prob)
     tot = 0.0
-    for terms, it in zip(dims, iters):
+    for f, terms, it in zip(prob.frags, dims, iters):
         per = sum(2.0 * dt * ds * (ds + dt) for dt, ds in terms)
-        tot += per * (int(it) + (1 if grad and int(it) > 0 else 0))
+        sweeps = int(it) + (1 if warm and f[2] >= 0 else 0)
+        tot += per * (sweeps + (1 if grad and sweeps > 0 else 0))
     return tot
 
 
 def traffic_from_profile(kernel_file, launches_per_step):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source
-    (sha256 of the .hip file); None otherwise."""
+    (sha256 of the .hip file) with the same launches per step (the chunking
+    decides what one launch covers); None otherwise."""
     path = os.path.join(ROOT, "profiles", "solve_water40u_traffic.json")
     src = os.path.join(ROOT, "paper_2603_16575_amd", "csrc", kernel_file)
     try:
@@ -81,7 +84,7 @@ def traffic_from_profile(kernel_file, launches_per_step):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != sha or rec.get("dispatches") != launches_per_step:
         return None
     return float(rec["bytes_per_launch"])
 

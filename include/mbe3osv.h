@@ -126,6 +126,11 @@ typedef struct mbe3_problem {
   int32_t max_iter; /* maximum amplitude updates per fragment               */
   double tau_S;     /* drop pair-overlap eigenvalues <= tau_S               */
   int32_t precision; /* MBE3_FP64 or MBE3_MIXED_BF16                       */
+  /* 0: every fragment starts from T = 0.  1: monomers and dimers are solved
+     first and each trimer starts from their converged amplitudes (its
+     diagonal pairs from the monomers, its pairs from the dimers); the
+     solution is the same to the convergence threshold, in fewer updates.  */
+  int32_t warm_start;
 } mbe3_problem;
 
 /* Sizes of the packed arrays exchanged between the calls. */

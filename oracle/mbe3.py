@@ -195,10 +195,13 @@ class Oracle:
         return R
 
     # ---- O5 + O6: one fragment, Alg. 7 (close clusters) -------------------
-    def solve_fragment(self, frag: Sequence[int], tol: float, max_iter: int):
+    def solve_fragment(self, frag: Sequence[int], tol: float, max_iter: int,
+                       T0: Optional[dict] = None):
         """Iterate a cluster's residual equations to convergence.
 
-        T starts at zero.  Each sweep evaluates every pair residual from the
+        T starts at zero, or at T0[(p, q)] for the pairs T0 lists (the
+        initial amplitudes are left open by Alg. 7; the fixed point does not
+        depend on them).  Each sweep evaluates every pair residual from the
         same amplitudes (Jacobi order), transforms it to the pseudo-canonical
         basis, R~ = X^T R X, stops when max|R~| < tol, and otherwise applies
         T += X (R~ / E~) X^T (Alg. 7).  The energy is the Hylleraas
@@ -211,7 +214,7 @@ class Oracle:
         T = {}
         for (p, q) in plist:
             d = sum(self.r[x] for x in orbs(p, q))
-            T[(p, q)] = np.zeros((d, d))
+            T[(p, q)] = np.zeros((d, d)) if not T0 or (p, q) not in T0 else T0[(p, q)].copy()
         it = 0
         while True:
             R = {t: self.residual(t[0], t[1], frag, T) for t in plist}
@@ -303,6 +306,26 @@ def mbe3_coefficients(n_occ: int, frags: np.ndarray) -> np.ndarray:
 # Driver: the whole forward path
 # --------------------------------------------------------------------------
 _POOL_ORACLE = None
+_POOL_WARM = None
+
+
+def _own_pair(f) -> Optional[Tuple[int, int]]:
+    """The pair slot a monomer or dimer fragment is the fragment of."""
+    o = [int(x) for x in f if x >= 0]
+    if len(o) == 1:
+        return (o[0], o[0])
+    if len(o) == 2:
+        return (min(o), max(o))
+    return None
+
+
+def _warm_T0(f, warm):
+    """Initial amplitudes of a trimer: each of its pairs from the solution of
+    that pair's own fragment (monomer or dimer)."""
+    if warm is None or (np.asarray(f) >= 0).sum() < 3:
+        return None
+    o = sorted(int(x) for x in f if x >= 0)
+    return {(p, q): warm[(p, q)] for a, p in enumerate(o) for q in o[a:]}
 
 
 def _solve_chunk(args):
@@ -310,7 +333,7 @@ def _solve_chunk(args):
     ora = _POOL_ORACLE
     out = []
     for f in frags:
-        s = ora.solve_fragment(f, tol, max_iter)
+        s = ora.solve_fragment(f, tol, max_iter, _warm_T0(f, _POOL_WARM))
         if not keep_T:
             s.pop("T")
         out.append(s)
@@ -333,31 +356,53 @@ def prepare(ora: Oracle, frags: np.ndarray) -> None:
         ora.S(q, p)
 
 
+def _solve_list(ora, frags, tol, max_iter, keep_T, workers, warm):
+    global _POOL_ORACLE, _POOL_WARM
+    if workers <= 1 or len(frags) < 64:
+        return [ora.solve_fragment(f, tol, max_iter, _warm_T0(f, warm)) for f in frags]
+    import multiprocessing as mp
+    _POOL_ORACLE, _POOL_WARM = ora, warm
+    chunks = np.array_split(np.arange(len(frags)), workers * 8)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        parts = pool.map(_solve_chunk,
+                         [(frags[c], tol, max_iter, keep_T) for c in chunks])
+    _POOL_ORACLE, _POOL_WARM = None, None
+    return [s for part in parts for s in part]
+
+
 def run(prob, frags: Optional[np.ndarray] = None, workers: int = 1,
-        keep_T: bool = False, ora: Optional[Oracle] = None):
+        keep_T: bool = False, ora: Optional[Oracle] = None,
+        warm_start: bool = False):
     """Solve ``frags`` (default: all fragments) and return per-fragment data.
 
+    warm_start: every monomer and dimer is solved first from T = 0 (those of
+    the trimers in ``frags`` too, if absent), and each trimer starts from
+    the solutions of its pairs' own fragments; otherwise all start at T = 0.
     Returns dict with e_frag, e_lin, iters, converged (arrays in fragment
     order) and, if keep_T, the list of amplitude dicts.
     """
-    global _POOL_ORACLE
     if frags is None:
         frags = prob.frags
     ora = ora or Oracle(prob)
     prepare(ora, frags)
     tol, max_iter = prob.tol, prob.max_iter
-    if workers <= 1 or len(frags) < 64:
-        res = [ora.solve_fragment(f, tol, max_iter) for f in frags]
-    else:
-        import multiprocessing as mp
-        _POOL_ORACLE = ora
-        chunks = np.array_split(np.arange(len(frags)), workers * 8)
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
-            parts = pool.map(_solve_chunk,
-                             [(frags[c], tol, max_iter, keep_T) for c in chunks])
-        _POOL_ORACLE = None
-        res = [s for part in parts for s in part]
+    warm = None
+    if warm_start:
+        need = set()
+        for f in frags:
+            o = sorted(int(x) for x in f if x >= 0)
+            for a, p in enumerate(o):
+                for q in o[a:]:
+                    need.add((p, q))
+        own = np.array([[p, -1, -1] if p == q else [p, q, -1] for (p, q) in sorted(need)],
+                       dtype=np.int32).reshape(-1, 3)
+        sub = _solve_list(ora, own, tol, max_iter, True, workers, None)
+        warm = {}
+        for f, s in zip(own, sub):
+            t = _own_pair(f)
+            warm[t] = s["T"][t]
+    res = _solve_list(ora, frags, tol, max_iter, keep_T, workers, warm)
     out = dict(e_frag=np.array([s["E"] for s in res]),
                e_lin=np.array([s["E_lin"] for s in res]),
                iters=np.array([s["iters"] for s in res], dtype=np.int64),

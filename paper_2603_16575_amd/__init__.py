@@ -36,11 +36,13 @@ class Mbe3:
     Q, eps_vir, f_occ, w_ia, w_iP (or slab): contiguous float64 CUDA tensors,
     kept referenced by the handle.  r, pairs, frags: host int arrays.
     precision: MBE3_FP64 or MBE3_MIXED_BF16 (osv_project and pair_K only).
+    warm_start: trimers start from the converged monomer/dimer amplitudes
+    (same solution to the threshold, fewer updates); False: T = 0 throughout.
     """
 
     def __init__(self, *, r, Q, eps_vir, f_occ, pairs, frags, seed=0,
                  w_ia=None, w_iP=None, slab=None, tol=1e-8, max_iter=100,
-                 tau_S=1e-8, stream=None, precision=MBE3_FP64):
+                 tau_S=1e-8, stream=None, precision=MBE3_FP64, warm_start=True):
         import torch
         lib = _lib.load()
         self._keep = [Q, eps_vir, f_occ, w_ia, w_iP, slab]
@@ -73,6 +75,7 @@ class Mbe3:
         p.max_iter = int(max_iter)
         p.tau_S = float(tau_S)
         p.precision = int(precision)
+        p.warm_start = int(bool(warm_start))
         self.precision = int(precision)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -279,7 +282,8 @@ def from_problem(prob, device="cuda:0", **kw):
 
 
 def plan_check(*, r, pairs, frags, n_vir, n_aux, tol=1e-8, max_iter=100,
-               tau_S=1e-8, explicit_slab=False, precision=MBE3_FP64):
+               tau_S=1e-8, explicit_slab=False, precision=MBE3_FP64,
+               warm_start=True):
     """Build and bounds-check every execution plan without a device.
 
     Returns the layout; raises Mbe3Error with the library's message on
@@ -300,6 +304,7 @@ def plan_check(*, r, pairs, frags, n_vir, n_aux, tol=1e-8, max_iter=100,
     p.n_frag = len(frags)
     p.frags = _lib.ptr(frags)
     p.tol, p.max_iter, p.tau_S, p.precision = tol, max_iter, tau_S, int(precision)
+    p.warm_start = int(bool(warm_start))
     lay = _lib.Mbe3Layout()
     rc = lib.mbe3_plan_check(ctypes.byref(p), ctypes.byref(lay))
     _lib.check(rc, None)

@@ -48,6 +48,7 @@ class Mbe3Problem(ctypes.Structure):
         ("n_frag", ctypes.c_int64), ("frags", ctypes.c_void_p),
         ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
         ("tau_S", ctypes.c_double), ("precision", ctypes.c_int32),
+        ("warm_start", ctypes.c_int32),
     ]
 
 

@@ -77,6 +77,8 @@ struct mbe3_handle {
   double tol = 1e-8, tau_S = 1e-8;
   int max_iter = 100;
   int precision = MBE3_FP64;
+  bool warm_start = false;
+  double *warm = nullptr;  // converged Y of every slot's own fragment
   int ldk_vir = 0, ldk_aux = 0;  // padded row pitch of split planes
   hipStream_t stream = nullptr;
   std::string err;
@@ -315,6 +317,9 @@ int validate_and_copy(mbe3_handle *h, const mbe3_problem *p) {
   if (p->precision != MBE3_FP64 && p->precision != MBE3_MIXED_BF16)
     return h->fail(MBE3_EINVAL, "unsupported precision %d", p->precision);
   h->precision = p->precision;
+  if (p->warm_start != 0 && p->warm_start != 1)
+    return h->fail(MBE3_EINVAL, "warm_start must be 0 or 1");
+  h->warm_start = p->warm_start == 1;
   h->ldk_vir = (p->n_vir + 7) & ~7;
   h->ldk_aux = (p->n_aux + 7) & ~7;
   h->n_occ = p->n_occ; h->n_vir = p->n_vir; h->n_aux = p->n_aux;
@@ -756,8 +761,13 @@ int build_plans(mbe3_handle *h) {
   }
   std::vector<int> order(h->frags.size());
   for (size_t m = 0; m < order.size(); ++m) order[m] = (int)m;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return cost[a] > cost[b]; });
+  // heavy first; with warm starts every monomer and dimer comes before the
+  // trimers (their solutions seed the trimers' pairs)
+  auto is_tri = [&](int m) { return h->frags[m][2] >= 0; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (h->warm_start && is_tri(a) != is_tri(b)) return !is_tri(a);
+    return cost[a] > cost[b];
+  });
 
   Chunk cur;
   std::vector<FragDesc> fds;
@@ -821,8 +831,10 @@ int build_plans(mbe3_handle *h) {
           need += (dt * ds + dt * Ds + 2 * Dt * Ds) * 8;
         }
     }
+    const bool phase_change = h->warm_start && nf == 3 && !cur.frag_ids.empty() &&
+                              !is_tri(cur.frag_ids.back());
     if (!cur.frag_ids.empty() &&
-        (ca_total + cm_total + st1_total) * 8 + need > CHUNK_BUDGET) {
+        ((ca_total + cm_total + st1_total) * 8 + need > CHUNK_BUDGET || phase_change)) {
       if ((rc = flush())) return rc;
     }
     FragDesc fd;
@@ -841,6 +853,8 @@ int build_plans(mbe3_handle *h) {
       cur.dmax = std::max(cur.dmax, D);
     }
     fd.ny = ny;
+    fd.warm_in = h->warm_start && nf == 3 ? 1 : 0;
+    fd.warm_out = !h->warm_start ? -1 : (nf == 1 ? 0 : (nf == 2 ? 2 : -1));
     fd.yout = cur.ny_total;
     cur.ny_total += ny;
     cur.ny_max = std::max(cur.ny_max, ny);
@@ -1000,6 +1014,7 @@ int alloc_workspace(mbe3_handle *h) {
   if ((rc = dev_alloc(h, &h->ev0, h->et_off[h->n_slot]))) return rc;
   if ((rc = dev_alloc(h, &h->rank, h->n_slot))) return rc;
   if ((rc = dev_alloc(h, &h->sflag, h->n_slot))) return rc;
+  if (h->warm_start && (rc = dev_alloc(h, &h->warm, h->kt_off[h->n_slot]))) return rc;
   {
     const int md = max_d(h), nl = eig_lds_max_order();
     if (md > nl) {
@@ -1730,6 +1745,7 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
     a.e_frag = e_frag;
     a.iters = iters;
     a.status = h->status;
+    a.warm = h->warm;
     if (W) {
       a.yfin = h->yfin;
       a.gterm = h->gterm;

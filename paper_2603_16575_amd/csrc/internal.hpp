@@ -160,6 +160,9 @@ struct FragDesc {
   int32_t sym[6];       // 1 for diagonal slots (residual symmetrised)
   int32_t wgt[6];       // energy weight 1 (diagonal) or 2 (pair)
   int32_t ny;           // sum of D^2 over the fragment's slots
+  int32_t warm_in;      // 1: start every slot from the warm store, else T = 0
+  int32_t warm_out;     // local slot whose converged Y goes to the warm store
+                        // (the fragment's own pair: monomer 0, dimer 2), or -1
   int32_t pad_;
   double coef;          // MBE(3) coefficient c_F
   int64_t yout;         // offset of the converged Y blocks in the chunk store
@@ -190,6 +193,7 @@ struct SolveArgs {
   double *e_frag;
   int32_t *iters;
   int32_t *status;       // [2 * workgroup]: non-finite seen, non-converged seen
+  double *warm;          // converged Y per slot (K~ layout), or null
   // gradient mode (all null otherwise): Y~ = 2Y - Y^T of the converged
   // blocks per fragment (at FragDesc::yout), per-term contractions <Y~_t, S~ Y_s^(T) S~^T>
   // (<Y_t + Y_t^T, .> for diagonal targets) indexed by term, and per-target

@@ -144,6 +144,26 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     const int f_tb = fdp->term_begin, f_te = fdp->term_end;
     int cur = 0;
     bool gpass = false;  // GRAD: the extra pass at the converged amplitudes
+    // amplitudes present: after a warm start from the solutions of the
+    // fragment's own pairs (monomers, dimers), or after the first update
+    bool hasY = false;
+    if (fdp->warm_in && a.warm) {
+      for (int tl = 0; tl < f_nt; ++tl) {
+        const SlotInfo sl = a.slots[fdp->slot[tl]];
+        const int D = sl.D;
+        const double *src = a.warm + sl.kt_off;
+        double *y = Y0 + fdp->ysub[tl];
+        double *yt = YT0 + fdp->ysub[tl];
+        for (int e = tid; e < D * D; e += 256) {
+          const int i = e / D, j = e - i * D;
+          const double v = src[e];
+          y[e] = v;
+          yt[(int64_t)j * D + i] = v;
+        }
+      }
+      __syncthreads();
+      hasY = true;
+    }
     for (int it = 0;; ++it) {
       double mres = 0.0, epart = 0.0;
       int bad = 0;
@@ -178,7 +198,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     if (++p_m >= (ds_ >> 4)) { p_m = 0; ++p_ti; }                              \
   } while (0)
 
-      if (it > 0 && f_tb < f_te) MBE3_LOAD_PANEL();
+      if (hasY && f_tb < f_te) MBE3_LOAD_PANEL();
 
       for (int tl = 0; tl < f_nt; ++tl) {
         const SlotInfo sl = a.slots[fdp->slot[tl]];
@@ -190,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
 #pragma unroll
           for (int jb = 0; jb < MAXNT; ++jb) acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
 
-        if (it > 0) {
+        if (hasY) {
           for (int ti = f_tb; ti < f_te; ++ti) {
             const Term tm = a.terms[ti];
             if (tm.target != tl) continue;
@@ -281,8 +301,8 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
                 for (int v = 0; v < 4; ++v) {
                   const int i = ib * 16 + lq + 4 * v;
                   const int64_t ij = (int64_t)i * Dt + j;
-                  const double y = it > 0 ? Yc[ij] : 0.0;
-                  const double yt = it > 0 ? YTc[ij] : 0.0;
+                  const double y = hasY ? Yc[ij] : 0.0;
+                  const double yt = hasY ? YTc[ij] : 0.0;
                   const double kij = Kt[ij];
                   const double den = fpq - et[i] - ej;
                   const double sacc = sym ? acc[rb][jb][v] + Sl[j * Dt + i] : acc[rb][jb][v];
@@ -326,8 +346,17 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           if (B) st[0] = 1;
           if (!conv && !B) st[1] = 1;
         }
+        if (fdp->warm_out >= 0 && a.warm) {
+          // the fragment's own pair seeds the trimers that contain it: its
+          // last amplitudes, converged or not (zero after a non-finite
+          // residual), so every trimer starts from defined values
+          const SlotInfo sl = a.slots[fdp->slot[fdp->warm_out]];
+          const double *src = Ycb + fdp->ysub[fdp->warm_out];
+          for (int e = tid; e < sl.D * sl.D; e += 256)
+            a.warm[sl.kt_off + e] = hasY && !B ? src[e] : 0.0;
+        }
         if (GRAD && conv && !B) {
-          if (it == 0) {
+          if (!hasY) {
             // converged at T = 0 (K~ below the threshold): all zero
             for (int e = tid; e < fdp->ny; e += 256) a.yfin[fdp->yout + e] = 0.0;
             for (int ti = f_tb + tid; ti < f_te; ti += 256) a.gterm[ti] = 0.0;
@@ -343,6 +372,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         }
         break;
       }
+      hasY = true;
       cur ^= 1;
     }
   }

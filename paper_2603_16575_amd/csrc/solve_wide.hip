@@ -80,6 +80,26 @@ void solve_wide_kernel(SolveArgs a) {
     const int f_tb = fdp->term_begin, f_te = fdp->term_end;
     int cur = 0;
     bool gpass = false;  // GRAD: the extra pass at the converged amplitudes
+    // amplitudes present: after a warm start from the solutions of the
+    // fragment's own pairs (monomers, dimers), or after the first update
+    bool hasY = false;
+    if (fdp->warm_in && a.warm) {
+      for (int tl = 0; tl < f_nt; ++tl) {
+        const SlotInfo sl = a.slots[fdp->slot[tl]];
+        const int D = sl.D;
+        const double *src = a.warm + sl.kt_off;
+        double *y = Y0 + fdp->ysub[tl];
+        double *yt = YT0 + fdp->ysub[tl];
+        for (int e = tid; e < D * D; e += NTH) {
+          const int i = e / D, j = e - i * D;
+          const double v = src[e];
+          y[e] = v;
+          yt[(int64_t)j * D + i] = v;
+        }
+      }
+      __syncthreads();
+      hasY = true;
+    }
     for (int it = 0;; ++it) {
       double mres = 0.0, epart = 0.0;
       int bad = 0;
@@ -95,7 +115,7 @@ void solve_wide_kernel(SolveArgs a) {
         const int sym = fdp->sym[tl];
         for (int e = tid; e < Dt * Dt; e += NTH) R[e] = 0.0;
         __syncthreads();
-        if (it > 0) {
+        if (hasY) {
           for (int ti = f_tb; ti < f_te; ++ti) {
             const Term tm = a.terms[ti];
             if (tm.target != tl) continue;
@@ -208,8 +228,8 @@ void solve_wide_kernel(SolveArgs a) {
         const double w = (double)fdp->wgt[tl];
         for (int e = tid; e < Dt * Dt; e += NTH) {
           const int i = e / Dt, j = e - i * Dt;
-          const double y = it > 0 ? Yc[e] : 0.0;
-          const double yt = it > 0 ? YTc[e] : 0.0;
+          const double y = hasY ? Yc[e] : 0.0;
+          const double yt = hasY ? YTc[e] : 0.0;
           const double s = sym ? R[e] + R[(int64_t)j * Dt + i] : R[e];
           const double kij = Kt[e];
           const double den = fpq - et[i] - et[j];
@@ -254,8 +274,17 @@ void solve_wide_kernel(SolveArgs a) {
           if (B) st[0] = 1;
           if (!conv && !B) st[1] = 1;
         }
+        if (fdp->warm_out >= 0 && a.warm) {
+          // the fragment's own pair seeds the trimers that contain it: its
+          // last amplitudes, converged or not (zero after a non-finite
+          // residual), so every trimer starts from defined values
+          const SlotInfo sl = a.slots[fdp->slot[fdp->warm_out]];
+          const double *src = Ycb + fdp->ysub[fdp->warm_out];
+          for (int e = tid; e < sl.D * sl.D; e += NTH)
+            a.warm[sl.kt_off + e] = hasY && !B ? src[e] : 0.0;
+        }
         if (GRAD && conv && !B) {
-          if (it == 0) {
+          if (!hasY) {
             for (int e = tid; e < fdp->ny; e += NTH) a.yfin[fdp->yout + e] = 0.0;
             for (int ti = f_tb + tid; ti < f_te; ti += NTH) a.gterm[ti] = 0.0;
             if (tid < f_nt) a.gdiag[6 * fi + tid] = 0.0;
@@ -269,6 +298,7 @@ void solve_wide_kernel(SolveArgs a) {
         }
         break;
       }
+      hasY = true;
       cur ^= 1;
     }
   }

@@ -1,9 +1,11 @@
-"""Write tests/golden/water40u_oracle.json from the CPU oracle only.
+"""Write tests/golden/water40u_oracle.json (every fragment from T = 0) or,
+with --warm, water40u_oracle_warm.json (trimers started from their
+monomer/dimer solutions) from the CPU oracle only.
 
 Full MBE(3) energy of configuration 1 (water40u, 89969 fragments), its
 update-count histogram and every 1000th fragment energy, computed by
 oracle.run with a process pool.  Usage:
-    python tests/golden/make_golden.py [workers]
+    python tests/golden/make_golden.py [workers] [--warm]
 """
 import json
 import os
@@ -20,14 +22,17 @@ import synth  # noqa: E402
 
 
 def main():
-    workers = int(sys.argv[1]) if len(sys.argv) > 1 else os.cpu_count()
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    warm = "--warm" in sys.argv[1:]
+    workers = int(args[0]) if args else os.cpu_count()
     t0 = time.time()
     prob = synth.config(1)
-    out = oracle.run(prob, workers=workers)
+    out = oracle.run(prob, workers=workers, warm_start=warm)
     E, _ = oracle.mbe3_energy(prob.frags, out["e_frag"])
     idx = np.arange(0, prob.n_frag, 1000)
     rec = {
         "workload": "configuration 1 (water40u)",
+        "start": "trimers from monomer/dimer solutions" if warm else "T = 0",
         "n_frag": int(prob.n_frag),
         "E_total": repr(float(E)),
         "converged": bool(out["converged"].all()),
@@ -37,7 +42,8 @@ def main():
         "oracle_seconds": round(time.time() - t0, 1),
         "workers": workers,
     }
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "water40u_oracle.json")
+    name = "water40u_oracle_warm.json" if warm else "water40u_oracle.json"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     print(path, rec["E_total"], rec["oracle_seconds"], "s")

@@ -51,7 +51,7 @@ def rel(a, b):
 
 def check_vs_oracle(m, prob, tol_rel):
     import torch
-    h = m.from_problem(prob)
+    h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
     out = h.forward(grad=True)
     dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device="cuda:0")
     dB, probe = h.mbe3_backward(out["gamma"], out["W"], dEdF=dF, probe=True)
@@ -122,7 +122,8 @@ def test_energy_fn_autograd(m):
     slab = torch.as_tensor(np.stack([oracle.slab(prob, i) for i in range(prob.n_occ)]),
                            device="cuda:0").requires_grad_(True)
     f = torch.as_tensor(prob.f_occ.copy(), device="cuda:0").requires_grad_(True)
-    h = m.from_problem(prob, slab=slab.detach(), f_occ=f.detach(), w_ia=None, w_iP=None)
+    h = m.from_problem(prob, slab=slab.detach(), f_occ=f.detach(), w_ia=None, w_iP=None,
+                       warm_start=False)
     E = m.energy_fn(h, slab, f)
     (3.0 * E).backward()
     g = oracle.gradient(prob)
@@ -203,7 +204,7 @@ def test_backward_water40u_sampled(m):
     import torch
     say("case: water40u (configs 1) backward, sampled oracle slots")
     prob = synth.config(1)
-    h = m.from_problem(prob)
+    h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
     out = h.forward(grad=True)
     dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device="cuda:0")
     dG, probe = h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_GAMMA,

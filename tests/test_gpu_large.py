@@ -48,7 +48,7 @@ def test_large_pairs_energy_vs_oracle(m):
     d = np.concatenate([prob.r, prob.r[prob.pairs[:, 0]] + prob.r[prob.pairs[:, 1]]])
     say(f"pair dims {sorted(set(int(x) for x in d))}")
     assert d.max() > 96
-    h = m.from_problem(prob)
+    h = m.from_problem(prob, warm_start=False)
     out = h.forward()
     ref = oracle.run(prob)
     e = out["e_frag"].cpu().numpy()
@@ -78,7 +78,7 @@ def test_large_pairs_backward_vs_oracle(m):
     import torch
     say("case: micro n_occ=4, r 56-80, backward vs oracle.gradient")
     prob = big_micro()
-    h = m.from_problem(prob)
+    h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
     out = h.forward(grad=True)
     dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device="cuda:0")
     dB, _ = h.mbe3_backward(out["gamma"], out["W"], dEdF=dF)
@@ -119,7 +119,7 @@ def test_water128u_sampled(m):
     import torch
     say("case: water128u (configs 2) full forward, sampled oracle trimer")
     prob = synth.config(2)
-    h = m.from_problem(prob)
+    h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
     out = h.forward()
     e = out["e_frag"].cpu().numpy()
     it = out["iters"].cpu().numpy()

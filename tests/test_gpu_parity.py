@@ -56,9 +56,9 @@ def run_all(m, prob, **kw):
 
 
 def test_chain8_end_to_end(m):
-    say("case: chain8 (configs 0) full forward vs oracle")
+    say("case: chain8 (configs 0) full forward vs oracle (T = 0 starts)")
     prob = synth.config(0)
-    h, out = run_all(m, prob)
+    h, out = run_all(m, prob, warm_start=False)
     ref = oracle.run(prob)
     ora = ref["oracle"]
     E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
@@ -134,7 +134,7 @@ def test_slab_regeneration_ulps(m):
 def test_micro_strong_coupling(m, n_occ):
     say(f"case: micro n_occ={n_occ} strong coupling, all fragments")
     prob = dataclasses.replace(strong(synth.micro(n_occ)), tol=1e-12, max_iter=300)
-    h, out = run_all(m, prob)
+    h, out = run_all(m, prob, warm_start=False)
     ref = oracle.run(prob)
     e = out["e_frag"].cpu().numpy()
     assert np.abs(e - ref["e_frag"]).max() <= 1e-13
@@ -163,7 +163,7 @@ def test_water40u_sampled(m):
     one; projected blocks and K of sampled orbitals/pairs."""
     say("case: water40u (configs 1) full forward, sampled oracle fragments")
     prob = synth.config(1)
-    h, out = run_all(m, prob)
+    h, out = run_all(m, prob, warm_start=False)  # the oracle's iterates
     e = out["e_frag"].cpu().numpy()
     it = out["iters"].cpu().numpy()
     assert (it >= 0).all() and np.isfinite(e).all()
@@ -238,9 +238,60 @@ def test_water40u_total_vs_golden(m):
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                     "water40u_oracle.json")))
     prob = synth.config(1)
-    h, out = run_all(m, prob)
+    h, out = run_all(m, prob, warm_start=False)
     E_ref = float(g["E_total"])
     say(f"water40u: E_gpu={out['E']:.13f} E_oracle={E_ref:.13f} "
+        f"dE={out['E'] - E_ref:.3e}")
+    assert abs(out["E"] - E_ref) <= 1e-10
+    it = out["iters"].cpu().numpy()
+    assert np.bincount(it).tolist() == g["iters_hist"]
+    e = out["e_frag"].cpu().numpy()
+    idx = np.array(g["sample_index"])
+    ref = np.array([float(x) for x in g["sample_e_frag"]])
+    assert np.abs(e[idx] - ref).max() <= 1e-12
+    h.close()
+
+
+def test_warm_start_water40u(m):
+    """Trimers started from their monomer/dimer solutions converge to the same
+    energies in fewer updates than from T = 0.  Both stop at max|R~| < 1e-7;
+    the Hylleraas error of a stopping point is second order in the residual
+    and of one sign, so over 84k trimers the two totals may differ by a few
+    1e-9 Eh (each fragment by ~1e-12)."""
+    say("case: water40u (configs 1) warm vs T = 0 starts")
+    prob = synth.config(1)
+    hc, oc = run_all(m, prob, warm_start=False)
+    ec, ic = oc["e_frag"].cpu().numpy(), oc["iters"].cpu().numpy()
+    Ec = oc["E"]
+    hc.close()
+    hw, ow = run_all(m, prob)
+    ew, iw = ow["e_frag"].cpu().numpy(), ow["iters"].cpu().numpy()
+    hw.close()
+    tri = prob.frags[:, 2] >= 0
+    say(f"warm: dE = {ow['E'] - Ec:.3e}, max |dE_F| = {np.abs(ew - ec).max():.3e}, "
+        f"trimer updates {ic[tri].mean():.3f} -> {iw[tri].mean():.3f}")
+    # monomers and dimers start from T = 0 either way (their chunks may use a
+    # different kernel instance, so only rounding may differ)
+    assert np.abs(ew[~tri] - ec[~tri]).max() <= 1e-14 and np.array_equal(iw[~tri], ic[~tri])
+    assert np.abs(ew - ec).max() <= 1e-11
+    assert abs(ow["E"] - Ec) <= 2e-8
+    assert iw[tri].mean() < ic[tri].mean()
+
+
+def test_water40u_warm_vs_golden(m):
+    """Full configuration 1 as the benchmark runs it (trimers warm started)
+    against the oracle's full run with the same starts (written by
+    tests/golden/make_golden.py --warm): |dE| <= 1e-10 Eh, the update-count
+    histogram, and every 1000th fragment energy."""
+    import json
+    import os
+    say("case: water40u (configs 1) warm-started total vs golden oracle run")
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "water40u_oracle_warm.json")))
+    prob = synth.config(1)
+    h, out = run_all(m, prob)
+    E_ref = float(g["E_total"])
+    say(f"water40u warm: E_gpu={out['E']:.13f} E_oracle={E_ref:.13f} "
         f"dE={out['E'] - E_ref:.3e}")
     assert abs(out["E"] - E_ref) <= 1e-10
     it = out["iters"].cpu().numpy()

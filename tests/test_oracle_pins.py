@@ -65,6 +65,25 @@ def test_fragments_match_kronecker_solve(n_occ, scale):
             assert np.allclose(V @ Tab @ V.T, t[(a, b)], atol=1e-12 * np.abs(t[(a, b)]).max())
 
 
+@pytest.mark.parametrize("n_occ", [3, 4])
+def test_warm_started_fragments_match_kronecker_solve(n_occ):
+    """Trimers started from their monomer/dimer solutions converge to the
+    same dense solution, in fewer updates than from T = 0."""
+    p = dataclasses.replace(_strong_coupling(synth.micro(n_occ), 8.0), tol=1e-13,
+                            max_iter=400)
+    ora = oracle.Oracle(p)
+    cold = oracle.run(p, ora=ora)
+    warm = oracle.run(p, ora=ora, warm_start=True)
+    B = [ora.B(i) for i in range(p.n_occ)]
+    tri = p.frags[:, 2] >= 0
+    for k in np.nonzero(tri)[0]:
+        fr = [int(x) for x in p.frags[k] if x >= 0]
+        Ek, _ = _pins.kron_fragment_solve(B, p.Q, p.eps_vir, p.f_occ, fr)
+        assert abs(warm["e_frag"][k] - Ek) <= 1e-12 * abs(Ek)
+    assert np.array_equal(warm["e_frag"][~tri], cold["e_frag"][~tri])
+    assert warm["iters"][tri].sum() < cold["iters"][tri].sum()
+
+
 def test_three_orbital_fragment_equals_full_system():
     """A 3-orbital system: MBE(3) telescopes to the trimer, which is the whole
     (unexpanded) OSV-MP2 problem."""
