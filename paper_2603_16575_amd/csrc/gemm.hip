@@ -1,9 +1,11 @@
 // Grouped FP64 GEMM engine on the CDNA matrix cores (v_mfma_f64_16x16x4).
 //
 // One workgroup (4 wave64) computes one BM x BN tile of one task.  Operand
-// tiles of depth 16 are staged through LDS with coalesced global reads
-// (k-contiguous or m/n-contiguous depending on the transpose flags) and laid
-// out k-major so that each MFMA operand read is 16 consecutive doubles.
+// tiles of depth 16 are staged through two LDS buffers with coalesced global
+// reads (k-contiguous or m/n-contiguous depending on the transpose flags):
+// the next tile is loaded into registers while the current one feeds the
+// matrix cores, then stored to the other buffer, one barrier per step.  LDS
+// tiles are k-major so each MFMA operand read is 16 consecutive doubles.
 // Stored rows of either operand may be gathered through an index list (rows
 // of A = M index when A is not transposed, K index when it is; rows of B = K
 // index when B is not transposed, N index when it is), which lets one task
@@ -17,13 +19,15 @@ namespace mbe3 {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_tasks_kernel(
+__global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
     const GemmTask *__restrict__ tasks, int n_tasks, GemmBases bases) {
   constexpr int BK = 16;
-  constexpr int PA = BM + 4;
-  constexpr int PB = BN + 4;
-  __shared__ double As[BK * PA];
-  __shared__ double Bs[BK * PB];
+  // pitch = BM + 16: the four k-rows an MFMA read touches (lane / 16) start
+  // 2 PA = 32 (mod 64) banks apart, so each half-wave reads distinct banks
+  constexpr int PA = BM + 16;
+  constexpr int PB = BN + 16;
+  __shared__ double As[2][BK * PA];
+  __shared__ double Bs[2][BK * PB];
 
   const int64_t tile = blockIdx.x;
   int lo = 0, hi = n_tasks - 1;
@@ -56,80 +60,100 @@ __global__ __launch_bounds__(256) void gemm_tasks_kernel(
   constexpr int EA = BM * BK / 256;  // A elements per thread
   constexpr int EB = BN * BK / 256;
 
-  // Per-thread physical row for a k-contiguous A load (transA = 0).
+  // Per-thread source positions.  k-contiguous A (transA = 0): EA consecutive
+  // k of one row; m-contiguous A (transA = 1): EA consecutive m of one k row.
+  // B likewise.  Gathered rows are resolved per k-row as they come.
   const int a_tpr = BK / EA;
   const int a_r = tid / a_tpr, a_k = (tid % a_tpr) * EA;
   int64_t a_row = -1;
   if (!t.transA && m0 + a_r < t.M)
     a_row = (t.a_rows >= 0) ? rows[t.a_rows + m0 + a_r] : (m0 + a_r);
+  const int a_tpk = BM / EA;
+  const int a_kk = tid / a_tpk, a_mm = (tid % a_tpk) * EA;
   const int b_tpr = BK / EB;
   const int b_r = tid / b_tpr, b_k = (tid % b_tpr) * EB;
   int64_t b_row = -1;
   if (t.transB && n0 + b_r < t.N)
     b_row = (t.b_rows >= 0) ? rows[t.b_rows + n0 + b_r] : (n0 + b_r);
+  const int b_tpk = BN / EB;
+  const int b_kk = tid / b_tpk, b_nn = (tid % b_tpk) * EB;
 
+  double ra[EA], rb[EB];  // the next tile, in flight during the products
+#define MBE3_GEMM_LOAD(K0)                                                     \
+  do {                                                                         \
+    if (!t.transA) {                                                           \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) {                         \
+        const int k = (K0) + a_k + e;                                          \
+        ra[e] = (a_row >= 0 && k < t.K) ? A[a_row * (int64_t)t.lda + k] : 0.0; \
+      }                                                                        \
+    } else {                                                                   \
+      const int k = (K0) + a_kk;                                               \
+      const int64_t krow = k < t.K ? (t.a_rows >= 0 ? rows[t.a_rows + k] : k) : 0; \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) {                         \
+        const int m = m0 + a_mm + e;                                           \
+        ra[e] = (m < t.M && k < t.K) ? A[krow * t.lda + m] : 0.0;              \
+      }                                                                        \
+    }                                                                          \
+    if (!t.transB) {                                                           \
+      const int k = (K0) + b_kk;                                               \
+      const int64_t krow = k < t.K ? (t.b_rows >= 0 ? rows[t.b_rows + k] : k) : 0; \
+      _Pragma("unroll") for (int e = 0; e < EB; ++e) {                         \
+        const int n = n0 + b_nn + e;                                           \
+        rb[e] = (n < t.N && k < t.K) ? B[krow * t.ldb + n] : 0.0;              \
+      }                                                                        \
+    } else {                                                                   \
+      _Pragma("unroll") for (int e = 0; e < EB; ++e) {                         \
+        const int k = (K0) + b_k + e;                                          \
+        rb[e] = (b_row >= 0 && k < t.K) ? B[b_row * (int64_t)t.ldb + k] : 0.0; \
+      }                                                                        \
+    }                                                                          \
+  } while (0)
+#define MBE3_GEMM_STORE(BUF)                                                   \
+  do {                                                                         \
+    double *as_ = As[BUF];                                                     \
+    double *bs_ = Bs[BUF];                                                     \
+    if (!t.transA) {                                                           \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) as_[(a_k + e) * PA + a_r] = ra[e]; \
+    } else {                                                                   \
+      _Pragma("unroll") for (int e = 0; e < EA; ++e) as_[a_kk * PA + a_mm + e] = ra[e]; \
+    }                                                                          \
+    if (!t.transB) {                                                           \
+      _Pragma("unroll") for (int e = 0; e < EB; ++e) bs_[b_kk * PB + b_nn + e] = rb[e]; \
+    } else {                                                                   \
+      _Pragma("unroll") for (int e = 0; e < EB; ++e) bs_[(b_k + e) * PB + b_r] = rb[e]; \
+    }                                                                          \
+  } while (0)
+
+  MBE3_GEMM_LOAD(0);
+  MBE3_GEMM_STORE(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < t.K; k0 += BK) {
-    // ---- stage A (BM x BK) as As[k][m] ----
-    if (!t.transA) {
-#pragma unroll
-      for (int e = 0; e < EA; ++e) {
-        const int k = k0 + a_k + e;
-        double v = 0.0;
-        if (a_row >= 0 && k < t.K) v = A[a_row * (int64_t)t.lda + k];
-        As[(a_k + e) * PA + a_r] = v;
-      }
-    } else {
-      const int tpk = BM / EA;
-      const int kk = tid / tpk, mm = (tid % tpk) * EA;
-      const int k = k0 + kk;
-      const int64_t krow = k < t.K ? (t.a_rows >= 0 ? rows[t.a_rows + k] : k) : 0;
-#pragma unroll
-      for (int e = 0; e < EA; ++e) {
-        const int m = m0 + mm + e;
-        double v = 0.0;
-        if (m < t.M && k < t.K) v = A[krow * t.lda + m];
-        As[kk * PA + mm + e] = v;
-      }
-    }
-    // ---- stage B (BK x BN) as Bs[k][n] ----
-    if (!t.transB) {
-      const int tpk = BN / EB;
-      const int kk = tid / tpk, nn = (tid % tpk) * EB;
-      const int k = k0 + kk;
-      const int64_t krow = k < t.K ? (t.b_rows >= 0 ? rows[t.b_rows + k] : k) : 0;
-#pragma unroll
-      for (int e = 0; e < EB; ++e) {
-        const int n = n0 + nn + e;
-        double v = 0.0;
-        if (n < t.N && k < t.K) v = B[krow * t.ldb + n];
-        Bs[kk * PB + nn + e] = v;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < EB; ++e) {
-        const int k = k0 + b_k + e;
-        double v = 0.0;
-        if (b_row >= 0 && k < t.K) v = B[b_row * (int64_t)t.ldb + k];
-        Bs[(b_k + e) * PB + b_r] = v;
-      }
-    }
-    __syncthreads();
+    const bool more = k0 + BK < t.K;
+    if (more) MBE3_GEMM_LOAD(k0 + BK);
+    const double *as = As[buf];
+    const double *bs = Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
       double a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kr * PA + wr * WM + i * 16 + (lane & 15)];
+      for (int i = 0; i < TM; ++i) a[i] = as[kr * PA + wr * WM + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kr * PB + wc * WN + j * 16 + (lane & 15)];
+      for (int j = 0; j < TN; ++j) b[j] = bs[kr * PB + wc * WN + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) MBE3_GEMM_STORE(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
+#undef MBE3_GEMM_LOAD
+#undef MBE3_GEMM_STORE
 
   // ---- epilogue: D layout of v_mfma_f64_16x16x4: register v of lane l holds
   //      row (l / 16) + 4 v, column l % 16
