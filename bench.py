@@ -5,8 +5,10 @@ osv_project (slab regeneration + OSV projection) -> pair_K -> fragment_solve
 (pair bases, coupling blocks, residual iterations of every fragment, and the
 MBE multipliers W with dE/df_occ) -> mbe3_energy -> mbe3_backward (dense
 dE/d(ia|P) and dE/df_occ).  Inputs (Q, eps, f, slab weights, lists) are
-resident in HBM before the timed region.  The same K steps without the
-backward are timed afterwards and reported as "forward_only".  Prints ONE
+resident in HBM before the timed region.  The step is recorded once as a
+HIP graph (mbe3_graph_begin/end) and the timed region replays it; the
+call-by-call step and the recorded step without the backward
+("forward_only") are timed afterwards.  Prints ONE
 JSON line on stdout; progress goes to stderr.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
@@ -204,37 +206,35 @@ def cpu_baseline(prob, budget_workers):
                                    dEdB_assembly=TD))
 
 
-def mixed_run(m, prob, args, dev, E64, e64, h64):
-    """The same forward + backward steps with osv_project and pair_K in the
-    split-precision form (MBE3_MIXED_BF16); energy deviations against the
-    FP64 run of this process."""
+def timed_replays(h, args, label):
+    """Warm-up and timed replays of the handle's recorded graph; returns
+    (ms per step, last energy, per-phase timing of the timed replays)."""
     import torch
-    h = m.from_problem(prob, device=str(dev), precision=m.MBE3_MIXED_BF16)
-    gamma, K, W = h.empty_gamma(), h.empty_K(), h.empty_K()
-    e = torch.empty(h.n_frag, dtype=torch.float64, device=dev)
-    it = torch.empty(h.n_frag, dtype=torch.int32, device=dev)
-    dB = torch.empty((prob.n_occ, prob.n_vir, prob.n_aux), dtype=torch.float64, device=dev)
-    dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device=dev)
-
-    def step():
-        h.osv_project(gamma)
-        h.pair_K(gamma, K)
-        h.fragment_solve(K, e, it, W)
-        E = h.mbe3_energy(e)
-        h.mbe3_backward(gamma, W, 1.0, m.MBE3_GRAD_SLAB, out=dB, dEdF=dF)
-        return E
-
-    for _ in range(args.warmup):
-        step()
+    E = None
+    for w in range(args.warmup):
+        E = h.graph_launch()
+        log(f"bench: {label} warmup {w + 1}/{args.warmup} E={E:.12f}")
+    h.set_timing(True)  # clears the accumulators; the graph keeps its events
     torch.cuda.synchronize()
-    h.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        E = step()
+        E = h.graph_launch()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     ph = h.get_timing()
+    return ms, E, ph
+
+
+def mixed_run(m, prob, args, dev, E64, e64, h64):
+    """The same recorded forward + backward step with osv_project and pair_K
+    in the split-precision form (MBE3_MIXED_BF16); energy deviations against
+    the FP64 run of this process."""
+    h = m.from_problem(prob, device=str(dev), precision=m.MBE3_MIXED_BF16)
+    h.set_timing(True)
+    bufs = h.capture_step(grad=True)
+    ms, E, ph = timed_replays(h, args, "mixed")
     h.set_timing(False)
+    e = bufs["e_frag"]
     d = np.abs(e.cpu().numpy() - e64)
     ldk_vir = (prob.n_vir + 7) // 8 * 8
     ldk_aux = (prob.n_aux + 7) // 8 * 8
@@ -325,32 +325,41 @@ def main():
             h.mbe3_backward(gamma, W, 1.0, m.MBE3_GRAD_SLAB, out=dB, dEdF=dF)
         return E
 
-    for w in range(args.warmup):
-        E = step()
-        log(f"bench: warmup {w + 1}/{args.warmup} E={E:.12f}")
+    # the step run call by call: plans the gradient workspace, and is the
+    # reference the recorded step must reproduce bit for bit
+    E_eager = step()
     torch.cuda.synchronize()
+    e_eager = e.clone()
+    log(f"bench: eager step E={E_eager:.12f}")
+
+    # timed region: replays of the whole step recorded as one HIP graph, with
+    # the phase events (HIP events on the library's stream) inside it
     h.set_timing(True)
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        E = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ph = h.get_timing()
+    bufs = h.capture_step(grad=True)
+    ms_step, E, ph = timed_replays(h, args, "fwd+bwd")
     h.set_timing(False)
-    ms_step = (t1 - t0) * 1000.0 / args.steps
     value = prob.n_frag / (ms_step / 1000.0)
     log(f"bench: {args.steps} steps, {ms_step:.2f} ms/step, {value:.1f} fragments/s, E={E:.12f}")
+    if E != E_eager or not torch.equal(bufs["e_frag"], e_eager):
+        raise SystemExit(f"bench: recorded step differs from the eager one "
+                         f"(E {E!r} vs {E_eager!r})")
+    e, it, dB = bufs["e_frag"], bufs["iters"], bufs["dB"]
     gnorm = float(torch.linalg.vector_norm(dB))
     e64 = e.cpu().numpy().copy()
     E64 = E
-    # the same steps without the backward
-    step(False)
+    # call-by-call steps, for the cost of launching without the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        E_f = step(False)
+        step()
     torch.cuda.synchronize()
-    ms_fwd = (time.perf_counter() - t0) * 1000.0 / args.steps
+    ms_eager = (time.perf_counter() - t0) * 1000.0 / args.steps
+    log(f"bench: call-by-call step {ms_eager:.2f} ms")
+    # the same step without the backward, recorded
+    del bufs
+    fw = h.capture_step(grad=False)
+    ms_fwd, E_f, _ = timed_replays(h, args, "forward")
+    del fw
     log(f"bench: forward only {ms_fwd:.2f} ms/step, {prob.n_frag / (ms_fwd / 1e3):.1f} fragments/s")
 
     iters = it.cpu().numpy()
@@ -417,10 +426,12 @@ def main():
                                f"n_vir={n_vir}, n_aux={n_aux}, r={prob.r.min()}-{prob.r.max()}, "
                                f"cutoff 6, {len(prob.pairs)} pairs, {len(prob.trimers)} trimers, "
                                f"{prob.n_frag} fragments, tol {prob.tol:g}",
-                   "step": "forward + backward (dE/d(ia|P), dE/df_occ)",
+                   "step": "forward + backward (dE/d(ia|P), dE/df_occ), "
+                           "replayed as one recorded HIP graph",
                    "precision": "fp64", "E_total": E,
                    "grad_norm_dB": gnorm,
                    "iters_hist": np.bincount(np.maximum(iters, 0)).tolist()},
+        "call_by_call_ms_per_step": round(ms_eager, 3),
         "forward_only": {"ms_per_step": round(ms_fwd, 3),
                          "fragments_per_s": round(prob.n_frag / (ms_fwd / 1e3), 2),
                          "E_total": E_f},

@@ -270,6 +270,44 @@ int mbe3_get_timing(mbe3_handle *h, double *ms, int64_t *launches);
 /* Offsets for mbe3_pair_basis: host xoff[n_slot+1], eoff[n_slot+1]. */
 int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
 
+/*
+ * Recorded launches (one HIP graph per handle) for the batched form of
+ * Algorithm 7: thousands of fragments per call, replayed without host work.
+ *
+ * mbe3_graph_begin starts recording: until mbe3_graph_end, the calls
+ * osv_project, pair_K, fragment_solve, mbe3_energy, mbe3_backward (without
+ * probe) and mbe3_pair_basis on h enqueue their launches into the graph
+ * instead of running them, bound to the pointers they are given (which must
+ * stay valid while the graph is used).  They do not synchronise; their
+ * status codes then cover argument checks only: fragment_solve's
+ * convergence and finiteness are reported by mbe3_graph_launch, and
+ * mbe3_energy writes NaN to *e_total (the energy comes from
+ * mbe3_graph_launch).  with_grad != 0 plans and allocates the gradient
+ * workspace first (fragment_solve with W and mbe3_backward need it; they
+ * fail while recording if it is missing).  Any failing call marks the
+ * recording failed.  mbe3_set_timing, mbe3_get_timing and a second
+ * mbe3_graph_begin fail while recording.  Recording happens on a private
+ * stream of the handle; beginning a new recording synchronises h's stream
+ * and releases the previous graph.  If timing is on while recording, each
+ * timed phase becomes a graph of its own and mbe3_graph_launch, with
+ * timing on, brackets its replay with HIP events on h's stream (the
+ * mbe3_get_timing accumulators); otherwise the recording is one graph.
+ *
+ * mbe3_graph_end instantiates the graph: MBE3_EINVAL if a call failed while
+ * recording (the message names it; nothing is kept), MBE3_EHIP if HIP
+ * refused the capture.
+ *
+ * mbe3_graph_launch replays the graph on h's stream and synchronises, then
+ * reports like the recorded calls would have: MBE3_ENONFINITE / MBE3_ENOCONV
+ * from a recorded fragment_solve, and the MBE(3) energy of a recorded
+ * mbe3_energy in *e_total (host, nullable).  After a successful replay that
+ * contains fragment_solve with W, mbe3_backward may use dE/df.  Nothing is
+ * allocated per replay.
+ */
+int mbe3_graph_begin(mbe3_handle *h, int with_grad);
+int mbe3_graph_end(mbe3_handle *h);
+int mbe3_graph_launch(mbe3_handle *h, double *e_total);
+
 #ifdef __cplusplus
 }
 #endif

@@ -186,6 +186,51 @@ class Mbe3:
         _lib.check(_lib.load().mbe3_get_timing(self._h, _lib.ptr(ms), _lib.ptr(n)), self._h)
         return {ph: (float(ms[k]), int(n[k])) for k, ph in enumerate(_lib.PHASES)}
 
+    # ---- recorded launches (one HIP graph per handle) ----
+    def graph_begin(self, with_grad=False):
+        _lib.check(_lib.load().mbe3_graph_begin(self._h, int(bool(with_grad))), self._h)
+
+    def graph_end(self):
+        _lib.check(_lib.load().mbe3_graph_end(self._h), self._h)
+
+    def graph_launch(self):
+        """Replay the recorded graph; returns the MBE(3) energy if the
+        recording contained mbe3_energy, else None."""
+        out = np.full(1, np.nan, dtype=np.float64)
+        _lib.check(_lib.load().mbe3_graph_launch(self._h, _lib.ptr(out)), self._h)
+        return None if np.isnan(out[0]) else float(out[0])
+
+    def capture_step(self, grad=False, dB=None, dEdF=None):
+        """Record one forward (osv_project -> pair_K -> fragment_solve ->
+        mbe3_energy) and, with grad=True, the backward into dB
+        (dE/d(ia|P), [n_occ, n_vir, n_aux], allocated if None) and dEdF.
+        Returns the buffers the graph writes on every graph_launch()."""
+        import torch
+        gamma, K = self.empty_gamma(), self.empty_K()
+        e = torch.empty(self.n_frag, dtype=torch.float64, device=self.device)
+        it = torch.empty(self.n_frag, dtype=torch.int32, device=self.device)
+        W = self.empty_K() if grad else None
+        if grad and dB is None:
+            dB = torch.empty((self.n_occ, self.n_vir, self.n_aux), dtype=torch.float64,
+                             device=self.device)
+        if grad and dEdF is None:
+            dEdF = torch.empty((self.n_occ, self.n_occ), dtype=torch.float64,
+                               device=self.device)
+        torch.cuda.synchronize(self.device)  # the buffers exist before replays
+        self.graph_begin(with_grad=grad)
+        try:
+            self.osv_project(gamma)
+            self.pair_K(gamma, K)
+            self.fragment_solve(K, e, it, W)
+            self.mbe3_energy(e)
+            if grad:
+                self.mbe3_backward(gamma, W, dE=1.0, mode=MBE3_GRAD_SLAB, out=dB,
+                                   dEdF=dEdF)
+        finally:
+            self.graph_end()
+        return dict(gamma=gamma, K=K, e_frag=e, iters=it, W=W,
+                    dB=dB if grad else None, dEdF=dEdF if grad else None)
+
     def forward(self, grad=False):
         """osv_project -> pair_K -> fragment_solve -> mbe3_energy; with
         grad=True fragment_solve also returns the multipliers W."""

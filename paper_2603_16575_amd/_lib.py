@@ -29,7 +29,8 @@ EXPORTS = [
     "mbe3_gamma_offsets", "mbe3_k_offsets", "mbe3_basis_offsets",
     "osv_project", "pair_K", "fragment_solve", "mbe3_energy",
     "mbe3_pair_basis", "mbe3_plan_check", "mbe3_set_timing",
-    "mbe3_get_timing", "mbe3_backward",
+    "mbe3_get_timing", "mbe3_backward", "mbe3_graph_begin", "mbe3_graph_end",
+    "mbe3_graph_launch",
 ]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
           "energy", "grad", "backward"]
@@ -94,6 +95,9 @@ def load():
         "mbe3_get_timing": [vp, vp, vp],
         "mbe3_backward": [vp, ctypes.c_double, vp, vp, ctypes.c_int, vp, i64,
                           vp, vp],
+        "mbe3_graph_begin": [vp, ctypes.c_int],
+        "mbe3_graph_end": [vp],
+        "mbe3_graph_launch": [vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -185,6 +185,18 @@ struct mbe3_handle {
   double phase_ms[MBE3_NPHASE] = {0};
   int64_t phase_n[MBE3_NPHASE] = {0};
 
+  // ---- HIP graph of a recorded call sequence (mbe3_graph_begin/end) ----
+  hipStream_t user_stream = nullptr;  // the caller's stream while recording
+  hipStream_t cap_stream = nullptr;   // private stream the calls record on
+  bool recording = false, rec_failed = false;
+  bool rec_solve = false, rec_grad = false, rec_energy = false;
+  bool g_solve = false, g_grad = false, g_energy = false;  // in the graph
+  // one segment per phase scope when timing is on (events go between the
+  // segment launches), else a single segment
+  struct Segment { int phase; hipGraph_t g; hipGraphExec_t x; };
+  std::vector<Segment> segs;
+  int seg_phase = -1;  // phase of the segment being recorded
+
   // ---- host mirrors of the plans, for the bounds check ----
   bool dry = false;  // plan only: no device allocation or copies
   int64_t at_total = 0, mt_total = 0, st0_total = 0;
@@ -203,9 +215,15 @@ struct mbe3_handle {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     err = buf;
+    if (recording) rec_failed = true;
     return code;
   }
   ~mbe3_handle() {
+    for (auto &sg : segs) {
+      if (sg.x) (void)hipGraphExecDestroy(sg.x);
+      if (sg.g) (void)hipGraphDestroy(sg.g);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
     if (h_status) (void)hipHostFree(h_status);
@@ -233,14 +251,56 @@ hipEvent_t next_event(mbe3_handle *h) {
   }
   return h->event_pool[h->event_next++];
 }
+// Close the graph segment being recorded (kept if it holds any node) and
+// start the next one, of phase `next`.
+void cut_segment(mbe3_handle *h, int next, bool reopen) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (e == hipSuccess && g) {
+    size_t n = 0;
+    e = hipGraphGetNodes(g, nullptr, &n);
+    if (e == hipSuccess && n > 0) {
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiateWithFlags(&x, g, 0);
+      if (e == hipSuccess) {
+        h->segs.push_back({h->seg_phase, g, x});
+        g = nullptr;
+      }
+    }
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->rec_failed = true;
+    h->err = std::string("graph segment: ") + hipGetErrorString(e);
+  }
+  h->seg_phase = next;
+  if (reopen && hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    h->rec_failed = true;
+    h->err = "hipStreamBeginCapture failed";
+  }
+}
+
+// Times the launches of one phase: HIP events around them when timing is
+// on; while recording with timing, a graph segment of their own.
 struct PhaseScope {
   mbe3_handle *h;
   int phase;
   hipEvent_t a = nullptr;
+  bool seg = false;
   PhaseScope(mbe3_handle *hh, int ph) : h(hh), phase(ph) {
-    if (h->timing && (a = next_event(h))) (void)hipEventRecord(a, h->stream);
+    if (!h->timing) return;
+    if (h->recording) {
+      cut_segment(h, phase, true);
+      seg = true;
+    } else if ((a = next_event(h))) {
+      (void)hipEventRecord(a, h->stream);
+    }
   }
   ~PhaseScope() {
+    if (seg) {
+      cut_segment(h, -1, true);
+      return;
+    }
     if (!a) return;
     hipEvent_t b = next_event(h);
     if (!b) return;
@@ -1341,6 +1401,8 @@ int validate_plans(mbe3_handle *h) {
 // ---------------------------------------------------------------------------
 int build_grad_plans(mbe3_handle *h) {
   if (h->grad_planned) return MBE3_OK;
+  if (h->recording)
+    return h->fail(MBE3_EINVAL, "gradient plans allocate: start the recording with with_grad = 1");
   const int n = h->n_occ, na = h->n_aux, nv = h->n_vir;
   int rc;
   auto bad = [&](const char *what, size_t k) {
@@ -1558,6 +1620,28 @@ int build_grad_plans(mbe3_handle *h) {
 // ===========================================================================
 static thread_local std::string g_create_error = "no handle";
 
+// Status words of the last solve (host copy already synchronised).
+int solve_status(mbe3_handle *h) {
+  int bad = 0, nconv = 0;
+  for (int k = 0; k < SOLVE_WG; ++k) {
+    bad |= h->h_status[2 * k];
+    nconv |= h->h_status[2 * k + 1];
+  }
+  if (bad) return h->fail(MBE3_ENONFINITE, "non-finite residual in some fragment (e_frag = NaN)");
+  if (nconv) return h->fail(MBE3_ENOCONV, "some fragment did not converge in %d updates (iters < 0)",
+                            h->max_iter);
+  return MBE3_OK;
+}
+
+void release_graph(mbe3_handle *h) {
+  for (auto &sg : h->segs) {
+    if (sg.x) (void)hipGraphExecDestroy(sg.x);
+    if (sg.g) (void)hipGraphDestroy(sg.g);
+  }
+  h->segs.clear();
+  h->g_solve = h->g_grad = h->g_energy = false;
+}
+
 extern "C" {
 
 int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
@@ -1598,6 +1682,13 @@ int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out) {
 
 int mbe3_destroy(mbe3_handle *h) {
   if (!h) return MBE3_EINVAL;
+  if (h->recording) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    h->stream = h->user_stream;
+    h->recording = false;
+  }
   (void)hipStreamSynchronize(h->stream);
   delete h;
   return MBE3_OK;
@@ -1706,7 +1797,7 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
   if (!h) return MBE3_EINVAL;
   if (!K || !e_frag || !iters) return h->fail(MBE3_EINVAL, "K, e_frag, iters required");
   hipStream_t s = h->stream;
-  h->grad_ready = false;
+  if (!h->recording) h->grad_ready = false;
   int rc;
   if (W && (rc = build_grad_plans(h))) return rc;
   if ((rc = prepare_pairs(h, K))) return rc;
@@ -1782,15 +1873,13 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
   }
   HIP_TRY(h, hipMemcpyAsync(h->h_status, h->status, 2 * SOLVE_WG * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
-  HIP_TRY(h, hipStreamSynchronize(s));
-  int bad = 0, nconv = 0;
-  for (int k = 0; k < SOLVE_WG; ++k) {
-    bad |= h->h_status[2 * k];
-    nconv |= h->h_status[2 * k + 1];
+  if (h->recording) {  // checked by mbe3_graph_launch after each replay
+    h->rec_solve = true;
+    h->rec_grad = W != nullptr;
+    return MBE3_OK;
   }
-  if (bad) return h->fail(MBE3_ENONFINITE, "non-finite residual in some fragment (e_frag = NaN)");
-  if (nconv) return h->fail(MBE3_ENOCONV, "some fragment did not converge in %d updates (iters < 0)",
-                            h->max_iter);
+  HIP_TRY(h, hipStreamSynchronize(s));
+  if ((rc = solve_status(h))) return rc;
   h->grad_ready = W != nullptr;
   return MBE3_OK;
 }
@@ -1809,8 +1898,10 @@ int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
   if (out_elems < need)
     return h->fail(MBE3_EINVAL, "out needs %lld doubles, got %lld", (long long)need,
                    (long long)out_elems);
-  if (dEdF && !h->grad_ready)
+  if (dEdF && !(h->recording ? h->rec_grad : h->grad_ready))
     return h->fail(MBE3_EINVAL, "dE/df needs a preceding successful fragment_solve with W");
+  if (probe && h->recording)
+    return h->fail(MBE3_EINVAL, "the probe is read on the host: not available while recording");
   int rc = build_grad_plans(h);
   if (rc) return rc;
   hipStream_t s = h->stream;
@@ -1854,6 +1945,11 @@ int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
   }
   HIP_TRY(h, hipMemcpyAsync(h->h_e3, h->d_e3, 3 * sizeof(double),
                             hipMemcpyDeviceToHost, s));
+  if (h->recording) {  // the energy comes back from mbe3_graph_launch
+    h->rec_energy = true;
+    *e_total = std::nan("");
+    return MBE3_OK;
+  }
   HIP_TRY(h, hipStreamSynchronize(s));
   *e_total = h->h_e3[0];
   if (!std::isfinite(*e_total))
@@ -1863,6 +1959,7 @@ int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
 
 int mbe3_set_timing(mbe3_handle *h, int enable) {
   if (!h) return MBE3_EINVAL;
+  if (h->recording) return h->fail(MBE3_EINVAL, "timing cannot change while recording");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->timing = enable != 0;
   h->regions.clear();
@@ -1873,6 +1970,7 @@ int mbe3_set_timing(mbe3_handle *h, int enable) {
 
 int mbe3_get_timing(mbe3_handle *h, double *ms, int64_t *launches) {
   if (!h || !ms) return MBE3_EINVAL;
+  if (h->recording) return h->fail(MBE3_EINVAL, "timing is not readable while recording");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   for (auto &r : h->regions) {
     float t = 0.f;
@@ -1901,6 +1999,72 @@ int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank) {
                             hipMemcpyDeviceToDevice, s));
   HIP_TRY(h, hipMemcpyAsync(rank, h->rank, h->n_slot * sizeof(int32_t),
                             hipMemcpyDeviceToDevice, s));
+  return MBE3_OK;
+}
+
+int mbe3_graph_begin(mbe3_handle *h, int with_grad) {
+  if (!h) return MBE3_EINVAL;
+  if (h->dry) return h->fail(MBE3_EINVAL, "plan-only handle");
+  if (h->recording) return h->fail(MBE3_EINVAL, "already recording");
+  int rc;
+  if (with_grad && (rc = build_grad_plans(h))) return rc;
+  if (!h->cap_stream)
+    HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));  // a replay may still use the old graph
+  release_graph(h);
+  HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+  h->user_stream = h->stream;
+  h->stream = h->cap_stream;
+  h->recording = true;
+  h->rec_failed = false;
+  h->rec_solve = h->rec_grad = h->rec_energy = false;
+  h->seg_phase = -1;
+  return MBE3_OK;
+}
+
+int mbe3_graph_end(mbe3_handle *h) {
+  if (!h) return MBE3_EINVAL;
+  if (!h->recording) return h->fail(MBE3_EINVAL, "not recording");
+  cut_segment(h, -1, false);
+  h->stream = h->user_stream;
+  h->recording = false;
+  if (h->rec_failed || h->segs.empty()) {
+    release_graph(h);
+    if (h->segs.empty() && !h->rec_failed) return h->fail(MBE3_EINVAL, "nothing was recorded");
+    return h->fail(MBE3_EINVAL, "recording failed: %s", h->err.c_str());
+  }
+  h->g_solve = h->rec_solve;
+  h->g_grad = h->rec_grad;
+  h->g_energy = h->rec_energy;
+  return MBE3_OK;
+}
+
+int mbe3_graph_launch(mbe3_handle *h, double *e_total) {
+  if (!h) return MBE3_EINVAL;
+  if (h->recording) return h->fail(MBE3_EINVAL, "still recording");
+  if (h->segs.empty()) return h->fail(MBE3_EINVAL, "no recorded graph");
+  for (auto &sg : h->segs) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (h->timing && sg.phase >= 0 && (a = next_event(h)))
+      HIP_TRY(h, hipEventRecord(a, h->stream));
+    HIP_TRY(h, hipGraphLaunch(sg.x, h->stream));
+    if (a && (b = next_event(h))) {
+      HIP_TRY(h, hipEventRecord(b, h->stream));
+      h->regions.push_back({sg.phase, a, b});
+    }
+  }
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (h->g_solve) {
+    h->grad_ready = false;
+    const int rc = solve_status(h);
+    if (rc) return rc;
+    h->grad_ready = h->g_grad;
+  }
+  if (h->g_energy && e_total) {
+    *e_total = h->h_e3[0];
+    if (!std::isfinite(*e_total))
+      return h->fail(MBE3_ENONFINITE, "MBE(3) energy is not finite");
+  }
   return MBE3_OK;
 }
 
