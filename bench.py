@@ -206,6 +206,22 @@ def cpu_baseline(prob, budget_workers):
                                    dEdB_assembly=TD))
 
 
+def tune_choices(report):
+    """{list name: {"chosen": shape, "ms": {shape: ms per launch}}} from
+    mbe3_tune_report's lines."""
+    out = {}
+    for ln in report.splitlines():
+        if "->" not in ln:
+            continue
+        head, tail = ln.split(":", 1)
+        name = head.split(" ", 1)[1].rsplit(" (", 1)[0]
+        times, choice = tail.split("->")
+        tok = times.split()
+        ms = {tok[k]: float(tok[k + 1]) for k in range(0, len(tok) - 2, 3)}
+        out[name] = {"chosen": choice.split("(")[0].strip(), "ms": ms}
+    return out
+
+
 def timed_replays(h, args, label):
     """Warm-up and timed replays of the handle's recorded graph; returns
     (ms per step, last energy, per-phase timing of the timed replays)."""
@@ -230,6 +246,8 @@ def mixed_run(m, prob, args, dev, E64, e64, h64):
     in the split-precision form (MBE3_MIXED_BF16); energy deviations against
     the FP64 run of this process."""
     h = m.from_problem(prob, device=str(dev), precision=m.MBE3_MIXED_BF16)
+    h.forward(grad=True)  # plans the gradient lists (outputs discarded)
+    h.autotune(reps=2)
     h.set_timing(True)
     bufs = h.capture_step(grad=True)
     ms, E, ph = timed_replays(h, args, "mixed")
@@ -326,11 +344,21 @@ def main():
         return E
 
     # the step run call by call: plans the gradient workspace, and is the
-    # reference the recorded step must reproduce bit for bit
+    # reference the tuned and the recorded steps must reproduce bit for bit
     E_eager = step()
     torch.cuda.synchronize()
     e_eager = e.clone()
     log(f"bench: eager step E={E_eager:.12f}")
+    t0 = time.perf_counter()
+    report = h.autotune(reps=2)
+    t_tune = time.perf_counter() - t0
+    tuned = tune_choices(report)
+    log(f"bench: autotune {t_tune:.1f} s: " +
+        ", ".join(f"{k} {v['chosen']}" for k, v in tuned.items()))
+    E_t = step()
+    torch.cuda.synchronize()
+    if E_t != E_eager or not torch.equal(e, e_eager):
+        raise SystemExit(f"bench: tuned step differs from the planned one ({E_t!r} vs {E_eager!r})")
 
     # timed region: replays of the whole step recorded as one HIP graph, with
     # the phase events (HIP events on the library's stream) inside it
@@ -432,6 +460,7 @@ def main():
                    "grad_norm_dB": gnorm,
                    "iters_hist": np.bincount(np.maximum(iters, 0)).tolist()},
         "call_by_call_ms_per_step": round(ms_eager, 3),
+        "autotune": {"seconds": round(t_tune, 2), "gemm_tiles": tuned},
         "forward_only": {"ms_per_step": round(ms_fwd, 3),
                          "fragments_per_s": round(prob.n_frag / (ms_fwd / 1e3), 2),
                          "E_total": E_f},

@@ -304,6 +304,35 @@ int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
  * contains fragment_solve with W, mbe3_backward may use dE/df.  Nothing is
  * allocated per replay.
  */
+/*
+ * Tile shapes of the grouped FP64 GEMMs (the batched products of
+ * Algorithms 5 and 6 and of the gradient): each task list of the handle has
+ * one shape, BM x BN of the output per workgroup, from
+ *   0: 64x64, 1: 128x128, 2: 32x32, 3: 32x128, 4: 64x128.
+ * Every shape accumulates each output element over k in the same order, so
+ * the results are bitwise the same whichever shape runs.
+ *
+ * mbe3_autotune times every shape on every task list of the handle (its
+ * own tasks and sizes: `reps` timed launches after one warm-up, HIP events
+ * on h's stream) and keeps the fastest per list.  gamma, K (device, the
+ * layout's sizes) and dB (device, n_occ*n_vir*n_aux doubles, or NULL to
+ * leave the un-projection list as planned) serve as the products' operands
+ * and outputs: their contents are undefined afterwards, as are the handle's
+ * intermediate results (the next fragment_solve recomputes them).  The
+ * gradient lists are included once gradients are planned (fragment_solve
+ * with W, or mbe3_graph_begin with with_grad).  Synchronises; releases a
+ * recorded graph.  mbe3_tune_report returns one line per list: index, name,
+ * task count, the time of each shape and the choice.
+ *
+ * mbe3_set_gemm_shape sets the shape of list `list` (its index in the
+ * report; -1: all lists) without timing, and re-checks every task against
+ * its buffers.  Synchronises; releases a recorded graph.
+ */
+int mbe3_autotune(mbe3_handle *h, double *gamma, int64_t gamma_elems, double *K,
+                  int64_t k_elems, double *dB, int64_t dB_elems, int reps);
+int mbe3_set_gemm_shape(mbe3_handle *h, int list, int shape);
+const char *mbe3_tune_report(const mbe3_handle *h);
+
 int mbe3_graph_begin(mbe3_handle *h, int with_grad);
 int mbe3_graph_end(mbe3_handle *h);
 int mbe3_graph_launch(mbe3_handle *h, double *e_total);

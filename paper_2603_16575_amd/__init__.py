@@ -186,6 +186,34 @@ class Mbe3:
         _lib.check(_lib.load().mbe3_get_timing(self._h, _lib.ptr(ms), _lib.ptr(n)), self._h)
         return {ph: (float(ms[k]), int(n[k])) for k, ph in enumerate(_lib.PHASES)}
 
+    # ---- tile shapes of the grouped GEMMs ----
+    def autotune(self, reps=3, dB=True):
+        """Time every GEMM tile shape on every task list of this handle and
+        keep the fastest; returns the report (one line per list).  Uses
+        scratch gamma / K / dB buffers of the layout's sizes."""
+        import torch
+        gamma, K = self.empty_gamma(), self.empty_K()
+        gamma.zero_()
+        K.zero_()
+        d = None
+        if dB:
+            d = torch.zeros((self.n_occ, self.n_vir, self.n_aux), dtype=torch.float64,
+                            device=self.device)
+        torch.cuda.synchronize(self.device)
+        lib = _lib.load()
+        _lib.check(lib.mbe3_autotune(self._h, _lib.ptr(gamma), gamma.numel(),
+                                     _lib.ptr(K), K.numel(), _lib.ptr(d),
+                                     0 if d is None else d.numel(), int(reps)), self._h)
+        return lib.mbe3_tune_report(self._h).decode()
+
+    def set_gemm_shape(self, shape, list_index=-1):
+        """Force one tile shape (index into _lib.GEMM_SHAPES, or its name)
+        on one task list or (-1) on all."""
+        if isinstance(shape, str):
+            shape = _lib.GEMM_SHAPES.index(shape)
+        _lib.check(_lib.load().mbe3_set_gemm_shape(self._h, int(list_index), int(shape)),
+                   self._h)
+
     # ---- recorded launches (one HIP graph per handle) ----
     def graph_begin(self, with_grad=False):
         _lib.check(_lib.load().mbe3_graph_begin(self._h, int(bool(with_grad))), self._h)

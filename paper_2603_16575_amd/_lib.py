@@ -30,8 +30,10 @@ EXPORTS = [
     "osv_project", "pair_K", "fragment_solve", "mbe3_energy",
     "mbe3_pair_basis", "mbe3_plan_check", "mbe3_set_timing",
     "mbe3_get_timing", "mbe3_backward", "mbe3_graph_begin", "mbe3_graph_end",
-    "mbe3_graph_launch",
+    "mbe3_graph_launch", "mbe3_autotune", "mbe3_set_gemm_shape",
+    "mbe3_tune_report",
 ]
+GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128"]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
           "energy", "grad", "backward"]
 
@@ -98,6 +100,8 @@ def load():
         "mbe3_graph_begin": [vp, ctypes.c_int],
         "mbe3_graph_end": [vp],
         "mbe3_graph_launch": [vp, vp],
+        "mbe3_autotune": [vp, vp, i64, vp, i64, vp, i64, ctypes.c_int],
+        "mbe3_set_gemm_shape": [vp, ctypes.c_int, ctypes.c_int],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -105,6 +109,8 @@ def load():
         fn.restype = ctypes.c_int
     lib.mbe3_last_error.argtypes = [vp]
     lib.mbe3_last_error.restype = ctypes.c_char_p
+    lib.mbe3_tune_report.argtypes = [vp]
+    lib.mbe3_tune_report.restype = ctypes.c_char_p
     _lib = lib
     return lib
 

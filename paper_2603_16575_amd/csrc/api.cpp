@@ -41,9 +41,7 @@ static_assert(B_COUNT <= NBASE, "too many GEMM bases");
 
 struct Chunk {
   std::vector<int> frag_ids;  // fragment indices (heavy first)
-  GemmTask *d_m = nullptr, *d_s1 = nullptr, *d_s2 = nullptr;
-  int n_gemm = 0;
-  int64_t tiles_m = 0, tiles_s1 = 0, tiles_s2 = 0;
+  int L_m = -1, L_s1 = -1, L_s2 = -1;  // cross S~ GEMM lists (glists)
   AssembleTask *d_asm = nullptr;
   int n_asm = 0;
   FragDesc *d_frags = nullptr;
@@ -60,6 +58,19 @@ struct Chunk {
   GDest *d_gd = nullptr;
   GEntry *d_ge = nullptr;
   int n_gd = 0;
+};
+
+// One grouped-GEMM task list: its tasks (tile fields for `shape`), the
+// device copy, and the row-gather table its tasks index (0: the plan's,
+// 1: the gradient's).  The shape is the planner's default until
+// mbe3_autotune measures the alternatives.
+struct GemmList {
+  std::string name;
+  std::vector<GemmTask> host;
+  GemmTask *d = nullptr;
+  int64_t tiles = 0;
+  GemmShape shape = GEMM_64x64;
+  int rows_table = 0;
 };
 
 }  // namespace
@@ -124,26 +135,16 @@ struct mbe3_handle {
 
   // ---- plans ----
   std::vector<std::pair<int, int>> proj_batches;  // [i0, i1)
-  std::vector<GemmTask *> d_proj;
-  std::vector<int> n_proj;
-  std::vector<int64_t> t_proj;
-  GemmTask *d_pk = nullptr;
-  int n_pk = 0;
-  int64_t t_pk = 0;
-  GemmTask *d_sf = nullptr;
-  int n_sf = 0;
-  int64_t t_sf = 0;
+  std::vector<GemmList> glists;  // every GEMM task list of the handle
+  std::vector<int> L_proj;       // indices into glists (-1: none)
+  int L_pk = -1, L_sf = -1;
   AssembleTask *d_asm_pair = nullptr;
   int n_asm_pair = 0;
   EigTask *d_eig0 = nullptr, *d_eig1 = nullptr;
-  GemmTask *d_g_m1 = nullptr, *d_g_fp = nullptr, *d_g_x = nullptr,
-           *d_g_m2 = nullptr, *d_g_kt = nullptr;
-  int64_t t_m1 = 0, t_fp = 0, t_x = 0, t_m2 = 0, t_kt = 0;
+  int L_m1 = -1, L_fp = -1, L_x = -1, L_m2 = -1, L_kt = -1;
   AssembleTask *d_asm_st = nullptr;
   int n_asm_st = 0;
-  GemmTask *d_g_stm = nullptr, *d_g_st1 = nullptr, *d_g_st2 = nullptr;
-  int n_g_st = 0;
-  int64_t t_stm = 0, t_st1 = 0, t_st2 = 0;
+  int L_stm = -1, L_st1 = -1, L_st2 = -1;
   std::vector<Chunk> chunks;
   int64_t gamma_rows = 0;
   int64_t k_elems = 0;
@@ -168,10 +169,8 @@ struct mbe3_handle {
   double *ga = nullptr, *dg = nullptr;
   double *dot_part = nullptr, *d_probe = nullptr, *h_probe = nullptr;
   int64_t yfin_max = 1, gterm_max = 1, gdiag_max = 1, ga_total = 1;
-  GemmTask *d_g_wm = nullptr, *d_g_ww = nullptr, *d_g_dg = nullptr,
-           *d_g_up = nullptr;
-  int64_t t_wm = 0, t_ww = 0, t_dg = 0, t_up = 0;
-  int n_dg = 0;
+  int L_wm = -1, L_ww = -1, L_dg = -1, L_up = -1;
+  std::vector<int32_t> h_grows;  // host copy of d_grows, for the bounds check
   GASeg *d_ga = nullptr;
   int n_ga = 0;
   int32_t *d_grows = nullptr;
@@ -201,7 +200,7 @@ struct mbe3_handle {
   bool dry = false;  // plan only: no device allocation or copies
   int64_t at_total = 0, mt_total = 0, st0_total = 0;
   int64_t max_ca = 1, max_cm = 1, max_st1 = 1, n_rows = 0;
-  std::vector<std::pair<std::string, std::vector<GemmTask>>> h_gemm;
+  std::string tune_report;  // last mbe3_autotune, one line per list
   std::vector<std::pair<std::array<int64_t, 2>, std::vector<AssembleTask>>> h_asm;
   std::vector<std::pair<int, std::vector<EigTask>>> h_eig;
   std::vector<std::vector<FragDesc>> h_fds;
@@ -339,13 +338,36 @@ int upload(mbe3_handle *h, T **dst, const std::vector<T> &v) {
 // Finalise a task list: tile prefix sums for the given shape.
 int64_t finish_tasks(std::vector<GemmTask> &ts, GemmShape shape) {
   int64_t acc = 0;
-  const int b = shape == GEMM_128x128 ? 128 : 64;
+  const int bn = gemm_tile_n(shape);
   for (auto &t : ts) {
-    t.tiles_n = (t.N + b - 1) / b;
+    t.tiles_n = (t.N + bn - 1) / bn;
     t.tile_begin = acc;
     acc += gemm_tile_count(t, shape);
   }
   return acc;
+}
+
+// Register a task list (tiled for `shape`) with its device copy; *idx gets
+// its index in h->glists.
+int add_list(mbe3_handle *h, const std::string &name, std::vector<GemmTask> &ts,
+             GemmShape shape, int rows_table, int *idx) {
+  GemmList L;
+  L.name = name;
+  L.shape = shape;
+  L.rows_table = rows_table;
+  L.tiles = finish_tasks(ts, shape);
+  L.host = ts;
+  const int rc = upload(h, &L.d, ts);
+  if (rc) return rc;
+  *idx = (int)h->glists.size();
+  h->glists.push_back(std::move(L));
+  return MBE3_OK;
+}
+
+hipError_t launch_list(mbe3_handle *h, int idx, const GemmBases &b, hipStream_t s) {
+  if (idx < 0) return hipSuccess;
+  const GemmList &L = h->glists[idx];
+  return launch_gemm_tasks(L.d, (int)L.host.size(), L.tiles, b, L.shape, s);
 }
 
 GemmTask gemm(int a_buf, int64_t a_off, int lda, int transA, int b_buf,
@@ -591,12 +613,13 @@ int build_plans(mbe3_handle *h) {
         for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->q_off[x] + mu));
       ts.push_back(t);
     }
-    h->t_proj.push_back(finish_tasks(ts, GEMM_128x128));
-    h->n_proj.push_back((int)ts.size());
-    GemmTask *d = nullptr;
-    h->h_gemm.push_back({"project", ts});
-    if ((rc = upload(h, &d, ts))) return rc;
-    h->d_proj.push_back(d);
+    if (!mixed) {  // the split-precision form has its own task lists
+      int li = -1;
+      if ((rc = add_list(h, "project " + std::to_string(h->L_proj.size()), ts,
+                         GEMM_128x128, 0, &li)))
+        return rc;
+      h->L_proj.push_back(li);
+    }
   }
 
   // ---- pair K: K_s = L R^T with gathered rows of gamma ----
@@ -614,10 +637,7 @@ int build_plans(mbe3_handle *h) {
         for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
       ts.push_back(t);
     }
-    h->t_pk = finish_tasks(ts, GEMM_64x64);
-    h->n_pk = (int)ts.size();
-    h->h_gemm.push_back({"pair_K", ts});
-    if ((rc = upload(h, &h->d_pk, ts))) return rc;
+    if (!mixed && (rc = add_list(h, "pair_K", ts, GEMM_64x64, 0, &h->L_pk))) return rc;
   }
   h->n_rows = (int64_t)rows.size();
   h->h_rows = rows;
@@ -698,10 +718,7 @@ int build_plans(mbe3_handle *h) {
           ts.push_back(gemm(B_Q, h->q_off[x] * nv, nv, 0, B_EQ, h->q_off[y] * nv, nv, 1,
                             B_FS, off, h->r[y], h->r[x], h->r[y], nv));
         }
-    h->t_sf = finish_tasks(ts, GEMM_64x64);
-    h->n_sf = (int)ts.size();
-    h->h_gemm.push_back({"S/F blocks", ts});
-    if ((rc = upload(h, &h->d_sf, ts))) return rc;
+    if ((rc = add_list(h, "S/F blocks", ts, GEMM_64x64, 0, &h->L_sf))) return rc;
   }
 
   // ---- pair 4-block S, F (k layout) and the basis pipeline ----
@@ -740,24 +757,14 @@ int build_plans(mbe3_handle *h) {
     if ((rc = upload(h, &h->d_asm_pair, as))) return rc;
     if ((rc = upload(h, &h->d_eig0, e0))) return rc;
     if ((rc = upload(h, &h->d_eig1, e1))) return rc;
-    h->t_m1 = finish_tasks(m1, GEMM_64x64);
-    h->t_fp = finish_tasks(fpt, GEMM_64x64);
-    h->t_x = finish_tasks(xt, GEMM_64x64);
-    h->t_m2 = finish_tasks(m2, GEMM_64x64);
-    h->t_kt = finish_tasks(ktt, GEMM_64x64);
-    h->h_gemm.push_back({"M1", m1});
-    h->h_gemm.push_back({"F'", fpt});
-    h->h_gemm.push_back({"X", xt});
-    h->h_gemm.push_back({"M2", m2});
-    h->h_gemm.push_back({"K~", ktt});
     h->h_asm.push_back({{B_PS, B_PF}, as});
     h->h_eig.push_back({0, e0});
     h->h_eig.push_back({1, e1});
-    if ((rc = upload(h, &h->d_g_m1, m1))) return rc;
-    if ((rc = upload(h, &h->d_g_fp, fpt))) return rc;
-    if ((rc = upload(h, &h->d_g_x, xt))) return rc;
-    if ((rc = upload(h, &h->d_g_m2, m2))) return rc;
-    if ((rc = upload(h, &h->d_g_kt, ktt))) return rc;
+    if ((rc = add_list(h, "M1", m1, GEMM_64x64, 0, &h->L_m1))) return rc;
+    if ((rc = add_list(h, "F'", fpt, GEMM_64x64, 0, &h->L_fp))) return rc;
+    if ((rc = add_list(h, "X", xt, GEMM_64x64, 0, &h->L_x))) return rc;
+    if ((rc = add_list(h, "M2", m2, GEMM_64x64, 0, &h->L_m2))) return rc;
+    if ((rc = add_list(h, "K~", ktt, GEMM_64x64, 0, &h->L_kt))) return rc;
   }
 
   // ---- pair-level S~ between a pair slot and its two diagonal slots ----
@@ -792,18 +799,13 @@ int build_plans(mbe3_handle *h) {
       }
     }
     h->n_asm_st = (int)as.size();
-    h->n_g_st = (int)gm.size();
-    h->t_stm = finish_tasks(gm, GEMM_64x64);
-    h->t_st1 = finish_tasks(g1, GEMM_64x64);
-    h->t_st2 = finish_tasks(g2, GEMM_64x64);
     h->h_asm.push_back({{B_AT, -1}, as});
-    h->h_gemm.push_back({"S~ M", gm});
-    h->h_gemm.push_back({"S~ tu", g1});
-    h->h_gemm.push_back({"S~ ut", g2});
     if ((rc = upload(h, &h->d_asm_st, as))) return rc;
-    if ((rc = upload(h, &h->d_g_stm, gm))) return rc;
-    if ((rc = upload(h, &h->d_g_st1, g1))) return rc;
-    if ((rc = upload(h, &h->d_g_st2, g2))) return rc;
+    if (!gm.empty()) {
+      if ((rc = add_list(h, "S~ M", gm, GEMM_64x64, 0, &h->L_stm))) return rc;
+      if ((rc = add_list(h, "S~ tu", g1, GEMM_64x64, 0, &h->L_st1))) return rc;
+      if ((rc = add_list(h, "S~ ut", g2, GEMM_64x64, 0, &h->L_st2))) return rc;
+    }
     h->at_total = at_total; h->mt_total = mt_total; h->st0_total = st0_total;
     if ((rc = dev_alloc(h, &h->at, at_total))) return rc;
     if ((rc = dev_alloc(h, &h->mt, mt_total))) return rc;
@@ -841,24 +843,18 @@ int build_plans(mbe3_handle *h) {
     cur.n_frag = (int)fds.size();
     cur.n_terms = (int)terms.size();
     cur.n_asm = (int)cas.size();
-    cur.n_gemm = (int)cgm.size();
-    cur.tiles_m = finish_tasks(cgm, GEMM_64x64);
-    cur.tiles_s1 = finish_tasks(cg1, GEMM_64x64);
-    cur.tiles_s2 = finish_tasks(cg2, GEMM_64x64);
     int rc2;
     h->h_fds.push_back(fds);
     h->h_terms.push_back(terms);
     h->h_asm.push_back({{B_CA, -1}, cas});
-    h->h_gemm.push_back({"cross M", cgm});
-    h->h_gemm.push_back({"cross tu", cg1});
-    h->h_gemm.push_back({"cross ut", cg2});
     if ((rc2 = upload(h, &cur.d_frags, fds))) return rc2;
     if ((rc2 = upload(h, &cur.d_terms, terms))) return rc2;
     if (!cas.empty()) {
+      const std::string c = " " + std::to_string(h->chunks.size());
       if ((rc2 = upload(h, &cur.d_asm, cas))) return rc2;
-      if ((rc2 = upload(h, &cur.d_m, cgm))) return rc2;
-      if ((rc2 = upload(h, &cur.d_s1, cg1))) return rc2;
-      if ((rc2 = upload(h, &cur.d_s2, cg2))) return rc2;
+      if ((rc2 = add_list(h, "cross M" + c, cgm, GEMM_64x64, 0, &cur.L_m))) return rc2;
+      if ((rc2 = add_list(h, "cross tu" + c, cg1, GEMM_64x64, 0, &cur.L_s1))) return rc2;
+      if ((rc2 = add_list(h, "cross ut" + c, cg2, GEMM_64x64, 0, &cur.L_s2))) return rc2;
     }
     max_ca = std::max(max_ca, ca_total);
     max_cm = std::max(max_cm, cm_total);
@@ -1142,7 +1138,7 @@ int prepare_bases(mbe3_handle *h) {
   GemmBases b = bases(h);
   const int64_t nq = h->q_off[h->n_occ];
   HIP_TRY(h, launch_scale_rows(h->eq, h->Q, h->eps, nq, h->n_vir, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_sf, h->n_sf, h->t_sf, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_list(h, h->L_sf, b, s));
   HIP_TRY(h, launch_assemble(h->d_asm_pair, h->n_asm_pair, h->sstore, h->fstore,
                              h->ps, h->pf, s));
   const int md = max_d(h);
@@ -1152,12 +1148,12 @@ int prepare_bases(mbe3_handle *h) {
   HIP_TRY(h, launch_jacobi(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
                            h->rank, 0, h->tau_S, h->sflag, h->eig_ws,
                            h->eig_ws_doubles, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_m1, (int)h->n_slot, h->t_m1, b, GEMM_64x64, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_fp, (int)h->n_slot, h->t_fp, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_list(h, h->L_m1, b, s));
+  HIP_TRY(h, launch_list(h, h->L_fp, b, s));
   HIP_TRY(h, launch_jacobi(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
                            h->rank, 1, h->tau_S, nullptr, h->eig_ws,
                            h->eig_ws_doubles, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_x, (int)h->n_slot, h->t_x, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_list(h, h->L_x, b, s));
   return MBE3_OK;
 }
 
@@ -1169,13 +1165,13 @@ int prepare_pairs(mbe3_handle *h, const double *K) {
   PhaseScope ps_(h, MBE3_PHASE_PAIRS);
   GemmBases b = bases(h);
   b.p[B_K] = const_cast<double *>(K);
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_m2, (int)h->n_slot, h->t_m2, b, GEMM_64x64, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_kt, (int)h->n_slot, h->t_kt, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_list(h, h->L_m2, b, s));
+  HIP_TRY(h, launch_list(h, h->L_kt, b, s));
   HIP_TRY(h, launch_assemble(h->d_asm_st, h->n_asm_st, h->sstore, h->fstore, h->at,
                              nullptr, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_stm, h->n_g_st, h->t_stm, b, GEMM_64x64, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_st1, h->n_g_st, h->t_st1, b, GEMM_64x64, s));
-  HIP_TRY(h, launch_gemm_tasks(h->d_g_st2, h->n_g_st, h->t_st2, b, GEMM_64x64, s));
+  HIP_TRY(h, launch_list(h, h->L_stm, b, s));
+  HIP_TRY(h, launch_list(h, h->L_st1, b, s));
+  HIP_TRY(h, launch_list(h, h->L_st2, b, s));
   return MBE3_OK;
 }
 
@@ -1183,7 +1179,8 @@ int prepare_pairs(mbe3_handle *h, const double *K) {
 // and the row-gather table it uses.
 int check_gemm_list(mbe3_handle *h, const std::string &name,
                     const std::vector<GemmTask> &ts, const int64_t *sz,
-                    const std::vector<int32_t> &rows, int tile) {
+                    const std::vector<int32_t> &rows, GemmShape shape) {
+  const int tm = gemm_tile_m(shape), tn = gemm_tile_n(shape);
   auto bad = [&](const std::string &what, size_t k) {
     return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
   };
@@ -1196,8 +1193,8 @@ int check_gemm_list(mbe3_handle *h, const std::string &name,
       return bad(name + " (buffer id)", k);
     if (t.M < 1 || t.N < 1 || t.K < 1) return bad(name + " (empty)", k);
     if (t.tile_begin != tb) return bad(name + " (tile prefix)", k);
-    if (t.tiles_n != (t.N + tile - 1) / tile) return bad(name + " (tiles_n)", k);
-    tb += (int64_t)((t.M + tile - 1) / tile) * t.tiles_n;
+    if (t.tiles_n != (t.N + tn - 1) / tn) return bad(name + " (tiles_n)", k);
+    tb += (int64_t)((t.M + tm - 1) / tm) * t.tiles_n;
     auto rmax = [&](int32_t off, int n, int64_t &out) {
       if (off < 0) { out = n - 1; return true; }
       if ((int64_t)off + n > n_rows) return false;
@@ -1238,7 +1235,10 @@ void base_sizes(const mbe3_handle *h, int64_t *sz) {
   const int64_t nv = h->n_vir, na = h->n_aux;
   for (int k = 0; k < B_COUNT; ++k) sz[k] = 0;
   sz[B_Q] = sz[B_EQ] = h->q_off[h->n_occ] * nv;
-  sz[B_SLAB] = (h->slab ? (int64_t)h->n_occ : (int64_t)h->slab_nb) * nv * na;
+  // the FP64 slab tile buffer exists only for regenerated slabs in FP64
+  const int64_t slabs = h->slab ? (int64_t)h->n_occ
+                                : (h->precision == MBE3_FP64 ? (int64_t)h->slab_nb : 0);
+  sz[B_SLAB] = slabs * nv * na;
   sz[B_GAMMA] = sz[B_DG] = h->gamma_rows * na;
   sz[B_K] = sz[B_PS] = sz[B_PF] = sz[B_W] = h->k_elems;
   sz[B_SS] = sz[B_FS] = h->sb_total;
@@ -1252,6 +1252,14 @@ void base_sizes(const mbe3_handle *h, int64_t *sz) {
   sz[B_ST1] = h->max_st1;
   sz[B_GA] = h->ga_total;
   sz[B_DB] = (int64_t)h->n_occ * nv * na;
+}
+
+// Bounds of registered list li (its own shape and row table).
+int check_list(mbe3_handle *h, int li, const int64_t *sz) {
+  if (li < 0) return MBE3_OK;
+  const GemmList &L = h->glists[li];
+  return check_gemm_list(h, L.name, L.host, sz, L.rows_table ? h->h_grows : h->h_rows,
+                         L.shape);
 }
 
 // Host-side bounds check of every plan against the buffers it addresses,
@@ -1313,9 +1321,8 @@ int validate_plans(mbe3_handle *h) {
   auto bad = [&](const std::string &what, size_t k) {
     return h->fail(MBE3_EINVAL, "internal plan check failed: %s task %zu", what.c_str(), k);
   };
-  for (auto &pl : h->h_gemm) {
-    const int rc = check_gemm_list(h, pl.first, pl.second, sz, h->h_rows,
-                                   pl.first == "project" ? 128 : 64);
+  for (size_t li = 0; li < h->glists.size(); ++li) {
+    const int rc = check_list(h, (int)li, sz);
     if (rc) return rc;
   }
   for (auto &pl : h->h_asm) {
@@ -1478,7 +1485,6 @@ int build_grad_plans(mbe3_handle *h) {
   h->gterm_max = tmax;
   h->gdiag_max = gmax;
 
-  std::vector<std::pair<std::string, std::vector<GemmTask>>> lists;
   // ---- W_s = X_s W~_s X_s^T ----
   {
     std::vector<GemmTask> wm, ww;
@@ -1489,12 +1495,8 @@ int build_grad_plans(mbe3_handle *h) {
       ww.push_back(gemm(B_TMP, h->x_off[s], D, 0, B_X, h->x_off[s], D, 1, B_W,
                         h->k_off[s], d, d, d, D));
     }
-    h->t_wm = finish_tasks(wm, GEMM_64x64);
-    h->t_ww = finish_tasks(ww, GEMM_64x64);
-    if ((rc = upload(h, &h->d_g_wm, wm))) return rc;
-    if ((rc = upload(h, &h->d_g_ww, ww))) return rc;
-    lists.push_back({"W left", wm});
-    lists.push_back({"W right", ww});
+    if ((rc = add_list(h, "W left", wm, GEMM_64x64, 0, &h->L_wm))) return rc;
+    if ((rc = add_list(h, "W right", ww, GEMM_64x64, 0, &h->L_ww))) return rc;
   }
   // ---- dGamma~ per destination block (i, x) ----
   std::vector<int32_t> rows;
@@ -1566,22 +1568,18 @@ int build_grad_plans(mbe3_handle *h) {
     up.push_back(t);
   }
   h->ga_total = std::max<int64_t>(1, ga_total);
-  h->t_dg = finish_tasks(dg, GEMM_64x64);
-  h->n_dg = (int)dg.size();
-  h->t_up = finish_tasks(up, GEMM_128x128);
   h->n_ga = (int)segs.size();
-  if ((rc = upload(h, &h->d_g_dg, dg))) return rc;
-  if ((rc = upload(h, &h->d_g_up, up))) return rc;
+  if ((rc = add_list(h, "dGamma", dg, GEMM_64x64, 1, &h->L_dg))) return rc;
+  if ((rc = add_list(h, "unproject", up, GEMM_128x128, 1, &h->L_up))) return rc;
   if ((rc = upload(h, &h->d_ga, segs))) return rc;
   if ((rc = upload(h, &h->d_grows, rows))) return rc;
+  h->h_grows = rows;
 
   // ---- bounds ----
   int64_t sz[B_COUNT];
   base_sizes(h, sz);
-  for (auto &pl : lists)
-    if ((rc = check_gemm_list(h, pl.first, pl.second, sz, h->h_rows, 64))) return rc;
-  if ((rc = check_gemm_list(h, "dGamma", dg, sz, rows, 64))) return rc;
-  if ((rc = check_gemm_list(h, "unproject", up, sz, rows, 128))) return rc;
+  for (int li : {h->L_wm, h->L_ww, h->L_dg, h->L_up})
+    if ((rc = check_list(h, li, sz))) return rc;
   for (size_t k = 0; k < segs.size(); ++k) {
     const GASeg &a = segs[k];
     if (a.rows < 1 || a.kseg < 1 || a.k0 + a.kseg > a.ga_ld) return bad("segment shape", k);
@@ -1674,6 +1672,8 @@ int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out) {
   if (!rc) rc = alloc_workspace(h);
   if (!rc) rc = validate_plans(h);
   if (!rc) rc = build_grad_plans(h);
+  // every tile shape mbe3_autotune may choose keeps every task in bounds
+  for (int sh = 0; sh < GEMM_NSHAPE && !rc; ++sh) rc = mbe3_set_gemm_shape(h, -1, sh);
   if (!rc && out) mbe3_get_layout(h, out);
   g_create_error = rc ? h->err : std::string("ok");
   delete h;
@@ -1765,8 +1765,7 @@ int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems) {
                                    h->seed, h->w_ia, h->w_iP, s));
     }
     PhaseScope ps_(h, MBE3_PHASE_PROJECT);
-    HIP_TRY(h, launch_gemm_tasks(h->d_proj[k], h->n_proj[k], h->t_proj[k], b,
-                                 GEMM_128x128, s));
+    HIP_TRY(h, launch_list(h, h->L_proj[k], b, s));
   }
   return MBE3_OK;
 }
@@ -1788,7 +1787,7 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems) {
   GemmBases b = bases(h);
   b.p[B_GAMMA] = const_cast<double *>(gamma);
   b.p[B_K] = K;
-  HIP_TRY(h, launch_gemm_tasks(h->d_pk, h->n_pk, h->t_pk, b, GEMM_64x64, h->stream));
+  HIP_TRY(h, launch_list(h, h->L_pk, b, h->stream));
   return MBE3_OK;
 }
 
@@ -1813,9 +1812,9 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
       PhaseScope ps_(h, MBE3_PHASE_CROSS);
       HIP_TRY(h, launch_assemble(c.d_asm, c.n_asm, h->sstore, h->fstore, h->ca,
                                  nullptr, s));
-      HIP_TRY(h, launch_gemm_tasks(c.d_m, c.n_gemm, c.tiles_m, b, GEMM_64x64, s));
-      HIP_TRY(h, launch_gemm_tasks(c.d_s1, c.n_gemm, c.tiles_s1, b, GEMM_64x64, s));
-      HIP_TRY(h, launch_gemm_tasks(c.d_s2, c.n_gemm, c.tiles_s2, b, GEMM_64x64, s));
+      HIP_TRY(h, launch_list(h, c.L_m, b, s));
+      HIP_TRY(h, launch_list(h, c.L_s1, b, s));
+      HIP_TRY(h, launch_list(h, c.L_s2, b, s));
     }
     SolveArgs a;
     std::memset(&a, 0, sizeof a);
@@ -1868,8 +1867,8 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
   if (W) {
     PhaseScope ps_(h, MBE3_PHASE_GRAD);
     b.p[B_W] = W;
-    HIP_TRY(h, launch_gemm_tasks(h->d_g_wm, (int)h->n_slot, h->t_wm, b, GEMM_64x64, s));
-    HIP_TRY(h, launch_gemm_tasks(h->d_g_ww, (int)h->n_slot, h->t_ww, b, GEMM_64x64, s));
+    HIP_TRY(h, launch_list(h, h->L_wm, b, s));
+    HIP_TRY(h, launch_list(h, h->L_ww, b, s));
   }
   HIP_TRY(h, hipMemcpyAsync(h->h_status, h->status, 2 * SOLVE_WG * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s));
@@ -1915,9 +1914,9 @@ int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
     b.p[B_DG] = dgam;
     b.p[B_DB] = out;
     HIP_TRY(h, launch_ga(h->d_ga, h->n_ga, W, dE, h->ga, s));
-    HIP_TRY(h, launch_gemm_tasks(h->d_g_dg, h->n_dg, h->t_dg, b, GEMM_64x64, s));
+    HIP_TRY(h, launch_list(h, h->L_dg, b, s));
     if (mode == MBE3_GRAD_SLAB)
-      HIP_TRY(h, launch_gemm_tasks(h->d_g_up, h->n_occ, h->t_up, b, GEMM_128x128, s));
+      HIP_TRY(h, launch_list(h, h->L_up, b, s));
     if (dEdF) HIP_TRY(h, launch_fsym(h->graw, h->n_occ, dE, dEdF, s));
     if (probe)
       HIP_TRY(h, launch_dot(dgam, gamma, h->gamma_rows * na, 1.0, h->dot_part,
@@ -2000,6 +1999,121 @@ int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank) {
   HIP_TRY(h, hipMemcpyAsync(rank, h->rank, h->n_slot * sizeof(int32_t),
                             hipMemcpyDeviceToDevice, s));
   return MBE3_OK;
+}
+
+// Retile list li for `shape` and upload its tasks (stream idle).
+static int set_list_shape(mbe3_handle *h, int li, GemmShape shape) {
+  GemmList &L = h->glists[li];
+  std::vector<GemmTask> ts = L.host;
+  const int64_t tiles = finish_tasks(ts, shape);
+  if (tiles > 0x7fffffffLL) return h->fail(MBE3_EINVAL, "%s: too many tiles for %s",
+                                            L.name.c_str(), gemm_shape_name(shape));
+  if (!ts.empty())
+    HIP_TRY(h, hipMemcpy(L.d, ts.data(), ts.size() * sizeof(GemmTask),
+                         hipMemcpyHostToDevice));
+  L.host.swap(ts);
+  L.tiles = tiles;
+  L.shape = shape;
+  return MBE3_OK;
+}
+
+int mbe3_autotune(mbe3_handle *h, double *gamma, int64_t gamma_elems, double *K,
+                  int64_t k_elems, double *dB, int64_t dB_elems, int reps) {
+  if (!h) return MBE3_EINVAL;
+  if (h->dry) return h->fail(MBE3_EINVAL, "plan-only handle");
+  if (h->recording) return h->fail(MBE3_EINVAL, "not available while recording");
+  if (!gamma || gamma_elems < h->gamma_rows * h->n_aux || !K || k_elems < h->k_elems)
+    return h->fail(MBE3_EINVAL, "gamma and K of the layout's sizes are required");
+  const int64_t nb = (int64_t)h->n_occ * h->n_vir * h->n_aux;
+  if (dB && dB_elems < nb) return h->fail(MBE3_EINVAL, "dB needs %lld doubles", (long long)nb);
+  if (reps < 1) reps = 3;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  release_graph(h);  // its launches were recorded with the old tilings
+  GemmBases b = bases(h);
+  b.p[B_GAMMA] = gamma;
+  b.p[B_K] = K;
+  b.p[B_W] = K;  // W lists: the K layout stands in for the multipliers
+  b.p[B_DB] = dB;
+  GemmBases bg = b;
+  bg.rows = h->d_grows;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  std::string rep;
+  int rc = MBE3_OK;
+  for (size_t li = 0; li < h->glists.size() && rc == MBE3_OK; ++li) {
+    GemmList &L = h->glists[li];
+    if (L.host.empty()) continue;
+    if (L.name == "unproject" && !dB) continue;
+    const GemmShape orig = L.shape;
+    GemmShape best = orig;
+    double best_ms = 1e300;
+    char line[512];
+    int pos = snprintf(line, sizeof line, "%zu %s (%zu tasks):", li, L.name.c_str(),
+                       L.host.size());
+    for (int sh = 0; sh < GEMM_NSHAPE && rc == MBE3_OK; ++sh) {
+      if ((rc = set_list_shape(h, (int)li, (GemmShape)sh))) break;
+      const GemmBases &bb = L.rows_table ? bg : b;
+      hipError_t e = launch_list(h, (int)li, bb, h->stream);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_list(h, (int)li, bb, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = h->fail(MBE3_EHIP, "autotune %s %s: %s", L.name.c_str(),
+                     gemm_shape_name((GemmShape)sh), hipGetErrorString(e));
+        break;
+      }
+      const double per = ms / reps;
+      if (pos < (int)sizeof line)
+        pos += snprintf(line + pos, sizeof line - pos, " %s %.4f ms",
+                        gemm_shape_name((GemmShape)sh), per);
+      if (per < best_ms) { best_ms = per; best = (GemmShape)sh; }
+    }
+    if (rc) break;
+    if ((rc = set_list_shape(h, (int)li, best))) break;
+    rep += std::string(line) + " -> " + gemm_shape_name(best) + " (planned " +
+           gemm_shape_name(orig) + ")\n";
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tune_report = rep;
+  return rc;
+}
+
+int mbe3_set_gemm_shape(mbe3_handle *h, int list, int shape) {
+  if (!h) return MBE3_EINVAL;
+  if (h->recording) return h->fail(MBE3_EINVAL, "not available while recording");
+  if (shape < 0 || shape >= GEMM_NSHAPE) return h->fail(MBE3_EINVAL, "unknown shape %d", shape);
+  if (list < -1 || list >= (int)h->glists.size())
+    return h->fail(MBE3_EINVAL, "list %d out of range (%zu lists)", list, h->glists.size());
+  if (!h->dry) HIP_TRY(h, hipStreamSynchronize(h->stream));
+  release_graph(h);
+  for (int li = 0; li < (int)h->glists.size(); ++li) {
+    if (list >= 0 && li != list) continue;
+    int rc;
+    if (h->dry) {
+      GemmList &L = h->glists[li];
+      L.tiles = finish_tasks(L.host, (GemmShape)shape);
+      L.shape = (GemmShape)shape;
+    } else if ((rc = set_list_shape(h, li, (GemmShape)shape))) {
+      return rc;
+    }
+  }
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  for (int li = 0; li < (int)h->glists.size(); ++li) {
+    const int rc = check_list(h, li, sz);
+    if (rc) return rc;
+  }
+  return MBE3_OK;
+}
+
+const char *mbe3_tune_report(const mbe3_handle *h) {
+  if (!h) return "";
+  return h->tune_report.c_str();
 }
 
 int mbe3_graph_begin(mbe3_handle *h, int with_grad) {

@@ -175,9 +175,36 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
     }
 }
 
+int gemm_tile_m(GemmShape shape) {
+  switch (shape) {
+    case GEMM_128x128: return 128;
+    case GEMM_32x32:
+    case GEMM_32x128: return 32;
+    default: return 64;
+  }
+}
+
+int gemm_tile_n(GemmShape shape) {
+  switch (shape) {
+    case GEMM_32x32: return 32;
+    case GEMM_64x64: return 64;
+    default: return 128;
+  }
+}
+
+const char *gemm_shape_name(GemmShape shape) {
+  switch (shape) {
+    case GEMM_64x64: return "64x64";
+    case GEMM_128x128: return "128x128";
+    case GEMM_32x32: return "32x32";
+    case GEMM_32x128: return "32x128";
+    case GEMM_64x128: return "64x128";
+    default: return "?";
+  }
+}
+
 int64_t gemm_tile_count(const GemmTask &t, GemmShape shape) {
-  const int bm = shape == GEMM_128x128 ? 128 : 64;
-  const int bn = bm;
+  const int bm = gemm_tile_m(shape), bn = gemm_tile_n(shape);
   return (int64_t)((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
 }
 
@@ -187,12 +214,29 @@ hipError_t launch_gemm_tasks(const GemmTask *d_tasks, int n_tasks,
   if (n_tasks <= 0 || n_tiles <= 0) return hipSuccess;
   if (n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)n_tiles), block(256);
-  if (shape == GEMM_128x128)
-    hipLaunchKernelGGL((gemm_tasks_kernel<128, 128>), grid, block, 0, s,
-                       d_tasks, n_tasks, bases);
-  else
-    hipLaunchKernelGGL((gemm_tasks_kernel<64, 64>), grid, block, 0, s,
-                       d_tasks, n_tasks, bases);
+  switch (shape) {
+    case GEMM_64x64:
+      hipLaunchKernelGGL((gemm_tasks_kernel<64, 64>), grid, block, 0, s, d_tasks,
+                         n_tasks, bases);
+      break;
+    case GEMM_128x128:
+      hipLaunchKernelGGL((gemm_tasks_kernel<128, 128>), grid, block, 0, s, d_tasks,
+                         n_tasks, bases);
+      break;
+    case GEMM_32x32:
+      hipLaunchKernelGGL((gemm_tasks_kernel<32, 32>), grid, block, 0, s, d_tasks,
+                         n_tasks, bases);
+      break;
+    case GEMM_32x128:
+      hipLaunchKernelGGL((gemm_tasks_kernel<32, 128>), grid, block, 0, s, d_tasks,
+                         n_tasks, bases);
+      break;
+    case GEMM_64x128:
+      hipLaunchKernelGGL((gemm_tasks_kernel<64, 128>), grid, block, 0, s, d_tasks,
+                         n_tasks, bases);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

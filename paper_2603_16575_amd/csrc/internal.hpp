@@ -34,8 +34,20 @@ struct GemmTask {
   double alpha, beta;
 };
 
-// Tile shape ids for launch_gemm_tasks.
-enum GemmShape { GEMM_64x64 = 0, GEMM_128x128 = 1 };
+// Tile shape ids for launch_gemm_tasks (BM x BN of C per workgroup).  Every
+// shape accumulates each output over k in the same order, so the results do
+// not depend on the shape.
+enum GemmShape {
+  GEMM_64x64 = 0,
+  GEMM_128x128 = 1,
+  GEMM_32x32 = 2,
+  GEMM_32x128 = 3,
+  GEMM_64x128 = 4,
+  GEMM_NSHAPE = 5
+};
+int gemm_tile_m(GemmShape shape);
+int gemm_tile_n(GemmShape shape);
+const char *gemm_shape_name(GemmShape shape);
 int64_t gemm_tile_count(const GemmTask &t, GemmShape shape);
 hipError_t launch_gemm_tasks(const GemmTask *d_tasks, int n_tasks,
                              int64_t n_tiles, const GemmBases &bases,
