@@ -1145,12 +1145,12 @@ int prepare_bases(mbe3_handle *h) {
   HIP_TRY(h, launch_cholesky(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
                              h->rank, h->sflag, h->tau_S, h->eig_ws,
                              h->eig_ws_doubles, s));
-  HIP_TRY(h, launch_jacobi(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
+  HIP_TRY(h, launch_eigh(h->d_eig0, (int)h->n_slot, md, h->ps, h->x0, h->ev0,
                            h->rank, 0, h->tau_S, h->sflag, h->eig_ws,
                            h->eig_ws_doubles, s));
   HIP_TRY(h, launch_list(h, h->L_m1, b, s));
   HIP_TRY(h, launch_list(h, h->L_fp, b, s));
-  HIP_TRY(h, launch_jacobi(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
+  HIP_TRY(h, launch_eigh(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
                            h->rank, 1, h->tau_S, nullptr, h->eig_ws,
                            h->eig_ws_doubles, s));
   HIP_TRY(h, launch_list(h, h->L_x, b, s));

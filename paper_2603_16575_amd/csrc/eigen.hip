@@ -1,18 +1,19 @@
-// Batched symmetric eigensolver for the pair preconditioner (eq. prec_eig):
-// one workgroup per pair matrix, cyclic Jacobi with the round-robin
-// (circle) ordering so that n/2 disjoint rotations run concurrently, matrix
-// and eigenvectors resident in LDS.  A round is two phases: the rotations,
-// then J^T A J applied as independent 2x2 blocks J_k1^T A_(k1,k2) J_k2 (upper
-// blocks only, mirrored) together with V <- V J.  The paper also diagonalises each pair
-// on one thread block with Jacobi; here the generalized problem is reduced by
-// canonical orthogonalisation (two Jacobi solves) instead of a Cholesky
-// factor, so rank-deficient pair overlaps are handled by dropping
-// eigenvalues <= tau.
+// Batched symmetric eigensolvers for the pair preconditioner (eq. prec_eig).
+// The generalized problem F x = e S x of a pair is reduced by canonical
+// orthogonalisation (an overlap step, then a Fock step), so rank-deficient
+// pair overlaps are handled by dropping overlap eigenvalues <= tau; the
+// paper factors the overlap by Cholesky instead, which is the first try here
+// too (cholesky_kernel), the eigen route taking over for slots it flags.
 //
-// Workspace: matrix, vectors and the small per-round arrays live in LDS when
-// they fit (n up to ~96); larger pair domains run a second launch with the
-// same code on a per-workgroup slice of global memory (L2 resident), the
-// workgroups looping over their share of the tasks.
+// Matrices whose workspace fits in LDS (order up to ~139) go to
+// tridiag_qr_kernel: one wave per matrix, Householder reduction to
+// tridiagonal form, the reflections accumulated in place, implicit QR steps
+// with the Wilkinson shift, no workgroup barriers in the iteration.  Larger
+// orders run cyclic Jacobi (jacobi_kernel) on a per-workgroup slice of global
+// memory (L2 resident), the workgroups looping over their share of the
+// tasks: the round-robin (circle) ordering lets n/2 disjoint rotations run
+// concurrently, and a round applies J^T A J as independent 2x2 blocks
+// J_k1^T A_(k1,k2) J_k2 (upper blocks only, mirrored) together with V <- V J.
 //
 // Rotation (Golub & Van Loan, sym.schur2): for a_pq != 0,
 //   tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
@@ -298,6 +299,298 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tridiagonal QR eigensolver, one wave per matrix (the default path).
+//
+// 1. Householder reduction A = Q T Q^T, T symmetric tridiagonal (Golub &
+//    Van Loan, sec. 8.3.1): step k annihilates A[k+2:, k] with
+//    H_k = I - tau_k v v^T, v = (1, v_{k+2}, ..., v_{n-1}), applied to the
+//    trailing block as A22 <- A22 - v w^T - w v^T, p = tau A22 v,
+//    w = p - (tau/2)(p.v) v.  v_{k+2..} is kept in column k.
+// 2. Q = H_0 H_1 ... H_{n-3}, accumulated from the last reflector back to the
+//    first over the same storage: the block of Q under construction
+//    (rows and columns > k) never holds a reflector still to be applied.
+// 3. Implicit symmetric QR steps with the Wilkinson shift (Golub & Van Loan,
+//    Alg. 8.3.2) on the diagonal d and subdiagonal e: the bulge is chased
+//    by Givens rotations that also rotate the columns of Q; a subdiagonal
+//    entry at or below eps (|d_k| + |d_k+1|) splits the problem, and the
+//    trailing unreduced block is iterated until its last entry splits off.
+// Every lane evaluates the scalar recurrences of steps 1-3 itself (the same
+// values in every lane, so no lane waits for another) and owns rows
+// lane, lane + 64, ... for the vector work.  The matrix lives in LDS with an
+// odd row pitch, the rows of a lane's column reads falling on distinct banks.
+// ---------------------------------------------------------------------------
+static __host__ __device__ inline int qr_pitch(int n) { return (n & 1) ? n : n + 1; }
+
+static size_t qr_smem(int n) {
+  return sizeof(double) * ((size_t)n * qr_pitch(n) + 5 * (size_t)n + 1) +
+         sizeof(int) * ((size_t)n + 1);
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// 1 / sqrt(h) for h > 0: the hardware estimate and two Newton steps.
+__device__ inline double rsqrt_nr(double h) {
+  double y = __builtin_amdgcn_rsq(h);
+  for (int it = 0; it < 2; ++it) {
+    const double t = h * y;
+    const double e = fma(-t, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+template <int RPL>
+__global__ __launch_bounds__(64) void tridiag_qr_kernel(
+    const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
+    double *__restrict__ out, double *__restrict__ evals,
+    int32_t *__restrict__ rank, int mode, double tau,
+    const int32_t *__restrict__ only_flagged, int n_lo, int n_hi) {
+  extern __shared__ double sm[];
+  const int lane = threadIdx.x;
+  for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+    const EigTask t = tasks[ti];
+    if (t.n < n_lo || t.n > n_hi) continue;  // another launch's task
+    if (only_flagged && only_flagged[t.slot] == 0) continue;
+    const int n = mode == 0 ? t.n : rank[t.slot];
+    const int D = t.D;
+    const int ld = qr_pitch(n);
+    double *const M = sm;
+    double *const dd = M + (size_t)n * ld;
+    double *const ee = dd + n;
+    double *const vv = ee + n;
+    double *const ww = vv + n;
+    double *const taus = ww + n;
+    int *const perm = reinterpret_cast<int *>(taus + n + 1);
+
+    for (int e = lane; e < n * n; e += 64) {
+      const int r = e / n, c = e - r * n;
+      M[r * ld + c] = in[t.a_off + (int64_t)r * t.lda + c];
+    }
+    __syncthreads();
+
+    // ---- 1. Householder reduction ----
+    for (int k = 0; k + 2 < n; ++k) {
+      double sig = 0.0;
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const int i = lane + 64 * j;
+        if (i >= k + 2 && i < n) {
+          const double x = M[i * ld + k];
+          sig += x * x;
+        }
+      }
+      sig = wave_sum(sig);
+      const double alpha = M[(k + 1) * ld + k];
+      double tk = 0.0, beta = alpha;
+      if (sig > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sig);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tk = (beta - alpha) / beta;
+        const double sc = 1.0 / (alpha - beta);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int i = lane + 64 * j;
+          if (i >= k + 2 && i < n) {
+            const double v = M[i * ld + k] * sc;
+            M[i * ld + k] = v;
+            vv[i] = v;
+          }
+        }
+        if (lane == 0) vv[k + 1] = 1.0;
+      }
+      if (lane == 0) {
+        ee[k] = beta;
+        taus[k] = tk;
+        dd[k] = M[k * ld + k];
+      }
+      __syncthreads();
+      if (tk != 0.0) {
+        double p[RPL];
+        double pv = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int i = lane + 64 * j;
+          p[j] = 0.0;
+          if (i >= k + 1 && i < n) {
+            double acc = 0.0;
+            for (int c = k + 1; c < n; ++c) acc += M[i * ld + c] * vv[c];
+            p[j] = tk * acc;
+            pv += p[j] * vv[i];
+          }
+        }
+        const double kk = 0.5 * tk * wave_sum(pv);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int i = lane + 64 * j;
+          if (i >= k + 1 && i < n) ww[i] = p[j] - kk * vv[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int i = lane + 64 * j;
+          if (i >= k + 1 && i < n) {
+            const double vi = vv[i], wi = ww[i];
+            for (int c = k + 1; c < n; ++c) M[i * ld + c] -= vi * ww[c] + wi * vv[c];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (lane == 0 && n >= 1) {
+      if (n >= 2) {
+        dd[n - 2] = M[(n - 2) * ld + n - 2];
+        ee[n - 2] = M[(n - 1) * ld + n - 2];
+      }
+      dd[n - 1] = M[(n - 1) * ld + n - 1];
+      ee[n - 1] = 0.0;
+    }
+    __syncthreads();
+
+    // ---- 2. Q in place, last reflector first ----
+    if (n >= 2) {
+      if (lane < 4) {
+        const int r = n - 2 + (lane >> 1), c = n - 2 + (lane & 1);
+        M[r * ld + c] = r == c ? 1.0 : 0.0;
+      }
+    } else if (n == 1 && lane == 0) {
+      M[0] = 1.0;
+    }
+    __syncthreads();
+    for (int k = n - 3; k >= 0; --k) {
+      // row and column k + 1 of the block become the unit vector
+      for (int c = k + 2 + lane; c < n; c += 64) {
+        M[(k + 1) * ld + c] = 0.0;
+        M[c * ld + k + 1] = 0.0;
+      }
+      if (lane == 0) M[(k + 1) * ld + k + 1] = 1.0;
+      __syncthreads();
+      const double tk = taus[k];
+      if (tk != 0.0) {
+        for (int c = k + 1 + lane; c < n; c += 64) {  // one column per lane
+          double u = M[(k + 1) * ld + c];
+          for (int i = k + 2; i < n; ++i) u += M[i * ld + k] * M[i * ld + c];
+          u *= tk;
+          M[(k + 1) * ld + c] -= u;
+          for (int i = k + 2; i < n; ++i) M[i * ld + c] -= M[i * ld + k] * u;
+        }
+        __syncthreads();
+      }
+    }
+    if (n >= 2) {
+      for (int c = 1 + lane; c < n; c += 64) {
+        M[c] = 0.0;
+        M[c * ld] = 0.0;
+      }
+      if (lane == 0) M[0] = 1.0;
+    }
+    __syncthreads();
+
+    // ---- 3. implicit QR steps with the Wilkinson shift ----
+    constexpr double EPS = 2.220446049250313e-16;
+    int m = n - 1;
+    int steps = 0;
+    const int max_steps = 30 * n + 30;
+    while (m > 0 && steps < max_steps) {
+      int l = m;
+      while (l > 0 && fabs(ee[l - 1]) > EPS * (fabs(dd[l - 1]) + fabs(dd[l]))) --l;
+      if (l == m) {  // d[m] has split off
+        --m;
+        continue;
+      }
+      ++steps;
+      const double dm1 = dd[m - 1], dm = dd[m], b = ee[m - 1];
+      const double del = 0.5 * (dm1 - dm);
+      const double hyp = sqrt(del * del + b * b);
+      const double mu = dm - b * b / (del + (del >= 0.0 ? hyp : -hyp));
+      double dk = dd[l], ek = ee[l];
+      double x = dk - mu, z = ek;
+      for (int k = l; k < m; ++k) {
+        const double dk1 = dd[k + 1];
+        double c = 1.0, s = 0.0, r = x;
+        const double hh = x * x + z * z;
+        if (hh > 0.0) {
+          const double ir = rsqrt_nr(hh);
+          r = hh * ir;
+          c = x * ir;
+          s = -z * ir;
+        }
+        if (k > l) ee[k - 1] = r;  // the bulge is chased down: same value in every lane
+        const double cs = c * s, c2 = c * c, s2 = s * s;
+        const double nd0 = c2 * dk - 2.0 * cs * ek + s2 * dk1;
+        const double nd1 = s2 * dk + 2.0 * cs * ek + c2 * dk1;
+        const double ne = cs * (dk - dk1) + (c2 - s2) * ek;
+        dd[k] = nd0;
+        if (k + 1 < m) {
+          const double ek1 = ee[k + 1];
+          z = -s * ek1;  // new bulge at (k + 2, k)
+          ek = c * ek1;
+          x = ne;
+          dk = nd1;
+        } else {
+          dd[k + 1] = nd1;
+          ee[k] = ne;
+        }
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int i = lane + 64 * j;
+          if (i < n) {
+            const double q0 = M[i * ld + k], q1 = M[i * ld + k + 1];
+            M[i * ld + k] = c * q0 - s * q1;
+            M[i * ld + k + 1] = s * q0 + c * q1;
+          }
+        }
+      }
+    }
+    const bool failed = m > 0;  // did not converge: reported as NaN eigenvalues
+    __syncthreads();
+
+    // ---- ascending order (ties by index) and outputs ----
+    for (int i = lane; i < n; i += 64) {
+      const double li = dd[i];
+      int r = 0;
+      for (int j = 0; j < n; ++j) {
+        const double lj = dd[j];
+        r += (lj < li) || (lj == li && j < i);
+      }
+      perm[r] = i;
+    }
+    __syncthreads();
+    const double nanv = __builtin_nan("");
+    if (mode == 0) {
+      int f = n;
+      for (int r = 0; r < n; ++r)
+        if (dd[perm[r]] > tau) { f = r; break; }
+      const int nk = n - f;
+      if (lane == 0) rank[t.slot] = nk;
+      for (int e = lane; e < n * D; e += 64) {
+        const int r = e / D, c = e - r * D;
+        double v = 0.0;
+        if (c < nk) {
+          const int src = perm[f + c];
+          v = M[r * ld + src] / sqrt(dd[src]);
+        }
+        out[t.o_off + (int64_t)r * D + c] = v;
+      }
+      for (int c = lane; c < D; c += 64)
+        evals[t.e_off + c] = c < nk ? (failed ? nanv : dd[perm[f + c]]) : EV_SENTINEL;
+    } else {
+      for (int e = lane; e < D * D; e += 64) {
+        const int r = e / D, c = e - r * D;
+        double v = 0.0;
+        if (r < n && c < n) v = M[r * ld + perm[c]];
+        out[t.o_off + (int64_t)r * D + c] = v;
+      }
+      for (int c = lane; c < D; c += 64)
+        evals[t.e_off + c] = c < n ? (failed ? nanv : dd[perm[c]]) : EV_SENTINEL;
+    }
+    __syncthreads();  // the workspace is reused by the next task
+  }
+}
+
 static size_t cholesky_smem(int n) { return sizeof(double) * (size_t)2 * n * (n + 1); }
 
 static size_t jacobi_smem(int n) {
@@ -355,24 +648,51 @@ hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
                       });
 }
 
-hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
-                         const double *in, double *out, double *evals,
-                         int32_t *rank, int mode, double tau,
-                         const int32_t *only_flagged, double *gws,
-                         int64_t gws_doubles, hipStream_t s) {
+template <int RPL>
+static hipError_t launch_qr(const EigTask *d_tasks, int n_tasks, int lo, int hi,
+                            const double *in, double *out, double *evals,
+                            int32_t *rank, int mode, double tau,
+                            const int32_t *only_flagged, hipStream_t s) {
+  const size_t smem = qr_smem(hi);
+  hipError_t e = hipFuncSetAttribute((const void *)tridiag_qr_kernel<RPL>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((tridiag_qr_kernel<RPL>), dim3(n_tasks), dim3(64), smem, s, d_tasks,
+                     n_tasks, in, out, evals, rank, mode, tau, only_flagged, lo, hi);
+  return hipGetLastError();
+}
+
+int eig_qr_max_order() { return std::min(lds_order(qr_smem), 192); }
+
+hipError_t launch_eigh(const EigTask *d_tasks, int n_tasks, int max_n,
+                       const double *in, double *out, double *evals, int32_t *rank,
+                       int mode, double tau, const int32_t *only_flagged, double *gws,
+                       int64_t gws_doubles, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
-  return two_launches(n_tasks, max_n, jacobi_smem, gws, gws_doubles,
-                      [&](int grid, int lo, int hi, double *ws, int64_t stride,
-                          size_t smem) -> hipError_t {
-                        hipError_t e = hipFuncSetAttribute(
-                            (const void *)jacobi_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-                        if (e != hipSuccess) return e;
-                        hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), smem, s,
-                                           d_tasks, n_tasks, in, out, evals, rank, mode,
-                                           tau, only_flagged, lo, hi, ws, stride);
-                        return hipGetLastError();
-                      });
+  // orders up to the LDS limit: one wave per matrix, in ranges of 64 rows
+  // so that each launch reserves the LDS of its own largest order
+  const int nq = eig_qr_max_order();
+  hipError_t e = hipSuccess;
+  for (int lo = 1; lo <= std::min(max_n, nq) && e == hipSuccess; lo += 64) {
+    const int hi = std::min(std::min(max_n, nq), lo + 63);
+    if (hi <= 64)
+      e = launch_qr<1>(d_tasks, n_tasks, lo, hi, in, out, evals, rank, mode, tau,
+                       only_flagged, s);
+    else if (hi <= 128)
+      e = launch_qr<2>(d_tasks, n_tasks, lo, hi, in, out, evals, rank, mode, tau,
+                       only_flagged, s);
+    else
+      e = launch_qr<3>(d_tasks, n_tasks, lo, hi, in, out, evals, rank, mode, tau,
+                       only_flagged, s);
+  }
+  if (e != hipSuccess || max_n <= nq) return e;
+  // larger orders: cyclic Jacobi on a global-memory slice per workgroup
+  const int64_t stride = eig_workspace_doubles(max_n);
+  if (!gws || gws_doubles < stride) return hipErrorInvalidValue;
+  const int grid = (int)std::min<int64_t>(n_tasks, gws_doubles / stride);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), 0, s, d_tasks, n_tasks, in, out,
+                     evals, rank, mode, tau, only_flagged, nq + 1, max_n, gws, stride);
+  return hipGetLastError();
 }
 
 }  // namespace mbe3

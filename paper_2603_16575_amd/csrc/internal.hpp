@@ -137,15 +137,17 @@ struct EigTask {
 // mode 1: Fock step.  Order = rank[slot].  Writes Z (D x D: eigenvectors in
 //         the leading rank x rank block, zero elsewhere) and eps~ ascending
 //         (sentinel 1e30 beyond rank).
-// Tasks of order above eig_lds_max_order() run on a global workspace of
+// Tasks of order above eig_qr_max_order() run on a global workspace of
 // gws_doubles (>= eig_workspace_doubles(max_n); one slice per workgroup).
-hipError_t launch_jacobi(const EigTask *d_tasks, int n_tasks, int max_n,
-                         const double *in, double *out, double *evals,
-                         int32_t *rank, int mode, double tau,
-                         const int32_t *only_flagged, double *gws,
-                         int64_t gws_doubles, hipStream_t s);
+// Orders up to eig_qr_max_order() by Householder reduction and implicit QR
+// steps, one wave per matrix in LDS; larger orders by cyclic Jacobi.
+hipError_t launch_eigh(const EigTask *d_tasks, int n_tasks, int max_n,
+                       const double *in, double *out, double *evals, int32_t *rank,
+                       int mode, double tau, const int32_t *only_flagged, double *gws,
+                       int64_t gws_doubles, hipStream_t s);
+int eig_qr_max_order();
 // Overlap step by Cholesky (X0 = L^-T, full rank).  Slots whose pivots drop
-// to <= tau get flag[slot] = 1 and are redone by launch_jacobi(mode 0,
+// to <= tau get flag[slot] = 1 and are redone by launch_eigh(mode 0,
 // only_flagged = flag).
 hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
                            const double *in, double *out, double *evals,
