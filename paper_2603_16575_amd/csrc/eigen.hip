@@ -416,9 +416,17 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
           const int i = lane + 64 * j;
           p[j] = 0.0;
           if (i >= k + 1 && i < n) {
-            double acc = 0.0;
-            for (int c = k + 1; c < n; ++c) acc += M[i * ld + c] * vv[c];
-            p[j] = tk * acc;
+            const double *row = M + i * ld;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int c = k + 1;
+            for (; c + 3 < n; c += 4) {  // four chains keep loads in flight
+              a0 += row[c] * vv[c];
+              a1 += row[c + 1] * vv[c + 1];
+              a2 += row[c + 2] * vv[c + 2];
+              a3 += row[c + 3] * vv[c + 3];
+            }
+            for (; c < n; ++c) a0 += row[c] * vv[c];
+            p[j] = tk * ((a0 + a1) + (a2 + a3));
             pv += p[j] * vv[i];
           }
         }
@@ -434,7 +442,9 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
           const int i = lane + 64 * j;
           if (i >= k + 1 && i < n) {
             const double vi = vv[i], wi = ww[i];
-            for (int c = k + 1; c < n; ++c) M[i * ld + c] -= vi * ww[c] + wi * vv[c];
+            double *row = M + i * ld;
+#pragma unroll 4
+            for (int c = k + 1; c < n; ++c) row[c] -= vi * ww[c] + wi * vv[c];
           }
         }
         __syncthreads();
@@ -471,11 +481,19 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
       const double tk = taus[k];
       if (tk != 0.0) {
         for (int c = k + 1 + lane; c < n; c += 64) {  // one column per lane
-          double u = M[(k + 1) * ld + c];
-          for (int i = k + 2; i < n; ++i) u += M[i * ld + k] * M[i * ld + c];
-          u *= tk;
+          double u0 = M[(k + 1) * ld + c], u1 = 0.0, u2 = 0.0, u3 = 0.0;
+          int i = k + 2;
+          for (; i + 3 < n; i += 4) {
+            u0 += M[i * ld + k] * M[i * ld + c];
+            u1 += M[(i + 1) * ld + k] * M[(i + 1) * ld + c];
+            u2 += M[(i + 2) * ld + k] * M[(i + 2) * ld + c];
+            u3 += M[(i + 3) * ld + k] * M[(i + 3) * ld + c];
+          }
+          for (; i < n; ++i) u0 += M[i * ld + k] * M[i * ld + c];
+          const double u = tk * ((u0 + u1) + (u2 + u3));
           M[(k + 1) * ld + c] -= u;
-          for (int i = k + 2; i < n; ++i) M[i * ld + c] -= M[i * ld + k] * u;
+#pragma unroll 4
+          for (int i2 = k + 2; i2 < n; ++i2) M[i2 * ld + c] -= M[i2 * ld + k] * u;
         }
         __syncthreads();
       }
@@ -495,8 +513,17 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
     int steps = 0;
     const int max_steps = 30 * n + 30;
     while (m > 0 && steps < max_steps) {
-      int l = m;
-      while (l > 0 && fabs(ee[l - 1]) > EPS * (fabs(dd[l - 1]) + fabs(dd[l]))) --l;
+      // l = 1 + the largest k < m with a negligible e[k] (0 if none): one
+      // ballot over the lanes per 64 entries
+      int l = 0;
+#pragma unroll
+      for (int j = RPL - 1; j >= 0; --j) {
+        const int k = lane + 64 * j;
+        const bool neg =
+            k < m && fabs(ee[k]) <= EPS * (fabs(dd[k]) + fabs(dd[k + 1]));
+        const unsigned long long b = __ballot(neg);
+        if (l == 0 && b != 0ULL) l = 64 * j + 64 - __clzll((long long)b);
+      }
       if (l == m) {  // d[m] has split off
         --m;
         continue;
@@ -506,10 +533,28 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
       const double del = 0.5 * (dm1 - dm);
       const double hyp = sqrt(del * del + b * b);
       const double mu = dm - b * b / (del + (del >= 0.0 ? hyp : -hyp));
+      // d[k], e[k], d[k+1], e[k+1] and columns k, k+1 of Q travel in
+      // registers; the next rotation's operands are loaded one step ahead
       double dk = dd[l], ek = ee[l];
+      double dk1 = dd[l + 1];
+      double ek1 = l + 1 < m ? ee[l + 1] : 0.0;
       double x = dk - mu, z = ek;
+      double qc[RPL], qn[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const int i = lane + 64 * j;
+        qc[j] = i < n ? M[i * ld + l] : 0.0;
+        qn[j] = i < n ? M[i * ld + l + 1] : 0.0;
+      }
       for (int k = l; k < m; ++k) {
-        const double dk1 = dd[k + 1];
+        const double dk2 = k + 2 <= m ? dd[k + 2] : 0.0;
+        const double ek2 = k + 2 < m ? ee[k + 2] : 0.0;
+        double qnn[RPL];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          const int i = lane + 64 * j;
+          qnn[j] = (k + 2 <= m && i < n) ? M[i * ld + k + 2] : 0.0;
+        }
         double c = 1.0, s = 0.0, r = x;
         const double hh = x * x + z * z;
         if (hh > 0.0) {
@@ -524,25 +569,30 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
         const double nd1 = s2 * dk + 2.0 * cs * ek + c2 * dk1;
         const double ne = cs * (dk - dk1) + (c2 - s2) * ek;
         dd[k] = nd0;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {  // column k is final, k + 1 carried
+          const int i = lane + 64 * j;
+          const double q0 = qc[j], q1 = qn[j];
+          if (i < n) M[i * ld + k] = c * q0 - s * q1;
+          qc[j] = s * q0 + c * q1;
+          qn[j] = qnn[j];
+        }
         if (k + 1 < m) {
-          const double ek1 = ee[k + 1];
           z = -s * ek1;  // new bulge at (k + 2, k)
           ek = c * ek1;
           x = ne;
           dk = nd1;
+          dk1 = dk2;
+          ek1 = ek2;
         } else {
           dd[k + 1] = nd1;
           ee[k] = ne;
         }
+      }
 #pragma unroll
-        for (int j = 0; j < RPL; ++j) {
-          const int i = lane + 64 * j;
-          if (i < n) {
-            const double q0 = M[i * ld + k], q1 = M[i * ld + k + 1];
-            M[i * ld + k] = c * q0 - s * q1;
-            M[i * ld + k + 1] = s * q0 + c * q1;
-          }
-        }
+      for (int j = 0; j < RPL; ++j) {
+        const int i = lane + 64 * j;
+        if (i < n) M[i * ld + m] = qc[j];
       }
     }
     const bool failed = m > 0;  // did not converge: reported as NaN eigenvalues
