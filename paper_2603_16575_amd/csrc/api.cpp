@@ -1448,14 +1448,29 @@ int build_grad_plans(mbe3_handle *h) {
     std::vector<WSlot> ws;
     std::vector<WEntry> we;
     for (auto &kv : bs) {
-      WSlot w;
-      std::memset(&w, 0, sizeof w);
-      w.wt_off = h->kt_off[kv.first];
-      w.D = h->sD[kv.first];
-      w.e_begin = (int32_t)we.size();
+      // a slot found in many fragments is split over several work items by
+      // element range (about 32 entries' worth of reads per 256 elements)
+      const int D = h->sD[kv.first];
+      const int nel = D * D;
+      const int ne = (int)kv.second.size();
+      const int pieces = std::max(1, std::min((ne + 31) / 32, (nel + 255) / 256));
+      const int span = ((nel + pieces - 1) / pieces + 63) / 64 * 64;
+      const int32_t eb = (int32_t)we.size();
       we.insert(we.end(), kv.second.begin(), kv.second.end());
-      w.e_end = (int32_t)we.size();
-      ws.push_back(w);
+      for (int y0 = 0; y0 < nel; y0 += span) {
+        WSlot w;
+        std::memset(&w, 0, sizeof w);
+        w.wt_off = h->kt_off[kv.first] + y0;
+        w.y0 = y0;
+        w.n = std::min(span, nel - y0);
+        w.e_begin = eb;
+        w.e_end = (int32_t)we.size();
+        ws.push_back(w);
+      }
+      // bounds: W~ block of the slot, each entry's Y~ block in the store
+      if (h->kt_off[kv.first] + nel > h->kt_off[h->n_slot]) return bad("W~ slot", kv.first);
+      for (const WEntry &e : kv.second)
+        if (e.yoff < 0 || e.yoff + nel > ch.ny_total) return bad("W~ entry", kv.first);
     }
     std::vector<GDest> gd;
     std::vector<GEntry> ge;

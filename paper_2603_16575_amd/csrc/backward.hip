@@ -15,17 +15,55 @@
 namespace mbe3 {
 
 // W~_slot += sum_entries c Y~ (Y~ = 2Y - Y^T stored by the solver), one
-// workgroup per slot; entries in fragment order.
+// workgroup per work item (an element range of a slot); every element sums
+// its entries in fragment order.  A thread keeps WT_J elements in registers
+// and reads WT_U entries ahead before adding them in order, so that each
+// round trip to memory carries WT_U * WT_J independent loads.
+constexpr int WT_J = 2, WT_U = 8;
 __global__ __launch_bounds__(256) void wtilde_kernel(
     const WSlot *__restrict__ slots, const WEntry *__restrict__ ents,
     const double *__restrict__ yfin, double *__restrict__ wt) {
   const WSlot sl = slots[blockIdx.x];
-  const int n = sl.D * sl.D;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    double acc = wt[sl.wt_off + e];
-    for (int k = sl.e_begin; k < sl.e_end; ++k)
-      acc += ents[k].coef * yfin[ents[k].yoff + e];
-    wt[sl.wt_off + e] = acc;
+  for (int base = 0; base < sl.n; base += 256 * WT_J) {
+    double acc[WT_J];
+#pragma unroll
+    for (int j = 0; j < WT_J; ++j) {
+      const int e = base + (int)threadIdx.x + 256 * j;
+      acc[j] = e < sl.n ? wt[sl.wt_off + e] : 0.0;
+    }
+    int k = sl.e_begin;
+    for (; k + WT_U <= sl.e_end; k += WT_U) {
+      double c[WT_U], y[WT_U][WT_J];
+#pragma unroll
+      for (int u = 0; u < WT_U; ++u) {
+        const WEntry en = ents[k + u];
+        c[u] = en.coef;
+        const double *yp = yfin + en.yoff + sl.y0;
+#pragma unroll
+        for (int j = 0; j < WT_J; ++j) {
+          const int e = base + (int)threadIdx.x + 256 * j;
+          y[u][j] = e < sl.n ? yp[e] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < WT_U; ++u)
+#pragma unroll
+        for (int j = 0; j < WT_J; ++j) acc[j] += c[u] * y[u][j];
+    }
+    for (; k < sl.e_end; ++k) {
+      const WEntry en = ents[k];
+      const double *yp = yfin + en.yoff + sl.y0;
+#pragma unroll
+      for (int j = 0; j < WT_J; ++j) {
+        const int e = base + (int)threadIdx.x + 256 * j;
+        if (e < sl.n) acc[j] += en.coef * yp[e];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WT_J; ++j) {
+      const int e = base + (int)threadIdx.x + 256 * j;
+      if (e < sl.n) wt[sl.wt_off + e] = acc[j];
+    }
   }
 }
 

@@ -230,9 +230,12 @@ size_t solve_lds_bytes(int dmax);
 // Backward (backward.hip)
 // ---------------------------------------------------------------------------
 // W~ of one slot (D x D at wt_off) += sum of its entries [e_begin, e_end).
+// One work item of the W~ reduction: elements [y0, y0 + n) of a slot's
+// D x D block, summed over the entries [e_begin, e_end) (a slot in many
+// fragments is split over several items by element range).
 struct WSlot {
-  int64_t wt_off;
-  int32_t D, e_begin, e_end, pad_;
+  int64_t wt_off;  // W~ offset of element y0
+  int32_t n, e_begin, e_end, y0;
 };
 struct WEntry {
   int64_t yoff;  // converged Y~ = 2Y - Y^T block (D x D) in the chunk's store

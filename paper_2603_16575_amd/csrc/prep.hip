@@ -14,20 +14,26 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   double *o = (t.out_buf ? out1 : out0) + t.out_off;
   const int rtot = t.rsz[0] + (t.nrb > 1 ? t.rsz[1] : 0);
   const int ctot = t.csz[0] + (t.ncb > 1 ? t.csz[1] : 0);
-  const int n = t.rows_out * t.cols_out;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int r = e / t.cols_out, c = e - r * t.cols_out;
-    double v = 0.0;
-    if (r < rtot && c < ctot) {
-      const int rb = r < t.rsz[0] ? 0 : 1;
-      const int cb = c < t.csz[0] ? 0 : 1;
-      const int rl = rb ? r - t.rsz[0] : r;
-      const int cl = cb ? c - t.csz[0] : c;
-      const BlockSrc b = t.b[rb][cb];
-      v = b.trans ? src[b.off + (int64_t)cl * b.ld + rl]
-                  : src[b.off + (int64_t)rl * b.ld + cl];
+  const int lane = threadIdx.x & 63;
+  // one wave per output row; the source blocks are picked with constant
+  // indices (a dynamically indexed block table would live in scratch)
+  for (int r = threadIdx.x >> 6; r < t.rows_out; r += blockDim.x >> 6) {
+    const bool lower = r >= t.rsz[0];
+    const int rl = lower ? r - t.rsz[0] : r;
+    const BlockSrc bl = lower ? t.b[1][0] : t.b[0][0];
+    const BlockSrc br = lower ? t.b[1][1] : t.b[0][1];
+    for (int c = lane; c < t.cols_out; c += 64) {
+      double v = 0.0;
+      if (r < rtot && c < ctot) {
+        const bool right = c >= t.csz[0];
+        const int cl = right ? c - t.csz[0] : c;
+        const int64_t off = right ? br.off : bl.off;
+        const int64_t ld = right ? br.ld : bl.ld;
+        const bool tr = right ? br.trans : bl.trans;
+        v = tr ? src[off + cl * ld + rl] : src[off + rl * ld + cl];
+      }
+      o[(int64_t)r * t.ld_out + c] = v;
     }
-    o[(int64_t)r * t.ld_out + c] = v;
   }
 }
 
