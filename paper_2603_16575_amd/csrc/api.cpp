@@ -41,7 +41,7 @@ static_assert(B_COUNT <= NBASE, "too many GEMM bases");
 
 struct Chunk {
   std::vector<int> frag_ids;  // fragment indices (heavy first)
-  int L_m = -1, L_s1 = -1, L_s2 = -1;  // cross S~ GEMM lists (glists)
+  int L_m = -1, L_s1 = -1;  // cross S~ GEMM lists (glists)
   AssembleTask *d_asm = nullptr;
   int n_asm = 0;
   FragDesc *d_frags = nullptr;
@@ -144,7 +144,7 @@ struct mbe3_handle {
   int L_m1 = -1, L_fp = -1, L_x = -1, L_m2 = -1, L_kt = -1;
   AssembleTask *d_asm_st = nullptr;
   int n_asm_st = 0;
-  int L_stm = -1, L_st1 = -1, L_st2 = -1;
+  int L_stm = -1, L_st1 = -1;
   std::vector<Chunk> chunks;
   int64_t gamma_rows = 0;
   int64_t k_elems = 0;
@@ -382,6 +382,7 @@ GemmTask gemm(int a_buf, int64_t a_off, int lda, int transA, int b_buf,
   t.M = M; t.N = N; t.K = K;
   t.alpha = alpha; t.beta = beta;
   t.a_rows = -1; t.b_rows = -1;
+  t.ct_off = -1;
   return t;
 }
 
@@ -775,7 +776,7 @@ int build_plans(mbe3_handle *h) {
   int64_t st0_total = 0;
   {
     std::vector<AssembleTask> as;
-    std::vector<GemmTask> gm, g1, g2;
+    std::vector<GemmTask> gm, g1;
     int64_t at_total = 0, mt_total = 0;
     for (int64_t s = n; s < h->n_slot; ++s) {
       const int dt = h->sd[s], Dt = h->sD[s];
@@ -786,14 +787,15 @@ int build_plans(mbe3_handle *h) {
         as.push_back(asm_task(h, o, {u}, 0, 0, at_total, ru, dt, ru));
         gm.push_back(gemm(B_AT, at_total, ru, 0, B_X, h->x_off[u], Du, 0, B_MT,
                           mt_total, Du, dt, Du, ru));
+        // S~_(t,u) (Dt x Du) and, by the same task, its transpose S~_(u,t)
         st0_tu[2 * s + k] = st0_total;
-        g1.push_back(gemm(B_X, h->x_off[s], Dt, 1, B_MT, mt_total, Du, 0, B_ST0,
-                          st0_total, Du, Dt, Du, dt));
-        st0_total += (int64_t)Dt * Du;
-        st0_ut[2 * s + k] = st0_total;
-        g2.push_back(gemm(B_MT, mt_total, Du, 1, B_X, h->x_off[s], Dt, 0, B_ST0,
-                          st0_total, Dt, Du, Dt, dt));
-        st0_total += (int64_t)Du * Dt;
+        st0_ut[2 * s + k] = st0_total + (int64_t)Dt * Du;
+        GemmTask t1 = gemm(B_X, h->x_off[s], Dt, 1, B_MT, mt_total, Du, 0, B_ST0,
+                           st0_total, Du, Dt, Du, dt);
+        t1.ct_off = st0_ut[2 * s + k];
+        t1.ldct = Dt;
+        g1.push_back(t1);
+        st0_total += 2LL * Dt * Du;
         at_total += (int64_t)dt * ru;
         mt_total += (int64_t)dt * Du;
       }
@@ -803,8 +805,7 @@ int build_plans(mbe3_handle *h) {
     if ((rc = upload(h, &h->d_asm_st, as))) return rc;
     if (!gm.empty()) {
       if ((rc = add_list(h, "S~ M", gm, GEMM_64x64, 0, &h->L_stm))) return rc;
-      if ((rc = add_list(h, "S~ tu", g1, GEMM_64x64, 0, &h->L_st1))) return rc;
-      if ((rc = add_list(h, "S~ ut", g2, GEMM_64x64, 0, &h->L_st2))) return rc;
+      if ((rc = add_list(h, "S~", g1, GEMM_64x64, 0, &h->L_st1))) return rc;
     }
     h->at_total = at_total; h->mt_total = mt_total; h->st0_total = st0_total;
     if ((rc = dev_alloc(h, &h->at, at_total))) return rc;
@@ -835,7 +836,7 @@ int build_plans(mbe3_handle *h) {
   std::vector<FragDesc> fds;
   std::vector<Term> terms;
   std::vector<AssembleTask> cas;
-  std::vector<GemmTask> cgm, cg1, cg2;
+  std::vector<GemmTask> cgm, cg1;
   int64_t ca_total = 0, cm_total = 0, st1_total = 0;
   int64_t max_ca = 1, max_cm = 1, max_st1 = 1;
   auto flush = [&](void) -> int {
@@ -853,15 +854,14 @@ int build_plans(mbe3_handle *h) {
       const std::string c = " " + std::to_string(h->chunks.size());
       if ((rc2 = upload(h, &cur.d_asm, cas))) return rc2;
       if ((rc2 = add_list(h, "cross M" + c, cgm, GEMM_64x64, 0, &cur.L_m))) return rc2;
-      if ((rc2 = add_list(h, "cross tu" + c, cg1, GEMM_64x64, 0, &cur.L_s1))) return rc2;
-      if ((rc2 = add_list(h, "cross ut" + c, cg2, GEMM_64x64, 0, &cur.L_s2))) return rc2;
+      if ((rc2 = add_list(h, "cross" + c, cg1, GEMM_64x64, 0, &cur.L_s1))) return rc2;
     }
     max_ca = std::max(max_ca, ca_total);
     max_cm = std::max(max_cm, cm_total);
     max_st1 = std::max(max_st1, st1_total);
     h->chunks.push_back(cur);
     cur = Chunk();
-    fds.clear(); terms.clear(); cas.clear(); cgm.clear(); cg1.clear(); cg2.clear();
+    fds.clear(); terms.clear(); cas.clear(); cgm.clear(); cg1.clear();
     ca_total = cm_total = st1_total = 0;
     return MBE3_OK;
   };
@@ -927,14 +927,16 @@ int build_plans(mbe3_handle *h) {
           // M = A X_s (dt x Ds)
           cgm.push_back(gemm(B_CA, ca_total, ds, 0, B_X, h->x_off[s], Ds, 0, B_CM,
                              cm_total, Ds, dt, Ds, ds));
-          cross[a][b] = st1_total;  // S~_(t,s) = X_t^T M  (Dt x Ds)
-          cg1.push_back(gemm(B_X, h->x_off[t], Dt, 1, B_CM, cm_total, Ds, 0, B_ST1,
-                             st1_total, Ds, Dt, Ds, dt));
-          st1_total += (int64_t)Dt * Ds;
-          cross[b][a] = st1_total;  // S~_(s,t) = M^T X_t  (Ds x Dt)
-          cg2.push_back(gemm(B_CM, cm_total, Ds, 1, B_X, h->x_off[t], Dt, 0, B_ST1,
-                             st1_total, Dt, Ds, Dt, dt));
-          st1_total += (int64_t)Ds * Dt;
+          // S~_(t,s) = X_t^T M  (Dt x Ds), stored with its transpose
+          // S~_(s,t) (Ds x Dt) by the same task
+          cross[a][b] = st1_total;
+          cross[b][a] = st1_total + (int64_t)Dt * Ds;
+          GemmTask g1 = gemm(B_X, h->x_off[t], Dt, 1, B_CM, cm_total, Ds, 0, B_ST1,
+                             st1_total, Ds, Dt, Ds, dt);
+          g1.ct_off = cross[b][a];
+          g1.ldct = Dt;
+          cg1.push_back(g1);
+          st1_total += 2LL * Dt * Ds;
           ca_total += (int64_t)dt * ds;
           cm_total += (int64_t)dt * Ds;
         }
@@ -1171,7 +1173,6 @@ int prepare_pairs(mbe3_handle *h, const double *K) {
                              nullptr, s));
   HIP_TRY(h, launch_list(h, h->L_stm, b, s));
   HIP_TRY(h, launch_list(h, h->L_st1, b, s));
-  HIP_TRY(h, launch_list(h, h->L_st2, b, s));
   return MBE3_OK;
 }
 
@@ -1226,6 +1227,10 @@ int check_gemm_list(mbe3_handle *h, const std::string &name,
     if (t.a_off < 0 || amax >= sz[t.a_buf]) return bad(name + " (A bounds)", k);
     if (t.b_off < 0 || bmax >= sz[t.b_buf]) return bad(name + " (B bounds)", k);
     if (t.c_off < 0 || cmax >= sz[t.c_buf]) return bad(name + " (C bounds)", k);
+    if (t.ct_off >= 0) {
+      const int64_t ctmax = t.ct_off + (int64_t)(t.N - 1) * t.ldct + t.M - 1;
+      if (t.ldct < t.M || ctmax >= sz[t.c_buf]) return bad(name + " (C^T bounds)", k);
+    }
   }
   return MBE3_OK;
 }
@@ -1829,7 +1834,6 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
                                  nullptr, s));
       HIP_TRY(h, launch_list(h, c.L_m, b, s));
       HIP_TRY(h, launch_list(h, c.L_s1, b, s));
-      HIP_TRY(h, launch_list(h, c.L_s2, b, s));
     }
     SolveArgs a;
     std::memset(&a, 0, sizeof a);

@@ -11,7 +11,8 @@
 // index when B is not transposed, N index when it is), which lets one task
 // project a slab onto the OSVs of all neighbours of an orbital, form a
 // 4-block pair K from two scattered row blocks, or contract gradient blocks
-// of many pairs in one K-concatenated product.
+// of many pairs in one K-concatenated product.  A task may also store C^T
+// (the coupling blocks are needed in both orientations).
 #include "internal.hpp"
 
 namespace mbe3 {
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
   const double *__restrict__ A = bases.p[t.a_buf] + t.a_off;
   const double *__restrict__ B = bases.p[t.b_buf] + t.b_off;
   double *__restrict__ C = bases.p[t.c_buf] + t.c_off;
+  double *__restrict__ CT = t.ct_off >= 0 ? bases.p[t.c_buf] + t.ct_off : nullptr;
   const int32_t *__restrict__ rows = bases.rows;
 
   const int tid = threadIdx.x;
@@ -170,6 +172,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
           double r = t.alpha * acc[i][j][v];
           if (t.beta != 0.0) r += t.beta * *c;
           *c = r;
+          if (CT) CT[(int64_t)n * t.ldct + m] = r;
         }
       }
     }

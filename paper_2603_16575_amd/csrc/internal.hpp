@@ -30,7 +30,8 @@ struct GemmTask {
   int32_t M, N, K, lda, ldb, ldc;
   int32_t transA, transB;
   int32_t tiles_n;
-  int32_t pad_;
+  int32_t ldct;    // leading dimension of the transposed copy
+  int64_t ct_off;  // >= 0: C^T is also stored at this offset of c_buf
   double alpha, beta;
 };
 
