@@ -224,7 +224,9 @@ def tune_choices(report):
 
 def timed_replays(h, args, label):
     """Warm-up and timed replays of the handle's recorded graph; returns
-    (ms per step, last energy, per-phase timing of the timed replays)."""
+    (ms per step, last energy, per-phase timing of the timed replays, median
+    ms of one replay).  Each replay ends synchronised (mbe3_graph_launch
+    reads the status back), so every step has its own wall time too."""
     import torch
     E = None
     for w in range(args.warmup):
@@ -232,13 +234,16 @@ def timed_replays(h, args, label):
         log(f"bench: {label} warmup {w + 1}/{args.warmup} E={E:.12f}")
     h.set_timing(True)  # clears the accumulators; the graph keeps its events
     torch.cuda.synchronize()
+    per = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         E = h.graph_launch()
+        per.append((time.perf_counter() - ts) * 1000.0)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     ph = h.get_timing()
-    return ms, E, ph
+    return ms, E, ph, float(np.median(per))
 
 
 def mixed_run(m, prob, args, dev, E64, e64, h64):
@@ -250,7 +255,7 @@ def mixed_run(m, prob, args, dev, E64, e64, h64):
     h.autotune(reps=2)
     h.set_timing(True)
     bufs = h.capture_step(grad=True)
-    ms, E, ph = timed_replays(h, args, "mixed")
+    ms, E, ph, _ = timed_replays(h, args, "mixed")
     h.set_timing(False)
     e = bufs["e_frag"]
     d = np.abs(e.cpu().numpy() - e64)
@@ -292,7 +297,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16)
@@ -364,7 +369,7 @@ def main():
     # the phase events (HIP events on the library's stream) inside it
     h.set_timing(True)
     bufs = h.capture_step(grad=True)
-    ms_step, E, ph = timed_replays(h, args, "fwd+bwd")
+    ms_step, E, ph, med_step = timed_replays(h, args, "fwd+bwd")
     h.set_timing(False)
     value = prob.n_frag / (ms_step / 1000.0)
     log(f"bench: {args.steps} steps, {ms_step:.2f} ms/step, {value:.1f} fragments/s, E={E:.12f}")
@@ -386,7 +391,7 @@ def main():
     # the same step without the backward, recorded
     del bufs
     fw = h.capture_step(grad=False)
-    ms_fwd, E_f, _ = timed_replays(h, args, "forward")
+    ms_fwd, E_f, _, med_fwd = timed_replays(h, args, "forward")
     del fw
     log(f"bench: forward only {ms_fwd:.2f} ms/step, {prob.n_frag / (ms_fwd / 1e3):.1f} fragments/s")
 
@@ -459,9 +464,12 @@ def main():
                    "precision": "fp64", "E_total": E,
                    "grad_norm_dB": gnorm,
                    "iters_hist": np.bincount(np.maximum(iters, 0)).tolist()},
+        "median_ms_per_step": round(med_step, 3),
+        "solve_only_fragments_per_s": round(prob.n_frag / (ph["solve"][0] / args.steps * 1e-3), 2),
         "call_by_call_ms_per_step": round(ms_eager, 3),
         "autotune": {"seconds": round(t_tune, 2), "gemm_tiles": tuned},
         "forward_only": {"ms_per_step": round(ms_fwd, 3),
+                         "median_ms_per_step": round(med_fwd, 3),
                          "fragments_per_s": round(prob.n_frag / (ms_fwd / 1e3), 2),
                          "E_total": E_f},
         "roofline": roofline,
