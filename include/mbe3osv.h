@@ -308,7 +308,7 @@ int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
  * Tile shapes of the grouped FP64 GEMMs (the batched products of
  * Algorithms 5 and 6 and of the gradient): each task list of the handle has
  * one shape, BM x BN of the output per workgroup, from
- *   0: 64x64, 1: 128x128, 2: 32x32, 3: 32x128, 4: 64x128.
+ *   0: 64x64, 1: 128x128, 2: 32x32, 3: 32x128, 4: 64x128, 5: 96x96.
  * Every shape accumulates each output element over k in the same order, so
  * the results are bitwise the same whichever shape runs.
  *

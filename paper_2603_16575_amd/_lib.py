@@ -33,7 +33,7 @@ EXPORTS = [
     "mbe3_graph_launch", "mbe3_autotune", "mbe3_set_gemm_shape",
     "mbe3_tune_report",
 ]
-GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128"]
+GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128", "96x96"]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
           "energy", "grad", "backward"]
 

@@ -137,7 +137,7 @@ struct mbe3_handle {
   std::vector<std::pair<int, int>> proj_batches;  // [i0, i1)
   std::vector<GemmList> glists;  // every GEMM task list of the handle
   std::vector<int> L_proj;       // indices into glists (-1: none)
-  int L_pk = -1, L_sf = -1;
+  int L_pk = -1, L_pkw = -1, L_sf = -1;
   AssembleTask *d_asm_pair = nullptr;
   int n_asm_pair = 0;
   EigTask *d_eig0 = nullptr, *d_eig1 = nullptr;
@@ -623,9 +623,10 @@ int build_plans(mbe3_handle *h) {
     }
   }
 
-  // ---- pair K: K_s = L R^T with gathered rows of gamma ----
+  // ---- pair K: K_s = L R^T with gathered rows of gamma; slots up to 64
+  //      wide and wider ones in separate lists (own tile shapes) ----
   {
-    std::vector<GemmTask> ts;
+    std::vector<GemmTask> ts, tw;
     for (int64_t s = 0; s < h->n_slot; ++s) {
       const int p = h->sp[s], q = h->sq[s], d = h->sd[s];
       GemmTask t = gemm(B_GAMMA, 0, na, 0, B_GAMMA, 0, na, 1, B_K, h->k_off[s],
@@ -636,9 +637,14 @@ int build_plans(mbe3_handle *h) {
       t.b_rows = (int32_t)rows.size();
       for (int x : slot_orbs(h, (int)s))
         for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
-      ts.push_back(t);
+      (d > 64 ? tw : ts).push_back(t);
     }
-    if (!mixed && (rc = add_list(h, "pair_K", ts, GEMM_64x64, 0, &h->L_pk))) return rc;
+    if (!mixed && !ts.empty() &&
+        (rc = add_list(h, "pair_K", ts, GEMM_64x64, 0, &h->L_pk)))
+      return rc;
+    if (!mixed && !tw.empty() &&
+        (rc = add_list(h, "pair_K wide", tw, GEMM_96x96, 0, &h->L_pkw)))
+      return rc;
   }
   h->n_rows = (int64_t)rows.size();
   h->h_rows = rows;
@@ -1808,6 +1814,7 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems) {
   b.p[B_GAMMA] = const_cast<double *>(gamma);
   b.p[B_K] = K;
   HIP_TRY(h, launch_list(h, h->L_pk, b, h->stream));
+  HIP_TRY(h, launch_list(h, h->L_pkw, b, h->stream));
   return MBE3_OK;
 }
 

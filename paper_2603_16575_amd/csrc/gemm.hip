@@ -59,8 +59,14 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  constexpr int EA = BM * BK / 256;  // A elements per thread
-  constexpr int EB = BN * BK / 256;
+  // A / B elements per thread: a tile of BM x 16 split evenly when that
+  // gives a power of two per thread, else 8 per thread on the first
+  // BM * 16 / 8 threads (the 96-wide tiles: 192 of 256 threads load)
+  constexpr int EA0 = BM * BK / 256, EB0 = BN * BK / 256;
+  constexpr int EA = (BK % EA0 == 0) ? EA0 : 8;
+  constexpr int EB = (BK % EB0 == 0) ? EB0 : 8;
+  const bool a_act = tid < BM * BK / EA;
+  const bool b_act = tid < BN * BK / EB;
 
   // Per-thread source positions.  k-contiguous A (transA = 0): EA consecutive
   // k of one row; m-contiguous A (transA = 1): EA consecutive m of one k row.
@@ -68,14 +74,14 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
   const int a_tpr = BK / EA;
   const int a_r = tid / a_tpr, a_k = (tid % a_tpr) * EA;
   int64_t a_row = -1;
-  if (!t.transA && m0 + a_r < t.M)
+  if (a_act && !t.transA && m0 + a_r < t.M)
     a_row = (t.a_rows >= 0) ? rows[t.a_rows + m0 + a_r] : (m0 + a_r);
   const int a_tpk = BM / EA;
   const int a_kk = tid / a_tpk, a_mm = (tid % a_tpk) * EA;
   const int b_tpr = BK / EB;
   const int b_r = tid / b_tpr, b_k = (tid % b_tpr) * EB;
   int64_t b_row = -1;
-  if (t.transB && n0 + b_r < t.N)
+  if (b_act && t.transB && n0 + b_r < t.N)
     b_row = (t.b_rows >= 0) ? rows[t.b_rows + n0 + b_r] : (n0 + b_r);
   const int b_tpk = BN / EB;
   const int b_kk = tid / b_tpk, b_nn = (tid % b_tpk) * EB;
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
       const int64_t krow = k < t.K ? (t.a_rows >= 0 ? rows[t.a_rows + k] : k) : 0; \
       _Pragma("unroll") for (int e = 0; e < EA; ++e) {                         \
         const int m = m0 + a_mm + e;                                           \
-        ra[e] = (m < t.M && k < t.K) ? A[krow * t.lda + m] : 0.0;              \
+        ra[e] = (a_act && m < t.M && k < t.K) ? A[krow * t.lda + m] : 0.0;     \
       }                                                                        \
     }                                                                          \
     if (!t.transB) {                                                           \
@@ -101,7 +107,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
       const int64_t krow = k < t.K ? (t.b_rows >= 0 ? rows[t.b_rows + k] : k) : 0; \
       _Pragma("unroll") for (int e = 0; e < EB; ++e) {                         \
         const int n = n0 + b_nn + e;                                           \
-        rb[e] = (n < t.N && k < t.K) ? B[krow * t.ldb + n] : 0.0;              \
+        rb[e] = (b_act && n < t.N && k < t.K) ? B[krow * t.ldb + n] : 0.0;     \
       }                                                                        \
     } else {                                                                   \
       _Pragma("unroll") for (int e = 0; e < EB; ++e) {                         \
@@ -114,12 +120,14 @@ __global__ __launch_bounds__(256, 2) void gemm_tasks_kernel(
   do {                                                                         \
     double *as_ = As[BUF];                                                     \
     double *bs_ = Bs[BUF];                                                     \
-    if (!t.transA) {                                                           \
+    if (!a_act) {                                                              \
+    } else if (!t.transA) {                                                    \
       _Pragma("unroll") for (int e = 0; e < EA; ++e) as_[(a_k + e) * PA + a_r] = ra[e]; \
     } else {                                                                   \
       _Pragma("unroll") for (int e = 0; e < EA; ++e) as_[a_kk * PA + a_mm + e] = ra[e]; \
     }                                                                          \
-    if (!t.transB) {                                                           \
+    if (!b_act) {                                                              \
+    } else if (!t.transB) {                                                    \
       _Pragma("unroll") for (int e = 0; e < EB; ++e) bs_[b_kk * PB + b_nn + e] = rb[e]; \
     } else {                                                                   \
       _Pragma("unroll") for (int e = 0; e < EB; ++e) bs_[(b_k + e) * PB + b_r] = rb[e]; \
@@ -183,6 +191,7 @@ int gemm_tile_m(GemmShape shape) {
     case GEMM_128x128: return 128;
     case GEMM_32x32:
     case GEMM_32x128: return 32;
+    case GEMM_96x96: return 96;
     default: return 64;
   }
 }
@@ -191,6 +200,7 @@ int gemm_tile_n(GemmShape shape) {
   switch (shape) {
     case GEMM_32x32: return 32;
     case GEMM_64x64: return 64;
+    case GEMM_96x96: return 96;
     default: return 128;
   }
 }
@@ -202,6 +212,7 @@ const char *gemm_shape_name(GemmShape shape) {
     case GEMM_32x32: return "32x32";
     case GEMM_32x128: return "32x128";
     case GEMM_64x128: return "64x128";
+    case GEMM_96x96: return "96x96";
     default: return "?";
   }
 }
@@ -236,6 +247,10 @@ hipError_t launch_gemm_tasks(const GemmTask *d_tasks, int n_tasks,
       break;
     case GEMM_64x128:
       hipLaunchKernelGGL((gemm_tasks_kernel<64, 128>), grid, block, 0, s, d_tasks,
+                         n_tasks, bases);
+      break;
+    case GEMM_96x96:
+      hipLaunchKernelGGL((gemm_tasks_kernel<96, 96>), grid, block, 0, s, d_tasks,
                          n_tasks, bases);
       break;
     default: return hipErrorInvalidValue;

@@ -44,7 +44,8 @@ enum GemmShape {
   GEMM_32x32 = 2,
   GEMM_32x128 = 3,
   GEMM_64x128 = 4,
-  GEMM_NSHAPE = 5
+  GEMM_96x96 = 5,
+  GEMM_NSHAPE = 6
 };
 int gemm_tile_m(GemmShape shape);
 int gemm_tile_n(GemmShape shape);
