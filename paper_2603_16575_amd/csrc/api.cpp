@@ -41,7 +41,8 @@ static_assert(B_COUNT <= NBASE, "too many GEMM bases");
 
 struct Chunk {
   std::vector<int> frag_ids;  // fragment indices (heavy first)
-  int L_m = -1, L_s1 = -1;  // cross S~ GEMM lists (glists)
+  // cross S~ GEMM lists (glists): outputs up to 64 wide, and wider
+  int L_m = -1, L_mw = -1, L_s1 = -1, L_s1w = -1;
   AssembleTask *d_asm = nullptr;
   int n_asm = 0;
   FragDesc *d_frags = nullptr;
@@ -361,6 +362,18 @@ int add_list(mbe3_handle *h, const std::string &name, std::vector<GemmTask> &ts,
   if (rc) return rc;
   *idx = (int)h->glists.size();
   h->glists.push_back(std::move(L));
+  return MBE3_OK;
+}
+
+// Register a list as two: tasks whose output is at most 64 wide (planned
+// 64x64 tiles) and the wider ones (planned 96x96), each with its own shape.
+int add_split_lists(mbe3_handle *h, const std::string &name, const std::vector<GemmTask> &ts,
+                    int *idx_narrow, int *idx_wide) {
+  std::vector<GemmTask> nt, wt;
+  for (const GemmTask &t : ts) (std::max(t.M, t.N) > 64 ? wt : nt).push_back(t);
+  int rc;
+  if (!nt.empty() && (rc = add_list(h, name, nt, GEMM_64x64, 0, idx_narrow))) return rc;
+  if (!wt.empty() && (rc = add_list(h, name + " wide", wt, GEMM_96x96, 0, idx_wide))) return rc;
   return MBE3_OK;
 }
 
@@ -859,8 +872,8 @@ int build_plans(mbe3_handle *h) {
     if (!cas.empty()) {
       const std::string c = " " + std::to_string(h->chunks.size());
       if ((rc2 = upload(h, &cur.d_asm, cas))) return rc2;
-      if ((rc2 = add_list(h, "cross M" + c, cgm, GEMM_64x64, 0, &cur.L_m))) return rc2;
-      if ((rc2 = add_list(h, "cross" + c, cg1, GEMM_64x64, 0, &cur.L_s1))) return rc2;
+      if ((rc2 = add_split_lists(h, "cross M" + c, cgm, &cur.L_m, &cur.L_mw))) return rc2;
+      if ((rc2 = add_split_lists(h, "cross" + c, cg1, &cur.L_s1, &cur.L_s1w))) return rc2;
     }
     max_ca = std::max(max_ca, ca_total);
     max_cm = std::max(max_cm, cm_total);
@@ -1840,7 +1853,9 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
       HIP_TRY(h, launch_assemble(c.d_asm, c.n_asm, h->sstore, h->fstore, h->ca,
                                  nullptr, s));
       HIP_TRY(h, launch_list(h, c.L_m, b, s));
+      HIP_TRY(h, launch_list(h, c.L_mw, b, s));  // every M before the S~ that read it
       HIP_TRY(h, launch_list(h, c.L_s1, b, s));
+      HIP_TRY(h, launch_list(h, c.L_s1w, b, s));
     }
     SolveArgs a;
     std::memset(&a, 0, sizeof a);
