@@ -61,14 +61,28 @@ extern "C" {
 
 /* Arithmetic of osv_project and pair_K (everything else is FP64 always). */
 #define MBE3_FP64 0
-/* Split precision: every FP64 operand of the two products is carried as
-   three bf16 pieces x = h + m + l (h = bf16(x), m = bf16(x - h),
-   l = bf16(x - h - m)); the six cross products with piece orders summing to
-   at most 2 run on bf16 matrix cores with FP32 accumulation, and the results
-   are stored in FP64.  Per product the relative error is about 2^-24 of
-   sum |a_k b_k| plus the FP32 accumulation error; the energy error this
-   causes is reported by the tests and the benchmark against MBE3_FP64. */
+/* Split precision (eq. osv_imua and eq. osv_close_k on bf16 matrix cores):
+   every FP64 operand of the two products is carried as three bf16 pieces
+   x = h + m + l with FP32 accumulation over a few 32-deep blocks and FP64
+   accumulation across them; results are stored in FP64.
+   - Projection: relative pieces (h = bf16(x), m = bf16(x - h),
+     l = bf16(x - h - m)) and the six cross products whose piece orders sum
+     to at most 2; per product the error is about 2^-24 of sum |a_k b_k|.
+   - pair_K (MBE3_MIXED_BF16 only): pieces on a fixed-point grid of each
+     row of gamma, (H1 + H2/2^8 + H3/2^16) 2^(e-7) with integers |Hk| <= 128
+     and 2^e above the row's largest magnitude, and all nine products.  Each
+     32-deep block of one product class is then summed exactly by the matrix
+     cores (whose product adder otherwise drops low bits of small products,
+     a downward bias), and keeping l l avoids the bias the grid noise of the
+     third piece would leave on the diagonal of K.  The representation error
+     is at most 2^-23 of the row's largest element, unbiased.
+   The energy error against MBE3_FP64 is reported by the tests and the
+   benchmark. */
 #define MBE3_MIXED_BF16 1
+/* Split-precision projection as above; pair_K in FP64 (the split pair_K
+   issues nine bf16 products per FP64 one and is memory bound, so FP64
+   matrix cores finish it sooner). */
+#define MBE3_MIXED_BF16_PROJ 2
 
 /* Phases reported by mbe3_get_timing. */
 #define MBE3_PHASE_REGEN 0   /* slab regeneration (osv_project)             */
@@ -125,7 +139,7 @@ typedef struct mbe3_problem {
   double tol;       /* convergence: max |X^T R X| < tol (every pair)       */
   int32_t max_iter; /* maximum amplitude updates per fragment               */
   double tau_S;     /* drop pair-overlap eigenvalues <= tau_S               */
-  int32_t precision; /* MBE3_FP64 or MBE3_MIXED_BF16                       */
+  int32_t precision; /* MBE3_FP64, MBE3_MIXED_BF16, MBE3_MIXED_BF16_PROJ */
   /* 0: every fragment starts from T = 0.  1: monomers and dimers are solved
      first and each trimer starts from their converged amplitudes (its
      diagonal pairs from the monomers, its pairs from the dimers); the

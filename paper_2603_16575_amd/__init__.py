@@ -15,13 +15,14 @@ import numpy as np
 from . import _lib
 from ._lib import (MBE3_EHIP, MBE3_EINVAL, MBE3_ENOCONV, MBE3_ENOMEM,
                    MBE3_ENONFINITE, MBE3_FP64, MBE3_GRAD_GAMMA, MBE3_GRAD_SLAB,
-                   MBE3_MIXED_BF16, MBE3_OK, Mbe3Error)
+                   MBE3_MIXED_BF16, MBE3_MIXED_BF16_PROJ, MBE3_OK, Mbe3Error)
 
 __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
            "mbe3_energy", "mbe3_backward", "mbe3_pair_basis", "energy_fn",
            "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
            "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
-           "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16"]
+           "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16",
+           "MBE3_MIXED_BF16_PROJ"]
 
 
 def _f64(t):
@@ -35,7 +36,8 @@ class Mbe3:
 
     Q, eps_vir, f_occ, w_ia, w_iP (or slab): contiguous float64 CUDA tensors,
     kept referenced by the handle.  r, pairs, frags: host int arrays.
-    precision: MBE3_FP64 or MBE3_MIXED_BF16 (osv_project and pair_K only).
+    precision: MBE3_FP64, MBE3_MIXED_BF16 (split projection and pair_K) or
+        MBE3_MIXED_BF16_PROJ (split projection, FP64 pair_K).
     warm_start: trimers start from the converged monomer/dimer amplitudes
     (same solution to the threshold, fewer updates); False: T = 0 throughout.
     """

@@ -21,6 +21,7 @@ MBE3_ENOCONV = -4
 MBE3_ENONFINITE = -5
 MBE3_FP64 = 0
 MBE3_MIXED_BF16 = 1
+MBE3_MIXED_BF16_PROJ = 2
 MBE3_GRAD_SLAB = 0
 MBE3_GRAD_GAMMA = 1
 

@@ -410,7 +410,8 @@ int validate_and_copy(mbe3_handle *h, const mbe3_problem *p) {
     return h->fail(MBE3_EINVAL, "either slab or (w_ia, w_iP) must be given");
   if (!(p->tol > 0.0) || p->max_iter < 0 || !(p->tau_S >= 0.0))
     return h->fail(MBE3_EINVAL, "tol > 0, max_iter >= 0, tau_S >= 0 required");
-  if (p->precision != MBE3_FP64 && p->precision != MBE3_MIXED_BF16)
+  if (p->precision != MBE3_FP64 && p->precision != MBE3_MIXED_BF16 &&
+      p->precision != MBE3_MIXED_BF16_PROJ)
     return h->fail(MBE3_EINVAL, "unsupported precision %d", p->precision);
   h->precision = p->precision;
   if (p->warm_start != 0 && p->warm_start != 1)
@@ -602,7 +603,9 @@ int build_plans(mbe3_handle *h) {
 
   // ---- projection: one GEMM per orbital, A rows gathered from Q ----
   const int64_t slab_elems = (int64_t)nv * na;
-  const bool mixed = h->precision == MBE3_MIXED_BF16;
+  // split projection in both mixed forms, split pair_K in MBE3_MIXED_BF16
+  const bool mixed = h->precision != MBE3_FP64;
+  const bool mixed_k = h->precision == MBE3_MIXED_BF16;
   if (mixed) {  // three bf16 planes per slab element
     int64_t nb = SLAB_BUDGET / ((int64_t)na * h->ldk_vir * 6);
     h->slab_nb = (int)std::max<int64_t>(1, std::min<int64_t>(nb, n));
@@ -652,10 +655,10 @@ int build_plans(mbe3_handle *h) {
         for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
       (d > 64 ? tw : ts).push_back(t);
     }
-    if (!mixed && !ts.empty() &&
+    if (!mixed_k && !ts.empty() &&
         (rc = add_list(h, "pair_K", ts, GEMM_64x64, 0, &h->L_pk)))
       return rc;
-    if (!mixed && !tw.empty() &&
+    if (!mixed_k && !tw.empty() &&
         (rc = add_list(h, "pair_K wide", tw, GEMM_96x96, 0, &h->L_pkw)))
       return rc;
   }
@@ -700,30 +703,32 @@ int build_plans(mbe3_handle *h) {
       h->d_mproj.push_back(d);
       h->h_mixed.push_back({"project (split)", ts});
     }
-    std::vector<MixedTask> ts;
-    for (int64_t sl = 0; sl < h->n_slot; ++sl) {
-      const int p = h->sp[sl], q = h->sq[sl], d = h->sd[sl];
-      MixedTask t;
-      std::memset(&t, 0, sizeof t);
-      t.a_rows = (int32_t)mr.size();
-      for (int x : slot_orbs(h, (int)sl))
-        for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->grow.at(key2(p, x)) + mu));
-      t.b_rows = (int32_t)mr.size();
-      for (int x : slot_orbs(h, (int)sl))
-        for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
-      t.c_off = h->k_off[sl];
-      t.M = d; t.N = d; t.K = la;
-      t.lda = la; t.ldb = la; t.ldc = d;
-      ts.push_back(t);
+    if (mixed_k) {
+      std::vector<MixedTask> ts;
+      for (int64_t sl = 0; sl < h->n_slot; ++sl) {
+        const int p = h->sp[sl], q = h->sq[sl], d = h->sd[sl];
+        MixedTask t;
+        std::memset(&t, 0, sizeof t);
+        t.a_rows = (int32_t)mr.size();
+        for (int x : slot_orbs(h, (int)sl))
+          for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->grow.at(key2(p, x)) + mu));
+        t.b_rows = (int32_t)mr.size();
+        for (int x : slot_orbs(h, (int)sl))
+          for (int mu = 0; mu < h->r[x]; ++mu) mr.push_back((int32_t)(h->grow.at(key2(q, x)) + mu));
+        t.c_off = h->k_off[sl];
+        t.M = d; t.N = d; t.K = la;
+        t.lda = la; t.ldb = la; t.ldc = d;
+        ts.push_back(t);
+      }
+      h->t_mpk = finish(ts, MIXED_32x64);
+      if ((rc = upload(h, &h->d_mpk, ts))) return rc;
+      h->h_mixed.push_back({"pair_K (split)", ts});
     }
-    h->t_mpk = finish(ts, MIXED_32x64);
-    if ((rc = upload(h, &h->d_mpk, ts))) return rc;
-    h->h_mixed.push_back({"pair_K (split)", ts});
     h->h_mrows = mr;
     if ((rc = upload(h, &h->d_mrows, mr))) return rc;
     h->q_ps = h->q_off[n] * lv;
     h->s_ps = (int64_t)h->slab_nb * na * lv;
-    h->g_ps = h->gamma_rows * la;
+    h->g_ps = mixed_k ? h->gamma_rows * la : 0;
   }
 
   // ---- S / F blocks ----
@@ -1066,10 +1071,10 @@ int max_d(const mbe3_handle *h);
 int alloc_workspace(mbe3_handle *h) {
   int rc;
   const int64_t nv = h->n_vir, na = h->n_aux;
-  if (h->precision == MBE3_MIXED_BF16) {
+  if (h->precision != MBE3_FP64) {
     if ((rc = dev_alloc(h, &h->qplanes, 3 * h->q_ps))) return rc;
     if ((rc = dev_alloc(h, &h->splanes, 3 * h->s_ps))) return rc;
-    if ((rc = dev_alloc(h, &h->gplanes, 3 * h->g_ps))) return rc;
+    if (h->g_ps && (rc = dev_alloc(h, &h->gplanes, 3 * h->g_ps))) return rc;
   } else if (!h->slab &&
              (rc = dev_alloc(h, &h->slab_buf, (int64_t)h->slab_nb * nv * na))) {
     return rc;
@@ -1332,7 +1337,7 @@ int check_mixed_list(mbe3_handle *h, const std::string &name,
 int validate_plans(mbe3_handle *h) {
   int64_t sz[B_COUNT];
   base_sizes(h, sz);
-  if (h->precision == MBE3_MIXED_BF16) {
+  if (h->precision != MBE3_FP64) {
     for (auto &pl : h->h_mixed) {
       const bool proj = pl.first[0] == 'p' && pl.first[1] == 'r';
       const int rc = proj ? check_mixed_list(h, pl.first, pl.second, h->q_ps, h->s_ps,
@@ -1773,7 +1778,7 @@ int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems) {
     return h->fail(MBE3_EINVAL, "gamma needs %lld doubles, got %lld",
                    (long long)(h->gamma_rows * h->n_aux), (long long)gamma_elems);
   hipStream_t s = h->stream;
-  if (h->precision == MBE3_MIXED_BF16) {
+  if (h->precision != MBE3_FP64) {
     {
       PhaseScope ps_(h, MBE3_PHASE_REGEN);
       HIP_TRY(h, launch_split_rows(h->Q, h->q_off[h->n_occ], h->n_vir, h->n_vir,
@@ -1816,8 +1821,8 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems) {
                    (long long)h->k_elems, (long long)k_elems);
   PhaseScope ps_(h, MBE3_PHASE_PAIR_K);
   if (h->precision == MBE3_MIXED_BF16) {
-    HIP_TRY(h, launch_split_rows(gamma, h->gamma_rows, h->n_aux, h->n_aux, h->gplanes,
-                                 h->g_ps, h->ldk_aux, h->stream));
+    HIP_TRY(h, launch_split_rows_fixed(gamma, h->gamma_rows, h->n_aux, h->n_aux,
+                                       h->gplanes, h->g_ps, h->ldk_aux, h->stream));
     HIP_TRY(h, launch_gemm_mixed(h->d_mpk, (int)h->n_slot, h->t_mpk, h->gplanes, h->g_ps,
                                  h->gplanes, h->g_ps, K, h->d_mrows, MIXED_32x64,
                                  h->stream));

@@ -2,13 +2,14 @@
 // pair exchange matrices (eq. osv_close_k) in the mixed form: each FP64
 // operand is carried as three bf16 pieces x = h + m + l, and
 //   a b ~ h_a h_b + h_a m_b + m_a h_b + h_a l_b + m_a m_b + l_a h_b
-// (the dropped products are below 2^-24 relative) runs on
+// (the projection: its pieces are relative roundings, so the dropped
+// products are below 2^-24 relative; pair_K forms all nine) runs on
 // v_mfma_f32_16x16x32_bf16 (each bf16 x bf16 product is exact in FP32).  The
 // leading product h_a h_b of every 32-deep block is formed from a zero
 // accumulator and added to an FP64 accumulator, so FP32 rounding touches it
 // once per block instead of growing with K; the five correction products,
-// 2^-8 and less of it, accumulate in FP32 over the whole K and join at the
-// end.  Results are stored in FP64.
+// 2^-8 and less of it, accumulate in FP32 over a few blocks at a time and
+// are then added to the FP64 accumulator too.  Results are stored in FP64.
 //
 // C = A B^T with both operands K-contiguous: lane l of a wave holds row l%16
 // of an A tile and row l%16 of a B tile (a column of B^T) with the eight
@@ -37,7 +38,16 @@ struct MixedArgs {
 // PF: load the next block's operands before this block's products (pays off
 // for the small pair_K tiles; the 64 x 128 projection tile is better served
 // by the occupancy the extra registers would cost).
-template <int TM, int TN, bool PF>
+// Correction products are summed in FP32 over MIXED_FLUSH 32-deep blocks,
+// then added to the FP64 accumulator (a long FP32 sum would gather rounding
+// error in proportion to K).  ALL forms all nine piece products: the pair_K
+// operands carry fixed-point pieces on the grid of their row, so every
+// element's third piece is grid noise of up to 2^-16 of the row's largest,
+// and dropping l l would bias each diagonal entry of K by minus the sum of
+// their squares.
+constexpr int MIXED_FLUSH = 4;
+
+template <int TM, int TN, bool PF, bool ALL>
 __global__ __launch_bounds__(256) void gemm_mixed_kernel(
     const MixedTask *__restrict__ tasks, int n_tasks, MixedArgs g) {
   const int64_t tile = blockIdx.x;
@@ -75,8 +85,8 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(
   }
   const int64_t aps = g.a_ps / 8, bps = g.b_ps / 8;  // plane strides in u4
 
-  f4 acc[TM][TN];   // correction products, FP32 over all of K
-  double dacc[TM][TN][4];  // leading product, FP64 over the 32-deep blocks
+  f4 acc[TM][TN];   // correction products, FP32 over MIXED_FLUSH blocks
+  double dacc[TM][TN][4];  // FP64 sum of the blocks' leading products and flushes
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -101,6 +111,7 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(
     }                                                                         \
   } while (0)
   if (PF) MBE3_LOAD(a, b, 0);
+  int nblk = 0;
   for (int k0 = 0; k0 < t.K; k0 += 32) {
     u4 an[3][TM], bn[3][TN];
     if (!PF) MBE3_LOAD(a, b, k0);
@@ -111,12 +122,28 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(                    \
           __builtin_bit_cast(bf8, a[PA][i]), __builtin_bit_cast(bf8, b[PB][j]), \
           acc[i][j], 0, 0, 0)
+    if (ALL) {
+      MBE3_PROD(2, 2);
+      MBE3_PROD(2, 1);
+      MBE3_PROD(1, 2);
+    }
     MBE3_PROD(2, 0);
     MBE3_PROD(1, 1);
     MBE3_PROD(0, 2);
     MBE3_PROD(1, 0);
     MBE3_PROD(0, 1);
 #undef MBE3_PROD
+    if (++nblk == MIXED_FLUSH || k0 + 32 >= t.K) {
+      nblk = 0;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dacc[i][j][v] += (double)acc[i][j][v];
+          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
     const f4 fz = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -148,7 +175,7 @@ __global__ __launch_bounds__(256) void gemm_mixed_kernel(
       for (int v = 0; v < 4; ++v) {
         const int m = mw + 16 * i + 4 * q + v;
         if (m < t.M)
-          g.C[t.c_off + (int64_t)m * t.ldc + n] = dacc[i][j][v] + (double)acc[i][j][v];
+          g.C[t.c_off + (int64_t)m * t.ldc + n] = dacc[i][j][v];
       }
     }
 }
@@ -169,10 +196,10 @@ hipError_t launch_gemm_mixed(const MixedTask *d_tasks, int n_tasks,
   if (n_tasks <= 0 || n_tiles <= 0) return hipSuccess;
   MixedArgs g{A, B, a_ps, b_ps, C, rows};
   if (shape == MIXED_64x128)
-    hipLaunchKernelGGL((gemm_mixed_kernel<2, 4, false>), dim3((unsigned)n_tiles),
+    hipLaunchKernelGGL((gemm_mixed_kernel<2, 4, false, false>), dim3((unsigned)n_tiles),
                        dim3(256), 0, s, d_tasks, n_tasks, g);
   else
-    hipLaunchKernelGGL((gemm_mixed_kernel<1, 2, true>), dim3((unsigned)n_tiles),
+    hipLaunchKernelGGL((gemm_mixed_kernel<1, 2, true, true>), dim3((unsigned)n_tiles),
                        dim3(256), 0, s, d_tasks, n_tasks, g);
   return hipGetLastError();
 }

@@ -71,6 +71,10 @@ hipError_t launch_regen_split(uint16_t *planes, int64_t ps, int i0, int nb,
 hipError_t launch_split_rows(const double *x, int64_t rows, int cols, int64_t ld,
                              uint16_t *planes, int64_t ps, int ldk,
                              hipStream_t s);
+// The same planes with the leading piece on a fixed-point grid of each row
+// (the pair_K operands: exact leading block sums on the matrix cores).
+hipError_t launch_split_rows_fixed(const double *x, int64_t rows, int cols, int64_t ld,
+                                   uint16_t *planes, int64_t ps, int ldk, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Split-precision grouped GEMM (gemm_mixed.hip): C = A B^T in FP64 storage

@@ -126,6 +126,40 @@ __global__ __launch_bounds__(256) void split_rows_kernel(
   }
 }
 
+// Rows for the pair_K operands: all three pieces on fixed-point grids of the
+// row, x ~ (H1 + H2 / 256 + H3 / 65536) u with integers |Hk| <= 128 and
+// u = 2^(e - 7), 2^e above the row's largest magnitude (representation error
+// at most u / 2^17, i.e. 2^-23 of the row's largest).  A product of two
+// pieces of two such rows is then an integer multiple of one unit per product
+// class, at most 2^14 units, so every 32-deep block is summed exactly by the
+// matrix cores.  Their product adder drops the bits of each product that lie
+// far below the block's largest one, which biases a sum downward however the
+// products' signs fall; exact classes leave no such bias.  One wave per row.
+__global__ __launch_bounds__(256) void split_rows_fixed_kernel(
+    const double *__restrict__ x, int64_t rows, int cols, int64_t ld,
+    uint16_t *__restrict__ planes, int64_t ps, int ldk) {
+  const int lane = threadIdx.x & 63;
+  const int64_t rw = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (rw >= rows) return;
+  const double *xr = x + rw * ld;
+  double mx = 0.0;
+  for (int c = lane; c < cols; c += 64) mx = fmax(mx, fabs(xr[c]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  int e = 0;
+  if (mx > 0.0) frexp(mx, &e);  // mx < 2^e
+  uint16_t *pr = planes + rw * ldk;
+  for (int c = lane; c < ldk; c += 64) {
+    double r = c < cols ? xr[c] : 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {  // |r| <= 2^(e - 8p) - 1/2 grid step
+      const int sh = 7 + 8 * p;
+      const double hv = rint(ldexp(r, sh - e));  // |hv| <= 128: exact in bf16
+      pr[p * ps + c] = bf16_bits(ldexp(hv, e - sh));
+      r -= ldexp(hv, e - sh);
+    }
+  }
+}
+
 static int64_t grid_for(int64_t total) {
   int64_t blocks = (total + 255) / 256;
   return blocks > 65536 ? 65536 : blocks;
@@ -150,6 +184,16 @@ hipError_t launch_split_rows(const double *x, int64_t rows, int cols, int64_t ld
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)grid_for(total)), dim3(256),
                      0, s, x, rows, cols, ld, planes, ps, ldk);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_rows_fixed(const double *x, int64_t rows, int cols, int64_t ld,
+                                   uint16_t *planes, int64_t ps, int ldk, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const int64_t blocks = (rows + 3) / 4;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_rows_fixed_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x,
+                     rows, cols, ld, planes, ps, ldk);
   return hipGetLastError();
 }
 

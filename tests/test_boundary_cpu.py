@@ -35,10 +35,11 @@ def test_header_symbols_exported(pkg):
 
 
 @pytest.mark.parametrize("k", [0, 1])
-@pytest.mark.parametrize("precision", ["fp64", "mixed_bf16"])
+@pytest.mark.parametrize("precision", ["MBE3_FP64", "MBE3_MIXED_BF16",
+                                       "MBE3_MIXED_BF16_PROJ"])
 def test_plan_check_configs(pkg, k, precision):
     p = synth.config(k)
-    prec = pkg.MBE3_FP64 if precision == "fp64" else pkg.MBE3_MIXED_BF16
+    prec = getattr(pkg, precision)
     lay = pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
                          n_aux=p.n_aux, precision=prec)
     rows = sum(int(p.r[p.neighbours(i)].sum()) for i in range(p.n_occ))
@@ -53,7 +54,7 @@ def test_plan_check_large_configs(pkg, k):
     """Configurations 2 (470k fragments, D <= 128) and 4 (D <= 160) plan and
     pass every bounds check, both precisions."""
     p = synth.config(k)
-    for prec in (pkg.MBE3_FP64, pkg.MBE3_MIXED_BF16):
+    for prec in (pkg.MBE3_FP64, pkg.MBE3_MIXED_BF16, pkg.MBE3_MIXED_BF16_PROJ):
         lay = pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
                              n_aux=p.n_aux, precision=prec)
         assert lay.n_frag == p.n_frag
@@ -64,9 +65,9 @@ def test_plan_check_micro_explicit_slab(pkg):
     pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
                    n_aux=p.n_aux, explicit_slab=True)
     # split planes pad rows to a multiple of 8: odd sizes plan as well
-    pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir + 3,
-                   n_aux=p.n_aux + 5, explicit_slab=True,
-                   precision=pkg.MBE3_MIXED_BF16)
+    for prec in (pkg.MBE3_MIXED_BF16, pkg.MBE3_MIXED_BF16_PROJ):
+        pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir + 3,
+                       n_aux=p.n_aux + 5, explicit_slab=True, precision=prec)
 
 
 def test_plan_check_rejects_unknown_precision(pkg):

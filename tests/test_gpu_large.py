@@ -202,3 +202,30 @@ def test_helix1024_forward_and_gradient(m):
     say(f"helix1024: dE/df_{x}{y} fd {fd:.10e} analytic {an:.10e}")
     assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-8)
     h.close()
+
+
+def test_water128u_mixed_vs_fp64(m):
+    """Both split-precision forms on the configs 2 workload (configs 3): total
+    and per-fragment deviation from the FP64 GPU path, which the test above
+    ties to the oracle on sampled fragments.  Budget 1e-6 Eh on the total."""
+    import torch
+    say("case: water128u (configs 3: split precision on configs 2) vs FP64 path")
+    prob = synth.config(2)
+    h = m.from_problem(prob)
+    out = h.forward()
+    E64, e64 = out["E"], out["e_frag"].cpu().numpy()
+    h.close()
+    del out, h
+    torch.cuda.empty_cache()
+    for form in ("MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"):
+        h = m.from_problem(prob, precision=getattr(m, form))
+        out = h.forward()
+        Em, em = out["E"], out["e_frag"].cpu().numpy()
+        h.close()
+        del out, h
+        torch.cuda.empty_cache()
+        d = np.abs(em - e64)
+        say(f"water128u {form}: E = {Em:.10f} (FP64 {E64:.10f}), "
+            f"|dE| = {abs(Em - E64):.3e}, max |dE_F| = {d.max():.3e}, mean {d.mean():.3e}")
+        assert np.isfinite(em).all()
+        assert abs(Em - E64) <= 1e-6

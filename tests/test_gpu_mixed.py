@@ -1,13 +1,21 @@
-"""Split-precision (MBE3_MIXED_BF16) projection and pair_K against the FP64
-oracle, through the C-ABI (needs an MI355X).
+"""Split-precision projection and pair_K (MBE3_MIXED_BF16, and
+MBE3_MIXED_BF16_PROJ with its FP64 pair_K) against the FP64 oracle, through
+the C-ABI (needs an MI355X).
 
-Error model of one product c = sum_k a_k b_k in the mixed form: each operand
-carries 24 significant bits (three bf16 pieces), the dropped cross products
-are below 3 * 2^-24 of |a_k b_k|, and the FP32 accumulation of K terms adds at
-most K * 2^-24 of sum |a_k b_k| (worst case, one rounding per step).  The
-tests bound |c_mixed - c| by (K + 8) * 2^-24 * sum_k |a_k| |b_k| element by
-element and require the typical error (RMS over elements, relative to the
-same scale) to be far below it."""
+Error model of one projection product c = sum_k a_k b_k: each operand
+carries 24 significant bits (three relative bf16 pieces), the dropped cross
+products are below 3 * 2^-24 of |a_k b_k|, and the FP32 accumulation of K
+terms adds at most K * 2^-24 of sum |a_k b_k| (worst case, one rounding per
+step).  The tests bound |c_mixed - c| by (K + 8) * 2^-24 * sum_k |a_k| |b_k|
+element by element and require the typical error (RMS over elements,
+relative to the same scale) to be far below it.
+
+The split pair_K carries each row of gamma on a fixed-point grid of the
+row, so an element is off by at most 2^-23 of its row's largest magnitude,
+and every block sum of one product class is exact; with all nine products
+kept, |K_mixed - K| <= 2^-23 (max|L_p| sum_P |R_qP| + max|R_q| sum_P |L_pP|)
+plus the FP32 rounding of the correction sums, below 2^-24 of
+sum_P |L_pP| |R_qP|."""
 import dataclasses
 import json
 import os
@@ -42,9 +50,9 @@ def gamma_rows_of(h, prob, gamma, i):
     return g[int(h.g_off[i]):int(h.g_off[i + 1])].cpu().numpy()
 
 
-def check_products(m, prob):
+def check_products(m, prob, prec):
     import torch
-    h = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    h = m.from_problem(prob, precision=prec)
     gamma = h.osv_project(h.empty_gamma())
     torch.cuda.synchronize()
     ora = oracle.Oracle(prob)
@@ -82,22 +90,32 @@ def check_products(m, prob):
         d = L.shape[0]
         got = Kn[h.k_off[s]:h.k_off[s] + d * d].reshape(d, d)
         scale = np.abs(L) @ np.abs(R).T
-        worst_k = max(worst_k, float((np.abs(got - L @ R.T) / scale).max()))
-    bound_k = (prob.n_aux + 8) * eps
-    say(f"pair_K: worst err/scale {worst_k:.3e}, bound {bound_k:.3e}")
-    assert worst_k <= bound_k
+        if prec == m.MBE3_MIXED_BF16:
+            grid = (np.abs(L).max(1)[:, None] * np.abs(R).sum(1)[None, :]
+                    + np.abs(L).sum(1)[:, None] * np.abs(R).max(1)[None, :])
+            bound = 2.0 ** -23 * grid + eps * scale
+        else:  # FP64 pair_K
+            bound = (prob.n_aux + 8) * 2.0 ** -53 * scale
+        worst_k = max(worst_k, float((np.abs(got - L @ R.T) / bound).max()))
+    say(f"pair_K: worst err / bound {worst_k:.3e}")
+    assert worst_k <= 1.0
     h.close()
 
 
-def test_mixed_products_chain8(m):
-    say("case: chain8 (configs 0) split-precision projection and pair_K vs oracle")
-    check_products(m, synth.config(0))
+FORMS = ["MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"]
 
 
-def test_mixed_products_padded_sizes(m):
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_products_chain8(m, form):
+    say(f"case: chain8 (configs 0) {form} projection and pair_K vs oracle")
+    check_products(m, synth.config(0), getattr(m, form))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_products_padded_sizes(m, form):
     """n_vir, n_aux not multiples of 8: zero-padded plane rows."""
-    say("case: micro n_occ=4, n_vir=21, n_aux=35, split-precision products vs oracle")
-    check_products(m, synth.micro(4, n_vir=21, n_aux=35))
+    say(f"case: micro n_occ=4, n_vir=21, n_aux=35, {form} products vs oracle")
+    check_products(m, synth.micro(4, n_vir=21, n_aux=35), getattr(m, form))
 
 
 def test_mixed_explicit_slab_equals_regenerated(m):
@@ -116,10 +134,11 @@ def test_mixed_explicit_slab_equals_regenerated(m):
     h2.close()
 
 
-def test_mixed_energy_micro(m):
-    say("case: micro n_occ=4 mixed precision energy vs oracle")
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_energy_micro(m, form):
+    say(f"case: micro n_occ=4 {form} energy vs oracle")
     prob = dataclasses.replace(synth.micro(4), tol=1e-12, max_iter=300)
-    h = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    h = m.from_problem(prob, precision=getattr(m, form))
     out = h.forward()
     ref = oracle.run(prob)
     E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
@@ -128,17 +147,18 @@ def test_mixed_energy_micro(m):
     h.close()
 
 
-def test_mixed_energy_water40u(m):
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_energy_water40u(m, form):
     """configs 1 in the benchmark's launch shape: the mixed total energy
     against the oracle's full run (|dE| <= 1e-6 Eh, the budget of the mixed
     form), and per-fragment deviations from the FP64 GPU path."""
     import torch
-    say("case: water40u (configs 1) mixed precision vs golden oracle and FP64 path")
+    say(f"case: water40u (configs 1) {form} vs golden oracle and FP64 path")
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                     "water40u_oracle.json")))
     E_ref = float(g["E_total"])
     prob = synth.config(1)
-    hm = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    hm = m.from_problem(prob, precision=getattr(m, form))
     om = hm.forward()
     E_m = om["E"]
     em = om["e_frag"].cpu().numpy()
@@ -150,7 +170,7 @@ def test_mixed_energy_water40u(m):
     ef = of["e_frag"].cpu().numpy()
     hf.close()
     d = np.abs(em - ef)
-    say(f"water40u mixed: E = {E_m:.12f}, |E - E_oracle| = {abs(E_m - E_ref):.3e}, "
+    say(f"water40u {form}: E = {E_m:.12f}, |E - E_oracle| = {abs(E_m - E_ref):.3e}, "
         f"max |dE_F| vs FP64 = {d.max():.3e}, mean {d.mean():.3e}")
     assert abs(E_m - E_ref) <= 1e-6
     assert d.max() <= 1e-7

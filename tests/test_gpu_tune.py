@@ -98,19 +98,23 @@ def test_autotune_water40u(m):
     torch.cuda.empty_cache()
 
 
-def test_autotune_mixed_micro(m):
-    """A split-precision handle tunes only the lists it launches (its FP64
-    projection and pair_K products have split-precision task lists
-    instead); the tuned step equals the planned one."""
-    say("case: micro n_occ=4 mixed precision, autotune, tuned vs planned")
+@pytest.mark.parametrize("form", ["MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"])
+def test_autotune_mixed_micro(m, form):
+    """A split-precision handle tunes only the lists it launches (the split
+    products have their own task lists instead of the FP64 ones: the
+    projection in both forms, pair_K in MBE3_MIXED_BF16); the tuned step
+    equals the planned one."""
+    say(f"case: micro n_occ=4 {form}, autotune, tuned vs planned")
     prob = dataclasses.replace(synth.micro(4), tol=1e-10, max_iter=300)
-    h = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    h = m.from_problem(prob, precision=getattr(m, form))
     ref = step(h)
     rep = h.autotune(reps=1)
     say(rep)
     heads = [ln.split(":", 1)[0] for ln in rep.splitlines() if ln.strip()]
     names = [hd.split(" ", 1)[1].rsplit(" (", 1)[0] for hd in heads]
-    assert names and not any(n.startswith("project") or n.startswith("pair_K") for n in names)
+    assert names and not any(n.startswith("project") for n in names)
+    has_pk = any(n.startswith("pair_K") for n in names)
+    assert has_pk == (form == "MBE3_MIXED_BF16_PROJ")
     out = step(h)
     bad = differing(out, ref)
     say(f"  tuned E = {out['E']!r} (planned {ref['E']!r}), differing: {bad}")
