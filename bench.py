@@ -246,7 +246,7 @@ def timed_replays(h, args, label):
     return ms, E, ph, float(np.median(per))
 
 
-def mixed_run(m, prob, args, dev, E64, e64, form):
+def mixed_run(m, prob, args, dev, E64, e64, ref64, form):
     """The same recorded forward + backward step in a split-precision form:
     MBE3_MIXED_BF16 (split projection and pair_K) or MBE3_MIXED_BF16_PROJ
     (split projection, FP64 pair_K); energy deviations against the FP64 run
@@ -260,6 +260,7 @@ def mixed_run(m, prob, args, dev, E64, e64, form):
     h.set_timing(False)
     e = bufs["e_frag"]
     d = np.abs(e.cpu().numpy() - e64)
+    est, _ = m.first_order_dE(h.k_off, prob.n_occ, bufs["K"].cpu().numpy(), *ref64)
     ldk_vir = (prob.n_vir + 7) // 8 * 8
     ldk_aux = (prob.n_aux + 7) // 8 * 8
     rows = float(h.layout.gamma_rows)
@@ -280,6 +281,8 @@ def mixed_run(m, prob, args, dev, E64, e64, form):
         "speedup_vs_fp64": None,
         "E_total": E,
         "abs_dE_total_vs_fp64": abs(E - E64),
+        "dE_total_vs_fp64": E - E64,
+        "dE_first_order_estimate": est,
         "max_abs_dE_fragment_vs_fp64": float(d.max()),
         "mean_abs_dE_fragment_vs_fp64": float(d.mean()),
         "budget_abs_dE_total": 1e-6,
@@ -389,6 +392,7 @@ def main():
     gnorm = float(torch.linalg.vector_norm(dB))
     e64 = e.cpu().numpy().copy()
     E64 = E
+    ref64 = (bufs["K"].cpu().numpy(), bufs["W"].cpu().numpy())  # for the mixed runs
     # call-by-call steps, for the cost of launching without the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -445,7 +449,7 @@ def main():
     mixed = {}
     if not args.no_mixed:
         for form in ("MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"):
-            mixed[form] = mixed_run(m, prob, args, dev, E64, e64, form)
+            mixed[form] = mixed_run(m, prob, args, dev, E64, e64, ref64, form)
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a host sample ...")
@@ -464,7 +468,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{prob.name}: configuration {args.config}, "
+        "config": {"workload": f"{prob.name}: "
                                f"{prob.n_occ} LMOs (lattice of 4-orbital units), "
                                f"n_vir={n_vir}, n_aux={n_aux}, r={prob.r.min()}-{prob.r.max()}, "
                                f"cutoff 6, {len(prob.pairs)} pairs, {len(prob.trimers)} trimers, "

@@ -22,7 +22,7 @@ __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
            "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
            "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
            "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16",
-           "MBE3_MIXED_BF16_PROJ"]
+           "MBE3_MIXED_BF16_PROJ", "first_order_dE"]
 
 
 def _f64(t):
@@ -316,6 +316,25 @@ def energy_fn(h, slab, f_occ):
     if _ENERGY_FN is None:
         _ENERGY_FN = _energy_function()
     return _ENERGY_FN.apply(h, slab, f_occ)
+
+
+def first_order_dE(k_off, n_occ, K_a, K_b, W):
+    """First-order change of the MBE(3) energy when K-bar moves from K_b to
+    K_a (host arrays in the K layout):
+        dE ~ sum_s c_s <K_a,s - K_b,s, W_s>,  c_s = 2 (diagonal slots),
+                                              c_s = 4 (pairs),
+    with W the multipliers fragment_solve returns for K_b (symmetric on the
+    diagonal slots, whose K-bar blocks G G^T are symmetric too).  The energy
+    depends on the projection and pair_K only through K-bar (eq. res_close
+    reads K~ = X^T K-bar X), so this attributes a split-precision energy
+    error to slots.  Returns (total, per-slot contributions)."""
+    k_off = np.asarray(k_off, dtype=np.int64)
+    prod = (np.asarray(K_a, dtype=np.float64) - np.asarray(K_b, dtype=np.float64)) \
+        * np.asarray(W, dtype=np.float64)
+    n_slot = len(k_off) - 1
+    per = np.add.reduceat(prod[:k_off[-1]], k_off[:-1]) if n_slot else np.zeros(0)
+    per *= np.where(np.arange(n_slot) < n_occ, 2.0, 4.0)
+    return float(per.sum()), per
 
 
 def osv_project(h, gamma):

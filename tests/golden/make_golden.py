@@ -2,7 +2,7 @@
 with --warm, water40u_oracle_warm.json (trimers started from their
 monomer/dimer solutions) from the CPU oracle only.
 
-Full MBE(3) energy of configuration 1 (water40u, 89969 fragments), its
+Full MBE(3) energy of water40u (160 LMOs, 89969 fragments), its
 update-count histogram and every 1000th fragment energy, computed by
 oracle.run with a process pool.  Usage:
     python tests/golden/make_golden.py [workers] [--warm]
@@ -31,7 +31,7 @@ def main():
     E, _ = oracle.mbe3_energy(prob.frags, out["e_frag"])
     idx = np.arange(0, prob.n_frag, 1000)
     rec = {
-        "workload": "configuration 1 (water40u)",
+        "workload": "water40u (160 LMOs, 89969 fragments)",
         "start": "trimers from monomer/dimer solutions" if warm else "T = 0",
         "n_frag": int(prob.n_frag),
         "E_total": repr(float(E)),

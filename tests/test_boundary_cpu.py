@@ -37,7 +37,7 @@ def test_header_symbols_exported(pkg):
 @pytest.mark.parametrize("k", [0, 1])
 @pytest.mark.parametrize("precision", ["MBE3_FP64", "MBE3_MIXED_BF16",
                                        "MBE3_MIXED_BF16_PROJ"])
-def test_plan_check_configs(pkg, k, precision):
+def test_plan_check_small_workloads(pkg, k, precision):
     p = synth.config(k)
     prec = getattr(pkg, precision)
     lay = pkg.plan_check(r=p.r, pairs=p.pairs, frags=p.frags, n_vir=p.n_vir,
@@ -50,7 +50,7 @@ def test_plan_check_configs(pkg, k, precision):
 
 
 @pytest.mark.parametrize("k", [2, 4])
-def test_plan_check_large_configs(pkg, k):
+def test_plan_check_large_workloads(pkg, k):
     """Configurations 2 (470k fragments, D <= 128) and 4 (D <= 160) plan and
     pass every bounds check, both precisions."""
     p = synth.config(k)

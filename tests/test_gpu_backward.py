@@ -88,7 +88,7 @@ def check_vs_oracle(m, prob, tol_rel):
 
 
 def test_backward_chain8_vs_oracle(m):
-    say("case: chain8 (configs 0) backward vs oracle.gradient, tol 1e-11")
+    say("case: chain8 backward vs oracle.gradient, tol 1e-11")
     prob = dataclasses.replace(synth.config(0), tol=1e-11, max_iter=300)
     check_vs_oracle(m, prob, 1e-10)
 
@@ -197,12 +197,12 @@ def test_backward_errors(m):
 
 
 def test_backward_water40u_sampled(m):
-    """configs 1 (160 LMOs, 89969 fragments) in the benchmark's launch shape:
+    """water40u (160 LMOs, 89969 fragments) in the benchmark's launch shape:
     multipliers of sampled pair slots and dE/df of the same pairs against
     the oracle (every fragment containing the pair, solved one by one), and
     sampled dGamma blocks recomputed on the host from the multipliers."""
     import torch
-    say("case: water40u (configs 1) backward, sampled oracle slots")
+    say("case: water40u backward, sampled oracle slots")
     prob = synth.config(1)
     h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
     out = h.forward(grad=True)

@@ -90,7 +90,7 @@ def test_graph_replays_micro_forward_backward(m):
 def test_graph_timing_chain8(m):
     """Timing on while recording: the phase events live in the graph and
     every replay adds one region per recorded phase scope."""
-    say("case: chain8 (configs 0), recorded forward with timing, 2 replays")
+    say("case: chain8, recorded forward with timing, 2 replays")
     prob = synth.config(0)
     h = m.from_problem(prob)
     h.set_timing(True)
@@ -109,11 +109,11 @@ def test_graph_timing_chain8(m):
 
 
 def test_graph_replays_water40u_forward_backward(m):
-    """Configuration 1 (89969 fragments) forward + backward as one graph:
+    """water40u (89969 fragments) forward + backward as one graph:
     replays equal the eager step and the energy matches the oracle's full
     run (trimers warm-started)."""
     import torch
-    say("case: water40u (configs 1), recorded forward + backward, 2 replays vs eager")
+    say("case: water40u, recorded forward + backward, 2 replays vs eager")
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                     "water40u_oracle_warm.json")))
     prob = synth.config(1)

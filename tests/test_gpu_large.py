@@ -112,12 +112,12 @@ def gamma_block(h, prob, gamma, i, x):
 
 
 def test_water128u_sampled(m):
-    """configs 2 (512 LMOs, n_vir 2432, n_aux 7040, D up to 128, 470k
+    """water128u (512 LMOs, n_vir 2432, n_aux 7040, D up to 128, 470k
     fragments) in full on the GPU: every fragment converged and finite, and
     the fragments of one trimer with a 128-wide pair (with its dimers and
     monomers) against the oracle, one by one; its projected blocks too."""
     import torch
-    say("case: water128u (configs 2) full forward, sampled oracle trimer")
+    say("case: water128u full forward, sampled oracle trimer")
     prob = synth.config(2)
     h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
     out = h.forward()
@@ -151,7 +151,7 @@ def test_water128u_sampled(m):
 
 
 def test_helix1024_forward_and_gradient(m):
-    """configs 4 (1024 LMOs, n_vir 4096, n_aux 12288, D up to 160), FP64:
+    """helix1024 (1024 LMOs, n_vir 4096, n_aux 12288, D up to 160), FP64:
     every fragment converged and finite; projected blocks of the two LMOs
     with the most OSVs against the oracle on a subset of auxiliary columns;
     the gradient in the compressed (Gamma) layout, since a dense dE/d(ia|P)
@@ -159,7 +159,7 @@ def test_helix1024_forward_and_gradient(m):
     against a central difference of the GPU energy (h = 1e-4: the difference
     E(+h) - E(-h) is ~6e-9 Eh against ~1e-14 Eh of rounding in E)."""
     import torch
-    say("case: helix1024 (configs 4) forward and backward, FP64, tol 1e-10")
+    say("case: helix1024 forward and backward, FP64, tol 1e-10")
     # converged tighter than the workload's 1e-7: the stationarity argument
     # leaves a first-order error of the size of the residual, which is 1e-5
     # of these small f derivatives at tol 1e-7
@@ -205,11 +205,11 @@ def test_helix1024_forward_and_gradient(m):
 
 
 def test_water128u_mixed_vs_fp64(m):
-    """Both split-precision forms on the configs 2 workload (configs 3): total
+    """Both split-precision forms on water128u (512 LMOs, 470k fragments): total
     and per-fragment deviation from the FP64 GPU path, which the test above
     ties to the oracle on sampled fragments.  Budget 1e-6 Eh on the total."""
     import torch
-    say("case: water128u (configs 3: split precision on configs 2) vs FP64 path")
+    say("case: water128u in split precision vs FP64 path")
     prob = synth.config(2)
     h = m.from_problem(prob)
     out = h.forward()

@@ -107,7 +107,7 @@ FORMS = ["MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"]
 
 @pytest.mark.parametrize("form", FORMS)
 def test_mixed_products_chain8(m, form):
-    say(f"case: chain8 (configs 0) {form} projection and pair_K vs oracle")
+    say(f"case: chain8 {form} projection and pair_K vs oracle")
     check_products(m, synth.config(0), getattr(m, form))
 
 
@@ -149,11 +149,11 @@ def test_mixed_energy_micro(m, form):
 
 @pytest.mark.parametrize("form", FORMS)
 def test_mixed_energy_water40u(m, form):
-    """configs 1 in the benchmark's launch shape: the mixed total energy
+    """water40u (160 LMOs) in the benchmark's launch shape: the mixed total energy
     against the oracle's full run (|dE| <= 1e-6 Eh, the budget of the mixed
     form), and per-fragment deviations from the FP64 GPU path."""
     import torch
-    say(f"case: water40u (configs 1) {form} vs golden oracle and FP64 path")
+    say(f"case: water40u {form} vs golden oracle and FP64 path")
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                     "water40u_oracle.json")))
     E_ref = float(g["E_total"])
@@ -162,15 +162,25 @@ def test_mixed_energy_water40u(m, form):
     om = hm.forward()
     E_m = om["E"]
     em = om["e_frag"].cpu().numpy()
+    Km = om["K"].cpu().numpy()
     hm.close()
     del om, hm
     torch.cuda.empty_cache()
     hf = m.from_problem(prob)
-    of = hf.forward()
+    of = hf.forward(grad=True)
     ef = of["e_frag"].cpu().numpy()
+    est, per = m.first_order_dE(hf.k_off, prob.n_occ, Km, of["K"].cpu().numpy(),
+                                of["W"].cpu().numpy())
+    E_f = of["E"]
     hf.close()
     d = np.abs(em - ef)
+    top = np.argsort(-np.abs(per))[:3]
     say(f"water40u {form}: E = {E_m:.12f}, |E - E_oracle| = {abs(E_m - E_ref):.3e}, "
         f"max |dE_F| vs FP64 = {d.max():.3e}, mean {d.mean():.3e}")
+    say(f"  E - E_fp64 = {E_m - E_f:.4e}, first-order estimate {est:.4e}; "
+        f"largest slots {top.tolist()}: {per[top].tolist()}")
     assert abs(E_m - E_ref) <= 1e-6
+    # E depends on the split products only through K-bar: the estimate
+    # holds to second order (and the solver's stopping threshold)
+    assert abs(est - (E_m - E_f)) <= 0.05 * abs(E_m - E_f) + 1e-9
     assert d.max() <= 1e-7

@@ -56,7 +56,7 @@ def run_all(m, prob, **kw):
 
 
 def test_chain8_end_to_end(m):
-    say("case: chain8 (configs 0) full forward vs oracle (T = 0 starts)")
+    say("case: chain8 full forward vs oracle (T = 0 starts)")
     prob = synth.config(0)
     h, out = run_all(m, prob, warm_start=False)
     ref = oracle.run(prob)
@@ -158,10 +158,10 @@ def test_explicit_slab_matches_regenerated(m):
 
 
 def test_water40u_sampled(m):
-    """configs 1 (160 LMOs, 89969 fragments) in the benchmark's launch shape:
+    """water40u (160 LMOs, 89969 fragments) in the benchmark's launch shape:
     fragment energies of a deterministic sample against the oracle, one by
     one; projected blocks and K of sampled orbitals/pairs."""
-    say("case: water40u (configs 1) full forward, sampled oracle fragments")
+    say("case: water40u full forward, sampled oracle fragments")
     prob = synth.config(1)
     h, out = run_all(m, prob, warm_start=False)  # the oracle's iterates
     e = out["e_frag"].cpu().numpy()
@@ -229,12 +229,12 @@ def test_deterministic(m):
 
 
 def test_water40u_total_vs_golden(m):
-    """Full configuration 1: E against the oracle's full run (written by
+    """Full water40u (160 LMOs): E against the oracle's full run (written by
     tests/golden/make_golden.py, oracle only), |dE| <= 1e-10 Eh; the update
     count histogram and every 1000th fragment energy as well."""
     import json
     import os
-    say("case: water40u (configs 1) total energy vs golden oracle run")
+    say("case: water40u total energy vs golden oracle run")
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                     "water40u_oracle.json")))
     prob = synth.config(1)
@@ -258,7 +258,7 @@ def test_warm_start_water40u(m):
     the Hylleraas error of a stopping point is second order in the residual
     and of one sign, so over 84k trimers the two totals may differ by a few
     1e-9 Eh (each fragment by ~1e-12)."""
-    say("case: water40u (configs 1) warm vs T = 0 starts")
+    say("case: water40u warm vs T = 0 starts")
     prob = synth.config(1)
     hc, oc = run_all(m, prob, warm_start=False)
     ec, ic = oc["e_frag"].cpu().numpy(), oc["iters"].cpu().numpy()
@@ -279,13 +279,13 @@ def test_warm_start_water40u(m):
 
 
 def test_water40u_warm_vs_golden(m):
-    """Full configuration 1 as the benchmark runs it (trimers warm started)
+    """Full water40u (160 LMOs) as the benchmark runs it (trimers warm started)
     against the oracle's full run with the same starts (written by
     tests/golden/make_golden.py --warm): |dE| <= 1e-10 Eh, the update-count
     histogram, and every 1000th fragment energy."""
     import json
     import os
-    say("case: water40u (configs 1) warm-started total vs golden oracle run")
+    say("case: water40u warm-started total vs golden oracle run")
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                     "water40u_oracle_warm.json")))
     prob = synth.config(1)

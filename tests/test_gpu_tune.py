@@ -74,10 +74,10 @@ def test_every_shape_bitwise(m, prob_name):
 
 
 def test_autotune_water40u(m):
-    """Configuration 1: the tuned step equals the planned one bit for bit,
+    """water40u (160 LMOs): the tuned step equals the planned one bit for bit,
     and every list's report lists all shapes."""
     import torch
-    say("case: water40u (configs 1), autotune, tuned forward + backward vs planned")
+    say("case: water40u, autotune, tuned forward + backward vs planned")
     prob = synth.config(1)
     h = m.from_problem(prob)
     ref = step(h)
