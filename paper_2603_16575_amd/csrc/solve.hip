@@ -27,7 +27,10 @@
 // Panels go global -> registers (prefetched one step ahead) -> LDS: the
 // term's S~ panels land in a resident D_s x D_t block reused by pass 2 (which
 // then needs no barrier and hides the next term's first load), the Y^(T)
-// rows in two alternating 16-row buffers.  LDS per workgroup is
+// rows in two alternating 16-row buffers.  Only Y is kept in memory: a panel
+// of Y^T (16 rows of it) is read as 16-column strips of Y's rows and
+// transposed on its way into LDS, and the residual reads Y^T elements
+// straight from Y, so each sweep writes its amplitudes once, coalesced.  LDS per workgroup is
 // D_max^2 + 32 D_max doubles, so two fragments share a CU.  A diagonal pair's
 // mirror terms f S~ Y S~^T and its transpose are formed once and symmetrised
 // through LDS.
@@ -72,8 +75,18 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
         d2 *y_ = reinterpret_cast<d2 *>(yb);                                   \
         _Pragma("unroll") for (int u = 0; u < MAXNT; ++u) {                    \
           const int e = tid + 256 * u;                                         \
-          if (e < p_n1) s_[e] = pf[u];                                         \
-          else if (e - p_n1 < p_n2) y_[e - p_n1] = pf[u];                      \
+          if (e < p_n1) {                                                      \
+            s_[e] = pf[u];                                                     \
+          } else if (e - p_n1 < p_n2) {                                        \
+            const int q_ = e - p_n1;                                           \
+            if (p_tr) { /* Y[k][16 mp + c, c + 1] -> rows c, c + 1, col k */   \
+              const int k_ = q_ >> 3, c_ = 2 * (q_ & 7);                       \
+              yb[c_ * Ds + k_] = pf[u].x;                                      \
+              yb[(c_ + 1) * Ds + k_] = pf[u].y;                                \
+            } else {                                                           \
+              y_[q_] = pf[u];                                                  \
+            }                                                                  \
+          }                                                                    \
         }                                                                      \
       }                                                                        \
       /* the next panel streams in under the products; a term's last panel   \
@@ -133,8 +146,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
 
   double *scr = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int64_t ny_cap = (a.scratch_stride - 2LL * a.dmax * a.dmax) / 4;
-  double *const Y0 = scr;
-  double *const YT0 = scr + 2 * ny_cap;
+  double *const Y0 = scr;  // two buffers of ny_cap (current, next)
 
   d2 pf[MAXNT];  // next panel: S~ rows then Y^(T) rows
 
@@ -153,13 +165,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         const int D = sl.D;
         const double *src = a.warm + sl.kt_off;
         double *y = Y0 + fdp->ysub[tl];
-        double *yt = YT0 + fdp->ysub[tl];
-        for (int e = tid; e < D * D; e += 256) {
-          const int i = e / D, j = e - i * D;
-          const double v = src[e];
-          y[e] = v;
-          yt[(int64_t)j * D + i] = v;
-        }
+        for (int e = tid; e < D * D; e += 256) y[e] = src[e];
       }
       __syncthreads();
       hasY = true;
@@ -168,13 +174,12 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
       double mres = 0.0, epart = 0.0;
       int bad = 0;
       double *const Ycb = Y0 + (cur ? ny_cap : 0);
-      double *const YTcb = YT0 + (cur ? ny_cap : 0);
       double *const Ynb = Y0 + (cur ? 0 : ny_cap);
-      double *const YTnb = YT0 + (cur ? 0 : ny_cap);
 
       // ---- panel pipeline: step (ti, m) = rows 16m.. of S~ and of Y^(T) ----
       int p_ti = f_tb, p_m = 0;  // step held in pf
       int p_n1 = 0, p_n2 = 0;
+      bool p_tr = false;  // the Y part of pf is a strip of Y columns
 #define MBE3_LOAD_PANEL()                                                      \
   do {                                                                         \
     const Term tm_ = a.terms[p_ti];                                            \
@@ -182,14 +187,21 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     const int ds_ = a.slots[fdp->slot[tm_.src]].D;                             \
     const d2 *st_ = reinterpret_cast<const d2 *>(                              \
         (tm_.st_buf ? a.st1 : a.st0) + tm_.st_off + (int64_t)16 * p_m * dt_);  \
+    /* rows 16m.. of Y, or (transposed source) columns 16m.. of every row */  \
+    const double *ys_ = Ycb + fdp->ysub[tm_.src];                              \
     const d2 *y_ = reinterpret_cast<const d2 *>(                               \
-        (tm_.trans ? YTcb : Ycb) + fdp->ysub[tm_.src] + (int64_t)16 * p_m * ds_); \
+        tm_.trans ? ys_ + 16 * p_m : ys_ + (int64_t)16 * p_m * ds_);           \
     p_n1 = 8 * dt_;                                                            \
     p_n2 = 8 * ds_;                                                            \
+    p_tr = tm_.trans != 0;                                                     \
     _Pragma("unroll") for (int u = 0; u < MAXNT; ++u) {                        \
       const int e = tid + 256 * u;                                             \
-      if (e < p_n1) pf[u] = st_[e];                                            \
-      else if (e - p_n1 < p_n2) pf[u] = y_[e - p_n1];                          \
+      if (e < p_n1) {                                                          \
+        pf[u] = st_[e];                                                        \
+      } else if (e - p_n1 < p_n2) {                                            \
+        const int q_ = e - p_n1;                                               \
+        pf[u] = p_tr ? y_[(q_ >> 3) * (ds_ >> 1) + (q_ & 7)] : y_[q_];         \
+      }                                                                        \
     }                                                                          \
   } while (0)
 #define MBE3_ADVANCE()                                                         \
@@ -224,7 +236,6 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
               // (Y + Y^T for a diagonal target, whose mirror term is folded)
               const int sy = fdp->sym[tl];
               const double *Yc = Ycb + fdp->ysub[tl];
-              const double *YTc = YTcb + fdp->ysub[tl];
               double part = 0.0;
 #pragma unroll
               for (int rb = 0; rb < MAXRB; ++rb) {
@@ -234,8 +245,9 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
                   if (ib < nT && jb < nT) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                      const int64_t ij = (int64_t)(ib * 16 + lq + 4 * v) * Dt + jb * 16 + l16;
-                      const double wy = sy ? Yc[ij] + YTc[ij] : 2.0 * Yc[ij] - YTc[ij];
+                      const int i = ib * 16 + lq + 4 * v, j = jb * 16 + l16;
+                      const double y = Yc[(int64_t)i * Dt + j], yt = Yc[(int64_t)j * Dt + i];
+                      const double wy = sy ? y + yt : 2.0 * y - yt;
                       part += wy * acc[rb][jb][v];
                     }
                   }
@@ -250,9 +262,11 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         if (GRAD && gpass) {
           // <Y~, Y> of the target, for the f_pp and f_qq inside E~
           const double *Yc = Ycb + fdp->ysub[tl];
-          const double *YTc = YTcb + fdp->ysub[tl];
           double part = 0.0;
-          for (int e = tid; e < Dt * Dt; e += 256) part += (2.0 * Yc[e] - YTc[e]) * Yc[e];
+          for (int e = tid; e < Dt * Dt; e += 256) {
+            const int i = e / Dt, j = e - i * Dt;
+            part += (2.0 * Yc[e] - Yc[(int64_t)j * Dt + i]) * Yc[e];
+          }
           const double tot = wg_sum(part, red_d);
           if (tid == 0) a.gdiag[6 * fi + tl] = tot;
           continue;
@@ -280,9 +294,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         // ---- residual, energy, update for the owned rows of target tl ----
         const int ysub = fdp->ysub[tl];
         const double *Yc = Ycb + ysub;
-        const double *YTc = YTcb + ysub;
         double *Yn = Ynb + ysub;
-        double *YTn = YTnb + ysub;
         const double *Kt = a.kt + sl.kt_off;
         const double *et = a.et + sl.et_off;
         const double fpq = a.f_occ[(int64_t)sl.p * a.n_occ + sl.p] +
@@ -302,7 +314,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
                   const int i = ib * 16 + lq + 4 * v;
                   const int64_t ij = (int64_t)i * Dt + j;
                   const double y = hasY ? Yc[ij] : 0.0;
-                  const double yt = hasY ? YTc[ij] : 0.0;
+                  const double yt = hasY ? Yc[(int64_t)j * Dt + i] : 0.0;
                   const double kij = Kt[ij];
                   const double den = fpq - et[i] - ej;
                   const double sacc = sym ? acc[rb][jb][v] + Sl[j * Dt + i] : acc[rb][jb][v];
@@ -313,7 +325,6 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
                   epart += w * (2.0 * y - yt) * (kij + r);
                   const double yn = y + r / den;
                   Yn[ij] = yn;
-                  YTn[(int64_t)j * Dt + i] = yn;
                 }
               }
             }
@@ -365,8 +376,15 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           }
           // Y~ = 2Y - Y^T for the multipliers W, then one more pass over the
           // same amplitudes with unit coefficients for dE/df
-          for (int e = tid; e < fdp->ny; e += 256)
-            a.yfin[fdp->yout + e] = 2.0 * Ycb[e] - YTcb[e];
+          for (int tl = 0; tl < f_nt; ++tl) {
+            const int D = a.slots[fdp->slot[tl]].D;
+            const double *y = Ycb + fdp->ysub[tl];
+            double *o = a.yfin + fdp->yout + fdp->ysub[tl];
+            for (int e = tid; e < D * D; e += 256) {
+              const int i = e / D, j = e - i * D;
+              o[e] = 2.0 * y[e] - y[(int64_t)j * D + i];
+            }
+          }
           gpass = true;
           continue;
         }
