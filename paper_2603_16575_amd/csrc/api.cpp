@@ -1895,8 +1895,14 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
       const int per_cu = (int)std::max<size_t>(
           1, std::min<size_t>(4, (160 * 1024) / (solve_lds_bytes(c.dmax) + 2048)));
       const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu);
-      PhaseScope ps_(h, MBE3_PHASE_SOLVE);
-      HIP_TRY(h, launch_solve(a, nwg, s));
+      {
+        PhaseScope ps_(h, MBE3_PHASE_SOLVE);
+        HIP_TRY(h, launch_solve(a, nwg, s));
+      }
+      if (W) {  // dE/df contractions and Y~ at the converged amplitudes
+        PhaseScope ps_(h, MBE3_PHASE_GRAD);
+        HIP_TRY(h, launch_solve_grad(a, nwg, s));
+      }
     } else {
       const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256);
       PhaseScope ps_(h, MBE3_PHASE_SOLVE);

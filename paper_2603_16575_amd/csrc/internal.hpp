@@ -215,14 +215,19 @@ struct SolveArgs {
   int32_t *status;       // [2 * workgroup]: non-finite seen, non-converged seen
   double *warm;          // converged Y per slot (K~ layout), or null
   // gradient mode (all null otherwise): Y~ = 2Y - Y^T of the converged
-  // blocks per fragment (at FragDesc::yout), per-term contractions <Y~_t, S~ Y_s^(T) S~^T>
-  // (<Y_t + Y_t^T, .> for diagonal targets) indexed by term, and per-target
-  // <Y~_t, Y_t> at 6 * fragment + target.
+  // blocks per fragment (at FragDesc::yout; the LDS-resident solver stores Y
+  // there and its gradient pass turns it into Y~), per-term contractions
+  // <Y~_t, S~ Y_s^(T) S~^T> (<Y_t + Y_t^T, .> for diagonal targets) indexed
+  // by term, and per-target <Y~_t, Y_t> at 6 * fragment + target.
   double *yfin;
   double *gterm;
   double *gdiag;
 };
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s);
+// The gradient pass over a chunk that launch_solve solved with yfin set (the
+// same arguments and grid): per-term contractions, <Y~_t, Y_t>, and Y~ into
+// the store.
+hipError_t launch_solve_grad(const SolveArgs &a, int n_wg, hipStream_t s);
 // Variant for 96 < dmax <= 160 (solve_wide.hip): one wave per 16-row block,
 // panels streamed for both products, per-workgroup term sums in the scratch
 // (which must hold 4 ny + 2 dmax^2 doubles, as solve_scratch_doubles gives).

@@ -126,9 +126,17 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   } while (0)
 
 // MAXNT: largest number of 16-blocks per pair dimension (dmax / 16).
-// GRAD: also run the gradient pass after convergence.
-template <int MAXNT, bool GRAD>
+// MODE 0: solve.  MODE 1: solve and store each converged fragment's Y at
+// FragDesc::yout (zero if it converged at T = 0) for the gradient pass.
+// MODE 2: the gradient pass alone, a separate launch over the same
+// fragments: the stored Y goes back into the scratch, every term's product
+// is formed once more with unit coefficient and contracted with Y~, and the
+// store then receives Y~ = 2Y - Y^T for the multipliers.  Fragments that did
+// not converge (iters < 0) are skipped.  Keeping the pass out of the solving
+// launch keeps its registers out of the iterations.
+template <int MAXNT, int MODE>
 __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
+  constexpr bool ST = MODE == 1, GP = MODE == 2;
   extern __shared__ double lds[];
   constexpr int MAXRB = (MAXNT + 3) / 4;  // row blocks per wave
   __shared__ double red_d[8];
@@ -155,11 +163,15 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     const int f_nt = fdp->nt, f_frag = fdp->frag;
     const int f_tb = fdp->term_begin, f_te = fdp->term_end;
     int cur = 0;
-    bool gpass = false;  // GRAD: the extra pass at the converged amplitudes
     // amplitudes present: after a warm start from the solutions of the
     // fragment's own pairs (monomers, dimers), or after the first update
     bool hasY = false;
-    if (fdp->warm_in && a.warm) {
+    if (GP) {
+      if (a.iters[f_frag] < 0) continue;  // uniform over the workgroup
+      for (int e = tid; e < fdp->ny; e += 256) Y0[e] = a.yfin[fdp->yout + e];
+      __syncthreads();
+      hasY = true;
+    } else if (fdp->warm_in && a.warm) {
       for (int tl = 0; tl < f_nt; ++tl) {
         const SlotInfo sl = a.slots[fdp->slot[tl]];
         const int D = sl.D;
@@ -227,11 +239,11 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             const Term tm = a.terms[ti];
             if (tm.target != tl) continue;
             const double coef =
-                (GRAD && gpass) ? 1.0 : a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
+                GP ? 1.0 : a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
             const int Ds = a.slots[fdp->slot[tm.src]].D;
             const int nS = Ds >> 4;
             MBE3_TERM_PRODUCTS(coef);
-            if (GRAD && gpass) {
+            if (GP) {
               // this term's product alone, contracted with Y~ = 2Y - Y^T
               // (Y + Y^T for a diagonal target, whose mirror term is folded)
               const int sy = fdp->sym[tl];
@@ -259,7 +271,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             }
           }
         }
-        if (GRAD && gpass) {
+        if (GP) {
           // <Y~, Y> of the target, for the f_pp and f_qq inside E~
           const double *Yc = Ycb + fdp->ysub[tl];
           double part = 0.0;
@@ -331,7 +343,20 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           }
         }
       }
-      if (GRAD && gpass) break;
+      if (GP) {
+        // Y~ = 2Y - Y^T for the multipliers, over the stored Y
+        for (int tl = 0; tl < f_nt; ++tl) {
+          const int D = a.slots[fdp->slot[tl]].D;
+          const double *y = Ycb + fdp->ysub[tl];
+          double *o = a.yfin + fdp->yout + fdp->ysub[tl];
+          for (int e = tid; e < D * D; e += 256) {
+            const int i = e / D, j = e - i * D;
+            o[e] = 2.0 * y[e] - y[(int64_t)j * D + i];
+          }
+        }
+        __syncthreads();  // the scratch is read; the next fragment refills it
+        break;
+      }
       // block reductions (fixed order: deterministic)
       for (int o = 32; o > 0; o >>= 1) {
         mres = fmax(mres, __shfl_xor(mres, o));
@@ -366,28 +391,13 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           for (int e = tid; e < sl.D * sl.D; e += 256)
             a.warm[sl.kt_off + e] = hasY && !B ? src[e] : 0.0;
         }
-        if (GRAD && conv && !B) {
-          if (!hasY) {
-            // converged at T = 0 (K~ below the threshold): all zero
-            for (int e = tid; e < fdp->ny; e += 256) a.yfin[fdp->yout + e] = 0.0;
-            for (int ti = f_tb + tid; ti < f_te; ti += 256) a.gterm[ti] = 0.0;
-            if (tid < f_nt) a.gdiag[6 * fi + tid] = 0.0;
-            break;
-          }
-          // Y~ = 2Y - Y^T for the multipliers W, then one more pass over the
-          // same amplitudes with unit coefficients for dE/df
-          for (int tl = 0; tl < f_nt; ++tl) {
-            const int D = a.slots[fdp->slot[tl]].D;
-            const double *y = Ycb + fdp->ysub[tl];
-            double *o = a.yfin + fdp->yout + fdp->ysub[tl];
-            for (int e = tid; e < D * D; e += 256) {
-              const int i = e / D, j = e - i * D;
-              o[e] = 2.0 * y[e] - y[(int64_t)j * D + i];
-            }
-          }
-          gpass = true;
-          continue;
+        if (ST && conv && !B) {
+          // the converged amplitudes (zero if converged at T = 0) for the
+          // gradient pass
+          for (int e = tid; e < fdp->ny; e += 256)
+            a.yfin[fdp->yout + e] = hasY ? Ycb[e] : 0.0;
         }
+        __syncthreads();  // the scratch is read; the next fragment refills it
         break;
       }
       hasY = true;
@@ -407,34 +417,39 @@ size_t solve_lds_bytes(int dmax) {
   return (size_t)(dmax * dmax + 32 * dmax) * sizeof(double);
 }
 
-template <int NT, bool GRAD>
+template <int NT, int MODE>
 static hipError_t launch_nt_g(const SolveArgs &a, int n_wg, hipStream_t s) {
   const size_t smem = solve_lds_bytes(a.dmax);
-  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT, GRAD>,
+  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT, MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((solve_kernel<NT, GRAD>), dim3(n_wg), dim3(256), smem, s, a);
+  hipLaunchKernelGGL((solve_kernel<NT, MODE>), dim3(n_wg), dim3(256), smem, s, a);
   return hipGetLastError();
 }
 
-template <int NT>
-static hipError_t launch_nt(const SolveArgs &a, int n_wg, hipStream_t s) {
-  return a.yfin ? launch_nt_g<NT, true>(a, n_wg, s) : launch_nt_g<NT, false>(a, n_wg, s);
-}
-
-hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s) {
+template <int MODE>
+static hipError_t launch_mode(const SolveArgs &a, int n_wg, hipStream_t s) {
   if (a.n_frag <= 0) return hipSuccess;
   if (solve_lds_bytes(a.dmax) > 150 * 1024) return hipErrorInvalidValue;
   switch (a.dmax / 16) {
     case 1:
-    case 2: return launch_nt<2>(a, n_wg, s);
-    case 3: return launch_nt<3>(a, n_wg, s);
-    case 4: return launch_nt<4>(a, n_wg, s);
-    case 5: return launch_nt<5>(a, n_wg, s);
-    case 6: return launch_nt<6>(a, n_wg, s);
+    case 2: return launch_nt_g<2, MODE>(a, n_wg, s);
+    case 3: return launch_nt_g<3, MODE>(a, n_wg, s);
+    case 4: return launch_nt_g<4, MODE>(a, n_wg, s);
+    case 5: return launch_nt_g<5, MODE>(a, n_wg, s);
+    case 6: return launch_nt_g<6, MODE>(a, n_wg, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s) {
+  return a.yfin ? launch_mode<1>(a, n_wg, s) : launch_mode<0>(a, n_wg, s);
+}
+
+hipError_t launch_solve_grad(const SolveArgs &a, int n_wg, hipStream_t s) {
+  if (!a.yfin || !a.gterm || !a.gdiag) return hipErrorInvalidValue;
+  return launch_mode<2>(a, n_wg, s);
 }
 
 }  // namespace mbe3
