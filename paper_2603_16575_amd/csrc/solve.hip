@@ -170,6 +170,23 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
       if (a.iters[f_frag] < 0) continue;  // uniform over the workgroup
       for (int e = tid; e < fdp->ny; e += 256) Y0[e] = a.yfin[fdp->yout + e];
       __syncthreads();
+      // the contraction weights of every target (Y + Y^T for a diagonal
+      // one, else 2Y - Y^T) into the second buffer, and <Y~_t, Y_t>
+      for (int tl = 0; tl < f_nt; ++tl) {
+        const int D = a.slots[fdp->slot[tl]].D;
+        const int sy = fdp->sym[tl];
+        const double *y = Y0 + fdp->ysub[tl];
+        double *wy = Y0 + ny_cap + fdp->ysub[tl];
+        double part = 0.0;
+        for (int e = tid; e < D * D; e += 256) {
+          const int i = e / D, j = e - i * D;
+          const double yv = y[e], yt = y[(int64_t)j * D + i];
+          wy[e] = sy ? yv + yt : 2.0 * yv - yt;
+          part += (2.0 * yv - yt) * yv;
+        }
+        const double tot = wg_sum(part, red_d);  // also orders the wy writes
+        if (tid == 0) a.gdiag[6 * fi + tl] = tot;
+      }
       hasY = true;
     } else if (fdp->warm_in && a.warm) {
       for (int tl = 0; tl < f_nt; ++tl) {
@@ -246,8 +263,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             if (GP) {
               // this term's product alone, contracted with Y~ = 2Y - Y^T
               // (Y + Y^T for a diagonal target, whose mirror term is folded)
-              const int sy = fdp->sym[tl];
-              const double *Yc = Ycb + fdp->ysub[tl];
+              const double *Wy = Y0 + ny_cap + fdp->ysub[tl];
               double part = 0.0;
 #pragma unroll
               for (int rb = 0; rb < MAXRB; ++rb) {
@@ -258,9 +274,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                       const int i = ib * 16 + lq + 4 * v, j = jb * 16 + l16;
-                      const double y = Yc[(int64_t)i * Dt + j], yt = Yc[(int64_t)j * Dt + i];
-                      const double wy = sy ? y + yt : 2.0 * y - yt;
-                      part += wy * acc[rb][jb][v];
+                      part += Wy[(int64_t)i * Dt + j] * acc[rb][jb][v];
                     }
                   }
                   acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
@@ -271,18 +285,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             }
           }
         }
-        if (GP) {
-          // <Y~, Y> of the target, for the f_pp and f_qq inside E~
-          const double *Yc = Ycb + fdp->ysub[tl];
-          double part = 0.0;
-          for (int e = tid; e < Dt * Dt; e += 256) {
-            const int i = e / Dt, j = e - i * Dt;
-            part += (2.0 * Yc[e] - Yc[(int64_t)j * Dt + i]) * Yc[e];
-          }
-          const double tot = wg_sum(part, red_d);
-          if (tid == 0) a.gdiag[6 * fi + tl] = tot;
-          continue;
-        }
+        if (GP) continue;  // no residual in the gradient pass
 
         const int sym = fdp->sym[tl];
         if (sym) {  // diagonal pair: R~ gets acc + acc^T (mirror terms)
