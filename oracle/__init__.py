@@ -16,6 +16,8 @@ equations and algorithms:
   O6 solve_fragment  Jacobi iterations + Hylleraas energy  (Alg. 7)
   O7 mbe3_energy     MBE(3) inclusion-exclusion            (eqs. tmbediag, tmbeoff)
   O8 gradient        dE/d(ia|P), dE/df via stationarity    (derived; no paper formula)
+  O9 weak.s2b, ...   pair metrics, classes, trimer screen  (eqs. s2b, s3b)
+  O10 weak.weak_pair one-block weak-pair amplitudes/energy (eqs. osv_weak_k, res_weak)
 
 Pins (tests/test_oracle_*.py) tie each step to something other than itself:
 numpy's own Philox, a full-space Kronecker dense solve, the canonical MP2
@@ -27,8 +29,9 @@ differences.
 from .mbe3 import (Oracle, gradient, energy, fragment_gradient,
                    mbe3_coefficients, mbe3_energy, orbs, run, slab, swap_blocks)
 from .philox import box_muller, philox4x64_10
+from . import weak
 
 __all__ = ["Oracle", "gradient", "energy", "fragment_gradient",
            "mbe3_coefficients", "mbe3_energy",
            "orbs", "run", "slab", "swap_blocks", "box_muller",
-           "philox4x64_10"]
+           "philox4x64_10", "weak"]
