@@ -285,6 +285,44 @@ int mbe3_get_timing(mbe3_handle *h, double *ms, int64_t *launches);
 int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
 
 /*
+ * Pair screening metric of eq. s2b for each listed pair:
+ *   s2b[k] = sum_{mu nu} <mu_i|nu_j>^2 / sqrt(r_i r_j),  (i, j) = pairs[k],
+ * the squared norm of the OSV overlap block S_(i,j) = Q_i^T Q_j.  The paper
+ * calls a pair distant below 1e-7, weak below 1e-2 and close otherwise, and
+ * keeps a trimer when the mean of its three pair metrics (eq. s3b) is at
+ * least 0.2; those decisions are the caller's.
+ * pairs: host [n][2], two distinct LMOs each, any order.  s2b: device [n].
+ * Allocates and frees device memory for the overlap blocks (sum r_i r_j
+ * doubles) inside the call, so it cannot be recorded; synchronises the
+ * stream.  MBE3_EINVAL for a bad pair or while recording.
+ */
+int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b);
+
+/*
+ * Weak pairs (the weak-pair part of Algorithm 7): energies of pairs left
+ * out of the fragment list, from the one-block exchange integrals
+ * K_(i,j) = Gamma~_(i,i) Gamma~_(j,j)^T (eq. osv_weak_k) and the one-block
+ * residual of eq. res_weak, read so that it type-checks,
+ *   R_(i,j) = K_(i,j) + T_(i,j) F_(j,j) + F_(i,i) T_(i,j)
+ *             - (f_ii + f_jj) T_(i,j) - f_ij [T_(i,i) S_(i,j) + S_(i,j) T_(j,j)],
+ * solved in one step in the diagonal pairs' pseudo-canonical bases
+ * (eq. prec_eig), and the energy of each unordered pair
+ *   e[k] = 4 <K_(i,j), T_(i,j)>
+ * (the close-pair energy restricted to the one block; the exchange block is
+ * dropped with the exchange amplitudes).  T_(i,i) are the MBE(3) diagonal
+ * amplitudes (eq. tmbediag): the diagonal-slot blocks of W.
+ * pairs: host [n][2] with 0 <= i < j < n_occ.  gamma: device, osv_project's
+ * output (FP64).  W: device, K layout; fragment_solve's multipliers (their
+ * diagonal slots are T^MBE_ii), or any caller blocks.  e: device [n].
+ * Runs the pair-basis preparation of fragment_solve, allocates and frees
+ * its blocks (about 3 sum r_i r_j + 2 sum D_i D_j + sum D_i r_j doubles)
+ * inside the call, so it cannot be recorded; synchronises the stream.
+ * MBE3_EINVAL for a bad pair or argument or while recording.
+ */
+int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const double *gamma,
+                    const double *W, double *e);
+
+/*
  * Recorded launches (one HIP graph per handle) for the batched form of
  * Algorithm 7: thousands of fragments per call, replayed without host work.
  *

@@ -22,7 +22,8 @@ __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
            "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
            "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
            "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16",
-           "MBE3_MIXED_BF16_PROJ", "first_order_dE"]
+           "MBE3_MIXED_BF16_PROJ", "first_order_dE",
+           "pair_classes", "keep_trimers"]
 
 
 def _f64(t):
@@ -177,6 +178,30 @@ class Mbe3:
         _lib.check(_lib.load().mbe3_pair_basis(self._h, _lib.ptr(X), _lib.ptr(et),
                                                _lib.ptr(rank)), self._h)
         return X, et, rank
+
+    def screen(self, pairs):
+        """s2b (eq. s2b) of each listed pair (host int array [n, 2]) as a
+        float64 tensor on the device; see pair_classes for the paper's
+        thresholds."""
+        import torch
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        out = torch.empty(len(pr), dtype=torch.float64, device=self.device)
+        _lib.check(_lib.load().mbe3_screen(self._h, _lib.ptr(pr), len(pr),
+                                           _lib.ptr(out)), self._h)
+        return out
+
+    def weak_pairs(self, pairs, gamma, W):
+        """Energies of weak pairs (host int array [n, 2], i < j) from
+        osv_project's gamma and fragment_solve's multipliers W (their
+        diagonal slots are the MBE(3) diagonal amplitudes), as a float64
+        tensor on the device."""
+        import torch
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        e = torch.empty(len(pr), dtype=torch.float64, device=self.device)
+        _lib.check(_lib.load().mbe3_weak_pairs(self._h, _lib.ptr(pr), len(pr),
+                                               _lib.ptr(_f64(gamma)), _lib.ptr(_f64(W)),
+                                               _lib.ptr(e)), self._h)
+        return e
 
     def set_timing(self, enable=True):
         _lib.check(_lib.load().mbe3_set_timing(self._h, int(bool(enable))), self._h)
@@ -335,6 +360,23 @@ def first_order_dE(k_off, n_occ, K_a, K_b, W):
     per = np.add.reduceat(prod[:k_off[-1]], k_off[:-1]) if n_slot else np.zeros(0)
     per *= np.where(np.arange(n_slot) < n_occ, 2.0, 4.0)
     return float(per.sum()), per
+
+
+# pair classes and trimer screening (section on OSV overlap and Fock
+# computation): s2b below 1e-7 distant, below 1e-2 weak, else close; trimers
+# whose mean pair metric (eq. s3b) is below 0.2 are dropped
+S2B_DISTANT, S2B_CLOSE, S3B_KEEP = 1e-7, 1e-2, 0.2
+
+
+def pair_classes(s2b):
+    """0 distant, 1 weak, 2 close for each s2b value (host array)."""
+    s = np.asarray(s2b, dtype=np.float64)
+    return np.where(s < S2B_DISTANT, 0, np.where(s < S2B_CLOSE, 1, 2)).astype(np.int8)
+
+
+def keep_trimers(s_ij, s_ik, s_jk):
+    """True where the trimer's s3b (eq. s3b) reaches the threshold."""
+    return (np.asarray(s_ij) + np.asarray(s_ik) + np.asarray(s_jk)) / 3.0 >= S3B_KEEP
 
 
 def osv_project(h, gamma):

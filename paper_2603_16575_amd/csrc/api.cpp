@@ -35,7 +35,9 @@ inline int64_t key2(int a, int b) { return ((int64_t)a << 32) | (uint32_t)b; }
 enum Base {
   B_Q = 0, B_EQ, B_SLAB, B_GAMMA, B_K, B_SS, B_FS, B_PS, B_PF, B_X0, B_X,
   B_TMP, B_FP, B_Z, B_KT, B_AT, B_MT, B_ST0, B_CA, B_CM, B_ST1,
-  B_WT, B_W, B_GA, B_DG, B_DB, B_COUNT
+  B_WT, B_W, B_GA, B_DG, B_DB,
+  // call-time blocks of mbe3_screen / mbe3_weak_pairs
+  B_PK, B_PS2, B_PM, B_PP, B_PKT, B_PDT, B_COUNT
 };
 static_assert(B_COUNT <= NBASE, "too many GEMM bases");
 
@@ -1684,6 +1686,83 @@ void release_graph(mbe3_handle *h) {
   h->g_solve = h->g_grad = h->g_energy = false;
 }
 
+// Device memory of one call, released (after the stream has drained) when
+// the call returns.
+struct CallTemp {
+  mbe3_handle *h;
+  std::vector<void *> ps;
+  explicit CallTemp(mbe3_handle *hh) : h(hh) {}
+  ~CallTemp() {
+    if (ps.empty()) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (void *p : ps) (void)hipFree(p);
+  }
+  template <class T>
+  int alloc(T **p, int64_t n) {
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return h->fail(MBE3_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+                     (long long)(n * (int64_t)sizeof(T)), hipGetErrorString(e));
+    }
+    ps.push_back(q);
+    *p = (T *)q;
+    return MBE3_OK;
+  }
+  template <class T>
+  int upload(T **p, const std::vector<T> &v) {
+    const int rc = alloc(p, (int64_t)v.size());
+    if (rc || v.empty()) return rc;
+    HIP_TRY(h, hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MBE3_OK;
+  }
+};
+
+// Pairs of a screening / weak-pair call, checked and laid out: r_i x r_j
+// blocks, D_i x D_j blocks and the X_i^T (.) temporaries (D_i x r_j).
+static int weak_layout(mbe3_handle *h, const int32_t *pairs, int64_t n, bool ordered,
+                       std::vector<WeakPair> &wp, int64_t *k_tot, int64_t *t_tot,
+                       int64_t *p_tot, std::vector<int64_t> &p_off) {
+  if (n > 0x7fffffffLL / 4) return h->fail(MBE3_EINVAL, "too many pairs (%lld)", (long long)n);
+  wp.resize(n);
+  p_off.resize(n);
+  int64_t ko = 0, to = 0, po = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const int i = pairs[2 * k], j = pairs[2 * k + 1];
+    if (i < 0 || j < 0 || i >= h->n_occ || j >= h->n_occ || i == j || (ordered && i > j))
+      return h->fail(MBE3_EINVAL, "pair %lld (%d, %d) is not %s", (long long)k, i, j,
+                     ordered ? "0 <= i < j < n_occ" : "two distinct LMOs");
+    WeakPair w;
+    w.i = i; w.j = j; w.ri = h->r[i]; w.rj = h->r[j];
+    w.Di = h->sD[i]; w.Dj = h->sD[j];  // the diagonal slots i and j
+    w.k_off = ko; w.t_off = to;
+    w.ei = h->et_off[i]; w.ej = h->et_off[j];
+    wp[k] = w;
+    p_off[k] = po;
+    ko += (int64_t)w.ri * w.rj;
+    to += (int64_t)w.Di * w.Dj;
+    po += (int64_t)w.Di * w.rj;
+  }
+  *k_tot = ko; *t_tot = to; *p_tot = po;
+  return MBE3_OK;
+}
+
+// One call-time task list: bounds-checked against sz, tiled, uploaded and
+// launched on the handle's stream.
+static int run_call_list(mbe3_handle *h, CallTemp &tmp, const char *name,
+                         std::vector<GemmTask> &ts, const int64_t *sz, const GemmBases &b,
+                         GemmShape shape) {
+  if (ts.empty()) return MBE3_OK;
+  const int64_t tiles = finish_tasks(ts, shape);
+  int rc = check_gemm_list(h, name, ts, sz, std::vector<int32_t>(), shape);
+  if (rc) return rc;
+  GemmTask *d = nullptr;
+  if ((rc = tmp.upload(&d, ts))) return rc;
+  HIP_TRY(h, launch_gemm_tasks(d, (int)ts.size(), tiles, b, shape, h->stream));
+  return MBE3_OK;
+}
+
 extern "C" {
 
 int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
@@ -2050,6 +2129,111 @@ int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank) {
                             hipMemcpyDeviceToDevice, s));
   HIP_TRY(h, hipMemcpyAsync(rank, h->rank, h->n_slot * sizeof(int32_t),
                             hipMemcpyDeviceToDevice, s));
+  return MBE3_OK;
+}
+
+int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
+  if (!h) return MBE3_EINVAL;
+  if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_screen allocates: not recordable");
+  if (n < 0 || (n > 0 && (!pairs || !s2b)))
+    return h->fail(MBE3_EINVAL, "pairs and s2b required for n > 0");
+  if (n == 0) return MBE3_OK;
+  std::vector<WeakPair> wp;
+  std::vector<int64_t> p_off;
+  int64_t ko, to, po;
+  int rc = weak_layout(h, pairs, n, false, wp, &ko, &to, &po, p_off);
+  if (rc) return rc;
+  CallTemp tmp(h);
+  double *S = nullptr;
+  WeakPair *d_wp = nullptr;
+  if ((rc = tmp.alloc(&S, ko)) || (rc = tmp.upload(&d_wp, wp))) return rc;
+  const int nv = h->n_vir;
+  std::vector<GemmTask> ts;
+  for (const WeakPair &w : wp)  // S_(i,j) = Q_i^T Q_j (rows of the packed Q)
+    ts.push_back(gemm(B_Q, h->q_off[w.i] * nv, nv, 0, B_Q, h->q_off[w.j] * nv, nv, 1,
+                      B_PS2, w.k_off, w.rj, w.ri, w.rj, nv));
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  sz[B_PS2] = ko;
+  GemmBases b = bases(h);
+  b.p[B_PS2] = S;
+  if ((rc = run_call_list(h, tmp, "screen S", ts, sz, b, GEMM_32x32))) return rc;
+  HIP_TRY(h, launch_s2b(d_wp, (int)n, S, s2b, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return MBE3_OK;
+}
+
+int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const double *gamma,
+                    const double *W, double *e) {
+  if (!h) return MBE3_EINVAL;
+  if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_weak_pairs allocates: not recordable");
+  if (n < 0 || (n > 0 && (!pairs || !gamma || !W || !e)))
+    return h->fail(MBE3_EINVAL, "pairs, gamma, W and e required for n > 0");
+  if (n == 0) return MBE3_OK;
+  std::vector<WeakPair> wp;
+  std::vector<int64_t> p_off;
+  int64_t ko, to, po;
+  int rc = weak_layout(h, pairs, n, true, wp, &ko, &to, &po, p_off);
+  if (rc) return rc;
+  if ((rc = prepare_bases(h))) return rc;  // X, eps~ and ranks of the diagonal slots
+  CallTemp tmp(h);
+  double *Kb = nullptr, *Sb = nullptr, *Mb = nullptr, *Pb = nullptr, *Kt = nullptr,
+         *Dt = nullptr;
+  WeakPair *d_wp = nullptr;
+  if ((rc = tmp.alloc(&Kb, ko)) || (rc = tmp.alloc(&Sb, ko)) || (rc = tmp.alloc(&Mb, ko)) ||
+      (rc = tmp.alloc(&Pb, po)) || (rc = tmp.alloc(&Kt, to)) || (rc = tmp.alloc(&Dt, to)) ||
+      (rc = tmp.upload(&d_wp, wp)))
+    return rc;
+  const int nv = h->n_vir, na = h->n_aux;
+  std::vector<GemmTask> lk, ls, lm1, lm2, lxk, lkx, lxm, lmx;
+  for (int64_t k = 0; k < n; ++k) {
+    const WeakPair &w = wp[k];
+    const int64_t gi = h->grow.at(key2(w.i, w.i)), gj = h->grow.at(key2(w.j, w.j));
+    // K_(i,j) = Gamma~_(i,i) Gamma~_(j,j)^T (eq. osv_weak_k)
+    lk.push_back(gemm(B_GAMMA, gi * na, na, 0, B_GAMMA, gj * na, na, 1, B_PK, w.k_off,
+                      w.rj, w.ri, w.rj, na));
+    // S_(i,j) = Q_i^T Q_j
+    ls.push_back(gemm(B_Q, h->q_off[w.i] * nv, nv, 0, B_Q, h->q_off[w.j] * nv, nv, 1,
+                      B_PS2, w.k_off, w.rj, w.ri, w.rj, nv));
+    // M = T_ii S_(i,j) + S_(i,j) T_jj, T_ii the diagonal slot blocks of W
+    lm1.push_back(gemm(B_W, h->k_off[w.i], w.ri, 0, B_PS2, w.k_off, w.rj, 0, B_PM, w.k_off,
+                       w.rj, w.ri, w.rj, w.ri));
+    lm2.push_back(gemm(B_PS2, w.k_off, w.rj, 0, B_W, h->k_off[w.j], w.rj, 0, B_PM, w.k_off,
+                       w.rj, w.ri, w.rj, w.rj, 1.0, 1.0));
+    // K~ = X_i^T K X_j and D~ = X_i^T M X_j (X: d x D, row-major)
+    lxk.push_back(gemm(B_X, h->x_off[w.i], w.Di, 1, B_PK, w.k_off, w.rj, 0, B_PP, p_off[k],
+                       w.rj, w.Di, w.rj, w.ri));
+    lkx.push_back(gemm(B_PP, p_off[k], w.rj, 0, B_X, h->x_off[w.j], w.Dj, 0, B_PKT, w.t_off,
+                       w.Dj, w.Di, w.Dj, w.rj));
+    lxm.push_back(gemm(B_X, h->x_off[w.i], w.Di, 1, B_PM, w.k_off, w.rj, 0, B_PP, p_off[k],
+                       w.rj, w.Di, w.rj, w.ri));
+    lmx.push_back(gemm(B_PP, p_off[k], w.rj, 0, B_X, h->x_off[w.j], w.Dj, 0, B_PDT, w.t_off,
+                       w.Dj, w.Di, w.Dj, w.rj));
+  }
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  sz[B_W] = h->k_elems;
+  sz[B_PK] = sz[B_PS2] = sz[B_PM] = ko;
+  sz[B_PP] = po;
+  sz[B_PKT] = sz[B_PDT] = to;
+  GemmBases b = bases(h);
+  b.p[B_GAMMA] = const_cast<double *>(gamma);
+  b.p[B_W] = const_cast<double *>(W);
+  b.p[B_PK] = Kb; b.p[B_PS2] = Sb; b.p[B_PM] = Mb; b.p[B_PP] = Pb;
+  b.p[B_PKT] = Kt; b.p[B_PDT] = Dt;
+  // stream order: each list reads what the ones before it wrote
+  if ((rc = run_call_list(h, tmp, "weak K", lk, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak S", ls, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak T S", lm1, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak S T", lm2, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak X^T K", lxk, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak K~", lkx, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak X^T M", lxm, sz, b, GEMM_32x32)) ||
+      (rc = run_call_list(h, tmp, "weak D~", lmx, sz, b, GEMM_32x32)))
+    return rc;
+  HIP_TRY(h, launch_weak_energy(d_wp, (int)n, Kt, Dt, h->et, h->rank, h->f, h->n_occ, e,
+                                h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
   return MBE3_OK;
 }
 

@@ -295,6 +295,21 @@ hipError_t launch_mbe_sum(const double *e_frag, const double *coef, int64_t n,
 hipError_t launch_increments(const double *e_frag, const int32_t *sub,
                              int64_t n, double *incr, hipStream_t s);
 hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Pair screening and weak pairs (weak.hip).  Per listed pair (i, j): its
+// r_i x r_j blocks at k_off (S_(i,j), K_(i,j)), its D_i x D_j blocks at t_off
+// (K~, D~) and the offsets of eps~ of the diagonal slots i and j.
+// ---------------------------------------------------------------------------
+struct WeakPair {
+  int32_t i, j, ri, rj, Di, Dj;
+  int64_t k_off, t_off, ei, ej;
+};
+hipError_t launch_s2b(const WeakPair *wp, int n, const double *S, double *out,
+                      hipStream_t s);
+hipError_t launch_weak_energy(const WeakPair *wp, int n, const double *Kt, const double *Dt,
+                              const double *et, const int32_t *rank, const double *f,
+                              int n_occ, double *e, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
 }  // namespace mbe3

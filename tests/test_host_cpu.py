@@ -58,3 +58,14 @@ def test_first_order_dE_matches_finite_difference(pkg):
     mask[:k_off[prob.n_occ]] = 1.0
     e_diag, _ = pkg.first_order_dE(k_off, prob.n_occ, K0 + mask * dK, K0, W)
     assert np.isclose(e_diag, 2.0 * float(np.sum((mask * dK) * W)))
+
+
+def test_pair_classes_match_oracle(pkg):
+    """The package's class and trimer helpers use the oracle's thresholds."""
+    from oracle import weak
+    vals = [0.0, 5e-8, 1e-7, 2e-4, 9.99e-3, 1e-2, 0.5]
+    names = {0: "distant", 1: "weak", 2: "close"}
+    got = pkg.pair_classes(vals)
+    assert [names[int(c)] for c in got] == [weak.pair_class(v) for v in vals]
+    trip = [(0.3, 0.2, 0.1 + 1e-12), (0.3, 0.2, 0.1 - 1e-9), (0.05, 0.01, 0.02)]
+    assert [bool(pkg.keep_trimers(*t)) for t in trip] == [weak.keep_trimer(*t) for t in trip]
