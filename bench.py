@@ -300,6 +300,39 @@ def mixed_run(m, prob, args, dev, E64, e64, ref64, form):
     return out
 
 
+def weak_run(m, prob, h, gamma, W, E_mbe3):
+    """Pairs the cutoff left out of the fragment list: s2b of each
+    (mbe3_screen), classes, and the weak-pair energies (mbe3_weak_pairs) of
+    those not distant, from the step's own gamma and multipliers.  Both calls
+    synchronise; the second of two runs is timed by the host clock."""
+    import torch
+    n = prob.n_occ
+    kept = set(map(tuple, np.asarray(prob.pairs).tolist()))
+    rest = np.array([(i, j) for i in range(n) for j in range(i + 1, n)
+                     if (i, j) not in kept], dtype=np.int32).reshape(-1, 2)
+    out = {"pairs_beyond_cutoff": int(len(rest))}
+    if not len(rest):
+        return out
+    for _ in range(2):
+        t0 = time.perf_counter()
+        s2b = h.screen(rest)
+        t_screen = (time.perf_counter() - t0) * 1e3
+    cls = m.pair_classes(s2b.cpu().numpy())
+    weak = rest[cls > 0]
+    for _ in range(2):
+        t0 = time.perf_counter()
+        e = h.weak_pairs(weak, gamma, W)
+        t_weak = (time.perf_counter() - t0) * 1e3
+    E_weak = float(e.sum())
+    out.update({"classes_distant_weak_close": np.bincount(cls, minlength=3).tolist(),
+                "pairs_treated_weak": int(len(weak)),
+                "screen_ms": round(t_screen, 3), "weak_pairs_ms": round(t_weak, 3),
+                "E_weak": E_weak, "E_mbe3_plus_weak": E_mbe3 + E_weak})
+    log(f"bench: weak pairs: {len(weak)} of {len(rest)} beyond the cutoff, "
+        f"E_weak {E_weak:.6e}, screen {t_screen:.2f} ms, weak {t_weak:.2f} ms")
+    return out
+
+
 def _call_pool_fn(x):
     from oracle import mbe3 as om
     return om._POOL_ORACLE(x)
@@ -393,6 +426,7 @@ def main():
     e64 = e.cpu().numpy().copy()
     E64 = E
     ref64 = (bufs["K"].cpu().numpy(), bufs["W"].cpu().numpy())  # for the mixed runs
+    weak_info = weak_run(m, prob, h, bufs["gamma"], bufs["W"], E)
     # call-by-call steps, for the cost of launching without the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -498,6 +532,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed_bf16": mixed.get("MBE3_MIXED_BF16"),
         "mixed_bf16_proj": mixed.get("MBE3_MIXED_BF16_PROJ"),
+        "weak_pairs": weak_info,
     }
     for mx in mixed.values():
         mx["speedup_vs_fp64"] = round(ms_step / mx["ms_per_step"], 4)
