@@ -314,9 +314,11 @@ int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b);
  * pairs: host [n][2] with 0 <= i < j < n_occ.  gamma: device, osv_project's
  * output (FP64).  W: device, K layout; fragment_solve's multipliers (their
  * diagonal slots are T^MBE_ii), or any caller blocks.  e: device [n].
- * Runs the pair-basis preparation of fragment_solve, allocates and frees
- * its blocks (about 3 sum r_i r_j + 2 sum D_i D_j + sum D_i r_j doubles)
- * inside the call, so it cannot be recorded; synchronises the stream.
+ * Uses the pair bases of the handle's last eager fragment_solve or
+ * mbe3_pair_basis call (prepares them when there was none), allocates and
+ * frees its blocks (about 3 sum r_i r_j + 2 sum D_i D_j + sum D_i r_j
+ * doubles) inside the call, so it cannot be recorded; synchronises the
+ * stream.
  * MBE3_EINVAL for a bad pair or argument or while recording.
  */
 int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const double *gamma,

@@ -120,6 +120,7 @@ struct mbe3_handle {
   double *tmp = nullptr, *fp = nullptr, *zb = nullptr, *kt = nullptr;
   double *et = nullptr, *ev0 = nullptr;
   int32_t *rank = nullptr;
+  bool bases_done = false;  // X, eps~, rank computed by an eager preparation
   int32_t *sflag = nullptr;  // per slot: overlap not safely positive definite
   double *eig_ws = nullptr;  // eigensolver workspace for orders beyond LDS
   int64_t eig_ws_doubles = 0;
@@ -1182,6 +1183,7 @@ int prepare_bases(mbe3_handle *h) {
                            h->rank, 1, h->tau_S, nullptr, h->eig_ws,
                            h->eig_ws_doubles, s));
   HIP_TRY(h, launch_list(h, h->L_x, b, s));
+  if (!h->recording) h->bases_done = true;  // replays do not set it
   return MBE3_OK;
 }
 
@@ -2175,7 +2177,9 @@ int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const doubl
   int64_t ko, to, po;
   int rc = weak_layout(h, pairs, n, true, wp, &ko, &to, &po, p_off);
   if (rc) return rc;
-  if ((rc = prepare_bases(h))) return rc;  // X, eps~ and ranks of the diagonal slots
+  // X, eps~ and ranks of the diagonal slots: those of the last eager
+  // preparation (fragment_solve, mbe3_pair_basis), else prepared here
+  if (!h->bases_done && (rc = prepare_bases(h))) return rc;
   CallTemp tmp(h);
   double *Kb = nullptr, *Sb = nullptr, *Mb = nullptr, *Pb = nullptr, *Kt = nullptr,
          *Dt = nullptr;
