@@ -168,21 +168,24 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     bool hasY = false;
     if (GP) {
       if (a.iters[f_frag] < 0) continue;  // uniform over the workgroup
-      for (int e = tid; e < fdp->ny; e += 256) Y0[e] = a.yfin[fdp->yout + e];
-      __syncthreads();
-      // the contraction weights of every target (Y + Y^T for a diagonal
-      // one, else 2Y - Y^T) into the second buffer, and <Y~_t, Y_t>
+      // the pass reads the stored Y in place; the contraction weights of
+      // every target (Y + Y^T for a diagonal one, else 2Y - Y^T = Y~) go to
+      // the second scratch buffer, Y~ of the diagonal targets to the third,
+      // and <Y~_t, Y_t> to gdiag
       for (int tl = 0; tl < f_nt; ++tl) {
         const int D = a.slots[fdp->slot[tl]].D;
         const int sy = fdp->sym[tl];
-        const double *y = Y0 + fdp->ysub[tl];
+        const double *y = a.yfin + fdp->yout + fdp->ysub[tl];
         double *wy = Y0 + ny_cap + fdp->ysub[tl];
+        double *yd = Y0 + 2 * ny_cap + fdp->ysub[tl];
         double part = 0.0;
         for (int e = tid; e < D * D; e += 256) {
           const int i = e / D, j = e - i * D;
           const double yv = y[e], yt = y[(int64_t)j * D + i];
-          wy[e] = sy ? yv + yt : 2.0 * yv - yt;
-          part += (2.0 * yv - yt) * yv;
+          const double ytil = 2.0 * yv - yt;
+          wy[e] = sy ? yv + yt : ytil;
+          if (sy) yd[e] = ytil;
+          part += ytil * yv;
         }
         const double tot = wg_sum(part, red_d);  // also orders the wy writes
         if (tid == 0) a.gdiag[6 * fi + tl] = tot;
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     for (int it = 0;; ++it) {
       double mres = 0.0, epart = 0.0;
       int bad = 0;
-      double *const Ycb = Y0 + (cur ? ny_cap : 0);
+      double *const Ycb = GP ? a.yfin + fdp->yout : Y0 + (cur ? ny_cap : 0);
       double *const Ynb = Y0 + (cur ? 0 : ny_cap);
 
       // ---- panel pipeline: step (ti, m) = rows 16m.. of S~ and of Y^(T) ----
@@ -347,15 +350,14 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         }
       }
       if (GP) {
-        // Y~ = 2Y - Y^T for the multipliers, over the stored Y
+        // Y~ over the stored Y (every read of it is done: the last term's
+        // contraction ended in a workgroup barrier, its last panel fetched
+        // nothing further)
         for (int tl = 0; tl < f_nt; ++tl) {
           const int D = a.slots[fdp->slot[tl]].D;
-          const double *y = Ycb + fdp->ysub[tl];
+          const double *src = Y0 + (fdp->sym[tl] ? 2 : 1) * ny_cap + fdp->ysub[tl];
           double *o = a.yfin + fdp->yout + fdp->ysub[tl];
-          for (int e = tid; e < D * D; e += 256) {
-            const int i = e / D, j = e - i * D;
-            o[e] = 2.0 * y[e] - y[(int64_t)j * D + i];
-          }
+          for (int e = tid; e < D * D; e += 256) o[e] = src[e];
         }
         __syncthreads();  // the scratch is read; the next fragment refills it
         break;
