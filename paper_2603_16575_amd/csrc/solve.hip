@@ -192,21 +192,20 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
       }
       hasY = true;
     } else if (fdp->warm_in && a.warm) {
-      for (int tl = 0; tl < f_nt; ++tl) {
-        const SlotInfo sl = a.slots[fdp->slot[tl]];
-        const int D = sl.D;
-        const double *src = a.warm + sl.kt_off;
-        double *y = Y0 + fdp->ysub[tl];
-        for (int e = tid; e < D * D; e += 256) y[e] = src[e];
-      }
-      __syncthreads();
       hasY = true;
     }
+    // a warm-started fragment's first sweep reads the solutions of its own
+    // pairs' fragments in place (warm store, one D x D block per slot)
+    bool wsrc = !GP && fdp->warm_in && a.warm;
     for (int it = 0;; ++it) {
       double mres = 0.0, epart = 0.0;
       int bad = 0;
       double *const Ycb = GP ? a.yfin + fdp->yout : Y0 + (cur ? ny_cap : 0);
       double *const Ynb = Y0 + (cur ? 0 : ny_cap);
+      // the current amplitudes of target / source slot tl
+      auto ysrc = [&](int tl) -> const double * {
+        return wsrc ? a.warm + a.slots[fdp->slot[tl]].kt_off : Ycb + fdp->ysub[tl];
+      };
 
       // ---- panel pipeline: step (ti, m) = rows 16m.. of S~ and of Y^(T) ----
       int p_ti = f_tb, p_m = 0;  // step held in pf
@@ -220,7 +219,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     const d2 *st_ = reinterpret_cast<const d2 *>(                              \
         (tm_.st_buf ? a.st1 : a.st0) + tm_.st_off + (int64_t)16 * p_m * dt_);  \
     /* rows 16m.. of Y, or (transposed source) columns 16m.. of every row */  \
-    const double *ys_ = Ycb + fdp->ysub[tm_.src];                              \
+    const double *ys_ = ysrc(tm_.src);                                         \
     const d2 *y_ = reinterpret_cast<const d2 *>(                               \
         tm_.trans ? ys_ + 16 * p_m : ys_ + (int64_t)16 * p_m * ds_);           \
     p_n1 = 8 * dt_;                                                            \
@@ -311,7 +310,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
 
         // ---- residual, energy, update for the owned rows of target tl ----
         const int ysub = fdp->ysub[tl];
-        const double *Yc = Ycb + ysub;
+        const double *Yc = ysrc(tl);
         double *Yn = Ynb + ysub;
         const double *Kt = a.kt + sl.kt_off;
         const double *et = a.et + sl.et_off;
@@ -392,20 +391,25 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           // last amplitudes, converged or not (zero after a non-finite
           // residual), so every trimer starts from defined values
           const SlotInfo sl = a.slots[fdp->slot[fdp->warm_out]];
-          const double *src = Ycb + fdp->ysub[fdp->warm_out];
+          const double *src = ysrc(fdp->warm_out);
           for (int e = tid; e < sl.D * sl.D; e += 256)
             a.warm[sl.kt_off + e] = hasY && !B ? src[e] : 0.0;
         }
         if (ST && conv && !B) {
           // the converged amplitudes (zero if converged at T = 0) for the
           // gradient pass
-          for (int e = tid; e < fdp->ny; e += 256)
-            a.yfin[fdp->yout + e] = hasY ? Ycb[e] : 0.0;
+          for (int tl = 0; tl < f_nt; ++tl) {
+            const int D = a.slots[fdp->slot[tl]].D;
+            const double *src = ysrc(tl);
+            double *dst = a.yfin + fdp->yout + fdp->ysub[tl];
+            for (int e = tid; e < D * D; e += 256) dst[e] = hasY ? src[e] : 0.0;
+          }
         }
         __syncthreads();  // the scratch is read; the next fragment refills it
         break;
       }
       hasY = true;
+      wsrc = false;
       cur ^= 1;
     }
   }
