@@ -1765,6 +1765,21 @@ static int run_call_list(mbe3_handle *h, CallTemp &tmp, const char *name,
   return MBE3_OK;
 }
 
+// No C++ exception crosses the C-ABI: host-side planning (containers, map
+// lookups) runs inside this guard, which turns one into a status.
+template <class F>
+static int no_throw(mbe3_handle *h, F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return h->fail(MBE3_ENOMEM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return h->fail(MBE3_EINVAL, "internal error: %s", e.what());
+  } catch (...) {
+    return h->fail(MBE3_EINVAL, "internal error");
+  }
+}
+
 extern "C" {
 
 int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
@@ -1773,11 +1788,14 @@ int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
   mbe3_handle *h = new (std::nothrow) mbe3_handle();
   if (!h) return MBE3_ENOMEM;
   h->stream = (hipStream_t)stream;
-  int rc = validate_and_copy(h, p);
-  if (!rc) rc = build_layout(h);
-  if (!rc) rc = build_plans(h);
-  if (!rc) rc = alloc_workspace(h);
-  if (!rc) rc = validate_plans(h);
+  int rc = no_throw(h, [&] {
+    int r = validate_and_copy(h, p);
+    if (!r) r = build_layout(h);
+    if (!r) r = build_plans(h);
+    if (!r) r = alloc_workspace(h);
+    if (!r) r = validate_plans(h);
+    return r;
+  });
   if (rc) {
     g_create_error = h->err;
     delete h;
@@ -1791,12 +1809,15 @@ int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out) {
   mbe3_handle *h = new (std::nothrow) mbe3_handle();
   if (!h) return MBE3_ENOMEM;
   h->dry = true;
-  int rc = validate_and_copy(h, p);
-  if (!rc) rc = build_layout(h);
-  if (!rc) rc = build_plans(h);
-  if (!rc) rc = alloc_workspace(h);
-  if (!rc) rc = validate_plans(h);
-  if (!rc) rc = build_grad_plans(h);
+  int rc = no_throw(h, [&] {
+    int r = validate_and_copy(h, p);
+    if (!r) r = build_layout(h);
+    if (!r) r = build_plans(h);
+    if (!r) r = alloc_workspace(h);
+    if (!r) r = validate_plans(h);
+    if (!r) r = build_grad_plans(h);
+    return r;
+  });
   // every tile shape mbe3_autotune may choose keeps every task in bounds
   for (int sh = 0; sh < GEMM_NSHAPE && !rc; ++sh) rc = mbe3_set_gemm_shape(h, -1, sh);
   if (!rc && out) mbe3_get_layout(h, out);
@@ -1924,7 +1945,7 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
   hipStream_t s = h->stream;
   if (!h->recording) h->grad_ready = false;
   int rc;
-  if (W && (rc = build_grad_plans(h))) return rc;
+  if (W && (rc = no_throw(h, [&] { return build_grad_plans(h); }))) return rc;
   if ((rc = prepare_pairs(h, K))) return rc;
   GemmBases b = bases(h);
   HIP_TRY(h, launch_fill_i32(h->status, 0, 2 * SOLVE_WG, s));
@@ -2034,7 +2055,7 @@ int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
     return h->fail(MBE3_EINVAL, "dE/df needs a preceding successful fragment_solve with W");
   if (probe && h->recording)
     return h->fail(MBE3_EINVAL, "the probe is read on the host: not available while recording");
-  int rc = build_grad_plans(h);
+  int rc = no_throw(h, [&] { return build_grad_plans(h); });
   if (rc) return rc;
   hipStream_t s = h->stream;
   double *dgam = mode == MBE3_GRAD_GAMMA ? out : h->dg;
@@ -2134,8 +2155,7 @@ int mbe3_pair_basis(mbe3_handle *h, double *X, double *eps_t, int32_t *rank) {
   return MBE3_OK;
 }
 
-int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
-  if (!h) return MBE3_EINVAL;
+static int screen_body(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
   if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_screen allocates: not recordable");
   if (n < 0 || (n > 0 && (!pairs || !s2b)))
     return h->fail(MBE3_EINVAL, "pairs and s2b required for n > 0");
@@ -2165,9 +2185,8 @@ int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
   return MBE3_OK;
 }
 
-int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const double *gamma,
-                    const double *W, double *e) {
-  if (!h) return MBE3_EINVAL;
+static int weak_body(mbe3_handle *h, const int32_t *pairs, int64_t n, const double *gamma,
+                     const double *W, double *e) {
   if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_weak_pairs allocates: not recordable");
   if (n < 0 || (n > 0 && (!pairs || !gamma || !W || !e)))
     return h->fail(MBE3_EINVAL, "pairs, gamma, W and e required for n > 0");
@@ -2192,7 +2211,11 @@ int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const doubl
   std::vector<GemmTask> lk, ls, lm1, lm2, lxk, lkx, lxm, lmx;
   for (int64_t k = 0; k < n; ++k) {
     const WeakPair &w = wp[k];
-    const int64_t gi = h->grow.at(key2(w.i, w.i)), gj = h->grow.at(key2(w.j, w.j));
+    const auto fi = h->grow.find(key2(w.i, w.i)), fj = h->grow.find(key2(w.j, w.j));
+    if (fi == h->grow.end() || fj == h->grow.end())  // every LMO projects onto itself
+      return h->fail(MBE3_EINVAL, "internal: no gamma rows of (%d,%d) or (%d,%d)", w.i, w.i,
+                     w.j, w.j);
+    const int64_t gi = fi->second, gj = fj->second;
     // K_(i,j) = Gamma~_(i,i) Gamma~_(j,j)^T (eq. osv_weak_k)
     lk.push_back(gemm(B_GAMMA, gi * na, na, 0, B_GAMMA, gj * na, na, 1, B_PK, w.k_off,
                       w.rj, w.ri, w.rj, na));
@@ -2239,6 +2262,17 @@ int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const doubl
                                 h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return MBE3_OK;
+}
+
+int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
+  if (!h) return MBE3_EINVAL;
+  return no_throw(h, [&] { return screen_body(h, pairs, n, s2b); });
+}
+
+int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const double *gamma,
+                    const double *W, double *e) {
+  if (!h) return MBE3_EINVAL;
+  return no_throw(h, [&] { return weak_body(h, pairs, n, gamma, W, e); });
 }
 
 // Retile list li for `shape` and upload its tasks (stream idle).
@@ -2361,7 +2395,7 @@ int mbe3_graph_begin(mbe3_handle *h, int with_grad) {
   if (h->dry) return h->fail(MBE3_EINVAL, "plan-only handle");
   if (h->recording) return h->fail(MBE3_EINVAL, "already recording");
   int rc;
-  if (with_grad && (rc = build_grad_plans(h))) return rc;
+  if (with_grad && (rc = no_throw(h, [&] { return build_grad_plans(h); }))) return rc;
   if (!h->cap_stream)
     HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   HIP_TRY(h, hipStreamSynchronize(h->stream));  // a replay may still use the old graph

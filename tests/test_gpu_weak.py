@@ -161,3 +161,28 @@ def test_weak_and_screen_errors(m):
     # still usable
     assert h.screen(np.array([[2, 0]])).cpu().numpy()[0] > 0
     h.close()
+
+
+def test_weak_and_screen_refused_while_recording(m):
+    """Both calls allocate, so a recording refuses them (MBE3_EINVAL) and
+    the handle stays usable eagerly afterwards."""
+    import torch
+    say("case: micro n_occ=3, screening and weak pairs while recording")
+    prob = dataclasses.replace(synth.micro(3), tol=1e-10, max_iter=300)
+    h = m.from_problem(prob)
+    out = h.forward(grad=True)
+    pr = all_pairs(prob.n_occ)
+    e_ref = h.weak_pairs(pr, out["gamma"], out["W"]).cpu().numpy()
+    torch.cuda.synchronize()
+    h.graph_begin(with_grad=False)
+    with pytest.raises(m.Mbe3Error) as ei:
+        h.screen(pr)
+    assert ei.value.code == m.MBE3_EINVAL
+    with pytest.raises(m.Mbe3Error) as ei:
+        h.weak_pairs(pr, out["gamma"], out["W"])
+    assert ei.value.code == m.MBE3_EINVAL
+    with pytest.raises(m.Mbe3Error):
+        h.graph_end()  # the recording saw an error
+    e = h.weak_pairs(pr, out["gamma"], out["W"]).cpu().numpy()
+    assert np.array_equal(e, e_ref)
+    h.close()
