@@ -171,3 +171,15 @@ def test_graph_errors(m):
     ref = eager_step(h, grad=True)
     check_replays(h, ref, grad=True, n_rep=2, between=False)
     h.close()
+
+
+@pytest.mark.parametrize("form", ["MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"])
+def test_graph_replays_split_precision(m, form):
+    """The split-precision forms recorded (their regeneration, splits and
+    bf16 products included): replays equal the eager step bit for bit."""
+    say(f"case: micro n_occ=4, {form}, recorded forward + backward, 2 replays vs eager")
+    prob = dataclasses.replace(synth.micro(4, n_vir=21, n_aux=35), tol=1e-10, max_iter=300)
+    h = m.from_problem(prob, precision=getattr(m, form))
+    ref = eager_step(h, grad=True)
+    check_replays(h, ref, grad=True, n_rep=2, between=True)
+    h.close()
