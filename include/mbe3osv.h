@@ -325,6 +325,37 @@ int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const doubl
                     const double *W, double *e);
 
 /*
+ * Sparse fitting domains (eq. sparse_fit_metric, section on the direct
+ * Gamma_i generator).  The metric of auxiliary function P for LMO i is
+ *   s_fit[i * n_aux + P] = sum_a B_i[a][P]^2
+ * over the slab's orbital index (the virtual MOs of the (ia|P) slab, which
+ * stands in for the paper's AO-indexed Gamma_i), summed in increasing a in
+ * FP64 from the regenerated (or given) slab elements; nothing is stored
+ * besides s_fit.  The fitting domain is D_i = {P : s_fit[i][P] > l_fit}
+ * (strict; the paper's threshold is 1e-6).
+ *
+ * mbe3_fit_metric: s_fit device, n_occ * n_aux doubles, written.  The same
+ * arithmetic in every precision mode.
+ *
+ * mbe3_fit_mask: restricts gamma-layout rows to the domains: element P of
+ * every row of LMO i's block (mbe3_gamma_offsets) is set to zero unless
+ * s_fit[i][P] > l_fit (a NaN metric drops P); kept elements are not
+ * touched.  g: device, g_elems >= gamma_elems doubles, in place.  Applied
+ * to osv_project's gamma before pair_K, every later step runs on the
+ * restricted integrals: each pair's exchange integrals then sum over
+ * D_i and D_j together (P in both domains).  Applied to mbe3_backward's
+ * MBE3_GRAD_GAMMA output computed from that restricted gamma, it gives the
+ * gradient of the restricted energy with respect to the unrestricted
+ * Gamma~ (the MBE3_GRAD_SLAB mode does not apply the domains).
+ * MBE3_EINVAL for a NULL pointer, a NaN l_fit or a short g.
+ *
+ * Both allocate nothing, leave the handle's state alone and may be recorded.
+ */
+int mbe3_fit_metric(mbe3_handle *h, double *s_fit);
+int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
+                  int64_t g_elems);
+
+/*
  * Recorded launches (one HIP graph per handle) for the batched form of
  * Algorithm 7: thousands of fragments per call, replayed without host work.
  *

@@ -18,6 +18,7 @@ equations and algorithms:
   O8 gradient        dE/d(ia|P), dE/df via stationarity    (derived; no paper formula)
   O9 weak.s2b, ...   pair metrics, classes, trimer screen  (eqs. s2b, s3b)
   O10 weak.weak_pair one-block weak-pair amplitudes/energy (eqs. osv_weak_k, res_weak)
+  O11 fit.fit_metric sparse fitting metric and domains     (eq. sparse_fit_metric)
 
 Pins (tests/test_oracle_*.py) tie each step to something other than itself:
 numpy's own Philox, a full-space Kronecker dense solve, the canonical MP2
@@ -29,9 +30,9 @@ differences.
 from .mbe3 import (Oracle, gradient, energy, fragment_gradient,
                    mbe3_coefficients, mbe3_energy, orbs, run, slab, swap_blocks)
 from .philox import box_muller, philox4x64_10
-from . import weak
+from . import fit, weak
 
 __all__ = ["Oracle", "gradient", "energy", "fragment_gradient",
            "mbe3_coefficients", "mbe3_energy",
            "orbs", "run", "slab", "swap_blocks", "box_muller",
-           "philox4x64_10", "weak"]
+           "philox4x64_10", "fit", "weak"]

@@ -242,6 +242,25 @@ class Mbe3:
                    self._h)
 
     # ---- recorded launches (one HIP graph per handle) ----
+    def fit_metric(self, out=None):
+        """Sparse fitting metric (eq. sparse_fit_metric) of every LMO and
+        auxiliary function, s_fit[i, P] = sum_a B_i[a, P]^2, as a float64
+        [n_occ, n_aux] tensor on the device."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_occ, self.n_aux), dtype=torch.float64,
+                              device=self.device)
+        _lib.check(_lib.load().mbe3_fit_metric(self._h, _lib.ptr(_f64(out))), self._h)
+        return out
+
+    def fit_mask(self, s_fit, l_fit, g):
+        """Zero, in place, the elements of gamma-layout ``g`` (Gamma~ or
+        dE/dGamma~) outside the fitting domains s_fit > l_fit; returns g."""
+        _lib.check(_lib.load().mbe3_fit_mask(self._h, _lib.ptr(_f64(s_fit)),
+                                             float(l_fit), _lib.ptr(_f64(g)),
+                                             g.numel()), self._h)
+        return g
+
     def graph_begin(self, with_grad=False):
         _lib.check(_lib.load().mbe3_graph_begin(self._h, int(bool(with_grad))), self._h)
 
@@ -286,18 +305,24 @@ class Mbe3:
         return dict(gamma=gamma, K=K, e_frag=e, iters=it, W=W,
                     dB=dB if grad else None, dEdF=dEdF if grad else None)
 
-    def forward(self, grad=False):
+    def forward(self, grad=False, l_fit=None):
         """osv_project -> pair_K -> fragment_solve -> mbe3_energy; with
-        grad=True fragment_solve also returns the multipliers W."""
+        grad=True fragment_solve also returns the multipliers W.  With
+        l_fit, Gamma~ is restricted to the sparse fitting domains
+        s_fit > l_fit before pair_K (s_fit returned as well)."""
         import torch
         gamma = self.osv_project(self.empty_gamma())
+        s_fit = None
+        if l_fit is not None:
+            s_fit = self.fit_metric()
+            self.fit_mask(s_fit, l_fit, gamma)
         K = self.pair_K(gamma, self.empty_K())
         e = torch.empty(self.n_frag, dtype=torch.float64, device=self.device)
         it = torch.empty(self.n_frag, dtype=torch.int32, device=self.device)
         W = self.empty_K() if grad else None
         self.fragment_solve(K, e, it, W)
         E = self.mbe3_energy(e)
-        return dict(E=E, gamma=gamma, K=K, e_frag=e, iters=it, W=W)
+        return dict(E=E, gamma=gamma, K=K, e_frag=e, iters=it, W=W, s_fit=s_fit)
 
 
 def _energy_function():
@@ -366,6 +391,8 @@ def first_order_dE(k_off, n_occ, K_a, K_b, W):
 # computation): s2b below 1e-7 distant, below 1e-2 weak, else close; trimers
 # whose mean pair metric (eq. s3b) is below 0.2 are dropped
 S2B_DISTANT, S2B_CLOSE, S3B_KEEP = 1e-7, 1e-2, 0.2
+# sparse fitting threshold of the paper's sparsity table (eq. sparse_fit_metric)
+L_FIT = 1e-6
 
 
 def pair_classes(s2b):

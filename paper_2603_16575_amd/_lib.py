@@ -32,7 +32,8 @@ EXPORTS = [
     "mbe3_pair_basis", "mbe3_plan_check", "mbe3_set_timing",
     "mbe3_get_timing", "mbe3_backward", "mbe3_graph_begin", "mbe3_graph_end",
     "mbe3_graph_launch", "mbe3_autotune", "mbe3_set_gemm_shape",
-    "mbe3_tune_report", "mbe3_screen", "mbe3_weak_pairs",
+    "mbe3_tune_report", "mbe3_screen", "mbe3_weak_pairs", "mbe3_fit_metric",
+    "mbe3_fit_mask",
 ]
 GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128", "96x96"]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
@@ -105,6 +106,8 @@ def load():
         "mbe3_set_gemm_shape": [vp, ctypes.c_int, ctypes.c_int],
         "mbe3_screen": [vp, vp, i64, vp],
         "mbe3_weak_pairs": [vp, vp, i64, vp, vp, vp],
+        "mbe3_fit_metric": [vp, vp],
+        "mbe3_fit_mask": [vp, vp, ctypes.c_double, vp, i64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -161,6 +161,7 @@ struct mbe3_handle {
   MixedTask *d_mpk = nullptr;
   int64_t t_mpk = 0;
   int32_t *d_mrows = nullptr;
+  int32_t *d_row_lmo = nullptr;  // LMO of every gamma row (fitting domains)
   std::vector<std::pair<std::string, std::vector<MixedTask>>> h_mixed;
   std::vector<int32_t> h_mrows;
 
@@ -1081,6 +1082,12 @@ int alloc_workspace(mbe3_handle *h) {
   } else if (!h->slab &&
              (rc = dev_alloc(h, &h->slab_buf, (int64_t)h->slab_nb * nv * na))) {
     return rc;
+  }
+  {
+    std::vector<int32_t> rl((size_t)h->gamma_rows);
+    for (int i = 0; i < h->n_occ; ++i)
+      for (int64_t row = h->g_off[i]; row < h->g_off[i + 1]; ++row) rl[(size_t)row] = i;
+    if ((rc = upload(h, &h->d_row_lmo, rl))) return rc;
   }
   const int64_t nq = h->q_off[h->n_occ];
   if ((rc = dev_alloc(h, &h->eq, nq * nv))) return rc;
@@ -2261,6 +2268,29 @@ static int weak_body(mbe3_handle *h, const int32_t *pairs, int64_t n, const doub
   HIP_TRY(h, launch_weak_energy(d_wp, (int)n, Kt, Dt, h->et, h->rank, h->f, h->n_occ, e,
                                 h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return MBE3_OK;
+}
+
+int mbe3_fit_metric(mbe3_handle *h, double *s_fit) {
+  if (!h) return MBE3_EINVAL;
+  if (!s_fit) return h->fail(MBE3_EINVAL, "s_fit required");
+  PhaseScope ps_(h, MBE3_PHASE_REGEN);
+  HIP_TRY(h, launch_fit_metric(s_fit, h->n_occ, h->n_vir, h->n_aux, h->seed, h->w_ia,
+                               h->w_iP, h->slab, h->stream));
+  return MBE3_OK;
+}
+
+int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
+                  int64_t g_elems) {
+  if (!h) return MBE3_EINVAL;
+  if (!s_fit || !g) return h->fail(MBE3_EINVAL, "s_fit and g required");
+  if (std::isnan(l_fit)) return h->fail(MBE3_EINVAL, "l_fit is NaN");
+  if (g_elems < h->gamma_rows * h->n_aux)
+    return h->fail(MBE3_EINVAL, "g needs %lld doubles, got %lld",
+                   (long long)(h->gamma_rows * h->n_aux), (long long)g_elems);
+  PhaseScope ps_(h, MBE3_PHASE_PROJECT);
+  HIP_TRY(h, launch_fit_mask(g, h->gamma_rows, h->n_aux, h->d_row_lmo, s_fit, l_fit,
+                             h->stream));
   return MBE3_OK;
 }
 

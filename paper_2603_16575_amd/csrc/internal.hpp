@@ -62,6 +62,15 @@ hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia,
                              const double *w_iP, hipStream_t s);
 
+// Sparse fitting metric s_fit[i][P] = sum_a B_i[a][P]^2 of the regenerated
+// (slab == nullptr) or given slabs, and the restriction of gamma-layout rows
+// (LMO of each row in row_lmo) to s_fit > l_fit (regen.hip).
+hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
+                             uint64_t seed, const double *w_ia, const double *w_iP,
+                             const double *slab, hipStream_t s);
+hipError_t launch_fit_mask(double *g, int64_t rows, int n_aux, const int32_t *row_lmo,
+                           const double *s_fit, double l_fit, hipStream_t s);
+
 // Split-precision operands (regen.hip): three bf16 planes (bit patterns),
 // plane stride ps elements, rows padded with zeros to ldk (a multiple of 8).
 hipError_t launch_regen_split(uint16_t *planes, int64_t ps, int i0, int nb,

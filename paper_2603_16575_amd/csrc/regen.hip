@@ -209,4 +209,78 @@ hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Sparse fitting domains (eq. sparse_fit_metric).  s_fit[i][P] is the sum
+// over a of B_i[a][P]^2, one thread per (i, P), summed in increasing a; the
+// slab elements are regenerated exactly as regen_slab_kernel writes them
+// (or read from a given [n_occ][n_vir][n_aux] slab), so nothing is stored.
+// Consecutive threads take consecutive P: the w_iP and given-slab reads are
+// coalesced rows, w_ia a broadcast.
+__global__ __launch_bounds__(256) void fit_metric_kernel(
+    double *__restrict__ s_fit, int n_occ, int n_vir, int n_aux, uint64_t seed,
+    const double *__restrict__ w_ia, const double *__restrict__ w_iP,
+    const double *__restrict__ slab) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_occ * n_aux) return;
+  const int i = (int)(e / n_aux);
+  const int P = (int)(e - (int64_t)i * n_aux);
+  double s = 0.0;
+  if (slab) {
+    const double *b = slab + (int64_t)i * n_vir * n_aux + P;
+    for (int a = 0; a < n_vir; ++a) {
+      const double v = b[(int64_t)a * n_aux];
+      s += v * v;
+    }
+  } else {
+    const double wp = w_iP[e];
+    const double *wa = w_ia + (int64_t)i * n_vir;
+    for (int a = 0; a < n_vir; ++a) {
+      uint64_t c0 = (uint64_t)P, c1 = (uint64_t)a, c2 = (uint64_t)i, c3 = 0;
+      philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+      const double v = (box_muller(c0, c1) * wa[a]) * wp;
+      s += v * v;
+    }
+  }
+  s_fit[e] = s;
+}
+
+// Restriction of gamma-layout rows (Gamma~, or a gradient with respect to
+// it) to the fitting domains: element P of a row of LMO i becomes zero
+// unless s_fit[i][P] > l_fit.  Kept elements are neither read nor written.
+// Threads run along P (coalesced), workgroups stride over rows.
+__global__ __launch_bounds__(256) void fit_mask_kernel(
+    double *__restrict__ g, int64_t rows, int n_aux,
+    const int32_t *__restrict__ row_lmo, const double *__restrict__ s_fit,
+    double l_fit) {
+  const int P = blockIdx.x * 256 + threadIdx.x;
+  if (P >= n_aux) return;
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const int i = row_lmo[row];
+    if (!(s_fit[(int64_t)i * n_aux + P] > l_fit)) g[row * n_aux + P] = 0.0;
+  }
+}
+
+hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
+                             uint64_t seed, const double *w_ia, const double *w_iP,
+                             const double *slab, hipStream_t s) {
+  const int64_t total = (int64_t)n_occ * n_aux;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fit_metric_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     s_fit, n_occ, n_vir, n_aux, seed, w_ia, w_iP, slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_mask(double *g, int64_t rows, int n_aux, const int32_t *row_lmo,
+                           const double *s_fit, double l_fit, hipStream_t s) {
+  if (rows <= 0 || n_aux <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)((n_aux + 255) / 256);
+  const unsigned gy = (unsigned)(rows < 4096 ? rows : 4096);
+  hipLaunchKernelGGL(fit_mask_kernel, dim3(gx, gy), dim3(256), 0, s, g, rows, n_aux,
+                     row_lmo, s_fit, l_fit);
+  return hipGetLastError();
+}
+
 }  // namespace mbe3

@@ -1,0 +1,249 @@
+"""Sparse fitting domains (mbe3_fit_metric, mbe3_fit_mask) through the C-ABI
+against the oracle (needs an MI355X): the metric of every (i, P) of the
+8-LMO chain and of sampled (i, P) of the 1024-LMO helix, the restricted
+Gamma~, pair integrals, fragment and MBE(3) energies at a threshold that
+splits the domains, the gradient of the restricted energy, the exact
+masking pattern, a recorded restriction replayed, and argument errors."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import fit
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2603_16575_amd as pkg
+    pkg._lib.load()
+    return pkg
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def split_threshold(s):
+    """The midpoint between the two middle metrics: about half of the
+    (i, P) leave their domains and no metric lies near the threshold."""
+    v = np.sort(np.asarray(s).ravel())
+    k = len(v) // 2
+    return 0.5 * (v[k - 1] + v[k])
+
+
+def gamma_block(h, prob, gamma, i, x):
+    nb = prob.neighbours(i)
+    row = int(h.g_off[i]) + int(sum(prob.r[y] for y in nb if y < x))
+    return gamma.view(-1, prob.n_aux)[row:row + int(prob.r[x])].cpu().numpy()
+
+
+def k_block(h, prob, K, s):
+    off = int(h.k_off[s])
+    p, q = (s, s) if s < prob.n_occ else tuple(prob.pairs[s - prob.n_occ])
+    d = int(prob.r[p] + (prob.r[q] if p != q else 0))
+    return K[off:off + d * d].view(d, d).cpu().numpy(), (int(p), int(q))
+
+
+def row_lmo(h, prob):
+    rl = np.empty(int(h.g_off[-1]), dtype=np.int64)
+    for i in range(prob.n_occ):
+        rl[int(h.g_off[i]):int(h.g_off[i + 1])] = i
+    return rl
+
+
+def test_fit_metric_chain8(m):
+    say("case: chain8, s_fit of all 8 x 192 (i, P) vs oracle")
+    prob = synth.config(0)
+    h = m.from_problem(prob)
+    s = h.fit_metric().cpu().numpy()
+    ref = fit.fit_metrics(oracle.Oracle(prob))
+    r = float(np.max(np.abs(s - ref) / ref))
+    say(f"  s_fit range {ref.min():.3e}..{ref.max():.3e}, max rel diff {r:.2e}")
+    assert r <= 1e-13
+    h.close()
+
+
+def test_fit_restricted_chain8(m):
+    """Restricted Gamma~, K and energies at a threshold splitting the
+    domains, both sides from T = 0 (the oracle's iterates)."""
+    import torch
+    say("case: chain8, restricted forward (split threshold) vs oracle")
+    prob = synth.config(0)
+    h = m.from_problem(prob, warm_start=False)
+    base = oracle.Oracle(prob)
+    s_ref = fit.fit_metrics(base)
+    l_fit = split_threshold(s_ref)
+    out = h.forward(l_fit=l_fit)
+    torch.cuda.synchronize()
+    s = out["s_fit"].cpu().numpy()
+    gap = float(np.min(np.abs(s_ref - l_fit)) / l_fit)
+    assert gap > 1e-10
+    assert np.array_equal(s > l_fit, s_ref > l_fit)
+    kept = float(np.mean(s_ref > l_fit))
+    say(f"  l_fit {l_fit:.3e}, kept {kept:.3f}, nearest metric {gap:.1e} (relative) away")
+    ora = fit.restricted_oracle(prob, l_fit, base=base, s_fit=s_ref)
+    for i in range(prob.n_occ):
+        for x in prob.neighbours(i):
+            g = gamma_block(h, prob, out["gamma"], i, int(x))
+            r = ora.gamma(i, int(x))
+            assert np.array_equal(g == 0.0, np.broadcast_to(~(s_ref[i] > l_fit), g.shape))
+            assert np.abs(g - r).max() <= 1e-13 * np.abs(r).max(), (i, x)
+    for sl in range(h.layout.n_slot):
+        k, (p, q) = k_block(h, prob, out["K"], sl)
+        r = ora.Kbar(p, q)
+        assert np.abs(k - r).max() <= 1e-13 * np.abs(r).max(), sl
+    ref = oracle.run(prob, ora=ora)
+    E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
+    e = out["e_frag"].cpu().numpy()
+    full = h.forward()
+    say(f"  E restricted GPU {out['E']:.14f} oracle {E_ref:.14f}; "
+        f"unrestricted {full['E']:.14f}")
+    assert np.abs(e - ref["e_frag"]).max() <= 1e-12
+    assert np.array_equal(out["iters"].cpu().numpy(), ref["iters"])
+    assert abs(out["E"] - E_ref) <= 1e-10
+    assert abs(out["E"] - full["E"]) > 1e-6 * abs(full["E"])
+    h.close()
+
+
+def test_fit_restricted_gradient_chain8(m):
+    """dE_r/dB of the restricted energy E_r(B) = E(B restricted): the
+    GRAD_GAMMA output at the restricted Gamma~, masked by mbe3_fit_mask and
+    un-projected here, against the oracle's slab gradient at the restricted
+    slabs with the dropped columns zeroed."""
+    import torch
+    say("case: chain8, gradient of the restricted energy vs oracle, tol 1e-11")
+    prob = dataclasses.replace(synth.config(0), tol=1e-11, max_iter=300)
+    h = m.from_problem(prob, warm_start=False)
+    base = oracle.Oracle(prob)
+    s_ref = fit.fit_metrics(base)
+    l_fit = split_threshold(s_ref)
+    out = h.forward(grad=True, l_fit=l_fit)
+    dG, _ = h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_GAMMA)
+    h.fit_mask(out["s_fit"], l_fit, dG)
+    torch.cuda.synchronize()
+    g = oracle.gradient(prob, ora=fit.restricted_oracle(prob, l_fit, base=base, s_fit=s_ref))
+    mask = s_ref > l_fit
+    dGn = dG.cpu().numpy().reshape(-1, prob.n_aux)
+    worst = 0.0
+    for i in range(prob.n_occ):
+        acc = np.zeros((prob.n_vir, prob.n_aux))
+        row = int(h.g_off[i])
+        for x in prob.neighbours(i):
+            rx = int(prob.r[x])
+            acc += base.Q[int(x)] @ dGn[row:row + rx]
+            row += rx
+        worst = max(worst, rel(acc, g["dB"][i] * mask[i][None, :]))
+        assert not np.any(acc[:, ~mask[i]])
+    say(f"  dE_r/dB rel {worst:.2e}")
+    assert worst <= 1e-10
+    h.close()
+
+
+def test_fit_mask_pattern_and_errors(m):
+    """The mask writes zeros exactly outside the domains and leaves every
+    other element bit for bit; bad arguments are refused."""
+    import torch
+    say("case: chain8, mask pattern on random rows, argument errors")
+    prob = synth.config(0)
+    h = m.from_problem(prob)
+    s = h.fit_metric()
+    sn = s.cpu().numpy()
+    l_fit = split_threshold(sn)
+    g = torch.randn(int(h.layout.gamma_elems), dtype=torch.float64, device="cuda:0")
+    g0 = g.cpu().numpy().reshape(-1, prob.n_aux)
+    h.fit_mask(s, l_fit, g)
+    keep = (sn > l_fit)[row_lmo(h, prob)]
+    got = g.cpu().numpy().reshape(-1, prob.n_aux)
+    assert np.array_equal(got, np.where(keep, g0, 0.0))
+    # below every metric: nothing changes; above every metric: all zero
+    g1 = torch.randn_like(g)
+    ref1 = g1.clone()
+    h.fit_mask(s, -1.0, g1)
+    assert torch.equal(g1, ref1)
+    h.fit_mask(s, float(sn.max()), g1)
+    assert not torch.any(g1)
+    for bad in (float("nan"),):
+        with pytest.raises(m.Mbe3Error) as ei:
+            h.fit_mask(s, bad, g)
+        assert ei.value.code == m.MBE3_EINVAL
+    with pytest.raises(m.Mbe3Error) as ei:
+        h.fit_mask(s, l_fit, g[:-1])
+    assert ei.value.code == m.MBE3_EINVAL
+    lib = m._lib.load()
+    assert lib.mbe3_fit_metric(h._h, None) == m.MBE3_EINVAL
+    assert lib.mbe3_fit_mask(h._h, None, 0.0, m._lib.ptr(g), g.numel()) == m.MBE3_EINVAL
+    # still usable
+    assert torch.equal(h.fit_metric(), s)
+    h.close()
+
+
+def test_fit_recorded_replays(m):
+    """osv_project, fit_metric, fit_mask and pair_K recorded once and
+    replayed three times, each replay equal bit for bit to the eager calls."""
+    import torch
+    say("case: chain8, recorded restriction replayed 3 times vs eager")
+    prob = synth.config(0)
+    h = m.from_problem(prob)
+    sn = h.fit_metric().cpu().numpy()
+    l_fit = split_threshold(sn)
+    eager = h.forward(l_fit=l_fit)
+    torch.cuda.synchronize()
+    gamma, K = h.empty_gamma(), h.empty_K()
+    s = torch.empty((prob.n_occ, prob.n_aux), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    h.graph_begin()
+    try:
+        h.osv_project(gamma)
+        h.fit_metric(out=s)
+        h.fit_mask(s, l_fit, gamma)
+        h.pair_K(gamma, K)
+    finally:
+        h.graph_end()
+    for rep in range(3):
+        gamma.fill_(1.0)
+        K.zero_()
+        s.zero_()
+        torch.cuda.synchronize()
+        h.graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(s, eager["s_fit"]), rep
+        assert torch.equal(gamma, eager["gamma"]), rep
+        assert torch.equal(K, eager["K"]), rep
+    h.close()
+
+
+def test_fit_metric_helix1024_sampled(m):
+    """Sampled (i, P) of the 1024-LMO helix against the oracle's slab
+    columns, and the share of each domain kept at the paper's threshold."""
+    import torch
+    say("case: helix1024, s_fit at 24 sampled (i, P) vs oracle slab columns")
+    prob = synth.config(4)
+    h = m.from_problem(prob)
+    s = h.fit_metric().cpu().numpy()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for _ in range(4):
+        i = int(rng.integers(prob.n_occ))
+        cols = np.sort(rng.choice(prob.n_aux, 6, replace=False))
+        B = oracle.slab(prob, i, cols=cols)
+        ref = np.sum(B * B, axis=0)
+        worst = max(worst, float(np.max(np.abs(s[i, cols] - ref) / ref)))
+    kept = float(np.mean(s > m.L_FIT))
+    say(f"  max rel diff {worst:.2e}; kept at l_fit = 1e-6: {kept:.4f}")
+    assert worst <= 1e-13
+    assert 0.0 < kept < 0.1
+    h.close()

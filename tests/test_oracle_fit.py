@@ -1,0 +1,124 @@
+"""Pins of the oracle's sparse fitting domains (oracle/fit.py) against what
+the mathematics fixes: the metric of a rank-one slab in closed form, its
+invariance under rotations of the orbital index (and not of the auxiliary
+one), its expectation for the seeded Gaussian slabs, the restricted pair
+integrals against an explicit sum over the intersection of two domains, the
+limits l_fit below every metric (the unrestricted method, bit for bit) and
+above every metric (no integrals, zero energy), and a restricted fragment
+against the Kronecker dense solve on the restricted slabs."""
+import numpy as np
+import pytest
+
+import _pins
+import oracle
+import synth
+from oracle import fit
+
+
+def test_metric_rank_one_closed_form():
+    """B_i = u v^T: s_fit[A] = v_A^2 |u|^2."""
+    p = synth.micro(3)
+    rng = np.random.default_rng(11)
+    slabs, expect = {}, {}
+    for i in range(p.n_occ):
+        u = rng.standard_normal(p.n_vir)
+        v = rng.standard_normal(p.n_aux)
+        slabs[i] = np.outer(u, v)
+        expect[i] = v * v * float(u @ u)
+    ora = oracle.Oracle(p, slabs=slabs)
+    for i in range(p.n_occ):
+        assert np.allclose(fit.fit_metric(ora, i), expect[i], rtol=1e-14, atol=0)
+
+
+def test_metric_rotation_of_orbital_index_only():
+    """Rotating the orbital index of a slab keeps every column norm; rotating
+    the auxiliary index does not (the sum runs over the right index)."""
+    p = synth.micro(3)
+    base = oracle.Oracle(p)
+    rng = np.random.default_rng(12)
+    U, _ = np.linalg.qr(rng.standard_normal((p.n_vir, p.n_vir)))
+    V, _ = np.linalg.qr(rng.standard_normal((p.n_aux, p.n_aux)))
+    rot_a = oracle.Oracle(p, slabs={i: U @ base.B(i) for i in range(p.n_occ)})
+    rot_P = oracle.Oracle(p, slabs={i: base.B(i) @ V for i in range(p.n_occ)})
+    for i in range(p.n_occ):
+        s = fit.fit_metric(base, i)
+        assert np.allclose(fit.fit_metric(rot_a, i), s, rtol=1e-12, atol=0)
+        assert not np.allclose(fit.fit_metric(rot_P, i), s, rtol=1e-3, atol=0)
+
+
+def test_metric_expectation_of_seeded_slabs():
+    """B_i[a,P] = z w_ia w_iP with z standard normal: E s_fit[i,P] =
+    w_iP^2 sum_a w_ia^2.  The ratio averaged over the 1536 (i, P) of the
+    8-LMO chain is 1 within four standard errors (each ratio has variance
+    at most 2)."""
+    p = synth.config(0)
+    ora = oracle.Oracle(p)
+    s = fit.fit_metrics(ora)
+    expect = (p.w_iP ** 2) * np.sum(p.w_ia ** 2, axis=1)[:, None]
+    ratio = s / expect
+    assert abs(ratio.mean() - 1.0) <= 4.0 * np.sqrt(2.0 / ratio.size)
+
+
+def partial_threshold(s):
+    """A threshold that splits every LMO's auxiliary set."""
+    return float(np.median(s))
+
+
+def test_restricted_K_is_the_intersection_sum():
+    """K_(pq) of the restricted oracle against an explicit loop over the
+    auxiliary functions in D_p and D_q, with the unrestricted projections."""
+    p = synth.micro(3)
+    base = oracle.Oracle(p)
+    s = fit.fit_metrics(base)
+    l_fit = partial_threshold(s)
+    D = [set(np.nonzero(fit.domain(s[i], l_fit))[0].tolist()) for i in range(p.n_occ)]
+    assert all(0 < len(d) < p.n_aux for d in D)
+    ora = fit.restricted_oracle(p, l_fit, base=base)
+    for a in range(p.n_occ):
+        for b in range(a, p.n_occ):
+            both = sorted(D[a] & D[b])
+            # the pin discriminates: neither domain alone is the intersection
+            if a != b:
+                assert len(both) < min(len(D[a]), len(D[b]))
+            o = oracle.orbs(a, b)
+            L = np.concatenate([base.gamma(a, x) for x in o], 0)
+            R = np.concatenate([base.gamma(b, x) for x in o], 0)
+            K = np.zeros((L.shape[0], R.shape[0]))
+            for A in both:
+                K += np.outer(L[:, A], R[:, A])
+            got = ora.Kbar(a, b)
+            assert np.allclose(got, K, rtol=0, atol=1e-14 * np.abs(K).max())
+
+
+def test_thresholds_at_the_limits():
+    p = synth.micro(3)
+    base = oracle.Oracle(p)
+    s = fit.fit_metrics(base)
+    assert s.min() > 0.0
+    every = fit.restricted_oracle(p, 0.0, base=base)
+    none = fit.restricted_oracle(p, float(s.max()), base=base)
+    for a in range(p.n_occ):
+        for b in range(a, p.n_occ):
+            assert np.array_equal(every.Kbar(a, b), base.Kbar(a, b))
+            assert not np.any(none.Kbar(a, b))
+    assert oracle.energy(p, ora=none) == 0.0
+
+
+def test_restricted_fragment_matches_kronecker_solve():
+    """The restricted trimer of a 3-orbital chain against the dense
+    full-space solve fed the slabs with the columns outside each domain
+    zeroed."""
+    p = synth.micro(3)
+    base = oracle.Oracle(p)
+    s = fit.fit_metrics(base)
+    l_fit = partial_threshold(s)
+    ora = fit.restricted_oracle(p, l_fit, base=base)
+    st = ora.solve_fragment([0, 1, 2], 1e-13, 400)
+    assert st["converged"]
+    mask = fit.domain(s, l_fit)
+    B = [np.where(mask[i][None, :], base.B(i), 0.0) for i in range(p.n_occ)]
+    Ek, _ = _pins.kron_fragment_solve(B, p.Q, p.eps_vir, p.f_occ, [0, 1, 2])
+    assert abs(st["E"] - Ek) <= 1e-12 * abs(Ek)
+    # and the restriction changes the energy
+    full = base.solve_fragment([0, 1, 2], 1e-13, 400)
+    assert abs(full["E"] - st["E"]) > 1e-6 * abs(full["E"])
