@@ -3,7 +3,9 @@ against the oracle (needs an MI355X): the metric of every (i, P) of the
 8-LMO chain and of sampled (i, P) of the 1024-LMO helix, the restricted
 Gamma~, pair integrals, fragment and MBE(3) energies at a threshold that
 splits the domains, the gradient of the restricted energy, the exact
-masking pattern, a recorded restriction replayed, and argument errors."""
+masking pattern, a recorded restriction replayed, argument errors, the
+metric of a given slab array, and the restriction in both split-precision
+forms."""
 import dataclasses
 import sys
 
@@ -246,4 +248,49 @@ def test_fit_metric_helix1024_sampled(m):
     say(f"  max rel diff {worst:.2e}; kept at l_fit = 1e-6: {kept:.4f}")
     assert worst <= 1e-13
     assert 0.0 < kept < 0.1
+    h.close()
+
+
+def test_fit_metric_given_slab(m):
+    """The metric read from a given slab array (no regeneration) against the
+    oracle's metric of the same slabs, and the regenerated one."""
+    import torch
+    say("case: micro n_occ=4, s_fit from an explicit slab vs oracle and regenerated")
+    prob = synth.micro(4)
+    slab = np.stack([oracle.slab(prob, i) for i in range(prob.n_occ)])
+    h = m.from_problem(prob, slab=torch.as_tensor(slab, device="cuda:0"),
+                       w_ia=None, w_iP=None)
+    s = h.fit_metric().cpu().numpy()
+    ref = fit.fit_metrics(oracle.Oracle(prob, slabs={i: slab[i] for i in range(prob.n_occ)}))
+    hr = m.from_problem(prob)
+    sr = hr.fit_metric().cpu().numpy()
+    r1 = float(np.max(np.abs(s - ref) / ref))
+    r2 = float(np.max(np.abs(s - sr) / sr))
+    say(f"  given vs oracle {r1:.2e}, given vs regenerated {r2:.2e}")
+    assert r1 <= 1e-13 and r2 <= 1e-13
+    h.close()
+    hr.close()
+
+
+@pytest.mark.parametrize("form", ["MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"])
+def test_fit_restricted_split_precision(m, form):
+    """The restriction in the split-precision forms: dropped Gamma~ elements
+    stay exactly zero and the restricted energy is within the FP64 path's
+    budget of the oracle's restricted energy."""
+    import torch
+    say(f"case: chain8, restricted forward in {form} vs oracle")
+    prob = synth.config(0)
+    base = oracle.Oracle(prob)
+    s_ref = fit.fit_metrics(base)
+    l_fit = split_threshold(s_ref)
+    h = m.from_problem(prob, warm_start=False, precision=getattr(m, form))
+    out = h.forward(l_fit=l_fit)
+    torch.cuda.synchronize()
+    g = out["gamma"].view(-1, prob.n_aux).cpu().numpy()
+    drop = ~(s_ref > l_fit)[row_lmo(h, prob)]
+    assert not np.any(g[drop])
+    ref = oracle.run(prob, ora=fit.restricted_oracle(prob, l_fit, base=base, s_fit=s_ref))
+    E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
+    say(f"  E {out['E']:.14f} oracle {E_ref:.14f} dE {out['E'] - E_ref:.2e}")
+    assert abs(out["E"] - E_ref) <= 1e-6
     h.close()
