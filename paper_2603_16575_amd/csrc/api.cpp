@@ -1414,6 +1414,7 @@ int validate_plans(mbe3_handle *h) {
       if (fd.frag < 0 || fd.frag >= (int)h->frags.size()) return bad("solve (frag)", k);
       if (fd.term_begin < 0 || fd.term_end < fd.term_begin || fd.term_end > (int)terms.size())
         return bad("solve (terms)", k);
+      if (fd.term_end - fd.term_begin > MAX_FRAG_TERMS) return bad("solve (term count)", k);
       for (int l = 0; l < fd.nt; ++l) {
         const int s = fd.slot[l];
         if (s < 0 || s >= h->n_slot) return bad("solve (slot)", k);

@@ -203,6 +203,9 @@ struct Term {
   int32_t st_buf;       // 0: pair-level S~ store, 1: per-chunk cross store
   int64_t st_off;       // row-major S~_(src,target)  (D_src x D_target)
 };
+// Most terms of one fragment: a trimer has two per diagonal target and four
+// per pair target (the solver stages them in LDS).
+constexpr int MAX_FRAG_TERMS = 18;
 struct SolveArgs {
   const FragDesc *frags;
   const Term *terms;

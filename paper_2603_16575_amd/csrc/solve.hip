@@ -47,6 +47,22 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// A fragment's terms and slots as the workgroup reads them, staged in LDS at
+// the start of each fragment: every panel step and residual block then reads
+// its descriptors from LDS instead of chasing term -> slot -> dimension
+// through global memory (each hop a full memory round trip on the critical
+// path of the panel pipeline).
+struct TermLds {
+  const double *st;  // row-major S~_(src, target)
+  double coef;       // f_occ[fx][fy]; 1 in the gradient pass
+  int32_t target, src, dt, ds, trans, pad_;
+};
+struct SlotLds {
+  int64_t kt_off, et_off;
+  double fpq;  // f_pp + f_qq
+  int32_t D, ysub, sym, wgt;
+};
+
 // Workgroup sum in a fixed order (wave shuffles, then the four waves).
 __device__ __forceinline__ double wg_sum(double v, double *red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -141,6 +157,8 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
   constexpr int MAXRB = (MAXNT + 3) / 4;  // row blocks per wave
   __shared__ double red_d[8];
   __shared__ int red_i[8];
+  __shared__ TermLds tc[MAX_FRAG_TERMS];
+  __shared__ SlotLds sc[6];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -166,18 +184,46 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     // amplitudes present: after a warm start from the solutions of the
     // fragment's own pairs (monomers, dimers), or after the first update
     bool hasY = false;
+    if (GP && a.iters[f_frag] < 0) continue;  // uniform over the workgroup
+    // stage the descriptors (the previous fragment's last reads of them came
+    // before its closing barrier)
+    if (tid < f_te - f_tb) {
+      const Term t = a.terms[f_tb + tid];
+      TermLds c;
+      c.st = (t.st_buf ? a.st1 : a.st0) + t.st_off;
+      c.coef = GP ? 1.0 : a.f_occ[(int64_t)t.fx * a.n_occ + t.fy];
+      c.target = t.target;
+      c.src = t.src;
+      c.dt = a.slots[fdp->slot[t.target]].D;
+      c.ds = a.slots[fdp->slot[t.src]].D;
+      c.trans = t.trans;
+      c.pad_ = 0;
+      tc[tid] = c;
+    } else if (tid >= 64 && tid - 64 < f_nt) {
+      const int tl = tid - 64;
+      const SlotInfo sl = a.slots[fdp->slot[tl]];
+      SlotLds c;
+      c.kt_off = sl.kt_off;
+      c.et_off = sl.et_off;
+      c.fpq = a.f_occ[(int64_t)sl.p * a.n_occ + sl.p] + a.f_occ[(int64_t)sl.q * a.n_occ + sl.q];
+      c.D = sl.D;
+      c.ysub = fdp->ysub[tl];
+      c.sym = fdp->sym[tl];
+      c.wgt = fdp->wgt[tl];
+      sc[tl] = c;
+    }
+    __syncthreads();
     if (GP) {
-      if (a.iters[f_frag] < 0) continue;  // uniform over the workgroup
       // the pass reads the stored Y in place; the contraction weights of
       // every target (Y + Y^T for a diagonal one, else 2Y - Y^T = Y~) go to
       // the second scratch buffer, Y~ of the diagonal targets to the third,
       // and <Y~_t, Y_t> to gdiag
       for (int tl = 0; tl < f_nt; ++tl) {
-        const int D = a.slots[fdp->slot[tl]].D;
-        const int sy = fdp->sym[tl];
-        const double *y = a.yfin + fdp->yout + fdp->ysub[tl];
-        double *wy = Y0 + ny_cap + fdp->ysub[tl];
-        double *yd = Y0 + 2 * ny_cap + fdp->ysub[tl];
+        const int D = sc[tl].D;
+        const int sy = sc[tl].sym;
+        const double *y = a.yfin + fdp->yout + sc[tl].ysub;
+        double *wy = Y0 + ny_cap + sc[tl].ysub;
+        double *yd = Y0 + 2 * ny_cap + sc[tl].ysub;
         double part = 0.0;
         for (int e = tid; e < D * D; e += 256) {
           const int i = e / D, j = e - i * D;
@@ -204,7 +250,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
       double *const Ynb = Y0 + (cur ? 0 : ny_cap);
       // the current amplitudes of target / source slot tl
       auto ysrc = [&](int tl) -> const double * {
-        return wsrc ? a.warm + a.slots[fdp->slot[tl]].kt_off : Ycb + fdp->ysub[tl];
+        return wsrc ? a.warm + sc[tl].kt_off : Ycb + sc[tl].ysub;
       };
 
       // ---- panel pipeline: step (ti, m) = rows 16m.. of S~ and of Y^(T) ----
@@ -213,11 +259,10 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
       bool p_tr = false;  // the Y part of pf is a strip of Y columns
 #define MBE3_LOAD_PANEL()                                                      \
   do {                                                                         \
-    const Term tm_ = a.terms[p_ti];                                            \
-    const int dt_ = a.slots[fdp->slot[tm_.target]].D;                          \
-    const int ds_ = a.slots[fdp->slot[tm_.src]].D;                             \
-    const d2 *st_ = reinterpret_cast<const d2 *>(                              \
-        (tm_.st_buf ? a.st1 : a.st0) + tm_.st_off + (int64_t)16 * p_m * dt_);  \
+    const TermLds &tm_ = tc[p_ti - f_tb];                                      \
+    const int dt_ = tm_.dt;                                                    \
+    const int ds_ = tm_.ds;                                                    \
+    const d2 *st_ = reinterpret_cast<const d2 *>(tm_.st + (int64_t)16 * p_m * dt_); \
     /* rows 16m.. of Y, or (transposed source) columns 16m.. of every row */  \
     const double *ys_ = ysrc(tm_.src);                                         \
     const d2 *y_ = reinterpret_cast<const d2 *>(                               \
@@ -237,14 +282,14 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
   } while (0)
 #define MBE3_ADVANCE()                                                         \
   do {                                                                         \
-    const int ds_ = a.slots[fdp->slot[a.terms[p_ti].src]].D;                   \
+    const int ds_ = tc[p_ti - f_tb].ds;                                        \
     if (++p_m >= (ds_ >> 4)) { p_m = 0; ++p_ti; }                              \
   } while (0)
 
       if (hasY && f_tb < f_te) MBE3_LOAD_PANEL();
 
       for (int tl = 0; tl < f_nt; ++tl) {
-        const SlotInfo sl = a.slots[fdp->slot[tl]];
+        const SlotLds sl = sc[tl];
         const int Dt = sl.D;
         const int nT = Dt >> 4;
         d4 acc[MAXRB][MAXNT];
@@ -255,17 +300,15 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
 
         if (hasY) {
           for (int ti = f_tb; ti < f_te; ++ti) {
-            const Term tm = a.terms[ti];
-            if (tm.target != tl) continue;
-            const double coef =
-                GP ? 1.0 : a.f_occ[(int64_t)tm.fx * a.n_occ + tm.fy];
-            const int Ds = a.slots[fdp->slot[tm.src]].D;
+            if (tc[ti - f_tb].target != tl) continue;
+            const double coef = tc[ti - f_tb].coef;
+            const int Ds = tc[ti - f_tb].ds;
             const int nS = Ds >> 4;
             MBE3_TERM_PRODUCTS(coef);
             if (GP) {
               // this term's product alone, contracted with Y~ = 2Y - Y^T
               // (Y + Y^T for a diagonal target, whose mirror term is folded)
-              const double *Wy = Y0 + ny_cap + fdp->ysub[tl];
+              const double *Wy = Y0 + ny_cap + sl.ysub;
               double part = 0.0;
 #pragma unroll
               for (int rb = 0; rb < MAXRB; ++rb) {
@@ -289,7 +332,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         }
         if (GP) continue;  // no residual in the gradient pass
 
-        const int sym = fdp->sym[tl];
+        const int sym = sl.sym;
         if (sym) {  // diagonal pair: R~ gets acc + acc^T (mirror terms)
           __syncthreads();  // S~ of the last term is no longer read
 #pragma unroll
@@ -309,14 +352,13 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         }
 
         // ---- residual, energy, update for the owned rows of target tl ----
-        const int ysub = fdp->ysub[tl];
+        const int ysub = sl.ysub;
         const double *Yc = ysrc(tl);
         double *Yn = Ynb + ysub;
         const double *Kt = a.kt + sl.kt_off;
         const double *et = a.et + sl.et_off;
-        const double fpq = a.f_occ[(int64_t)sl.p * a.n_occ + sl.p] +
-                           a.f_occ[(int64_t)sl.q * a.n_occ + sl.q];
-        const double w = (double)fdp->wgt[tl];
+        const double fpq = sl.fpq;
+        const double w = (double)sl.wgt;
 #pragma unroll
         for (int rb = 0; rb < MAXRB; ++rb) {
           const int ib = wave + 4 * rb;
@@ -353,9 +395,9 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         // contraction ended in a workgroup barrier, its last panel fetched
         // nothing further)
         for (int tl = 0; tl < f_nt; ++tl) {
-          const int D = a.slots[fdp->slot[tl]].D;
-          const double *src = Y0 + (fdp->sym[tl] ? 2 : 1) * ny_cap + fdp->ysub[tl];
-          double *o = a.yfin + fdp->yout + fdp->ysub[tl];
+          const int D = sc[tl].D;
+          const double *src = Y0 + (sc[tl].sym ? 2 : 1) * ny_cap + sc[tl].ysub;
+          double *o = a.yfin + fdp->yout + sc[tl].ysub;
           for (int e = tid; e < D * D; e += 256) o[e] = src[e];
         }
         __syncthreads();  // the scratch is read; the next fragment refills it
@@ -390,7 +432,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           // the fragment's own pair seeds the trimers that contain it: its
           // last amplitudes, converged or not (zero after a non-finite
           // residual), so every trimer starts from defined values
-          const SlotInfo sl = a.slots[fdp->slot[fdp->warm_out]];
+          const SlotLds sl = sc[fdp->warm_out];
           const double *src = ysrc(fdp->warm_out);
           for (int e = tid; e < sl.D * sl.D; e += 256)
             a.warm[sl.kt_off + e] = hasY && !B ? src[e] : 0.0;
@@ -399,9 +441,9 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           // the converged amplitudes (zero if converged at T = 0) for the
           // gradient pass
           for (int tl = 0; tl < f_nt; ++tl) {
-            const int D = a.slots[fdp->slot[tl]].D;
+            const int D = sc[tl].D;
             const double *src = ysrc(tl);
-            double *dst = a.yfin + fdp->yout + fdp->ysub[tl];
+            double *dst = a.yfin + fdp->yout + sc[tl].ysub;
             for (int e = tid; e < D * D; e += 256) dst[e] = hasY ? src[e] : 0.0;
           }
         }
