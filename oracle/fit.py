@@ -27,15 +27,20 @@ from typing import Dict, Optional
 
 import numpy as np
 
-from .mbe3 import Oracle
+from .mbe3 import Oracle, slab
 
 L_FIT = 1e-6  # the paper's fitting threshold (sparsity table)
 
 
-def fit_metric(ora: Oracle, i: int) -> np.ndarray:
-    """eq. sparse_fit_metric: s_fit[i, A] = sum_a B_i[a, A]^2, shape [n_aux]."""
-    B = ora.B(i)
+def column_metric(B: np.ndarray) -> np.ndarray:
+    """eq. sparse_fit_metric for one slab: sum over its first index of the
+    squared elements, one value per auxiliary function."""
     return np.sum(B * B, axis=0)
+
+
+def fit_metric(ora: Oracle, i: int) -> np.ndarray:
+    """s_fit[i, A] = sum_a B_i[a, A]^2, shape [n_aux]."""
+    return column_metric(ora.B(i))
 
 
 def fit_metrics(ora: Oracle) -> np.ndarray:
@@ -60,3 +65,22 @@ def restricted_oracle(prob, l_fit: float, base: Optional[Oracle] = None,
     slabs: Dict[int, np.ndarray] = {
         i: base.B(i) * mask[i][None, :] for i in range(prob.n_occ)}
     return Oracle(prob, slabs=slabs)
+
+
+class RestrictedOracle(Oracle):
+    """The restricted method with slabs restricted when first used (for
+    samples of large workloads): slab i is regenerated, its metric kept in
+    ``s[i]``, and its columns outside D_i set to zero, as in
+    restricted_oracle."""
+
+    def __init__(self, prob, l_fit: float):
+        super().__init__(prob)
+        self.l_fit = l_fit
+        self.s: Dict[int, np.ndarray] = {}
+
+    def B(self, i: int) -> np.ndarray:
+        if i not in self._slabs:
+            b = slab(self.prob, i)
+            self.s[i] = column_metric(b)
+            self._slabs[i] = b * domain(self.s[i], self.l_fit)[None, :]
+        return self._slabs[i]

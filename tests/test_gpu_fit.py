@@ -4,8 +4,9 @@ against the oracle (needs an MI355X): the metric of every (i, P) of the
 Gamma~, pair integrals, fragment and MBE(3) energies at a threshold that
 splits the domains, the gradient of the restricted energy, the exact
 masking pattern, a recorded restriction replayed, argument errors, the
-metric of a given slab array, and the restriction in both split-precision
-forms."""
+metric of a given slab array, the restriction in both split-precision
+forms, and sampled fragments of the restricted 160-LMO lattice at full
+size."""
 import dataclasses
 import sys
 
@@ -293,4 +294,43 @@ def test_fit_restricted_split_precision(m, form):
     E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
     say(f"  E {out['E']:.14f} oracle {E_ref:.14f} dE {out['E'] - E_ref:.2e}")
     assert abs(out["E"] - E_ref) <= 1e-6
+    h.close()
+
+
+def test_fit_restricted_water40u_sampled(m):
+    """The 160-LMO lattice in the benchmark's launch shape with the domains
+    cut at l_fit = 5e-3 (about half of each kept): the metric and domain
+    decisions of every LMO a sampled fragment touches, and the sampled
+    fragments' restricted energies and update counts, one by one, against
+    the oracle (both from T = 0)."""
+    import torch
+    say("case: water40u restricted forward (l_fit 5e-3), sampled oracle fragments")
+    prob = synth.config(1)
+    l_fit = 5e-3
+    h = m.from_problem(prob, warm_start=False)
+    out = h.forward(l_fit=l_fit)
+    torch.cuda.synchronize()
+    s = out["s_fit"].cpu().numpy()
+    e = out["e_frag"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert (it >= 0).all() and np.isfinite(e).all()
+    kept = float(np.mean(s > l_fit))
+    fr = prob.frags
+    i0 = np.nonzero((fr == 0).any(1))[0]
+    pick = np.unique(np.concatenate([i0[:6], i0[-6:], np.arange(0, len(fr), 19999),
+                                     [len(fr) - 1]]))
+    ora = fit.RestrictedOracle(prob, l_fit)
+    res = oracle.run(prob, frags=fr[pick], ora=ora)
+    worst_s, gap = 0.0, np.inf
+    for i, si in ora.s.items():
+        worst_s = max(worst_s, float(np.max(np.abs(s[i] - si) / si)))
+        gap = min(gap, float(np.min(np.abs(si - l_fit)) / l_fit))
+        assert np.array_equal(s[i] > l_fit, si > l_fit), i
+    dE = float(np.abs(e[pick] - res["e_frag"]).max())
+    say(f"  kept {kept:.3f}; {len(ora.s)} LMOs: s_fit rel {worst_s:.2e}, nearest metric "
+        f"{gap:.1e} from l_fit; {len(pick)} fragments: max |dE_F| {dE:.3e}; E = {out['E']:.10f}")
+    assert worst_s <= 1e-13 and gap > 1e-10
+    assert 0.3 < kept < 0.7
+    assert dE <= 1e-12
+    assert np.array_equal(it[pick], res["iters"])
     h.close()

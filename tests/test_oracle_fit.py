@@ -122,3 +122,19 @@ def test_restricted_fragment_matches_kronecker_solve():
     # and the restriction changes the energy
     full = base.solve_fragment([0, 1, 2], 1e-13, 400)
     assert abs(full["E"] - st["E"]) > 1e-6 * abs(full["E"])
+
+
+def test_lazy_restricted_oracle_matches_eager():
+    """RestrictedOracle (slabs restricted on first use) gives bit for bit the
+    metrics and pair integrals of restricted_oracle."""
+    p = synth.micro(4)
+    base = oracle.Oracle(p)
+    s = fit.fit_metrics(base)
+    l_fit = partial_threshold(s)
+    eager = fit.restricted_oracle(p, l_fit, base=base)
+    lazy = fit.RestrictedOracle(p, l_fit)
+    for a in range(p.n_occ):
+        for b in range(a, p.n_occ):
+            assert np.array_equal(lazy.Kbar(a, b), eager.Kbar(a, b))
+    for i in range(p.n_occ):
+        assert np.array_equal(lazy.s[i], s[i])
