@@ -356,6 +356,26 @@ int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
                   int64_t g_elems);
 
 /*
+ * osv_project restricted to the fitting domains, with the work of the
+ * restriction saved (the paper's reason for the domains): for every LMO i
+ * only the columns P with s_fit[i][P] > l_fit of its slab are regenerated
+ * and projected (eq. osv_imua over D_i), and gamma receives Gamma~ in
+ * osv_project's layout with every other column zero.  The products run in
+ * FP64 in every precision mode, each element summed over a in the order of
+ * osv_project's FP64 form, so on an MBE3_FP64 handle the result equals
+ * osv_project followed by mbe3_fit_mask bit for bit.
+ * s_fit: device, n_occ * n_aux doubles (mbe3_fit_metric's output or any
+ * caller metric).  gamma: device, gamma_elems >= gamma_elems of the layout.
+ * Copies s_fit to the host and synchronises the stream, allocates the
+ * compacted slabs and rows for the call (at most about 2 GiB of slabs at a
+ * time, plus sum_i rows_i |D_i| doubles), so it cannot be recorded.
+ * MBE3_EINVAL for a NULL pointer, a NaN l_fit, a short gamma or while
+ * recording; MBE3_ENOMEM if the compacted buffers cannot be allocated.
+ */
+int mbe3_project_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *gamma,
+                     int64_t gamma_elems);
+
+/*
  * Recorded launches (one HIP graph per handle) for the batched form of
  * Algorithm 7: thousands of fragments per call, replayed without host work.
  *

@@ -261,6 +261,14 @@ class Mbe3:
                                              g.numel()), self._h)
         return g
 
+    def project_fit(self, s_fit, l_fit, gamma):
+        """osv_project over the fitting domains s_fit > l_fit only: the kept
+        columns regenerated and projected, the others zero; returns gamma."""
+        _lib.check(_lib.load().mbe3_project_fit(self._h, _lib.ptr(_f64(s_fit)),
+                                                float(l_fit), _lib.ptr(_f64(gamma)),
+                                                gamma.numel()), self._h)
+        return gamma
+
     def graph_begin(self, with_grad=False):
         _lib.check(_lib.load().mbe3_graph_begin(self._h, int(bool(with_grad))), self._h)
 

@@ -2295,6 +2295,119 @@ int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
   return MBE3_OK;
 }
 
+// osv_project over the fitting domains only: per LMO the kept columns are
+// listed on the host (s_fit copied back), regenerated compacted, projected
+// by one GEMM per LMO over them and scattered into the zeroed dense gamma.
+static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, double *gamma,
+                            int64_t gamma_elems) {
+  if (h->recording)
+    return h->fail(MBE3_EINVAL, "mbe3_project_fit allocates: not recordable");
+  if (!s_fit || !gamma) return h->fail(MBE3_EINVAL, "s_fit and gamma required");
+  if (std::isnan(l_fit)) return h->fail(MBE3_EINVAL, "l_fit is NaN");
+  const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
+  if (gamma_elems < h->gamma_rows * na)
+    return h->fail(MBE3_EINVAL, "gamma needs %lld doubles, got %lld",
+                   (long long)(h->gamma_rows * na), (long long)gamma_elems);
+  hipStream_t s = h->stream;
+  std::vector<double> sf((size_t)n * na);
+  HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  std::vector<int32_t> cols, col_off((size_t)n + 1, 0);
+  std::vector<int64_t> gc_off((size_t)n + 1, 0);
+  int max_nc = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int P = 0; P < na; ++P)
+      if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
+    col_off[i + 1] = (int32_t)cols.size();
+    const int nc = col_off[i + 1] - col_off[i];
+    max_nc = std::max(max_nc, nc);
+    gc_off[i + 1] = gc_off[i] + (h->g_off[i + 1] - h->g_off[i]) * nc;
+  }
+  CallTemp tmp(h);
+  int32_t *d_cols = nullptr, *d_col_off = nullptr;
+  int64_t *d_goff = nullptr, *d_gcoff = nullptr;
+  double *gc = nullptr, *cs = nullptr;
+  int rc;
+  if ((rc = tmp.upload(&d_cols, cols)) || (rc = tmp.upload(&d_col_off, col_off)) ||
+      (rc = tmp.upload(&d_goff, h->g_off)) || (rc = tmp.upload(&d_gcoff, gc_off)) ||
+      (rc = tmp.alloc(&gc, gc_off[n])))
+    return rc;
+  // batches of LMOs whose compacted slabs fit the slab budget
+  const int64_t budget = SLAB_BUDGET / (int64_t)sizeof(double);
+  std::vector<std::pair<int, int>> batches;
+  int64_t cs_max = 0;
+  for (int i0 = 0; i0 < n;) {
+    int i1 = i0;
+    int64_t tot = 0;
+    while (i1 < n && i1 - i0 < 65535 &&
+           (i1 == i0 || tot + (int64_t)nv * (col_off[i1 + 1] - col_off[i1]) <= budget)) {
+      tot += (int64_t)nv * (col_off[i1 + 1] - col_off[i1]);
+      ++i1;
+    }
+    batches.push_back({i0, i1});
+    cs_max = std::max(cs_max, tot);
+    i0 = i1;
+  }
+  if ((rc = tmp.alloc(&cs, cs_max))) return rc;
+  HIP_TRY(h, launch_fill(gamma, 0.0, h->gamma_rows * na, s));
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  sz[B_SLAB] = cs_max;
+  sz[B_GAMMA] = gc_off[n];
+  for (const auto &bt : batches) {
+    const int i0 = bt.first, i1 = bt.second;
+    std::vector<int64_t> out_off;
+    std::vector<GemmTask> ts;
+    std::vector<int32_t> rows;
+    int64_t off = 0, max_elems = 0;
+    for (int i = i0; i < i1; ++i) {
+      const int nc = col_off[i + 1] - col_off[i];
+      out_off.push_back(off);
+      max_elems = std::max<int64_t>(max_elems, (int64_t)nv * nc);
+      if (nc > 0) {
+        GemmTask t = gemm(B_Q, 0, nv, 0, B_SLAB, off, nc, 0, B_GAMMA, gc_off[i], nc,
+                          (int)(h->g_off[i + 1] - h->g_off[i]), nc, nv);
+        t.a_rows = (int32_t)rows.size();
+        for (int x : h->nbr[i])
+          for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->q_off[x] + mu));
+        ts.push_back(t);
+      }
+      off += (int64_t)nv * nc;
+    }
+    if (ts.empty()) continue;
+    int64_t *d_out_off = nullptr;
+    int32_t *d_rows = nullptr;
+    GemmTask *d_ts = nullptr;
+    const int64_t tiles = finish_tasks(ts, GEMM_128x128);
+    if ((rc = check_gemm_list(h, "project (fitting domains)", ts, sz, rows, GEMM_128x128)))
+      return rc;
+    if ((rc = tmp.upload(&d_out_off, out_off)) || (rc = tmp.upload(&d_rows, rows)) ||
+        (rc = tmp.upload(&d_ts, ts)))
+      return rc;
+    {
+      PhaseScope ps_(h, MBE3_PHASE_REGEN);
+      HIP_TRY(h, launch_regen_cols(cs, d_out_off, d_cols, d_col_off, i0, i1 - i0, max_elems,
+                                   nv, na, h->seed, h->w_ia, h->w_iP, h->slab, s));
+    }
+    PhaseScope ps_(h, MBE3_PHASE_PROJECT);
+    GemmBases b = bases(h);
+    b.p[B_SLAB] = cs;
+    b.p[B_GAMMA] = gc;
+    b.rows = d_rows;
+    HIP_TRY(h, launch_gemm_tasks(d_ts, (int)ts.size(), tiles, b, GEMM_128x128, s));
+  }
+  HIP_TRY(h, launch_fit_scatter(gamma, gc, h->gamma_rows, na, max_nc, h->d_row_lmo, d_goff,
+                                d_gcoff, d_cols, d_col_off, s));
+  return MBE3_OK;
+}
+
+int mbe3_project_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *gamma,
+                     int64_t gamma_elems) {
+  if (!h) return MBE3_EINVAL;
+  return no_throw(h, [&] { return project_fit_body(h, s_fit, l_fit, gamma, gamma_elems); });
+}
+
 int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
   if (!h) return MBE3_EINVAL;
   return no_throw(h, [&] { return screen_body(h, pairs, n, s2b); });

@@ -70,6 +70,18 @@ hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
                              const double *slab, hipStream_t s);
 hipError_t launch_fit_mask(double *g, int64_t rows, int n_aux, const int32_t *row_lmo,
                            const double *s_fit, double l_fit, hipStream_t s);
+// Projection over the fitting domains only: the kept columns of a batch of
+// slabs compacted (LMO i's columns cols[col_off[i]..col_off[i+1]), batch
+// member b at out_off[b]), and compacted gamma rows scattered back into the
+// dense layout (regen.hip).
+hipError_t launch_regen_cols(double *out, const int64_t *out_off, const int32_t *cols,
+                             const int32_t *col_off, int i0, int nb, int64_t max_elems,
+                             int n_vir, int n_aux, uint64_t seed, const double *w_ia,
+                             const double *w_iP, const double *slab, hipStream_t s);
+hipError_t launch_fit_scatter(double *g, const double *gc, int64_t rows, int n_aux,
+                              int max_nc, const int32_t *row_lmo, const int64_t *g_off,
+                              const int64_t *gc_off, const int32_t *cols,
+                              const int32_t *col_off, hipStream_t s);
 
 // Split-precision operands (regen.hip): three bf16 planes (bit patterns),
 // plane stride ps elements, rows padded with zeros to ldk (a multiple of 8).

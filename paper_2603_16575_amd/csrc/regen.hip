@@ -261,6 +261,79 @@ __global__ __launch_bounds__(256) void fit_mask_kernel(
   }
 }
 
+// The kept columns of a batch of slabs, compacted: for LMO i = i0 + b with
+// domain columns cols[col_off[i] .. col_off[i + 1]) (nc of them),
+//   out[out_off[b] + a * nc + c] = B_i[a][cols[col_off[i] + c]],
+// each element regenerated exactly as regen_slab_kernel writes it (or read
+// from a given slab).  One workgroup row (blockIdx.y) per LMO of the batch.
+__global__ __launch_bounds__(256) void regen_cols_kernel(
+    double *__restrict__ out, const int64_t *__restrict__ out_off,
+    const int32_t *__restrict__ cols, const int32_t *__restrict__ col_off, int i0,
+    int n_vir, int n_aux, uint64_t seed, const double *__restrict__ w_ia,
+    const double *__restrict__ w_iP, const double *__restrict__ slab) {
+  const int i = i0 + (int)blockIdx.y;
+  const int c0 = col_off[i], nc = col_off[i + 1] - c0;
+  const int64_t total = (int64_t)n_vir * nc;
+  double *o = out + out_off[blockIdx.y];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / nc);
+    const int P = cols[c0 + (int)(e - (int64_t)a * nc)];
+    double v;
+    if (slab) {
+      v = slab[((int64_t)i * n_vir + a) * n_aux + P];
+    } else {
+      uint64_t k0 = (uint64_t)P, k1 = (uint64_t)a, k2 = (uint64_t)i, k3 = 0;
+      philox4x64_10(k0, k1, k2, k3, seed, 0ull);
+      v = (box_muller(k0, k1) * w_ia[(int64_t)i * n_vir + a]) * w_iP[(int64_t)i * n_aux + P];
+    }
+    o[e] = v;
+  }
+}
+
+// Compacted gamma rows back into the dense layout: row r of LMO i (r from
+// g_off[i]) holds its nc kept columns at gc[gc_off[i] + (r - g_off[i]) nc];
+// they go to columns cols[col_off[i] + c] of the dense row (the others were
+// zeroed before).  Threads along the kept columns, workgroups over rows.
+__global__ __launch_bounds__(256) void fit_scatter_kernel(
+    double *__restrict__ g, const double *__restrict__ gc, int64_t rows, int n_aux,
+    const int32_t *__restrict__ row_lmo, const int64_t *__restrict__ g_off,
+    const int64_t *__restrict__ gc_off, const int32_t *__restrict__ cols,
+    const int32_t *__restrict__ col_off) {
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const int i = row_lmo[row];
+    const int c0 = col_off[i], nc = col_off[i + 1] - c0;
+    const double *src = gc + gc_off[i] + (row - g_off[i]) * nc;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < nc; c += gridDim.x * 256)
+      g[row * n_aux + cols[c0 + c]] = src[c];
+  }
+}
+
+hipError_t launch_regen_cols(double *out, const int64_t *out_off, const int32_t *cols,
+                             const int32_t *col_off, int i0, int nb, int64_t max_elems,
+                             int n_vir, int n_aux, uint64_t seed, const double *w_ia,
+                             const double *w_iP, const double *slab, hipStream_t s) {
+  if (nb <= 0 || max_elems <= 0) return hipSuccess;
+  if (nb > 65535) return hipErrorInvalidValue;
+  int64_t gx = (max_elems + 255) / 256;
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(regen_cols_kernel, dim3((unsigned)gx, (unsigned)nb), dim3(256), 0, s,
+                     out, out_off, cols, col_off, i0, n_vir, n_aux, seed, w_ia, w_iP, slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_scatter(double *g, const double *gc, int64_t rows, int n_aux,
+                              int max_nc, const int32_t *row_lmo, const int64_t *g_off,
+                              const int64_t *gc_off, const int32_t *cols,
+                              const int32_t *col_off, hipStream_t s) {
+  if (rows <= 0 || max_nc <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)((max_nc + 255) / 256);
+  const unsigned gy = (unsigned)(rows < 4096 ? rows : 4096);
+  hipLaunchKernelGGL(fit_scatter_kernel, dim3(gx, gy), dim3(256), 0, s, g, gc, rows, n_aux,
+                     row_lmo, g_off, gc_off, cols, col_off);
+  return hipGetLastError();
+}
+
 hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia, const double *w_iP,
                              const double *slab, hipStream_t s) {

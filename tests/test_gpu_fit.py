@@ -334,3 +334,69 @@ def test_fit_restricted_water40u_sampled(m):
     assert dE <= 1e-12
     assert np.array_equal(it[pick], res["iters"])
     h.close()
+
+
+def test_project_fit_equals_project_then_mask(m):
+    """mbe3_project_fit (only the kept columns regenerated and projected)
+    against osv_project followed by mbe3_fit_mask, bit for bit, at a
+    splitting threshold and at both limits; a given slab array too."""
+    import torch
+    say("case: chain8 / micro4 given slab, restricted projection vs project + mask")
+    prob = synth.config(0)
+    h = m.from_problem(prob)
+    s = h.fit_metric()
+    sn = s.cpu().numpy()
+    for l_fit in (split_threshold(sn), -1.0, float(sn.max())):
+        ref = h.fit_mask(s, l_fit, h.osv_project(h.empty_gamma()))
+        got = h.project_fit(s, l_fit, h.empty_gamma())
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), l_fit
+    h.close()
+    p4 = synth.micro(4)
+    slab = np.stack([oracle.slab(p4, i) for i in range(p4.n_occ)])
+    h = m.from_problem(p4, slab=torch.as_tensor(slab, device="cuda:0"), w_ia=None, w_iP=None)
+    s = h.fit_metric()
+    l_fit = split_threshold(s.cpu().numpy())
+    ref = h.fit_mask(s, l_fit, h.osv_project(h.empty_gamma()))
+    got = h.project_fit(s, l_fit, h.empty_gamma())
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    with pytest.raises(m.Mbe3Error) as ei:
+        h.project_fit(s, float("nan"), got)
+    assert ei.value.code == m.MBE3_EINVAL
+    h.close()
+
+
+def test_project_fit_helix1024(m):
+    """The 1024-LMO helix at the paper's l_fit = 1e-6 (about 2% of each
+    domain kept): the restricted projection equals osv_project + mask bit
+    for bit over all of Gamma~, and both are timed."""
+    import time
+    import torch
+    say("case: helix1024, restricted projection at l_fit 1e-6 vs project + mask")
+    prob = synth.config(4)
+    h = m.from_problem(prob)
+    s = h.fit_metric()
+    g = h.empty_gamma()
+    times = {}
+    for name in ("dense", "restricted"):
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "dense":
+                h.osv_project(g)
+            else:
+                h.project_fit(s, m.L_FIT, g2)
+            torch.cuda.synchronize()
+            times[name] = time.perf_counter() - t0
+        if name == "dense":
+            h.fit_mask(s, m.L_FIT, g)
+            g2 = h.empty_gamma()
+    torch.cuda.synchronize()
+    kept = float((s > m.L_FIT).double().mean())
+    say(f"  kept {kept:.4f}; osv_project {times['dense'] * 1e3:.1f} ms, "
+        f"restricted projection {times['restricted'] * 1e3:.1f} ms")
+    assert torch.equal(g2, g)
+    h.close()
+    del g, g2
+    torch.cuda.empty_cache()
