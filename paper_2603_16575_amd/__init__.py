@@ -313,15 +313,22 @@ class Mbe3:
         return dict(gamma=gamma, K=K, e_frag=e, iters=it, W=W,
                     dB=dB if grad else None, dEdF=dEdF if grad else None)
 
-    def forward(self, grad=False, l_fit=None):
+    def forward(self, grad=False, l_fit=None, compact=False):
         """osv_project -> pair_K -> fragment_solve -> mbe3_energy; with
         grad=True fragment_solve also returns the multipliers W.  With
         l_fit, Gamma~ is restricted to the sparse fitting domains
-        s_fit > l_fit before pair_K (s_fit returned as well)."""
+        s_fit > l_fit before pair_K (s_fit returned as well): masked after
+        the full projection, or with compact=True projected over the
+        domains only (mbe3_project_fit; not recordable)."""
         import torch
-        gamma = self.osv_project(self.empty_gamma())
         s_fit = None
-        if l_fit is not None:
+        if l_fit is None:
+            gamma = self.osv_project(self.empty_gamma())
+        elif compact:
+            s_fit = self.fit_metric()
+            gamma = self.project_fit(s_fit, l_fit, self.empty_gamma())
+        else:
+            gamma = self.osv_project(self.empty_gamma())
             s_fit = self.fit_metric()
             self.fit_mask(s_fit, l_fit, gamma)
         K = self.pair_K(gamma, self.empty_K())

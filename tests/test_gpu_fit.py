@@ -111,6 +111,8 @@ def test_fit_restricted_chain8(m):
     ref = oracle.run(prob, ora=ora)
     E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
     e = out["e_frag"].cpu().numpy()
+    comp = h.forward(l_fit=l_fit, compact=True)
+    assert comp["E"] == out["E"] and torch.equal(comp["e_frag"], out["e_frag"])
     full = h.forward()
     say(f"  E restricted GPU {out['E']:.14f} oracle {E_ref:.14f}; "
         f"unrestricted {full['E']:.14f}")
