@@ -376,6 +376,25 @@ int mbe3_project_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *
                      int64_t gamma_elems);
 
 /*
+ * pair_K over the fitting domains (eq. osv_close_k with Gamma~_i stored on
+ * D_i only, eq. sparse_fit_metric): the kept columns of every slab are
+ * projected as in mbe3_project_fit, kept compacted and transposed inside
+ * the call, and each block of K_(pq,pq) is summed over the P in both D_p
+ * and D_q only (gathered rows of the two compacted operands).  The result
+ * is pair_K of the masked gamma up to the rounding of the skipped zero
+ * terms' grouping; blocks with an empty intersection are zero.  Gamma~
+ * itself is not written.  FP64 in every precision mode.
+ * s_fit: device, n_occ * n_aux doubles.  K: device, k_elems >= the
+ * layout's k_elems.  Copies s_fit to the host and synchronises the stream,
+ * allocates the compacted slabs (at most about 2 GiB at a time) and
+ * sum_i rows_i |D_i| doubles for the call, so it cannot be recorded.
+ * MBE3_EINVAL for a NULL pointer, a NaN l_fit, a short K or while
+ * recording; MBE3_ENOMEM if the buffers cannot be allocated.
+ */
+int mbe3_pair_K_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *K,
+                    int64_t k_elems);
+
+/*
  * Recorded launches (one HIP graph per handle) for the batched form of
  * Algorithm 7: thousands of fragments per call, replayed without host work.
  *

@@ -269,6 +269,15 @@ class Mbe3:
                                                 gamma.numel()), self._h)
         return gamma
 
+    def pair_K_fit(self, s_fit, l_fit, K):
+        """pair_K with every block summed over the intersection of the two
+        fitting domains (s_fit > l_fit), from the kept columns only (Gamma~
+        is not formed); returns K."""
+        _lib.check(_lib.load().mbe3_pair_K_fit(self._h, _lib.ptr(_f64(s_fit)),
+                                               float(l_fit), _lib.ptr(_f64(K)),
+                                               K.numel()), self._h)
+        return K
+
     def graph_begin(self, with_grad=False):
         _lib.check(_lib.load().mbe3_graph_begin(self._h, int(bool(with_grad))), self._h)
 

@@ -2402,6 +2402,183 @@ static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, d
   return MBE3_OK;
 }
 
+// pair_K over the fitting domains: the kept columns projected as in
+// project_fit but stored transposed and compacted (GT_i: kept column x gamma
+// row of LMO i), then each K block summed over D_p and D_q together by
+// gathering the intersection's rows of GT_p and GT_q (k-row gathers of the
+// grouped-GEMM engine).
+static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, double *K,
+                           int64_t k_elems) {
+  if (h->recording)
+    return h->fail(MBE3_EINVAL, "mbe3_pair_K_fit allocates: not recordable");
+  if (!s_fit || !K) return h->fail(MBE3_EINVAL, "s_fit and K required");
+  if (std::isnan(l_fit)) return h->fail(MBE3_EINVAL, "l_fit is NaN");
+  if (k_elems < h->k_elems)
+    return h->fail(MBE3_EINVAL, "K needs %lld doubles, got %lld", (long long)h->k_elems,
+                   (long long)k_elems);
+  const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
+  hipStream_t s = h->stream;
+  std::vector<double> sf((size_t)n * na);
+  HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  std::vector<int32_t> cols, col_off((size_t)n + 1, 0);
+  std::vector<int64_t> gt_off((size_t)n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int P = 0; P < na; ++P)
+      if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
+    col_off[i + 1] = (int32_t)cols.size();
+    gt_off[i + 1] = gt_off[i] + (h->g_off[i + 1] - h->g_off[i]) * (col_off[i + 1] - col_off[i]);
+  }
+  CallTemp tmp(h);
+  int32_t *d_cols = nullptr, *d_col_off = nullptr;
+  double *gt = nullptr, *cs = nullptr;
+  int rc;
+  if ((rc = tmp.upload(&d_cols, cols)) || (rc = tmp.upload(&d_col_off, col_off)) ||
+      (rc = tmp.alloc(&gt, gt_off[n])))
+    return rc;
+  const int64_t budget = SLAB_BUDGET / (int64_t)sizeof(double);
+  std::vector<std::pair<int, int>> batches;
+  int64_t cs_max = 0;
+  for (int i0 = 0; i0 < n;) {
+    int i1 = i0;
+    int64_t tot = 0;
+    while (i1 < n && i1 - i0 < 65535 &&
+           (i1 == i0 || tot + (int64_t)nv * (col_off[i1 + 1] - col_off[i1]) <= budget)) {
+      tot += (int64_t)nv * (col_off[i1 + 1] - col_off[i1]);
+      ++i1;
+    }
+    batches.push_back({i0, i1});
+    cs_max = std::max(cs_max, tot);
+    i0 = i1;
+  }
+  if ((rc = tmp.alloc(&cs, cs_max))) return rc;
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  sz[B_SLAB] = cs_max;
+  sz[B_GAMMA] = gt_off[n];
+  // GT_i = (B_i restricted to D_i)^T Q_{N+(i)}: A the compacted slab read
+  // transposed, B the gathered rows of Q^T read transposed
+  for (const auto &bt : batches) {
+    const int i0 = bt.first, i1 = bt.second;
+    std::vector<int64_t> out_off;
+    std::vector<GemmTask> ts;
+    std::vector<int32_t> rows;
+    int64_t off = 0, max_elems = 0;
+    for (int i = i0; i < i1; ++i) {
+      const int nc = col_off[i + 1] - col_off[i];
+      const int Mi = (int)(h->g_off[i + 1] - h->g_off[i]);
+      out_off.push_back(off);
+      max_elems = std::max<int64_t>(max_elems, (int64_t)nv * nc);
+      if (nc > 0) {
+        GemmTask t = gemm(B_SLAB, off, nc, 1, B_Q, 0, nv, 1, B_GAMMA, gt_off[i], Mi, nc, Mi,
+                          nv);
+        t.b_rows = (int32_t)rows.size();
+        for (int x : h->nbr[i])
+          for (int mu = 0; mu < h->r[x]; ++mu) rows.push_back((int32_t)(h->q_off[x] + mu));
+        ts.push_back(t);
+      }
+      off += (int64_t)nv * nc;
+    }
+    if (ts.empty()) continue;
+    int64_t *d_out_off = nullptr;
+    int32_t *d_rows = nullptr;
+    GemmTask *d_ts = nullptr;
+    const int64_t tiles = finish_tasks(ts, GEMM_64x64);
+    if ((rc = check_gemm_list(h, "project^T (fitting domains)", ts, sz, rows, GEMM_64x64)))
+      return rc;
+    if ((rc = tmp.upload(&d_out_off, out_off)) || (rc = tmp.upload(&d_rows, rows)) ||
+        (rc = tmp.upload(&d_ts, ts)))
+      return rc;
+    {
+      PhaseScope ps_(h, MBE3_PHASE_REGEN);
+      HIP_TRY(h, launch_regen_cols(cs, d_out_off, d_cols, d_col_off, i0, i1 - i0, max_elems,
+                                   nv, na, h->seed, h->w_ia, h->w_iP, h->slab, s));
+    }
+    PhaseScope ps_(h, MBE3_PHASE_PROJECT);
+    GemmBases b = bases(h);
+    b.p[B_SLAB] = cs;
+    b.p[B_GAMMA] = gt;
+    b.rows = d_rows;
+    HIP_TRY(h, launch_gemm_tasks(d_ts, (int)ts.size(), tiles, b, GEMM_64x64, s));
+  }
+  // K blocks (x, y) of every slot over the intersection of the domains
+  std::vector<GemmTask> kt;
+  std::vector<int32_t> krows;
+  std::vector<int32_t> ip, iq;
+  for (int sl = 0; sl < h->n_slot; ++sl) {
+    const int p = h->sp[sl], q = h->sq[sl];
+    ip.clear();
+    iq.clear();
+    for (int a = col_off[p], c = col_off[q]; a < col_off[p + 1] && c < col_off[q + 1];) {
+      if (cols[a] < cols[c]) {
+        ++a;
+      } else if (cols[c] < cols[a]) {
+        ++c;
+      } else {
+        ip.push_back(a - col_off[p]);
+        iq.push_back(c - col_off[q]);
+        ++a;
+        ++c;
+      }
+    }
+    if (ip.empty()) continue;
+    const int32_t ro_p = (int32_t)krows.size();
+    krows.insert(krows.end(), ip.begin(), ip.end());
+    const int32_t ro_q = (int32_t)krows.size();
+    krows.insert(krows.end(), iq.begin(), iq.end());
+    const int Mp = (int)(h->g_off[p + 1] - h->g_off[p]);
+    const int Mq = (int)(h->g_off[q + 1] - h->g_off[q]);
+    const int d = p == q ? h->r[p] : h->r[p] + h->r[q];
+    const int xs[2] = {p, q};
+    const int nx = p == q ? 1 : 2;
+    int ro = 0;
+    for (int xi = 0; xi < nx; ++xi) {
+      const int x = xs[xi];
+      const auto fx = h->grow.find(key2(p, x));
+      if (fx == h->grow.end()) return h->fail(MBE3_EINVAL, "internal: no rows of (%d,%d)", p, x);
+      int co = 0;
+      for (int yi = 0; yi < nx; ++yi) {
+        const int y = xs[yi];
+        const auto fy = h->grow.find(key2(q, y));
+        if (fy == h->grow.end())
+          return h->fail(MBE3_EINVAL, "internal: no rows of (%d,%d)", q, y);
+        GemmTask t = gemm(B_GAMMA, gt_off[p] + (fx->second - h->g_off[p]), Mp, 1, B_GAMMA,
+                          gt_off[q] + (fy->second - h->g_off[q]), Mq, 0, B_K,
+                          h->k_off[sl] + (int64_t)ro * d + co, d, h->r[x], h->r[y],
+                          (int)ip.size());
+        t.a_rows = ro_p;
+        t.b_rows = ro_q;
+        kt.push_back(t);
+        co += h->r[y];
+      }
+      ro += h->r[x];
+    }
+  }
+  HIP_TRY(h, launch_fill(K, 0.0, h->k_elems, s));
+  if (!kt.empty()) {
+    int32_t *d_krows = nullptr;
+    GemmTask *d_kt = nullptr;
+    const int64_t tiles = finish_tasks(kt, GEMM_32x32);
+    if ((rc = check_gemm_list(h, "pair_K (fitting domains)", kt, sz, krows, GEMM_32x32)))
+      return rc;
+    if ((rc = tmp.upload(&d_krows, krows)) || (rc = tmp.upload(&d_kt, kt))) return rc;
+    PhaseScope ps_(h, MBE3_PHASE_PAIR_K);
+    GemmBases b = bases(h);
+    b.p[B_GAMMA] = gt;
+    b.p[B_K] = K;
+    b.rows = d_krows;
+    HIP_TRY(h, launch_gemm_tasks(d_kt, (int)kt.size(), tiles, b, GEMM_32x32, s));
+  }
+  return MBE3_OK;
+}
+
+int mbe3_pair_K_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *K,
+                    int64_t k_elems) {
+  if (!h) return MBE3_EINVAL;
+  return no_throw(h, [&] { return pair_k_fit_body(h, s_fit, l_fit, K, k_elems); });
+}
+
 int mbe3_project_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *gamma,
                      int64_t gamma_elems) {
   if (!h) return MBE3_EINVAL;

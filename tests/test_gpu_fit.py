@@ -5,8 +5,9 @@ Gamma~, pair integrals, fragment and MBE(3) energies at a threshold that
 splits the domains, the gradient of the restricted energy, the exact
 masking pattern, a recorded restriction replayed, argument errors, the
 metric of a given slab array, the restriction in both split-precision
-forms, and sampled fragments of the restricted 160-LMO lattice at full
-size."""
+forms, sampled fragments of the restricted 160-LMO lattice at full size,
+the projection over the domains only and pair_K over their
+intersections (bit for bit the masked dense path, timed on the helix)."""
 import dataclasses
 import sys
 
@@ -402,3 +403,68 @@ def test_project_fit_helix1024(m):
     h.close()
     del g, g2
     torch.cuda.empty_cache()
+
+
+def test_pair_K_fit_chain8(m):
+    """pair_K over the domain intersections against pair_K of the masked
+    gamma and against the oracle's restricted K, at a splitting threshold,
+    below every metric (the unrestricted K) and above every metric (zero)."""
+    import torch
+    say("case: chain8, pair_K over D_p and D_q vs pair_K of the masked gamma and oracle")
+    prob = synth.config(0)
+    h = m.from_problem(prob)
+    s = h.fit_metric()
+    sn = s.cpu().numpy()
+    base = oracle.Oracle(prob)
+    for l_fit in (split_threshold(sn), -1.0, float(sn.max())):
+        g = h.fit_mask(s, l_fit, h.osv_project(h.empty_gamma()))
+        ref = h.pair_K(g, h.empty_K())
+        got = h.pair_K_fit(s, l_fit, h.empty_K())
+        torch.cuda.synchronize()
+        scale = float(ref.abs().max()) if float(ref.abs().max()) > 0 else 1.0
+        d = float((got - ref).abs().max()) / scale
+        say(f"  l_fit {l_fit:.3e}: max |K_fit - K(masked)| / max|K| = {d:.2e}")
+        assert d <= 1e-13
+        if l_fit == float(sn.max()):
+            assert not torch.any(got)
+    l_fit = split_threshold(sn)
+    ora = fit.restricted_oracle(prob, l_fit, base=base, s_fit=fit.fit_metrics(base))
+    K = h.pair_K_fit(s, l_fit, h.empty_K())
+    for sl in range(h.layout.n_slot):
+        k, (p, q) = k_block(h, prob, K, sl)
+        r = ora.Kbar(p, q)
+        assert np.abs(k - r).max() <= 1e-13 * np.abs(r).max(), sl
+    h.close()
+
+
+def test_pair_K_fit_helix1024(m):
+    """The 1024-LMO helix at l_fit = 1e-6: pair_K over the intersections
+    (projection of the kept columns included) against pair_K of the masked
+    dense gamma, both timed."""
+    import time
+    import torch
+    say("case: helix1024, pair_K over the domain intersections vs masked dense path")
+    prob = synth.config(4)
+    h = m.from_problem(prob)
+    s = h.fit_metric()
+    g = h.fit_mask(s, m.L_FIT, h.osv_project(h.empty_gamma()))
+    K_ref, K = h.empty_K(), h.empty_K()
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.pair_K(g, K_ref)
+        torch.cuda.synchronize()
+        t_dense = time.perf_counter() - t0
+    del g
+    torch.cuda.empty_cache()
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.pair_K_fit(s, m.L_FIT, K)
+        torch.cuda.synchronize()
+        t_fit = time.perf_counter() - t0
+    d = float((K - K_ref).abs().max()) / float(K_ref.abs().max())
+    say(f"  pair_K on the masked gamma {t_dense * 1e3:.1f} ms; projection + pair_K over "
+        f"the intersections {t_fit * 1e3:.1f} ms; max rel diff {d:.2e}")
+    assert d <= 1e-12
+    h.close()
