@@ -498,3 +498,5 @@ def test_fit_helix1024_restricted_energy(m):
     assert np.isfinite(E_fit) and (it >= 0).all()
     assert abs(rel) < 0.05
     h.close()
+    del out, K, s
+    torch.cuda.empty_cache()
