@@ -2295,6 +2295,44 @@ int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
   return MBE3_OK;
 }
 
+// The fitting domains of every LMO from a device metric (copied back; the
+// stream is synchronised): cols holds the kept auxiliary indices of LMO i at
+// [col_off[i], col_off[i + 1]), ascending.  batches: runs of LMOs whose
+// compacted slabs (n_vir x |D_i| each) fit the slab budget together (at
+// most 65535 per run, one workgroup row each); *cs_max the largest run.
+static int fit_domains(mbe3_handle *h, const double *s_fit, double l_fit,
+                       std::vector<int32_t> &cols, std::vector<int32_t> &col_off,
+                       std::vector<std::pair<int, int>> &batches, int64_t *cs_max) {
+  const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
+  std::vector<double> sf((size_t)n * na);
+  HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  cols.clear();
+  col_off.assign((size_t)n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int P = 0; P < na; ++P)
+      if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
+    col_off[i + 1] = (int32_t)cols.size();
+  }
+  const int64_t budget = SLAB_BUDGET / (int64_t)sizeof(double);
+  batches.clear();
+  *cs_max = 0;
+  for (int i0 = 0; i0 < n;) {
+    int i1 = i0;
+    int64_t tot = 0;
+    while (i1 < n && i1 - i0 < 65535 &&
+           (i1 == i0 || tot + (int64_t)nv * (col_off[i1 + 1] - col_off[i1]) <= budget)) {
+      tot += (int64_t)nv * (col_off[i1 + 1] - col_off[i1]);
+      ++i1;
+    }
+    batches.push_back({i0, i1});
+    *cs_max = std::max(*cs_max, tot);
+    i0 = i1;
+  }
+  return MBE3_OK;
+}
+
 // osv_project over the fitting domains only: per LMO the kept columns are
 // listed on the host (s_fit copied back), regenerated compacted, projected
 // by one GEMM per LMO over them and scattered into the zeroed dense gamma.
@@ -2309,17 +2347,14 @@ static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, d
     return h->fail(MBE3_EINVAL, "gamma needs %lld doubles, got %lld",
                    (long long)(h->gamma_rows * na), (long long)gamma_elems);
   hipStream_t s = h->stream;
-  std::vector<double> sf((size_t)n * na);
-  HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
-  HIP_TRY(h, hipStreamSynchronize(s));
-  std::vector<int32_t> cols, col_off((size_t)n + 1, 0);
+  std::vector<int32_t> cols, col_off;
+  std::vector<std::pair<int, int>> batches;
+  int64_t cs_max = 0;
+  int rc = fit_domains(h, s_fit, l_fit, cols, col_off, batches, &cs_max);
+  if (rc) return rc;
   std::vector<int64_t> gc_off((size_t)n + 1, 0);
   int max_nc = 0;
   for (int i = 0; i < n; ++i) {
-    for (int P = 0; P < na; ++P)
-      if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
-    col_off[i + 1] = (int32_t)cols.size();
     const int nc = col_off[i + 1] - col_off[i];
     max_nc = std::max(max_nc, nc);
     gc_off[i + 1] = gc_off[i] + (h->g_off[i + 1] - h->g_off[i]) * nc;
@@ -2328,28 +2363,10 @@ static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, d
   int32_t *d_cols = nullptr, *d_col_off = nullptr;
   int64_t *d_goff = nullptr, *d_gcoff = nullptr;
   double *gc = nullptr, *cs = nullptr;
-  int rc;
   if ((rc = tmp.upload(&d_cols, cols)) || (rc = tmp.upload(&d_col_off, col_off)) ||
       (rc = tmp.upload(&d_goff, h->g_off)) || (rc = tmp.upload(&d_gcoff, gc_off)) ||
-      (rc = tmp.alloc(&gc, gc_off[n])))
+      (rc = tmp.alloc(&gc, gc_off[n])) || (rc = tmp.alloc(&cs, cs_max)))
     return rc;
-  // batches of LMOs whose compacted slabs fit the slab budget
-  const int64_t budget = SLAB_BUDGET / (int64_t)sizeof(double);
-  std::vector<std::pair<int, int>> batches;
-  int64_t cs_max = 0;
-  for (int i0 = 0; i0 < n;) {
-    int i1 = i0;
-    int64_t tot = 0;
-    while (i1 < n && i1 - i0 < 65535 &&
-           (i1 == i0 || tot + (int64_t)nv * (col_off[i1 + 1] - col_off[i1]) <= budget)) {
-      tot += (int64_t)nv * (col_off[i1 + 1] - col_off[i1]);
-      ++i1;
-    }
-    batches.push_back({i0, i1});
-    cs_max = std::max(cs_max, tot);
-    i0 = i1;
-  }
-  if ((rc = tmp.alloc(&cs, cs_max))) return rc;
   HIP_TRY(h, launch_fill(gamma, 0.0, h->gamma_rows * na, s));
   int64_t sz[B_COUNT];
   base_sizes(h, sz);
@@ -2418,41 +2435,20 @@ static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, do
                    (long long)k_elems);
   const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
   hipStream_t s = h->stream;
-  std::vector<double> sf((size_t)n * na);
-  HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
-  HIP_TRY(h, hipStreamSynchronize(s));
-  std::vector<int32_t> cols, col_off((size_t)n + 1, 0);
+  std::vector<int32_t> cols, col_off;
+  std::vector<std::pair<int, int>> batches;
+  int64_t cs_max = 0;
+  int rc = fit_domains(h, s_fit, l_fit, cols, col_off, batches, &cs_max);
+  if (rc) return rc;
   std::vector<int64_t> gt_off((size_t)n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    for (int P = 0; P < na; ++P)
-      if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
-    col_off[i + 1] = (int32_t)cols.size();
+  for (int i = 0; i < n; ++i)
     gt_off[i + 1] = gt_off[i] + (h->g_off[i + 1] - h->g_off[i]) * (col_off[i + 1] - col_off[i]);
-  }
   CallTemp tmp(h);
   int32_t *d_cols = nullptr, *d_col_off = nullptr;
   double *gt = nullptr, *cs = nullptr;
-  int rc;
   if ((rc = tmp.upload(&d_cols, cols)) || (rc = tmp.upload(&d_col_off, col_off)) ||
-      (rc = tmp.alloc(&gt, gt_off[n])))
+      (rc = tmp.alloc(&gt, gt_off[n])) || (rc = tmp.alloc(&cs, cs_max)))
     return rc;
-  const int64_t budget = SLAB_BUDGET / (int64_t)sizeof(double);
-  std::vector<std::pair<int, int>> batches;
-  int64_t cs_max = 0;
-  for (int i0 = 0; i0 < n;) {
-    int i1 = i0;
-    int64_t tot = 0;
-    while (i1 < n && i1 - i0 < 65535 &&
-           (i1 == i0 || tot + (int64_t)nv * (col_off[i1 + 1] - col_off[i1]) <= budget)) {
-      tot += (int64_t)nv * (col_off[i1 + 1] - col_off[i1]);
-      ++i1;
-    }
-    batches.push_back({i0, i1});
-    cs_max = std::max(cs_max, tot);
-    i0 = i1;
-  }
-  if ((rc = tmp.alloc(&cs, cs_max))) return rc;
   int64_t sz[B_COUNT];
   base_sizes(h, sz);
   sz[B_SLAB] = cs_max;
