@@ -350,9 +350,29 @@ def fit_run(m, prob, h):
     elems = prob.n_occ * prob.n_vir * prob.n_aux
     log(f"bench: fit metric {t_ms:.2f} ms ({elems / t_ms / 1e6:.1f} Gelem/s), "
         f"kept at l_fit {m.L_FIT:g}: {kept:.4f}")
+    # osv_project against the projection over the domains only (the second
+    # of two calls each, host clock between synchronisations)
+    g = h.empty_gamma()
+
+    def timed(fn):
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3
+        return round(t, 3)
+
+    proj = {"osv_project_ms": timed(lambda: h.osv_project(g))}
+    for l_fit in (m.L_FIT, 5e-3):
+        proj[f"project_fit_ms_at_{l_fit:g}"] = timed(lambda: h.project_fit(s, l_fit, g))
+        proj[f"kept_fraction_at_{l_fit:g}"] = round(float((s > l_fit).double().mean()), 6)
+    del g
+    torch.cuda.empty_cache()
+    log("bench: projection " + ", ".join(f"{k} {v}" for k, v in proj.items()))
     return {"metric_ms": round(t_ms, 3), "slab_elements": elems,
             "gelem_per_s": round(elems / t_ms / 1e6, 2), "l_fit": m.L_FIT,
-            "kept_fraction": round(kept, 6)}
+            "kept_fraction": round(kept, 6), "projection": proj}
 
 
 def _call_pool_fn(x):
