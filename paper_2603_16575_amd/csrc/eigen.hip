@@ -223,8 +223,11 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
 // Overlap step by Cholesky: S = L L^T in LDS (right-looking, one column per
 // step), then L^{-1} column by column (forward substitution, one column per
 // thread) and X0 = L^{-T}, which satisfies X0^T S X0 = 1 with the full rank.
-// A pivot <= tau (S not safely positive definite) sets flag[slot] and leaves
-// the slot to the canonical-orthogonalisation Jacobi launch that follows.
+// The slot keeps this basis only when ||L^{-1}||_F^2 < 1 / tau, which proves
+// every eigenvalue of S above tau (the rank canonical orthogonalisation
+// keeps is then n as well).  A pivot <= tau or a larger norm sets
+// flag[slot] and leaves the slot to the canonical-orthogonalisation launch
+// that follows.
 __global__ __launch_bounds__(256) void cholesky_kernel(
     const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
     double *__restrict__ out, double *__restrict__ evals,
@@ -233,6 +236,7 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
   extern __shared__ double sm_dyn[];
   double *const sm = gws ? gws + (int64_t)blockIdx.x * gstride : sm_dyn;
   __shared__ int failed;
+  __shared__ double wsum[4];  // per-wave partial sums (256 threads)
   for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
   const EigTask t = tasks[ti];
   if (t.n < n_lo || t.n > n_hi) continue;  // the other launch's task
@@ -275,16 +279,39 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
     __syncthreads();
     continue;
   }
-  // L^{-1}: thread c solves L x = e_c for column c (rows >= c)
+  // L^{-1}: thread c solves L x = e_c for column c (rows >= c), summing the
+  // squares of the column as it goes
+  double ssq = 0.0;
   for (int c = tid; c < n; c += nt) {
     for (int i = 0; i < c; ++i) Li[i * ld + c] = 0.0;
     for (int i = c; i < n; ++i) {
       double acc = (i == c) ? 1.0 : 0.0;
       for (int m2 = c; m2 < i; ++m2) acc -= L[i * ld + m2] * Li[m2 * ld + c];
-      Li[i * ld + c] = acc / L[i * ld + i];
+      const double v = acc / L[i * ld + i];
+      Li[i * ld + c] = v;
+      ssq += v * v;
     }
   }
+  // Positive pivots do not bound the smallest eigenvalue of S; the trace of
+  // S^{-1} = L^{-T} L^{-1}, the squared Frobenius norm of L^{-1}, does:
+  // 1 / lambda_min <= trace(S^{-1}).  So when ||L^{-1}||_F^2 < 1 / tau every
+  // eigenvalue exceeds tau and canonical orthogonalisation would keep all n
+  // directions too; otherwise the slot goes to that route (flag).  Fixed-
+  // order sums: lane butterfly, then the four waves in order.
+  for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o, 64);
+  if ((tid & 63) == 0) wsum[tid >> 6] = ssq;
   __syncthreads();
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int w = 0; w < (nt + 63) / 64; ++w) tr += wsum[w];
+    if (!(tr * tau < 1.0)) failed = 1;  // NaN fails too
+  }
+  __syncthreads();
+  if (failed) {
+    if (tid == 0) flag[t.slot] = 1;
+    __syncthreads();
+    continue;
+  }
   // X0 = L^{-T}: X0[r][c] = Li[c][r]
   for (int e = tid; e < n * D; e += nt) {
     const int r = e / D, c = e - r * D;

@@ -8,6 +8,7 @@ import sys
 import numpy as np
 import pytest
 
+import _workloads
 import oracle
 import synth
 
@@ -150,6 +151,81 @@ def test_water128u_sampled(m):
     torch.cuda.empty_cache()
 
 
+def helix_problem():
+    """configuration 4 (1024-LMO helix), built once per test process."""
+    return _workloads.config(4)
+
+
+def overlap_eigs(prob, s):
+    """Eigenvalues of the pair overlap S_(pq,pq) of slot s (host, ascending),
+    written from the OSVs directly (eq. 4block_osv)."""
+    n = prob.n_occ
+    p, q = (s, s) if s < n else (int(prob.pairs[s - n][0]), int(prob.pairs[s - n][1]))
+    V = prob.Q[p] if p == q else np.concatenate([prob.Q[p], prob.Q[q]], 1)
+    return np.linalg.eigvalsh(V.T @ V)
+
+
+def test_helix1024_rank_and_sampled_fragments(m):
+    """helix1024 OSV spaces of neighbouring LMOs nearly coincide (pair-overlap
+    eigenvalues down to 1e-13), so the rank rule of the overlap step decides
+    which pair space each side solves in.  Every slot's kept rank on the GPU
+    must equal the number of overlap eigenvalues above tau_S (the oracle's
+    canonical orthogonalisation); then the fragments around the slots with
+    the smallest overlap eigenvalues and the one nearest tau_S, and every
+    fragment containing the pair (1, 2), one by one against the oracle."""
+    import torch
+    say("case: helix1024 overlap ranks of every slot, sampled fragments vs oracle")
+    prob = helix_problem()
+    n = prob.n_occ
+    h = m.from_problem(prob, warm_start=False)  # the oracle's iterates
+    out = h.forward()
+    _, _, rank = h.mbe3_pair_basis()
+    rank = rank.cpu().numpy()
+    e = out["e_frag"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert (it >= 0).all() and np.isfinite(e).all()
+    n_slot = int(h.layout.n_slot)
+    lam_min = np.empty(n_slot)
+    gap = np.empty(n_slot)
+    want = np.empty(n_slot, dtype=np.int64)
+    for s in range(n_slot):
+        ev = overlap_eigs(prob, s)
+        lam_min[s] = ev[0]
+        gap[s] = np.min(np.abs(ev - prob.tau_S)) / prob.tau_S
+        want[s] = int((ev > prob.tau_S).sum())
+    full = np.array([prob.r[s] if s < n else prob.r[prob.pairs[s - n][0]] + prob.r[prob.pairs[s - n][1]]
+                     for s in range(n_slot)])
+    bad = np.nonzero(rank != want)[0]
+    say(f"helix1024: {n_slot} slots, {int((want < full).sum())} rank deficient, "
+        f"min lambda {lam_min.min():.2e}, nearest |lambda - tau|/tau {gap.min():.2e}, "
+        f"rank mismatches {len(bad)} {bad[:8].tolist()}")
+    assert len(bad) == 0
+    # sampled fragments
+    fr = prob.frags
+    pick = set()
+    tight = [int(s) for s in np.argsort(lam_min)[:2]] + [int(np.argmin(gap))]
+    slot_pairs = [(s, s) if s < n else tuple(int(v) for v in prob.pairs[s - n]) for s in tight]
+    slot_pairs.append((1, 2))
+    for (p, q) in slot_pairs:
+        has = (fr == p).any(1) & (fr == q).any(1)
+        if p == q:
+            has &= fr[:, 1] < 0  # the monomer only
+        rows = np.nonzero(has)[0]
+        pick.update(int(x) for x in rows[:3] if (p, q) != (1, 2))
+        if (p, q) == (1, 2):
+            pick.update(int(x) for x in rows)
+    idx = np.array(sorted(pick))
+    say(f"sampled slots {slot_pairs}, {len(idx)} fragments: {fr[idx].tolist()}")
+    res = oracle.run(prob, frags=fr[idx])
+    dE = np.abs(e[idx] - res["e_frag"])
+    say(f"helix1024 sampled fragments: max |dE_F| = {dE.max():.3e}, "
+        f"iterations GPU {it[idx].tolist()} oracle {res['iters'].tolist()}")
+    assert dE.max() <= 1e-12
+    h.close()
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_helix1024_forward_and_gradient(m):
     """helix1024 (1024 LMOs, n_vir 4096, n_aux 12288, D up to 160), FP64:
     every fragment converged and finite; projected blocks of the two LMOs
@@ -163,7 +239,7 @@ def test_helix1024_forward_and_gradient(m):
     # converged tighter than the workload's 1e-7: the stationarity argument
     # leaves a first-order error of the size of the residual, which is 1e-5
     # of these small f derivatives at tol 1e-7
-    prob = dataclasses.replace(synth.config(4), tol=1e-10)
+    prob = dataclasses.replace(helix_problem(), tol=1e-10)
     f = torch.as_tensor(prob.f_occ.copy(), device="cuda:0")
     h = m.from_problem(prob, f_occ=f)
     out = h.forward(grad=True)
