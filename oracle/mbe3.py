@@ -35,16 +35,26 @@ STREAM_SLAB = 0
 # --------------------------------------------------------------------------
 # O1: regenerated slab (stand-in for the direct Gamma_i generator, Alg. 1)
 # --------------------------------------------------------------------------
-def slab(prob, i: int, cols=None) -> np.ndarray:
+def slab(prob, i: int, cols=None, impl: str = "c") -> np.ndarray:
     """B_i[a,P] = z(seed,i,a,P) * w_ia[i,a] * w_iP[i,P] (in that order).
 
     z is the Box-Muller normal of words 0 and 1 of the Philox4x64-10 block at
     counter (P, a, i, 0) under key (seed, 0).  The product is evaluated left to
     right.  Plays the role of the fitted Gamma_i of eq. fitting.  ``cols``
     (optional) restricts P to a list of auxiliary indices.
+
+    impl "c": the same definition in the oracle's own C routine
+    (oracle/csrc/slab.c, libm log and cos), fast enough for slabs of tens of
+    millions of elements; "numpy": vectorised numpy (its own log and cos).
+    The two agree bit for bit on the Philox words and to 4 ulp on the slab
+    (pinned in the test-suite).
     """
     nv = prob.n_vir
     P = np.arange(prob.n_aux) if cols is None else np.asarray(cols)
+    if impl == "c":
+        from . import _clib
+        return _clib.normal_slab((prob.seed, STREAM_SLAB), i, nv, P,
+                                 prob.w_ia[i], prob.w_iP[i])
     ctr = np.zeros((nv, len(P), 4), dtype=np.uint64)
     ctr[..., 0] = P.astype(np.uint64)[None, :]
     ctr[..., 1] = np.arange(nv, dtype=np.uint64)[:, None]
