@@ -108,3 +108,40 @@ def test_diagonal_amplitudes_match_multipliers():
     for i in range(prob.n_occ):
         W = g["W"][(i, i)]
         assert np.abs(Td[i] - W).max() <= 1e-10 * np.abs(W).max()
+
+
+def test_weak_residual_is_close_pair_block():
+    """Reading W1 pinned by another route: the close-pair residual of eq.
+    res_close (Oracle.residual, the dimer ij as the fragment) with every
+    block of T_ij zeroed except the direct (mu_i, nu_j) one, tau, and the
+    diagonal-pair amplitudes T_ii, T_jj set, has as its (mu_i, nu_j) block
+    the one-block residual at tau: K_(i,j) + F_ii tau + tau F_jj
+    - (f_ii + f_jj) tau - f_ij (T_ii S_ij + S_ij T_jj).  Checked at random
+    tau (so every term counts) and at the weak-pair solution (block zero);
+    f is made strongly non-diagonal so that the coupling term matters."""
+    prob = synth.micro(4)
+    f = prob.f_occ.copy()
+    off = ~np.eye(prob.n_occ, dtype=bool)
+    f[off] *= 8.0
+    prob = dataclasses.replace(prob, f_occ=f)
+    ora = oracle.Oracle(prob)
+    rng = np.random.default_rng(11)
+    Td = {}
+    for i in range(prob.n_occ):
+        a = rng.standard_normal((prob.r[i], prob.r[i])) * 1e-2
+        Td[i] = a + a.T
+    for i, j in ((0, 1), (0, 3), (1, 2)):
+        ri, rj = prob.r[i], prob.r[j]
+        T_sol, _, K = weak.weak_pair(ora, i, j, Td[i], Td[j])
+        coupling = np.abs(f[i, j] * (Td[i] @ ora.S(i, j) + ora.S(i, j) @ Td[j])).max()
+        assert coupling > 1e-3 * np.abs(K).max()  # the term is not negligible
+        for tau in (rng.standard_normal((ri, rj)) * 1e-2, T_sol):
+            Tij = np.zeros((ri + rj, ri + rj))
+            Tij[:ri, ri:] = tau
+            T = {(i, i): Td[i], (j, j): Td[j], (i, j): Tij}
+            R = ora.residual(i, j, (i, j), T)
+            block = R[:ri, ri:]
+            ref = weak.weak_residual(ora, i, j, tau, Td[i], Td[j])
+            assert np.abs(block - ref).max() <= 1e-13 * np.abs(K).max()
+        # at the solution the block vanishes
+        assert np.abs(block).max() <= 1e-12 * np.abs(K).max()
