@@ -1,17 +1,20 @@
 """Benchmark: MBE(3) fragments solved per second on one MI355X.
 
-One step = the whole hot path on one batch of seeded synthetic input:
-osv_project (slab regeneration + OSV projection) -> pair_K -> fragment_solve
-(pair bases, coupling blocks, residual iterations of every fragment, and the
-MBE multipliers W with dE/df_occ) -> mbe3_energy -> mbe3_backward (dense
-dE/d(ia|P) and dE/df_occ).  Inputs (Q, eps, f, slab weights, lists) are
-resident in HBM before the timed region.  The step is recorded once as a
-HIP graph (mbe3_graph_begin/end) and the timed region replays it; the
-call-by-call step and the recorded step without the backward
-("forward_only") are timed afterwards.  Prints ONE
-JSON line on stdout; progress goes to stderr.
+Headline (the metric's workload): the 512-LMO lattice (n_vir 2432, n_aux
+7040, r 24-64, 470k fragments), FP64.  One step = the whole forward hot path
+on one batch of seeded synthetic input: osv_project (slab regeneration + OSV
+projection) -> pair_K -> fragment_solve (pair bases, coupling blocks,
+residual iterations of every fragment) -> mbe3_energy.  Inputs (Q, eps, f,
+slab weights, lists) are resident in HBM before the timed region.  The step
+is recorded once as a HIP graph (mbe3_graph_begin/end) and the timed region
+replays it.  Extras on the same line: the same step in both split-precision
+forms (per-fragment and total energy change against the FP64 step), the
+160-LMO lattice forward + backward step, the paper's s2b / s3b screening of
+that lattice, the fitting-domain calls, and the CPU oracle on a bounded
+sample of the headline workload.  Prints ONE JSON line on stdout; progress
+goes to stderr.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
 """
 import argparse
 import hashlib
@@ -74,12 +77,12 @@ def solve_flops(prob, iters, grad=False, warm=True):
     return tot
 
 
-def traffic_from_profile(kernel_file, launches_per_step):
+def traffic_from_profile(workload, kernel_file, launches_per_step):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source
-    (sha256 of the .hip file) with the same launches per step (the chunking
-    decides what one launch covers); None otherwise."""
-    path = os.path.join(ROOT, "profiles", "solve_water40u_traffic.json")
+    rocprofv3 counter summary of this workload, if it was taken on the
+    current kernel source (sha256 of the .hip file) with the same launches
+    per step (the chunking decides what one launch covers); None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"solve_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_2603_16575_amd", "csrc", kernel_file)
     try:
         rec = json.load(open(path))
@@ -91,13 +94,23 @@ def traffic_from_profile(kernel_file, launches_per_step):
     return float(rec["bytes_per_launch"])
 
 
-def cpu_baseline(prob, budget_workers):
-    """Oracle throughput on the host for the same step (forward + gradient):
-    a stratified sample on the first 16 orbitals (their slabs + projections,
-    the K / bases of the pairs among them, every fragment among them by
-    class with its gradient contributions, then the dE/dB assembly of the
-    sampled orbitals), each stage on a pool of worker processes,
-    extrapolated by count to the whole workload."""
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(prob, budget_workers, grad=False):
+    """Oracle throughput on the host for the same step: a stratified sample
+    on the first 16 orbitals (their slabs + projections, the K / bases of
+    the pairs among them, every fragment among them by class, with grad its
+    gradient contributions and the dE/dB assembly of the sampled orbitals),
+    each stage on a pool of worker processes, extrapolated by count to the
+    whole workload."""
     import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     import oracle
@@ -149,6 +162,8 @@ def cpu_baseline(prob, budget_workers):
 
         def solve_grad(f):
             r = ora.solve_fragment(f, prob.tol, prob.max_iter)
+            if not grad:
+                return {}
             Tt, g = oracle.fragment_gradient(ora, f, r["T"])
             return Tt
         om._POOL_ORACLE = solve_grad
@@ -185,25 +200,28 @@ def cpu_baseline(prob, budget_workers):
                     V = np.concatenate([ora.Q[i], ora.Q[q]], 1)
                     acc += 4.0 * V @ (Wm @ np.vstack([G(q, i), G(q, q)]))
             return float(acc[0, 0])
-        om._POOL_ORACLE = unproject
-        t0 = time.perf_counter()
-        with ctx.Pool(W) as pool:
-            pool.map(_call_pool_fn, orbs)
-        tD = time.perf_counter() - t0
-        TD = tD * int(np.ceil(prob.n_occ / len(orbs)))
+        TD = 0.0
+        if grad:
+            om._POOL_ORACLE = unproject
+            t0 = time.perf_counter()
+            with ctx.Pool(W) as pool:
+                pool.map(_call_pool_fn, orbs)
+            tD = time.perf_counter() - t0
+            TD = tD * int(np.ceil(prob.n_occ / len(orbs)))
     om._POOL_ORACLE = None
     T = TA + TB + TC + TD
+    what = ("solved with their gradient terms, dE/dB of the "
+            f"{n_s} orbitals" if grad else "solved")
     return dict(value=prob.n_frag / T, unit="fragments/s", cores=W, kind="oracle",
-                sample=(f"orbitals 0-{n_s - 1}: {n_s} slabs+projections, "
+                cpu_model=cpu_model(),
+                sample=(f"{prob.name}, orbitals 0-{n_s - 1}: {n_s} slabs+projections, "
                         f"{len(slots)} pair K+bases, fragments among them "
                         f"(monomers {counts.get(1, 0)}, dimers {counts.get(2, 0)}, "
-                        f"trimers {counts.get(3, 0)}) solved with their gradient "
-                        f"terms, dE/dB of the {n_s} orbitals; each stage on {W} "
+                        f"trimers {counts.get(3, 0)}) {what}; each stage on {W} "
                         f"worker processes (1 BLAS thread each), extrapolated by "
                         f"count to all {prob.n_frag} fragments"),
                 stage_seconds=dict(slab_projection=TA, pair_k_bases=TB,
-                                   fragment_solves_with_gradient=TC,
-                                   dEdB_assembly=TD))
+                                   fragment_solves=TC, dEdB_assembly=TD))
 
 
 def tune_choices(report):
@@ -222,51 +240,158 @@ def tune_choices(report):
     return out
 
 
-def timed_replays(h, args, label):
-    """Warm-up and timed replays of the handle's recorded graph; returns
-    (ms per step, last energy, per-phase timing of the timed replays, median
-    ms of one replay).  Each replay ends synchronised (mbe3_graph_launch
-    reads the status back), so every step has its own wall time too."""
+def recorded_run(m, prob, args, dev, grad, label, steps=None, warmup=None, **kw):
+    """One handle on `prob`: the step run call by call (plans every list and
+    is the reference), the tile autotuner, the same step again (bitwise equal
+    to the first), then the step recorded as one HIP graph and replayed:
+    warm-up replays and `steps` timed ones.  Returns (handle, buffers of the
+    recording, dict of measurements)."""
     import torch
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    h = m.from_problem(prob, device=str(dev), **kw)
+    gamma, K = h.empty_gamma(), h.empty_K()
+    W = h.empty_K() if grad else None
+    e = torch.empty(h.n_frag, dtype=torch.float64, device=dev)
+    it = torch.empty(h.n_frag, dtype=torch.int32, device=dev)
+    dB = dF = None
+    if grad:
+        dB = torch.empty((prob.n_occ, prob.n_vir, prob.n_aux), dtype=torch.float64, device=dev)
+        dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device=dev)
+
+    def step():
+        h.osv_project(gamma)
+        h.pair_K(gamma, K)
+        h.fragment_solve(K, e, it, W)
+        E = h.mbe3_energy(e)
+        if grad:
+            h.mbe3_backward(gamma, W, 1.0, m.MBE3_GRAD_SLAB, out=dB, dEdF=dF)
+        return E
+
+    t0 = time.perf_counter()
+    E_eager = step()
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    e_eager = e.clone()
+    log(f"bench: {label} eager step E={E_eager:.12f} ({t_first:.1f} s with planning)")
+    t0 = time.perf_counter()
+    report = h.autotune(reps=2, dB=grad, gamma=gamma, K=K)
+    t_tune = time.perf_counter() - t0
+    tuned = tune_choices(report)
+    log(f"bench: {label} autotune {t_tune:.1f} s")
+    E_t = step()
+    torch.cuda.synchronize()
+    if E_t != E_eager or not torch.equal(e, e_eager):
+        raise SystemExit(f"bench: {label} tuned step differs ({E_t!r} vs {E_eager!r})")
+    t0 = time.perf_counter()
+    E_t = step()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3
+    del gamma, K, W, dB, dF
+    torch.cuda.empty_cache()
+    h.set_timing(True)
+    bufs = h.capture_step(grad=grad)
     E = None
-    for w in range(args.warmup):
+    for w in range(warmup):
         E = h.graph_launch()
-        log(f"bench: {label} warmup {w + 1}/{args.warmup} E={E:.12f}")
+        log(f"bench: {label} warmup {w + 1}/{warmup} E={E:.12f}")
     h.set_timing(True)  # clears the accumulators; the graph keeps its events
     torch.cuda.synchronize()
     per = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(steps):
         ts = time.perf_counter()
         E = h.graph_launch()
         per.append((time.perf_counter() - ts) * 1000.0)
+        if steps >= 10 and (k + 1) % 5 == 0:
+            log(f"bench: {label} step {k + 1}/{steps} {per[-1]:.1f} ms")
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
     ph = h.get_timing()
-    return ms, E, ph, float(np.median(per))
-
-
-def mixed_run(m, prob, args, dev, E64, e64, ref64, form):
-    """The same recorded forward + backward step in a split-precision form:
-    MBE3_MIXED_BF16 (split projection and pair_K) or MBE3_MIXED_BF16_PROJ
-    (split projection, FP64 pair_K); energy deviations against the FP64 run
-    of this process."""
-    h = m.from_problem(prob, device=str(dev), precision=getattr(m, form))
-    h.forward(grad=True)  # plans the gradient lists (outputs discarded)
-    h.autotune(reps=2)
-    h.set_timing(True)
-    bufs = h.capture_step(grad=True)
-    ms, E, ph, _ = timed_replays(h, args, "mixed")
     h.set_timing(False)
-    e = bufs["e_frag"]
-    d = np.abs(e.cpu().numpy() - e64)
-    est, _ = m.first_order_dE(h.k_off, prob.n_occ, bufs["K"].cpu().numpy(), *ref64)
+    if E != E_eager or not torch.equal(bufs["e_frag"], e_eager):
+        raise SystemExit(f"bench: {label} recorded step differs (E {E!r} vs {E_eager!r})")
+    log(f"bench: {label} {steps} steps, {ms:.2f} ms/step, "
+        f"{prob.n_frag / (ms / 1e3):.1f} fragments/s, E={E:.12f}")
+    return h, bufs, dict(ms=ms, median_ms=float(np.median(per)), E=E, ph=ph, steps=steps,
+                         warmup=warmup, call_by_call_ms=ms_eager, tune_s=t_tune,
+                         first_step_s=t_first, tuned=tuned)
+
+
+def phase_report(prob, h, res, grad, iters):
+    """Per-phase ms, TFLOP/s and fractions of the FP64 peak, and the roofline
+    entry of the dominant phase (average per timed region, i.e. per launch
+    of its kernel)."""
+    ph, steps = res["ph"], res["steps"]
+    n_aux, n_vir = prob.n_aux, prob.n_vir
+    d2 = np.diff(h.k_off).astype(np.float64)   # d_s^2 per slot
+    pair_d = prob.r[prob.pairs].sum(1) if len(prob.pairs) else np.zeros(1, np.int64)
+    wide = int((pair_d.max() + 15) // 16 * 16) > 96  # some chunk on the wide solver
+    sum_diag, sum_pair = float(d2[:prob.n_occ].sum()), float(d2[prob.n_occ:].sum())
+    work = {
+        "regen": ("alu", float(prob.n_occ) * n_vir * n_aux),
+        "project": ("mfma", 2.0 * n_vir * n_aux * float(h.layout.gamma_rows)),
+        "pair_K": ("mfma", 2.0 * n_aux * (sum_diag + sum_pair)),
+        # with gradients the LDS-resident solver (pair dimensions up to 96)
+        # runs its gradient pass as its own launch, timed in "grad" with the
+        # multiplier and dE/df reductions; the wide one inside "solve"
+        "solve": ("mfma", solve_flops(prob, iters, grad=grad and wide)),
+    }
+    if grad:
+        work["grad"] = ("mfma", 0.0 if wide else
+                        solve_flops(prob, iters, grad=True) - solve_flops(prob, iters))
+        # dGamma: every pair block feeds four destination blocks, every
+        # diagonal one; then the un-projection (projection-shaped)
+        work["backward"] = ("mfma", 2.0 * n_aux * (2.0 * sum_pair + sum_diag)
+                            + 2.0 * n_vir * n_aux * float(h.layout.gamma_rows))
+    phases = {}
+    for name, (ms, n) in ph.items():
+        if n == 0:
+            continue
+        ms_s = ms / steps
+        entry = {"ms_per_step": round(ms_s, 4), "regions_per_step": n // max(1, steps)}
+        if name in work and ms > 0:
+            kind, amount = work[name]
+            if kind == "mfma":
+                entry["tflops"] = round(amount / (ms_s * 1e-3) / 1e12, 3)
+                entry["frac_fp64_peak"] = round(entry["tflops"] / PEAK_FP64_TFLOPS, 4)
+            else:
+                entry["gelem_per_s"] = round(amount / (ms_s * 1e-3) / 1e9, 2)
+        phases[name] = entry
+    dom = max(ph, key=lambda k: ph[k][0])
+    launches = max(1, ph[dom][1] // steps)
+    ms_dom = ph[dom][0] / max(1, ph[dom][1])  # average timed region (launch)
+    roofline = None
+    if dom in ("project", "pair_K", "solve"):
+        per_launch = work[dom][1] / launches
+        ach = per_launch / (ms_dom * 1e-3) / 1e12
+        traffic = None
+        if dom == "solve":
+            traffic = traffic_from_profile(prob.name, "solve.hip", launches)
+        roofline = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3),
+                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                    "launches_per_step": launches,
+                    "flop_per_launch": per_launch}
+    return phases, roofline
+
+
+def mixed_run(m, prob, args, dev, E64, e64, form, steps, warmup):
+    """The recorded forward step in a split-precision form: MBE3_MIXED_BF16
+    (split projection and pair_K) or MBE3_MIXED_BF16_PROJ (split projection,
+    FP64 pair_K); energy deviations against the FP64 step of this process,
+    total and per fragment."""
+    import torch
+    h, bufs, res = recorded_run(m, prob, args, dev, False, form, steps=steps,
+                                warmup=warmup, precision=getattr(m, form))
+    ph, ms, E = res["ph"], res["ms"], res["E"]
+    d = np.abs(bufs["e_frag"].cpu().numpy() - e64)
     ldk_vir = (prob.n_vir + 7) // 8 * 8
     ldk_aux = (prob.n_aux + 7) // 8 * 8
     rows = float(h.layout.gamma_rows)
     d2 = float(np.diff(h.k_off).sum())
-    proj_ms = ph["project"][0] / args.steps
-    pk_ms = ph["pair_K"][0] / args.steps
+    proj_ms = ph["project"][0] / steps
+    pk_ms = ph["pair_K"][0] / steps
     pk_flop = 2.0 * prob.n_aux * d2
     if form == "MBE3_MIXED_BF16":  # nine bf16 products per FP64 one
         pk_frac = {"frac_bf16_peak_issued": round(
@@ -276,103 +401,117 @@ def mixed_run(m, prob, args, dev, E64, e64, ref64, form):
             pk_flop / (pk_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
     out = {
         "form": form,
+        "steps": steps, "warmup": warmup,
         "ms_per_step": round(ms, 3),
         "fragments_per_s": round(prob.n_frag / (ms / 1e3), 2),
         "speedup_vs_fp64": None,
         "E_total": E,
         "abs_dE_total_vs_fp64": abs(E - E64),
         "dE_total_vs_fp64": E - E64,
-        "dE_first_order_estimate": est,
         "max_abs_dE_fragment_vs_fp64": float(d.max()),
         "mean_abs_dE_fragment_vs_fp64": float(d.mean()),
         "budget_abs_dE_total": 1e-6,
+        "within_budget": bool(abs(E - E64) <= 1e-6),
         "project": {"ms_per_step": round(proj_ms, 4),
                     "tflops_fp64_equivalent": round(2.0 * prob.n_vir * prob.n_aux * rows / (proj_ms * 1e-3) / 1e12, 2),
                     "frac_bf16_peak_issued": round(6 * 2.0 * ldk_vir * prob.n_aux * rows / (proj_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)},
         "pair_K": {"ms_per_step": round(pk_ms, 4),
                    "tflops_fp64_equivalent": round(pk_flop / (pk_ms * 1e-3) / 1e12, 2),
                    **pk_frac},
-        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph.items()},
+        "phases_ms_per_step": {k: round(v[0] / steps, 4) for k, v in ph.items() if v[1]},
     }
     log(f"bench: {form} {ms:.2f} ms/step, |dE| vs fp64 {abs(E - E64):.3e}, "
         f"max |dE_F| {d.max():.3e}")
     h.close()
+    del bufs
+    torch.cuda.empty_cache()
     return out
 
 
-def weak_run(m, prob, h, gamma, W, E_mbe3):
-    """Pairs the cutoff left out of the fragment list: s2b of each
-    (mbe3_screen), classes, and the weak-pair energies (mbe3_weak_pairs) of
-    those not distant, from the step's own gamma and multipliers.  Both calls
-    synchronise; the second of two runs is timed by the host clock."""
+def classes_run(m, prob, dev):
+    """The paper's screening of the workload instead of the distance rule:
+    s2b of every pair on the GPU (mbe3_screen), classes and kept trimers
+    (mbe3_screen_lists), the forward step on those lists with the
+    multipliers, and the weak-pair energies (mbe3_weak_pairs) from that
+    step.  Host clock around each synchronised call (second of two)."""
+    import dataclasses
     import torch
     n = prob.n_occ
-    kept = set(map(tuple, np.asarray(prob.pairs).tolist()))
-    rest = np.array([(i, j) for i in range(n) for j in range(i + 1, n)
-                     if (i, j) not in kept], dtype=np.int32).reshape(-1, 2)
-    out = {"pairs_beyond_cutoff": int(len(rest))}
-    if not len(rest):
-        return out
+    cand = np.array([(i, j) for i in range(n) for j in range(i + 1, n)], dtype=np.int32)
+    mono = np.full((n, 3), -1, dtype=np.int32)
+    mono[:, 0] = np.arange(n)
+    h0 = m.from_problem(prob, device=str(dev), pairs=np.zeros((0, 2), np.int32), frags=mono)
     for _ in range(2):
         t0 = time.perf_counter()
-        s2b = h.screen(rest)
+        s2b = h0.screen(cand).cpu().numpy()
         t_screen = (time.perf_counter() - t0) * 1e3
-    cls = m.pair_classes(s2b.cpu().numpy())
-    weak = rest[cls > 0]
+    h0.close()
+    t0 = time.perf_counter()
+    lists = m.screen_lists(n, cand, s2b)
+    t_lists = (time.perf_counter() - t0) * 1e3
+    prob2 = dataclasses.replace(prob, pairs=lists["close"], trimers=lists["trimers"])
+    h = m.from_problem(prob2, device=str(dev))
+    out = h.forward(grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = h.forward(grad=True)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) * 1e3
     for _ in range(2):
         t0 = time.perf_counter()
-        e = h.weak_pairs(weak, gamma, W)
+        e = h.weak_pairs(lists["weak"], out["gamma"], out["W"])
         t_weak = (time.perf_counter() - t0) * 1e3
     E_weak = float(e.sum())
-    out.update({"classes_distant_weak_close": np.bincount(cls, minlength=3).tolist(),
-                "pairs_treated_weak": int(len(weak)),
-                "screen_ms": round(t_screen, 3), "weak_pairs_ms": round(t_weak, 3),
-                "E_weak": E_weak, "E_mbe3_plus_weak": E_mbe3 + E_weak})
-    log(f"bench: weak pairs: {len(weak)} of {len(rest)} beyond the cutoff, "
-        f"E_weak {E_weak:.6e}, screen {t_screen:.2f} ms, weak {t_weak:.2f} ms")
-    return out
+    res = {"candidate_pairs": int(len(cand)),
+           "classes_distant_weak_close": np.bincount(lists["classes"], minlength=3).tolist(),
+           "trimers_kept": int(len(lists["trimers"])), "fragments": int(prob2.n_frag),
+           "screen_ms": round(t_screen, 3), "screen_lists_ms": round(t_lists, 3),
+           "forward_with_multipliers_ms": round(t_fwd, 3), "weak_pairs_ms": round(t_weak, 3),
+           "E_mbe3": out["E"], "E_weak": E_weak, "E_total": out["E"] + E_weak}
+    log(f"bench: paper classes on {prob.name}: {res['classes_distant_weak_close']} "
+        f"(distant, weak, close), {res['trimers_kept']} trimers, forward {t_fwd:.1f} ms, "
+        f"E = {out['E']:.8f} + {E_weak:.8f}")
+    h.close()
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
-def fit_run(m, prob, h):
+def fit_run(m, prob, dev):
     """Sparse fitting metric (mbe3_fit_metric) of every LMO and auxiliary
-    function, regenerating every slab element once, and the share of the
-    domains kept at the paper's threshold.  The second of two calls is timed
-    by the host clock between stream synchronisations."""
+    function (every slab element regenerated once), the projection over the
+    domains (mbe3_project_fit) against osv_project, and pair_K over the
+    unions D_p u D_q (mbe3_pair_K_fit) against pair_K, at the paper's
+    threshold and at one keeping about half of each domain.  Host clock
+    between synchronisations, second of two calls each."""
     import torch
-    s = None
-    for _ in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s = h.fit_metric(out=s)
-        torch.cuda.synchronize()
-        t_ms = (time.perf_counter() - t0) * 1e3
-    kept = float((s > m.L_FIT).double().mean())
-    elems = prob.n_occ * prob.n_vir * prob.n_aux
-    log(f"bench: fit metric {t_ms:.2f} ms ({elems / t_ms / 1e6:.1f} Gelem/s), "
-        f"kept at l_fit {m.L_FIT:g}: {kept:.4f}")
-    # osv_project against the projection over the domains only (the second
-    # of two calls each, host clock between synchronisations)
-    g = h.empty_gamma()
+    h = m.from_problem(prob, device=str(dev))
 
     def timed(fn):
         for _ in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            fn()
+            r = fn()
             torch.cuda.synchronize()
             t = (time.perf_counter() - t0) * 1e3
-        return round(t, 3)
+        return round(t, 3), r
 
-    proj = {"osv_project_ms": timed(lambda: h.osv_project(g))}
+    t_ms, s = timed(lambda: h.fit_metric())
+    elems = prob.n_occ * prob.n_vir * prob.n_aux
+    g, K = h.empty_gamma(), h.empty_K()
+    out = {"metric_ms": t_ms, "slab_elements": elems,
+           "gelem_per_s": round(elems / t_ms / 1e6, 2), "l_fit": m.L_FIT}
+    out["osv_project_ms"], _ = timed(lambda: h.osv_project(g))
+    out["pair_K_ms"], _ = timed(lambda: h.pair_K(g, K))
     for l_fit in (m.L_FIT, 5e-3):
-        proj[f"project_fit_ms_at_{l_fit:g}"] = timed(lambda: h.project_fit(s, l_fit, g))
-        proj[f"kept_fraction_at_{l_fit:g}"] = round(float((s > l_fit).double().mean()), 6)
-    del g
+        out[f"kept_fraction_at_{l_fit:g}"] = round(float((s > l_fit).double().mean()), 6)
+        out[f"project_fit_ms_at_{l_fit:g}"], _ = timed(lambda: h.project_fit(s, l_fit, g))
+        out[f"pair_K_fit_ms_at_{l_fit:g}"], _ = timed(lambda: h.pair_K_fit(s, l_fit, K))
+    log("bench: fitting domains " + ", ".join(f"{k} {v}" for k, v in out.items()))
+    h.close()
+    del g, K
     torch.cuda.empty_cache()
-    log("bench: projection " + ", ".join(f"{k} {v}" for k, v in proj.items()))
-    return {"metric_ms": round(t_ms, 3), "slab_elements": elems,
-            "gelem_per_s": round(elems / t_ms / 1e6, 2), "l_fit": m.L_FIT,
-            "kept_fraction": round(kept, 6), "projection": proj}
+    return out
 
 
 def _call_pool_fn(x):
@@ -385,11 +524,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2,
+                    help="headline workload (2: the 512-LMO lattice, FP64)")
+    ap.add_argument("--extra-config", type=int, default=1,
+                    help="workload of the forward + backward, screening and "
+                         "fitting-domain extras (-1: none)")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="timed steps of each split-precision form (1 warm-up)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the split-precision (bf16) comparison run")
+                    help="skip the split-precision (bf16) comparison runs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device copy (a reference kernel "
                          "of known traffic for counter calibration)")
@@ -407,10 +552,6 @@ def main():
     if not torch.cuda.is_available():
         log("bench.py: no HIP device")
         sys.exit(1)
-    prob = synth.config(args.config)
-    log(f"bench: {prob.name} n_occ={prob.n_occ} n_vir={prob.n_vir} n_aux={prob.n_aux} "
-        f"pairs={len(prob.pairs)} trimers={len(prob.trimers)} fragments={prob.n_frag}")
-    h = m.from_problem(prob, device="cuda:0")
     dev = torch.device("cuda:0")
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -418,127 +559,59 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    gamma = h.empty_gamma()
-    K = h.empty_K()
-    W = h.empty_K()
-    e = torch.empty(h.n_frag, dtype=torch.float64, device=dev)
-    it = torch.empty(h.n_frag, dtype=torch.int32, device=dev)
-    dB = torch.empty((prob.n_occ, prob.n_vir, prob.n_aux), dtype=torch.float64, device=dev)
-    dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device=dev)
+    prob = synth.config(args.config)
+    log(f"bench: {prob.name} n_occ={prob.n_occ} n_vir={prob.n_vir} n_aux={prob.n_aux} "
+        f"pairs={len(prob.pairs)} trimers={len(prob.trimers)} fragments={prob.n_frag}")
 
-    def step(backward=True):
-        h.osv_project(gamma)
-        h.pair_K(gamma, K)
-        h.fragment_solve(K, e, it, W if backward else None)
-        E = h.mbe3_energy(e)
-        if backward:
-            h.mbe3_backward(gamma, W, 1.0, m.MBE3_GRAD_SLAB, out=dB, dEdF=dF)
-        return E
-
-    # the step run call by call: plans the gradient workspace, and is the
-    # reference the tuned and the recorded steps must reproduce bit for bit
-    E_eager = step()
-    torch.cuda.synchronize()
-    e_eager = e.clone()
-    log(f"bench: eager step E={E_eager:.12f}")
-    t0 = time.perf_counter()
-    report = h.autotune(reps=2)
-    t_tune = time.perf_counter() - t0
-    tuned = tune_choices(report)
-    log(f"bench: autotune {t_tune:.1f} s: " +
-        ", ".join(f"{k} {v['chosen']}" for k, v in tuned.items()))
-    E_t = step()
-    torch.cuda.synchronize()
-    if E_t != E_eager or not torch.equal(e, e_eager):
-        raise SystemExit(f"bench: tuned step differs from the planned one ({E_t!r} vs {E_eager!r})")
-
-    # timed region: replays of the whole step recorded as one HIP graph, with
-    # the phase events (HIP events on the library's stream) inside it
-    h.set_timing(True)
-    bufs = h.capture_step(grad=True)
-    ms_step, E, ph, med_step = timed_replays(h, args, "fwd+bwd")
-    h.set_timing(False)
+    # headline: the FP64 forward step, recorded and replayed
+    h, bufs, res = recorded_run(m, prob, args, dev, False, "fp64 forward")
+    iters = bufs["iters"].cpu().numpy()
+    phases, roofline = phase_report(prob, h, res, False, iters)
+    ms_step, E64 = res["ms"], res["E"]
     value = prob.n_frag / (ms_step / 1000.0)
-    log(f"bench: {args.steps} steps, {ms_step:.2f} ms/step, {value:.1f} fragments/s, E={E:.12f}")
-    if E != E_eager or not torch.equal(bufs["e_frag"], e_eager):
-        raise SystemExit(f"bench: recorded step differs from the eager one "
-                         f"(E {E!r} vs {E_eager!r})")
-    e, it, dB = bufs["e_frag"], bufs["iters"], bufs["dB"]
-    gnorm = float(torch.linalg.vector_norm(dB))
-    e64 = e.cpu().numpy().copy()
-    E64 = E
-    ref64 = (bufs["K"].cpu().numpy(), bufs["W"].cpu().numpy())  # for the mixed runs
-    weak_info = weak_run(m, prob, h, bufs["gamma"], bufs["W"], E)
-    fit_info = fit_run(m, prob, h)
-    # call-by-call steps, for the cost of launching without the graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1000.0 / args.steps
-    log(f"bench: call-by-call step {ms_eager:.2f} ms")
-    # the same step without the backward, recorded
+    e64 = bufs["e_frag"].cpu().numpy().copy()
+    kind = "lattice of 4-orbital units" if prob.name.startswith("water") else prob.name
+    workload = (f"{prob.name}: {prob.n_occ} LMOs ({kind}), n_vir={prob.n_vir}, "
+                f"n_aux={prob.n_aux}, r={prob.r.min()}-{prob.r.max()}, cutoff 6, "
+                f"{len(prob.pairs)} pairs, {len(prob.trimers)} trimers, "
+                f"{prob.n_frag} fragments, tol {prob.tol:g}")
+    h.close()
     del bufs
-    fw = h.capture_step(grad=False)
-    ms_fwd, E_f, _, med_fwd = timed_replays(h, args, "forward")
-    del fw
-    log(f"bench: forward only {ms_fwd:.2f} ms/step, {prob.n_frag / (ms_fwd / 1e3):.1f} fragments/s")
+    torch.cuda.empty_cache()
 
-    iters = it.cpu().numpy()
-    n_aux, n_vir = prob.n_aux, prob.n_vir
-    d2 = np.diff(h.k_off).astype(np.float64)   # d_s^2 per slot
-    pair_d = prob.r[prob.pairs].sum(1) if len(prob.pairs) else np.zeros(1, np.int64)
-    wide = int((pair_d.max() + 15) // 16 * 16) > 96  # some chunk on the wide solver
-    sum_diag, sum_pair = float(d2[:prob.n_occ].sum()), float(d2[prob.n_occ:].sum())
-    work = {
-        "regen": ("alu", float(prob.n_occ) * n_vir * n_aux),
-        "project": ("mfma", 2.0 * n_vir * n_aux * float(h.layout.gamma_rows)),
-        "pair_K": ("mfma", 2.0 * n_aux * (sum_diag + sum_pair)),
-        # the LDS-resident solver (pair dimensions up to 96) runs the
-        # gradient pass as its own launch, timed in the "grad" phase with
-        # the multiplier and dE/df reductions; the wide one inside "solve"
-        "solve": ("mfma", solve_flops(prob, iters, grad=wide)),
-        "grad": ("mfma", 0.0 if wide else
-                 solve_flops(prob, iters, grad=True) - solve_flops(prob, iters)),
-        # dGamma: every pair block feeds four destination blocks, every
-        # diagonal one; then the un-projection (projection-shaped)
-        "backward": ("mfma", 2.0 * n_aux * (2.0 * sum_pair + sum_diag)
-                     + 2.0 * n_vir * n_aux * float(h.layout.gamma_rows)),
-    }
-    phases = {}
-    for name, (ms, n) in ph.items():
-        ms_s = ms / args.steps
-        entry = {"ms_per_step": round(ms_s, 4), "regions_per_step": n // max(1, args.steps)}
-        if name in work and ms > 0:
-            kind, amount = work[name]
-            if kind == "mfma":
-                entry["tflops"] = round(amount / (ms_s * 1e-3) / 1e12, 3)
-                entry["frac_fp64_peak"] = round(entry["tflops"] / PEAK_FP64_TFLOPS, 4)
-            else:
-                entry["gelem_per_s"] = round(amount / (ms_s * 1e-3) / 1e9, 2)
-        phases[name] = entry
-    dom = max(ph, key=lambda k: ph[k][0])
-    ms_dom = ph[dom][0] / max(1, ph[dom][1])  # average timed region (launch)
-    roofline = None
-    if dom in ("project", "pair_K", "solve"):
-        per_launch = work[dom][1] / max(1, ph[dom][1] // args.steps)
-        ach = per_launch / (ms_dom * 1e-3) / 1e12
-        traffic = None
-        if dom == "solve":
-            traffic = traffic_from_profile("solve.hip", ph[dom][1] // args.steps)
-        roofline = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 3),
-                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic}
     mixed = {}
     if not args.no_mixed:
         for form in ("MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"):
-            mixed[form] = mixed_run(m, prob, args, dev, E64, e64, ref64, form)
+            mixed[form] = mixed_run(m, prob, args, dev, E64, e64, form,
+                                    steps=max(1, min(args.mixed_steps, args.steps)),
+                                    warmup=1)
+            mixed[form]["speedup_vs_fp64"] = round(ms_step / mixed[form]["ms_per_step"], 4)
+
+    extra = None
+    if args.extra_config >= 0:
+        p1 = synth.config(args.extra_config)
+        log(f"bench: extra {p1.name}: forward + backward, screening, fitting domains")
+        h1, b1, r1 = recorded_run(m, p1, args, dev, True, f"{p1.name} fwd+bwd")
+        ph1, rf1 = phase_report(p1, h1, r1, True, b1["iters"].cpu().numpy())
+        extra = {"workload": p1.name, "n_frag": int(p1.n_frag),
+                 "step": "forward + backward (dE/d(ia|P), dE/df_occ), recorded HIP graph",
+                 "ms_per_step": round(r1["ms"], 3),
+                 "fragments_per_s": round(p1.n_frag / (r1["ms"] / 1e3), 2),
+                 "E_total": r1["E"],
+                 "grad_norm_dB": float(torch.linalg.vector_norm(b1["dB"])),
+                 "roofline": rf1, "phases": ph1}
+        h1.close()
+        del b1
+        torch.cuda.empty_cache()
+        extra["paper_classes"] = classes_run(m, p1, dev)
+        extra["fit_domains"] = fit_run(m, p1, dev)
+
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a host sample ...")
         cpu = cpu_baseline(prob, args.cpu_workers)
-        log(f"bench: cpu oracle {cpu['value']:.2f} fragments/s on {cpu['cores']} cores")
+        log(f"bench: cpu oracle {cpu['value']:.2f} fragments/s on {cpu['cores']} cores "
+            f"({cpu['cpu_model']})")
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -552,36 +625,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{prob.name}: "
-                               f"{prob.n_occ} LMOs (lattice of 4-orbital units), "
-                               f"n_vir={n_vir}, n_aux={n_aux}, r={prob.r.min()}-{prob.r.max()}, "
-                               f"cutoff 6, {len(prob.pairs)} pairs, {len(prob.trimers)} trimers, "
-                               f"{prob.n_frag} fragments, tol {prob.tol:g}",
-                   "step": "forward + backward (dE/d(ia|P), dE/df_occ), "
+        "config": {"workload": workload,
+                   "step": "forward (osv_project, pair_K, fragment_solve, mbe3_energy), "
                            "replayed as one recorded HIP graph",
-                   "precision": "fp64", "E_total": E,
-                   "grad_norm_dB": gnorm,
+                   "precision": "fp64", "E_total": E64,
                    "iters_hist": np.bincount(np.maximum(iters, 0)).tolist()},
-        "median_ms_per_step": round(med_step, 3),
-        "solve_only_fragments_per_s": round(prob.n_frag / (ph["solve"][0] / args.steps * 1e-3), 2),
-        "call_by_call_ms_per_step": round(ms_eager, 3),
-        "autotune": {"seconds": round(t_tune, 2), "gemm_tiles": tuned},
-        "forward_only": {"ms_per_step": round(ms_fwd, 3),
-                         "median_ms_per_step": round(med_fwd, 3),
-                         "fragments_per_s": round(prob.n_frag / (ms_fwd / 1e3), 2),
-                         "E_total": E_f},
+        "median_ms_per_step": round(res["median_ms"], 3),
+        "solve_only_fragments_per_s": round(prob.n_frag / (res["ph"]["solve"][0] / args.steps * 1e-3), 2),
+        "call_by_call_ms_per_step": round(res["call_by_call_ms"], 3),
+        "first_step_s_with_planning": round(res["first_step_s"], 3),
+        "autotune": {"seconds": round(res["tune_s"], 2), "gemm_tiles": res["tuned"]},
         "roofline": roofline,
         "phases": phases,
         "cpu_baseline": cpu,
         "mixed_bf16": mixed.get("MBE3_MIXED_BF16"),
         "mixed_bf16_proj": mixed.get("MBE3_MIXED_BF16_PROJ"),
-        "weak_pairs": weak_info,
-        "fit_domains": fit_info,
+        "extra": extra,
     }
-    for mx in mixed.values():
-        mx["speedup_vs_fp64"] = round(ms_step / mx["ms_per_step"], 4)
     print(json.dumps(out), flush=True)
-    h.close()
 
 
 if __name__ == "__main__":

@@ -290,13 +290,46 @@ int mbe3_basis_offsets(const mbe3_handle *h, int64_t *xoff, int64_t *eoff);
  * the squared norm of the OSV overlap block S_(i,j) = Q_i^T Q_j.  The paper
  * calls a pair distant below 1e-7, weak below 1e-2 and close otherwise, and
  * keeps a trimer when the mean of its three pair metrics (eq. s3b) is at
- * least 0.2; those decisions are the caller's.
+ * least 0.2; mbe3_screen_lists takes those decisions.
  * pairs: host [n][2], two distinct LMOs each, any order.  s2b: device [n].
  * Allocates and frees device memory for the overlap blocks (sum r_i r_j
  * doubles) inside the call, so it cannot be recorded; synchronises the
  * stream.  MBE3_EINVAL for a bad pair or while recording.
  */
 int mbe3_screen(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b);
+
+/*
+ * Pair classes and trimer screening (section on OSV overlap and Fock
+ * computation; eqs. s2b and s3b).  Host only, no handle, no device.
+ * For candidate pair k = (pairs[2k], pairs[2k+1]) (either order, distinct
+ * LMOs in [0, n_occ), no pair twice) with metric s2b[k] (mbe3_screen):
+ *   cls[k] = 0 distant  (s2b < t_distant),
+ *            1 weak     (t_distant <= s2b < t_close),
+ *            2 close    (s2b >= t_close);
+ * the paper's thresholds are MBE3_S2B_DISTANT, MBE3_S2B_CLOSE.
+ * close_pairs / weak_pairs receive those classes' pairs as i < j in
+ * lexicographic order ([n][2] each, capacity n; nullable), *n_close and
+ * *n_weak their counts.  Trimers are the triples i < j < k whose three
+ * pairs are all close (each one a dimer fragment, so the fragment list
+ * stays downward closed) and whose mean metric
+ *   s3b = (s2b_ij + s2b_ik + s2b_jk) / 3   (eq. s3b)
+ * is at least t_trimer (the paper's MBE3_S3B_KEEP); they go to trimers
+ * ([tri_cap][3], lexicographic; nullable) and their count to *n_tri.  Call
+ * once with trimers = NULL for the count, then with room for it.  The
+ * close pairs and trimers with every monomer are a fragment list for
+ * mbe3_create; the weak pairs go to mbe3_weak_pairs; distant ones drop.
+ * host: pairs, s2b, cls, close_pairs, weak_pairs, trimers, counts.
+ * MBE3_EINVAL (message from mbe3_last_error(NULL)) for a bad or repeated
+ * pair, a non-finite metric or too small a tri_cap; MBE3_ENOMEM if host
+ * memory runs out.
+ */
+#define MBE3_S2B_DISTANT 1e-7
+#define MBE3_S2B_CLOSE 1e-2
+#define MBE3_S3B_KEEP 0.2
+int mbe3_screen_lists(int32_t n_occ, const int32_t *pairs, int64_t n, const double *s2b,
+                      double t_distant, double t_close, double t_trimer, int8_t *cls,
+                      int32_t *close_pairs, int64_t *n_close, int32_t *weak_pairs,
+                      int64_t *n_weak, int32_t *trimers, int64_t tri_cap, int64_t *n_tri);
 
 /*
  * Weak pairs (the weak-pair part of Algorithm 7): energies of pairs left
@@ -337,16 +370,17 @@ int mbe3_weak_pairs(mbe3_handle *h, const int32_t *pairs, int64_t n, const doubl
  * mbe3_fit_metric: s_fit device, n_occ * n_aux doubles, written.  The same
  * arithmetic in every precision mode.
  *
- * mbe3_fit_mask: restricts gamma-layout rows to the domains: element P of
- * every row of LMO i's block (mbe3_gamma_offsets) is set to zero unless
- * s_fit[i][P] > l_fit (a NaN metric drops P); kept elements are not
- * touched.  g: device, g_elems >= gamma_elems doubles, in place.  Applied
- * to osv_project's gamma before pair_K, every later step runs on the
- * restricted integrals: each pair's exchange integrals then sum over
- * D_i and D_j together (P in both domains).  Applied to mbe3_backward's
- * MBE3_GRAD_GAMMA output computed from that restricted gamma, it gives the
- * gradient of the restricted energy with respect to the unrestricted
- * Gamma~ (the MBE3_GRAD_SLAB mode does not apply the domains).
+ * mbe3_fit_mask: restricts gamma-layout rows to the auxiliary functions the
+ * domains select for them.  Eqs. osv_imua, osv_close_k and osv_weak_k run
+ * A' over D_i u D_j for the pair ij, so a row of block (i, x), x != i
+ * (G_{i,x} = Q_x^T B_i), keeps P in D_i u D_x, and a row of the diagonal
+ * block (i, i), which every pair (i, q) reads over D_i u D_q, keeps P in
+ * the union of D_q over q in N+(i).  Every other element is set to zero
+ * (a NaN metric drops P); kept elements are not touched.  g: device,
+ * g_elems >= gamma_elems doubles, in place.  This is Gamma~ as stored over
+ * the domains (mbe3_project_fit's output); the exchange integrals over the
+ * domains come from mbe3_pair_K_fit (pair_K of the masked gamma would sum
+ * the diagonal blocks' product over more than D_p u D_q).
  * MBE3_EINVAL for a NULL pointer, a NaN l_fit or a short g.
  *
  * Both allocate nothing, leave the handle's state alone and may be recorded.
@@ -358,17 +392,18 @@ int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
 /*
  * osv_project restricted to the fitting domains, with the work of the
  * restriction saved (the paper's reason for the domains): for every LMO i
- * only the columns P with s_fit[i][P] > l_fit of its slab are regenerated
- * and projected (eq. osv_imua over D_i), and gamma receives Gamma~ in
- * osv_project's layout with every other column zero.  The products run in
- * FP64 in every precision mode, each element summed over a in the order of
- * osv_project's FP64 form, so on an MBE3_FP64 handle the result equals
- * osv_project followed by mbe3_fit_mask bit for bit.
- * s_fit: device, n_occ * n_aux doubles (mbe3_fit_metric's output or any
- * caller metric).  gamma: device, gamma_elems >= gamma_elems of the layout.
- * Copies s_fit to the host and synchronises the stream, allocates the
- * compacted slabs and rows for the call (at most about 2 GiB of slabs at a
- * time, plus sum_i rows_i |D_i| doubles), so it cannot be recorded.
+ * only the columns P its rows are needed on (the union C_i of D_q over q in
+ * N+(i)) are regenerated and projected (eq. osv_imua), and gamma receives
+ * Gamma~ in osv_project's layout restricted as mbe3_fit_mask describes
+ * (block (i, x) on D_i u D_x, block (i, i) on C_i), every other column
+ * zero.  The products run in FP64 in every precision mode, each element
+ * summed over a in the order of osv_project's FP64 form, so on an MBE3_FP64
+ * handle the result equals osv_project followed by mbe3_fit_mask bit for
+ * bit.  s_fit: device, n_occ * n_aux doubles (mbe3_fit_metric's output or
+ * any caller metric).  gamma: device, gamma_elems >= gamma_elems of the
+ * layout.  Copies s_fit to the host and synchronises the stream, allocates
+ * the compacted slabs and rows for the call (at most about 2 GiB of slabs
+ * at a time, plus sum_i rows_i |C_i| doubles), so it cannot be recorded.
  * MBE3_EINVAL for a NULL pointer, a NaN l_fit, a short gamma or while
  * recording; MBE3_ENOMEM if the compacted buffers cannot be allocated.
  */
@@ -376,23 +411,75 @@ int mbe3_project_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *
                      int64_t gamma_elems);
 
 /*
- * pair_K over the fitting domains (eq. osv_close_k with Gamma~_i stored on
- * D_i only, eq. sparse_fit_metric): the kept columns of every slab are
- * projected as in mbe3_project_fit, kept compacted and transposed inside
- * the call, and each block of K_(pq,pq) is summed over the P in both D_p
- * and D_q only (gathered rows of the two compacted operands).  The result
- * is pair_K of the masked gamma up to the rounding of the skipped zero
- * terms' grouping; blocks with an empty intersection are zero.  Gamma~
+ * pair_K over the fitting domains (eq. osv_close_k with A' in D_p u D_q;
+ * eq. sparse_fit_metric): for slot (p, q)
+ *   K_s = sum_{A' in D_p u D_q} L[:, A'] R[:, A']^T,
+ *   L = [G_{p,p}; G_{p,q}], R = [G_{q,p}; G_{q,q}]  (unrestricted values),
+ * and for a diagonal slot the sum over D_p.  The columns C_i of every slab
+ * (the union of the domains of N+(i), which holds D_p u D_q for every pair
+ * of i) are projected as in mbe3_project_fit, kept compacted and transposed
+ * inside the call, and each block is summed over the union by gathering its
+ * rows from both operands.  Blocks with an empty union are zero.  Gamma~
  * itself is not written.  FP64 in every precision mode.
  * s_fit: device, n_occ * n_aux doubles.  K: device, k_elems >= the
  * layout's k_elems.  Copies s_fit to the host and synchronises the stream,
  * allocates the compacted slabs (at most about 2 GiB at a time) and
- * sum_i rows_i |D_i| doubles for the call, so it cannot be recorded.
+ * sum_i rows_i |C_i| doubles for the call, so it cannot be recorded.
  * MBE3_EINVAL for a NULL pointer, a NaN l_fit, a short K or while
  * recording; MBE3_ENOMEM if the buffers cannot be allocated.
  */
 int mbe3_pair_K_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *K,
                     int64_t k_elems);
+
+/*
+ * Randomized OSV generation (section on randomized OSV generation, Alg. 3):
+ * for every LMO i,
+ *   T_ii[a][b] = sum_{P in D_i} B_i[a][P] B_i[b][P] / (f_aa + f_bb - 2 f_ii)
+ *                                                          (eq. mp2_tkk)
+ * from the regenerated (or given) slab on the fitting domain D_i =
+ * {P : s_fit[i][P] > l_fit} (every P when s_fit is NULL); Gaussian test
+ * rows G: row s, column a is the Box-Muller normal of the Philox4x64-10
+ * block at counter (a, s, i, 0) under key (seed, 11), rows 0..9 the first
+ * block, rows 10 .. 10 + n_max - 1 the later samples; the adaptive range
+ * finder over the rows of Y = G T: while the largest of the 10 pending row
+ * norms exceeds l_osv / (10 sqrt(2/pi)) and fewer than n_max rows are
+ * accepted, the first pending row is orthogonalised against the accepted
+ * rows Z (eq. rsvd_za) and accepted, the next sample is appended after
+ * orthogonalisation against the earlier rows, and the new row's direction
+ * is removed from every pending row; then T~ = Z T (eq. tsub), its singular
+ * values w and left vectors Q~ (eq. tii_rsvd, through the eigenvectors of
+ * T~ T~^T) and Q_i = Z^T Q~ (eq. back_q), keeping the columns with
+ * w >= l_osv, largest first.
+ * s_fit: device n_occ * n_aux doubles or NULL.  n_max: 1 .. min(n_vir, the
+ * eigensolver's LDS order, at least 128).  Outputs, all device:
+ *   Q_out [n_occ][n_max][n_vir]: row mu of LMO i is OSV mu (a column of
+ *         Q_i), zero rows after the kept ones;
+ *   w_out [n_occ][n_max]: the kept singular values, decreasing, zeros after;
+ *   n_osv [n_occ]: kept counts;  rows [n_occ]: accepted range-finder rows
+ *   (n_max when the cap stopped the loop).
+ * Allocates per call (batches of LMOs whose n_vir x n_vir T fit 8 GiB) and
+ * synchronises the stream, so it cannot be recorded.  MBE3_EINVAL for a
+ * NULL output, a NaN l_fit, a non-positive l_osv, n_max out of range or
+ * while recording; MBE3_ENOMEM if the buffers cannot be allocated.
+ */
+int mbe3_rosv(mbe3_handle *h, const double *s_fit, double l_fit, double l_osv, int n_max,
+              double *Q_out, double *w_out, int32_t *n_osv, int32_t *rows);
+
+/*
+ * First-order energy change of a change of the pair integrals (the split-
+ * precision forms change the energy only through K; fragment_solve reads
+ * K~ = X^T K X):
+ *   per_slot[s] = c_s <K_a,s - K_b,s, W_s>,  c_s = 2 diagonal slots,
+ *                                            c_s = 4 pair slots,
+ *   *total = sum_s per_slot[s]  (double-double, fixed order),
+ * with W the multipliers fragment_solve returned for K_b (dE/dK_s =
+ * c_s W_s).  Attributes an energy difference to slots.  K_a, K_b, W:
+ * device, K layout.  per_slot: device [n_slot].  total: host, 1 double.
+ * Synchronises the stream; MBE3_EINVAL for a NULL pointer or while
+ * recording.
+ */
+int mbe3_first_order_dE(mbe3_handle *h, const double *K_a, const double *K_b,
+                        const double *W, double *per_slot, double *total);
 
 /*
  * Recorded launches (one HIP graph per handle) for the batched form of

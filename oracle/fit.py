@@ -5,19 +5,24 @@ TEST INFRASTRUCTURE ONLY: nothing in the product path may import this module.
   O11 fit_metric  s_fit[i, A] = sum over the slab's orbital index of
                   B_i[., A]^2, for every auxiliary function A
       domain      D_i = {A : s_fit[i, A] > l_fit}
-      restricted  the method with every product over the auxiliary index of
-                  slab i limited to D_i: an Oracle whose slabs are B_i with
-                  the columns outside D_i set to zero
+      restricted  the method with the exchange integrals of every pair
+                  (p, q) summed over A in D_p u D_q only (the diagonal pair
+                  over D_p), from the unrestricted slabs
 
 Readings (listed with the others in the design notes):
   F1  The metric sums over the slab's first index, the virtual MO a here,
       where the paper's fitted Gamma_i carries the AO index alpha; the slab
       stands in for Gamma_i throughout (O1).
-  F2  Gamma~_i exists on D_i only, so a pair's exchange integrals
-      K_(pq) = sum_A Gamma~_p[., A] Gamma~_q[., A] run over D_p and D_q
-      together, the intersection of the two domains: zeroing the columns
-      of each slab outside its own domain gives exactly that sum, and the
-      same restricted slabs feed every later step unchanged.
+  F2  Eqs. osv_imua, osv_close_k and osv_weak_k (and the contraction loop of
+      Alg. 6) run A' over D_i u D_j, the union of the two LMOs' domains.
+      K_(pq,pq) therefore sums over D_p u D_q, and every Gamma~ block it
+      reads is taken on that set, including Gamma~_{p,p} on D_q \\ D_p (Alg.
+      6 fetches the diagonal-pair blocks for each pair's union, so they are
+      known beyond their own LMO's domain); the diagonal slot (p, p) sums
+      over D_p.  Pair bases, residuals, energies and the MBE(3) sum run
+      unchanged on these integrals.  Stored per block, eq. osv_imua gives
+      Gamma~_{i,x} on D_i u D_x (x != i) and, for the diagonal block read by
+      every pair (i, q), on the union of D_q over q in N+(i).
   F3  Selection is strict, as printed: A is kept when s_fit > l_fit.  The
       sparsity table's threshold is 1e-6.
 """
@@ -27,7 +32,7 @@ from typing import Dict, Optional
 
 import numpy as np
 
-from .mbe3 import Oracle, slab
+from .mbe3 import Oracle, orbs
 
 L_FIT = 1e-6  # the paper's fitting threshold (sparsity table)
 
@@ -53,34 +58,70 @@ def domain(s_fit: np.ndarray, l_fit: float) -> np.ndarray:
     return s_fit > l_fit
 
 
-def restricted_oracle(prob, l_fit: float, base: Optional[Oracle] = None,
-                      s_fit: Optional[np.ndarray] = None) -> Oracle:
-    """An Oracle for the method restricted to the fitting domains (reading
-    F2): slab i keeps its columns in D_i and is zero elsewhere.  ``s_fit``
-    (optional) supplies the metric, else it is computed from ``base``."""
-    base = base or Oracle(prob)
-    if s_fit is None:
-        s_fit = fit_metrics(base)
-    mask = domain(s_fit, l_fit)
-    slabs: Dict[int, np.ndarray] = {
-        i: base.B(i) * mask[i][None, :] for i in range(prob.n_occ)}
-    return Oracle(prob, slabs=slabs)
-
-
 class RestrictedOracle(Oracle):
-    """The restricted method with slabs restricted when first used (for
-    samples of large workloads): slab i is regenerated, its metric kept in
-    ``s[i]``, and its columns outside D_i set to zero, as in
-    restricted_oracle."""
+    """The method restricted to the fitting domains (reading F2).
 
-    def __init__(self, prob, l_fit: float):
-        super().__init__(prob)
+    The slabs stay unrestricted; the metric of LMO i is computed from its
+    slab on first use (or taken from ``s_fit``), and K_(pq,pq) sums over
+    D_p u D_q only.  ``base`` (optional) lends its already regenerated
+    slabs."""
+
+    def __init__(self, prob, l_fit: float, base: Optional[Oracle] = None,
+                 s_fit: Optional[np.ndarray] = None):
+        super().__init__(prob, slabs=base._slabs if base is not None else None)
         self.l_fit = l_fit
         self.s: Dict[int, np.ndarray] = {}
+        if s_fit is not None:
+            self.s = {i: np.asarray(s_fit[i]) for i in range(prob.n_occ)}
 
-    def B(self, i: int) -> np.ndarray:
-        if i not in self._slabs:
-            b = slab(self.prob, i)
-            self.s[i] = column_metric(b)
-            self._slabs[i] = b * domain(self.s[i], self.l_fit)[None, :]
-        return self._slabs[i]
+    def metric(self, i: int) -> np.ndarray:
+        if i not in self.s:
+            self.s[i] = column_metric(self.B(i))
+        return self.s[i]
+
+    def dom(self, i: int) -> np.ndarray:
+        """D_i as a boolean mask over the auxiliary functions."""
+        return domain(self.metric(i), self.l_fit)
+
+    def pair_union(self, p: int, q: int) -> np.ndarray:
+        """The auxiliary functions a pair's integrals sum over: D_p u D_q."""
+        return self.dom(p) | self.dom(q)
+
+    def Kbar(self, p: int, q: int) -> np.ndarray:
+        """eq. osv_close_k over A' in D_p u D_q (reading F2):
+        K_(pq,pq) = sum_{A' in D_p u D_q} L[:, A'] R[:, A']^T with
+        L = [G~_{p,p}; G~_{p,q}], R = [G~_{q,p}; G~_{q,q}] (p <= q)."""
+        assert p <= q
+        key = (p, q)
+        if key not in self._K:
+            U = self.pair_union(p, q)
+            o = orbs(p, q)
+            L = np.concatenate([self.gamma(p, x)[:, U] for x in o], 0)
+            R = np.concatenate([self.gamma(q, x)[:, U] for x in o], 0)
+            self._K[key] = L @ R.T
+        return self._K[key]
+
+    def gamma_fit(self, i: int, x: int) -> np.ndarray:
+        """Gamma~_{i,x} as eq. osv_imua stores it over the domains (reading
+        F2): columns outside D_i u D_x (x != i), or outside the union of
+        D_q over q in N+(i) for the diagonal block, set to zero."""
+        if x != i:
+            keep = self.dom(i) | self.dom(x)
+        else:
+            keep = np.zeros(self.prob.n_aux, dtype=bool)
+            for q in self.prob.neighbours(i):
+                keep |= self.dom(int(q))
+        return np.where(keep[None, :], self.gamma(i, x), 0.0)
+
+    def weak_K(self, i: int, j: int) -> np.ndarray:
+        """eq. osv_weak_k over A' in D_i u D_j:
+        K_(i,j) = sum_{A'} G~_{i,i}[:, A'] G~_{j,j}[:, A']^T."""
+        U = self.pair_union(i, j)
+        return self.gamma(i, i)[:, U] @ self.gamma(j, j)[:, U].T
+
+
+def restricted_oracle(prob, l_fit: float, base: Optional[Oracle] = None,
+                      s_fit: Optional[np.ndarray] = None) -> RestrictedOracle:
+    """The restricted method (reading F2) with the metric ``s_fit`` if given,
+    else computed from the slabs (those of ``base`` when given)."""
+    return RestrictedOracle(prob, l_fit, base=base, s_fit=s_fit)

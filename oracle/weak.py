@@ -117,3 +117,26 @@ def weak_energies(ora, pairs: Iterable[Sequence[int]],
     amplitudes T_diag[i] (reading W2)."""
     return np.array([weak_pair(ora, int(i), int(j), T_diag[int(i)], T_diag[int(j)])[1]
                      for i, j in pairs])
+
+
+def screened_lists(n_occ: int, s2b_of: Dict[Tuple[int, int], float]):
+    """The pair and trimer lists the paper's screening gives (section on OSV
+    overlap and Fock computation), by brute force: every candidate pair
+    (i < j, metric s2b_of[(i, j)]) classed by pair_class; every triple
+    i < j < k whose three pairs are all close candidates kept when
+    keep_trimer holds.  Returns (close pairs, weak pairs, trimers) as sorted
+    lists of tuples."""
+    cls = {t: pair_class(v) for t, v in s2b_of.items()}
+    close = sorted(t for t, c in cls.items() if c == "close")
+    weak = sorted(t for t, c in cls.items() if c == "weak")
+    is_close = set(close)
+    tris = []
+    for i in range(n_occ):
+        for j in range(i + 1, n_occ):
+            if (i, j) not in is_close:
+                continue
+            for k in range(j + 1, n_occ):
+                if (i, k) in is_close and (j, k) in is_close and \
+                        keep_trimer(s2b_of[(i, j)], s2b_of[(i, k)], s2b_of[(j, k)]):
+                    tris.append((i, j, k))
+    return close, weak, tris

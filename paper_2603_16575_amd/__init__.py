@@ -22,8 +22,8 @@ __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
            "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
            "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
            "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16",
-           "MBE3_MIXED_BF16_PROJ", "first_order_dE",
-           "pair_classes", "keep_trimers"]
+           "MBE3_MIXED_BF16_PROJ", "L_FIT", "screen_lists",
+           "S2B_DISTANT", "S2B_CLOSE", "S3B_KEEP"]
 
 
 def _f64(t):
@@ -181,7 +181,7 @@ class Mbe3:
 
     def screen(self, pairs):
         """s2b (eq. s2b) of each listed pair (host int array [n, 2]) as a
-        float64 tensor on the device; see pair_classes for the paper's
+        float64 tensor on the device; screen_lists applies the paper's
         thresholds."""
         import torch
         pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
@@ -214,22 +214,27 @@ class Mbe3:
         return {ph: (float(ms[k]), int(n[k])) for k, ph in enumerate(_lib.PHASES)}
 
     # ---- tile shapes of the grouped GEMMs ----
-    def autotune(self, reps=3, dB=True):
+    def autotune(self, reps=3, dB=True, gamma=None, K=None):
         """Time every GEMM tile shape on every task list of this handle and
-        keep the fastest; returns the report (one line per list).  Uses
-        scratch gamma / K / dB buffers of the layout's sizes."""
+        keep the fastest; returns the report (one line per list).  gamma and
+        K (layout-sized, contents overwritten) serve as the products'
+        operands; new ones are made when not given, and a dB buffer when dB
+        is True."""
         import torch
-        gamma, K = self.empty_gamma(), self.empty_K()
-        gamma.zero_()
-        K.zero_()
+        if gamma is None:
+            gamma = self.empty_gamma()
+            gamma.zero_()
+        if K is None:
+            K = self.empty_K()
+            K.zero_()
         d = None
         if dB:
             d = torch.zeros((self.n_occ, self.n_vir, self.n_aux), dtype=torch.float64,
                             device=self.device)
         torch.cuda.synchronize(self.device)
         lib = _lib.load()
-        _lib.check(lib.mbe3_autotune(self._h, _lib.ptr(gamma), gamma.numel(),
-                                     _lib.ptr(K), K.numel(), _lib.ptr(d),
+        _lib.check(lib.mbe3_autotune(self._h, _lib.ptr(_f64(gamma)), gamma.numel(),
+                                     _lib.ptr(_f64(K)), K.numel(), _lib.ptr(d),
                                      0 if d is None else d.numel(), int(reps)), self._h)
         return lib.mbe3_tune_report(self._h).decode()
 
@@ -254,29 +259,65 @@ class Mbe3:
         return out
 
     def fit_mask(self, s_fit, l_fit, g):
-        """Zero, in place, the elements of gamma-layout ``g`` (Gamma~ or
-        dE/dGamma~) outside the fitting domains s_fit > l_fit; returns g."""
+        """Zero, in place, the elements of gamma-layout ``g`` outside the
+        columns the fitting domains D = {s_fit > l_fit} select for its rows
+        (block (i, x): D_i u D_x; block (i, i): the union of D_q over
+        N+(i)); returns g."""
         _lib.check(_lib.load().mbe3_fit_mask(self._h, _lib.ptr(_f64(s_fit)),
                                              float(l_fit), _lib.ptr(_f64(g)),
                                              g.numel()), self._h)
         return g
 
     def project_fit(self, s_fit, l_fit, gamma):
-        """osv_project over the fitting domains s_fit > l_fit only: the kept
-        columns regenerated and projected, the others zero; returns gamma."""
+        """osv_project over the fitting domains s_fit > l_fit only: the
+        columns each row needs regenerated and projected (as fit_mask
+        selects them), the others zero; returns gamma."""
         _lib.check(_lib.load().mbe3_project_fit(self._h, _lib.ptr(_f64(s_fit)),
                                                 float(l_fit), _lib.ptr(_f64(gamma)),
                                                 gamma.numel()), self._h)
         return gamma
 
     def pair_K_fit(self, s_fit, l_fit, K):
-        """pair_K with every block summed over the intersection of the two
-        fitting domains (s_fit > l_fit), from the kept columns only (Gamma~
-        is not formed); returns K."""
+        """pair_K with every slot (p, q) summed over the union of the two
+        fitting domains D_p u D_q (s_fit > l_fit; D_p for a diagonal slot),
+        from the needed columns only (Gamma~ is not formed); returns K."""
         _lib.check(_lib.load().mbe3_pair_K_fit(self._h, _lib.ptr(_f64(s_fit)),
                                                float(l_fit), _lib.ptr(_f64(K)),
                                                K.numel()), self._h)
         return K
+
+    def rosv(self, n_max=128, l_osv=1e-4, s_fit=None, l_fit=0.0):
+        """Randomized OSVs of every LMO (mbe3_rosv): T_ii from the slab on
+        the fitting domain s_fit > l_fit (all columns without s_fit), the
+        adaptive range finder, the SVD and the cut at l_osv.  Returns dict
+        Q [n_occ, n_max, n_vir] (rows = OSVs), w [n_occ, n_max], n_osv
+        [n_occ], rows [n_occ] (device tensors)."""
+        import torch
+        dev = self.device
+        Q = torch.empty((self.n_occ, n_max, self.n_vir), dtype=torch.float64, device=dev)
+        w = torch.empty((self.n_occ, n_max), dtype=torch.float64, device=dev)
+        k = torch.empty(self.n_occ, dtype=torch.int32, device=dev)
+        rows = torch.empty(self.n_occ, dtype=torch.int32, device=dev)
+        _lib.check(_lib.load().mbe3_rosv(
+            self._h, _lib.ptr(None if s_fit is None else _f64(s_fit)), float(l_fit),
+            float(l_osv), int(n_max), _lib.ptr(Q), _lib.ptr(w), _lib.ptr(k),
+            _lib.ptr(rows)), self._h)
+        return dict(Q=Q, w=w, n_osv=k, rows=rows)
+
+    def first_order_dE(self, K_a, K_b, W, per_slot=None):
+        """First-order energy change sum_s c_s <K_a,s - K_b,s, W_s> (c_s = 2
+        diagonal, 4 pair slots) of moving K from K_b to K_a, W the
+        multipliers of fragment_solve at K_b.  Returns (total, per-slot
+        float64 tensor on the device)."""
+        import torch
+        if per_slot is None:
+            per_slot = torch.empty(int(self.layout.n_slot), dtype=torch.float64,
+                                   device=self.device)
+        out = np.zeros(1, dtype=np.float64)
+        _lib.check(_lib.load().mbe3_first_order_dE(
+            self._h, _lib.ptr(_f64(K_a)), _lib.ptr(_f64(K_b)), _lib.ptr(_f64(W)),
+            _lib.ptr(_f64(per_slot)), _lib.ptr(out)), self._h)
+        return float(out[0]), per_slot
 
     def graph_begin(self, with_grad=False):
         _lib.check(_lib.load().mbe3_graph_begin(self._h, int(bool(with_grad))), self._h)
@@ -322,25 +363,20 @@ class Mbe3:
         return dict(gamma=gamma, K=K, e_frag=e, iters=it, W=W,
                     dB=dB if grad else None, dEdF=dEdF if grad else None)
 
-    def forward(self, grad=False, l_fit=None, compact=False):
+    def forward(self, grad=False, l_fit=None):
         """osv_project -> pair_K -> fragment_solve -> mbe3_energy; with
         grad=True fragment_solve also returns the multipliers W.  With
-        l_fit, Gamma~ is restricted to the sparse fitting domains
-        s_fit > l_fit before pair_K (s_fit returned as well): masked after
-        the full projection, or with compact=True projected over the
-        domains only (mbe3_project_fit; not recordable)."""
+        l_fit, the method over the sparse fitting domains s_fit > l_fit:
+        mbe3_fit_metric -> mbe3_pair_K_fit (each pair over D_p u D_q) ->
+        fragment_solve -> mbe3_energy (s_fit returned, no dense gamma)."""
         import torch
-        s_fit = None
+        s_fit = gamma = None
         if l_fit is None:
             gamma = self.osv_project(self.empty_gamma())
-        elif compact:
-            s_fit = self.fit_metric()
-            gamma = self.project_fit(s_fit, l_fit, self.empty_gamma())
+            K = self.pair_K(gamma, self.empty_K())
         else:
-            gamma = self.osv_project(self.empty_gamma())
             s_fit = self.fit_metric()
-            self.fit_mask(s_fit, l_fit, gamma)
-        K = self.pair_K(gamma, self.empty_K())
+            K = self.pair_K_fit(s_fit, l_fit, self.empty_K())
         e = torch.empty(self.n_frag, dtype=torch.float64, device=self.device)
         it = torch.empty(self.n_frag, dtype=torch.int32, device=self.device)
         W = self.empty_K() if grad else None
@@ -392,42 +428,35 @@ def energy_fn(h, slab, f_occ):
     return _ENERGY_FN.apply(h, slab, f_occ)
 
 
-def first_order_dE(k_off, n_occ, K_a, K_b, W):
-    """First-order change of the MBE(3) energy when K-bar moves from K_b to
-    K_a (host arrays in the K layout):
-        dE ~ sum_s c_s <K_a,s - K_b,s, W_s>,  c_s = 2 (diagonal slots),
-                                              c_s = 4 (pairs),
-    with W the multipliers fragment_solve returns for K_b (symmetric on the
-    diagonal slots, whose K-bar blocks G G^T are symmetric too).  The energy
-    depends on the projection and pair_K only through K-bar (eq. res_close
-    reads K~ = X^T K-bar X), so this attributes a split-precision energy
-    error to slots.  Returns (total, per-slot contributions)."""
-    k_off = np.asarray(k_off, dtype=np.int64)
-    prod = (np.asarray(K_a, dtype=np.float64) - np.asarray(K_b, dtype=np.float64)) \
-        * np.asarray(W, dtype=np.float64)
-    n_slot = len(k_off) - 1
-    per = np.add.reduceat(prod[:k_off[-1]], k_off[:-1]) if n_slot else np.zeros(0)
-    per *= np.where(np.arange(n_slot) < n_occ, 2.0, 4.0)
-    return float(per.sum()), per
-
-
-# pair classes and trimer screening (section on OSV overlap and Fock
-# computation): s2b below 1e-7 distant, below 1e-2 weak, else close; trimers
-# whose mean pair metric (eq. s3b) is below 0.2 are dropped
-S2B_DISTANT, S2B_CLOSE, S3B_KEEP = 1e-7, 1e-2, 0.2
 # sparse fitting threshold of the paper's sparsity table (eq. sparse_fit_metric)
 L_FIT = 1e-6
 
 
-def pair_classes(s2b):
-    """0 distant, 1 weak, 2 close for each s2b value (host array)."""
-    s = np.asarray(s2b, dtype=np.float64)
-    return np.where(s < S2B_DISTANT, 0, np.where(s < S2B_CLOSE, 1, 2)).astype(np.int8)
+S2B_DISTANT, S2B_CLOSE, S3B_KEEP = 1e-7, 1e-2, 0.2  # the paper's thresholds
 
 
-def keep_trimers(s_ij, s_ik, s_jk):
-    """True where the trimer's s3b (eq. s3b) reaches the threshold."""
-    return (np.asarray(s_ij) + np.asarray(s_ik) + np.asarray(s_jk)) / 3.0 >= S3B_KEEP
+def screen_lists(n_occ, pairs, s2b, t_distant=S2B_DISTANT, t_close=S2B_CLOSE,
+                 t_trimer=S3B_KEEP):
+    """Pair classes and kept trimers (mbe3_screen_lists) of candidate pairs
+    (host [n, 2]) with metrics s2b (host [n]): dict with classes (int8 per
+    pair: 0 distant, 1 weak, 2 close), close, weak ([m, 2], i < j) and
+    trimers ([t, 3])."""
+    lib = _lib.load()
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    sv = np.ascontiguousarray(np.asarray(s2b, dtype=np.float64).reshape(-1))
+    n = len(pr)
+    cls = np.zeros(n, dtype=np.int8)
+    close = np.zeros((n, 2), dtype=np.int32)
+    weak = np.zeros((n, 2), dtype=np.int32)
+    nc, nw, nt = (np.zeros(1, dtype=np.int64) for _ in range(3))
+    args = (int(n_occ), _lib.ptr(pr) if n else None, n, _lib.ptr(sv) if n else None,
+            float(t_distant), float(t_close), float(t_trimer), _lib.ptr(cls),
+            _lib.ptr(close), _lib.ptr(nc), _lib.ptr(weak), _lib.ptr(nw))
+    _lib.check(lib.mbe3_screen_lists(*args, None, 0, _lib.ptr(nt)), None)
+    tri = np.zeros((max(int(nt[0]), 1), 3), dtype=np.int32)
+    _lib.check(lib.mbe3_screen_lists(*args, _lib.ptr(tri), len(tri), _lib.ptr(nt)), None)
+    return dict(classes=cls, close=close[:int(nc[0])].copy(), weak=weak[:int(nw[0])].copy(),
+                trimers=tri[:int(nt[0])].copy())
 
 
 def osv_project(h, gamma):

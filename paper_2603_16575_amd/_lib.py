@@ -33,7 +33,8 @@ EXPORTS = [
     "mbe3_get_timing", "mbe3_backward", "mbe3_graph_begin", "mbe3_graph_end",
     "mbe3_graph_launch", "mbe3_autotune", "mbe3_set_gemm_shape",
     "mbe3_tune_report", "mbe3_screen", "mbe3_weak_pairs", "mbe3_fit_metric",
-    "mbe3_fit_mask", "mbe3_project_fit", "mbe3_pair_K_fit",
+    "mbe3_fit_mask", "mbe3_project_fit", "mbe3_pair_K_fit", "mbe3_first_order_dE",
+    "mbe3_screen_lists", "mbe3_rosv",
 ]
 GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128", "96x96"]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
@@ -110,6 +111,10 @@ def load():
         "mbe3_fit_mask": [vp, vp, ctypes.c_double, vp, i64],
         "mbe3_project_fit": [vp, vp, ctypes.c_double, vp, i64],
         "mbe3_pair_K_fit": [vp, vp, ctypes.c_double, vp, i64],
+        "mbe3_first_order_dE": [vp, vp, vp, vp, vp, vp],
+        "mbe3_rosv": [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp],
+        "mbe3_screen_lists": [ctypes.c_int32, vp, i64, vp, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, vp, vp, vp, vp, vp, vp, i64, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <new>
 #include <string>
@@ -161,7 +162,10 @@ struct mbe3_handle {
   MixedTask *d_mpk = nullptr;
   int64_t t_mpk = 0;
   int32_t *d_mrows = nullptr;
+  int64_t *d_k_off = nullptr;    // k_off on the device
   int32_t *d_row_lmo = nullptr;  // LMO of every gamma row (fitting domains)
+  int32_t *d_row_x = nullptr;    // OSV block (orbital x) of every gamma row
+  int32_t *d_nbr_off = nullptr, *d_nbr = nullptr;  // N+(i) as CSR on the device
   std::vector<std::pair<std::string, std::vector<MixedTask>>> h_mixed;
   std::vector<int32_t> h_mrows;
 
@@ -1084,10 +1088,23 @@ int alloc_workspace(mbe3_handle *h) {
     return rc;
   }
   {
-    std::vector<int32_t> rl((size_t)h->gamma_rows);
-    for (int i = 0; i < h->n_occ; ++i)
-      for (int64_t row = h->g_off[i]; row < h->g_off[i + 1]; ++row) rl[(size_t)row] = i;
-    if ((rc = upload(h, &h->d_row_lmo, rl))) return rc;
+    std::vector<int32_t> rl((size_t)h->gamma_rows), rx((size_t)h->gamma_rows);
+    std::vector<int32_t> noff((size_t)h->n_occ + 1, 0), nb;
+    for (int i = 0; i < h->n_occ; ++i) {
+      int64_t row = h->g_off[i];
+      for (int x : h->nbr[i]) {
+        nb.push_back(x);
+        for (int mu = 0; mu < h->r[x]; ++mu, ++row) {
+          rl[(size_t)row] = i;
+          rx[(size_t)row] = x;
+        }
+      }
+      noff[(size_t)i + 1] = (int32_t)nb.size();
+    }
+    if ((rc = upload(h, &h->d_k_off, h->k_off)) ||
+        (rc = upload(h, &h->d_row_lmo, rl)) || (rc = upload(h, &h->d_row_x, rx)) ||
+        (rc = upload(h, &h->d_nbr_off, noff)) || (rc = upload(h, &h->d_nbr, nb)))
+      return rc;
   }
   const int64_t nq = h->q_off[h->n_occ];
   if ((rc = dev_alloc(h, &h->eq, nq * nv))) return rc;
@@ -1834,6 +1851,92 @@ int mbe3_plan_check(const mbe3_problem *p, mbe3_layout *out) {
   return rc;
 }
 
+// Pair classes and trimer screening (section on OSV overlap and Fock
+// computation, eqs. s2b and s3b): host logic only, no handle.
+int mbe3_screen_lists(int32_t n_occ, const int32_t *pairs, int64_t n, const double *s2b,
+                      double t_distant, double t_close, double t_trimer, int8_t *cls,
+                      int32_t *close_pairs, int64_t *n_close, int32_t *weak_pairs,
+                      int64_t *n_weak, int32_t *trimers, int64_t tri_cap, int64_t *n_tri) {
+  auto fail = [](const char *fmt, long long a, long long b) {
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, a, b);
+    g_create_error = buf;
+    return MBE3_EINVAL;
+  };
+  if (n_occ < 1 || n < 0 || (n > 0 && (!pairs || !s2b)) || !n_close || !n_weak || !n_tri)
+    return fail("mbe3_screen_lists: bad arguments (n_occ %lld, n %lld)", n_occ, n);
+  try {
+    // normalised (i < j) pairs with their metric, keyed for lookup
+    std::unordered_map<int64_t, double> close_s2b;
+    std::vector<std::array<int32_t, 2>> cl, wk;
+    std::unordered_map<int64_t, int64_t> seen;
+    for (int64_t k = 0; k < n; ++k) {
+      int32_t i = pairs[2 * k], j = pairs[2 * k + 1];
+      if (i > j) std::swap(i, j);
+      if (i < 0 || j >= n_occ || i == j)
+        return fail("mbe3_screen_lists: pair %lld (%lld) out of range or repeated orbital",
+                    k, (long long)pairs[2 * k]);
+      const int64_t key = (int64_t)i * n_occ + j;
+      if (!seen.emplace(key, k).second)
+        return fail("mbe3_screen_lists: pair %lld repeats pair %lld", k, seen[key]);
+      const double v = s2b[k];
+      if (!std::isfinite(v))
+        return fail("mbe3_screen_lists: s2b[%lld] of pair %lld is not finite", k, k);
+      const int8_t c = v < t_distant ? 0 : (v < t_close ? 1 : 2);
+      if (cls) cls[k] = c;
+      if (c == 2) {
+        cl.push_back({i, j});
+        close_s2b[key] = v;
+      } else if (c == 1) {
+        wk.push_back({i, j});
+      }
+    }
+    std::sort(cl.begin(), cl.end());
+    std::sort(wk.begin(), wk.end());
+    *n_close = (int64_t)cl.size();
+    *n_weak = (int64_t)wk.size();
+    if (close_pairs)
+      for (size_t k = 0; k < cl.size(); ++k) {
+        close_pairs[2 * k] = cl[k][0];
+        close_pairs[2 * k + 1] = cl[k][1];
+      }
+    if (weak_pairs)
+      for (size_t k = 0; k < wk.size(); ++k) {
+        weak_pairs[2 * k] = wk[k][0];
+        weak_pairs[2 * k + 1] = wk[k][1];
+      }
+    // trimers of three close pairs whose mean metric (eq. s3b) reaches t_trimer
+    std::vector<std::vector<int32_t>> up((size_t)n_occ);  // close partners above i
+    for (auto &pq : cl) up[(size_t)pq[0]].push_back(pq[1]);
+    int64_t nt = 0;
+    for (auto &pq : cl) {
+      const int32_t i = pq[0], j = pq[1];
+      const double sij = close_s2b[(int64_t)i * n_occ + j];
+      for (int32_t k : up[(size_t)j]) {  // k > j, (j, k) close
+        const auto ik = close_s2b.find((int64_t)i * n_occ + k);
+        if (ik == close_s2b.end()) continue;
+        const double sjk = close_s2b[(int64_t)j * n_occ + k];
+        if ((sij + ik->second + sjk) / 3.0 >= t_trimer) {
+          if (trimers) {
+            if (nt >= tri_cap)
+              return fail("mbe3_screen_lists: trimer %lld exceeds tri_cap = %lld", nt, tri_cap);
+            trimers[3 * nt] = i;
+            trimers[3 * nt + 1] = j;
+            trimers[3 * nt + 2] = k;
+          }
+          ++nt;
+        }
+      }
+    }
+    *n_tri = nt;
+  } catch (const std::bad_alloc &) {
+    g_create_error = "mbe3_screen_lists: host allocation failed";
+    return MBE3_ENOMEM;
+  }
+  g_create_error = "ok";
+  return MBE3_OK;
+}
+
 int mbe3_destroy(mbe3_handle *h) {
   if (!h) return MBE3_EINVAL;
   if (h->recording) {
@@ -2118,6 +2221,21 @@ int mbe3_energy(mbe3_handle *h, const double *e_frag, double *e_total,
   return MBE3_OK;
 }
 
+int mbe3_first_order_dE(mbe3_handle *h, const double *K_a, const double *K_b,
+                        const double *W, double *per_slot, double *total) {
+  if (!h) return MBE3_EINVAL;
+  if (!K_a || !K_b || !W || !per_slot || !total)
+    return h->fail(MBE3_EINVAL, "K_a, K_b, W, per_slot and total required");
+  if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_first_order_dE synchronises: not recordable");
+  hipStream_t s = h->stream;
+  HIP_TRY(h, launch_slot_dot(K_a, K_b, W, h->d_k_off, h->n_occ, h->n_slot, per_slot, s));
+  HIP_TRY(h, launch_mbe_sum(per_slot, nullptr, h->n_slot, h->d_e3, s));
+  HIP_TRY(h, hipMemcpyAsync(h->h_e3, h->d_e3, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  *total = h->h_e3[0];
+  return MBE3_OK;
+}
+
 int mbe3_set_timing(mbe3_handle *h, int enable) {
   if (!h) return MBE3_EINVAL;
   if (h->recording) return h->fail(MBE3_EINVAL, "timing cannot change while recording");
@@ -2290,30 +2408,45 @@ int mbe3_fit_mask(mbe3_handle *h, const double *s_fit, double l_fit, double *g,
     return h->fail(MBE3_EINVAL, "g needs %lld doubles, got %lld",
                    (long long)(h->gamma_rows * h->n_aux), (long long)g_elems);
   PhaseScope ps_(h, MBE3_PHASE_PROJECT);
-  HIP_TRY(h, launch_fit_mask(g, h->gamma_rows, h->n_aux, h->d_row_lmo, s_fit, l_fit,
-                             h->stream));
+  HIP_TRY(h, launch_fit_mask(g, h->gamma_rows, h->n_aux, h->d_row_lmo, h->d_row_x,
+                             h->d_nbr_off, h->d_nbr, s_fit, l_fit, h->stream));
   return MBE3_OK;
 }
 
-// The fitting domains of every LMO from a device metric (copied back; the
-// stream is synchronised): cols holds the kept auxiliary indices of LMO i at
-// [col_off[i], col_off[i + 1]), ascending.  batches: runs of LMOs whose
-// compacted slabs (n_vir x |D_i| each) fit the slab budget together (at
-// most 65535 per run, one workgroup row each); *cs_max the largest run.
+// The fitting domains from a device metric (copied back; the stream is
+// synchronised): D_i = {P : s_fit[i][P] > l_fit} at dcols[dcol_off[i] ..
+// dcol_off[i + 1]), ascending.  Every integral of eq. osv_close_k for a pair
+// (p, q) sums over D_p u D_q (D_p for the diagonal slot), so LMO i's
+// projected rows are needed on C_i = the union of D_q over q in N+(i):
+// ccols[ccol_off[i] .. ccol_off[i + 1]), ascending.  batches: runs of LMOs
+// whose compacted slabs (n_vir x |C_i| each) fit the slab budget together
+// (at most 65535 per run, one workgroup row each); *cs_max the largest run.
 static int fit_domains(mbe3_handle *h, const double *s_fit, double l_fit,
-                       std::vector<int32_t> &cols, std::vector<int32_t> &col_off,
+                       std::vector<int32_t> &dcols, std::vector<int32_t> &dcol_off,
+                       std::vector<int32_t> &ccols, std::vector<int32_t> &ccol_off,
                        std::vector<std::pair<int, int>> &batches, int64_t *cs_max) {
   const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
   std::vector<double> sf((size_t)n * na);
   HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
                             hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  cols.clear();
-  col_off.assign((size_t)n + 1, 0);
+  dcols.clear();
+  dcol_off.assign((size_t)n + 1, 0);
   for (int i = 0; i < n; ++i) {
     for (int P = 0; P < na; ++P)
-      if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
-    col_off[i + 1] = (int32_t)cols.size();
+      if (sf[(size_t)i * na + P] > l_fit) dcols.push_back(P);
+    dcol_off[i + 1] = (int32_t)dcols.size();
+  }
+  ccols.clear();
+  ccol_off.assign((size_t)n + 1, 0);
+  std::vector<char> mark((size_t)na);
+  for (int i = 0; i < n; ++i) {
+    std::fill(mark.begin(), mark.end(), 0);
+    for (int q : h->nbr[i])
+      for (int c = dcol_off[q]; c < dcol_off[q + 1]; ++c) mark[(size_t)dcols[c]] = 1;
+    for (int P = 0; P < na; ++P)
+      if (mark[(size_t)P]) ccols.push_back(P);
+    ccol_off[i + 1] = (int32_t)ccols.size();
   }
   const int64_t budget = SLAB_BUDGET / (int64_t)sizeof(double);
   batches.clear();
@@ -2322,8 +2455,8 @@ static int fit_domains(mbe3_handle *h, const double *s_fit, double l_fit,
     int i1 = i0;
     int64_t tot = 0;
     while (i1 < n && i1 - i0 < 65535 &&
-           (i1 == i0 || tot + (int64_t)nv * (col_off[i1 + 1] - col_off[i1]) <= budget)) {
-      tot += (int64_t)nv * (col_off[i1 + 1] - col_off[i1]);
+           (i1 == i0 || tot + (int64_t)nv * (ccol_off[i1 + 1] - ccol_off[i1]) <= budget)) {
+      tot += (int64_t)nv * (ccol_off[i1 + 1] - ccol_off[i1]);
       ++i1;
     }
     batches.push_back({i0, i1});
@@ -2333,9 +2466,11 @@ static int fit_domains(mbe3_handle *h, const double *s_fit, double l_fit,
   return MBE3_OK;
 }
 
-// osv_project over the fitting domains only: per LMO the kept columns are
+// osv_project over the fitting domains only: per LMO i the columns C_i are
 // listed on the host (s_fit copied back), regenerated compacted, projected
-// by one GEMM per LMO over them and scattered into the zeroed dense gamma.
+// by one GEMM per LMO over them and scattered into the zeroed dense gamma;
+// the rows of blocks (i, x), x != i, are then cut to D_i u D_x by the mask
+// kernel (eq. osv_imua).
 static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, double *gamma,
                             int64_t gamma_elems) {
   if (h->recording)
@@ -2347,10 +2482,10 @@ static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, d
     return h->fail(MBE3_EINVAL, "gamma needs %lld doubles, got %lld",
                    (long long)(h->gamma_rows * na), (long long)gamma_elems);
   hipStream_t s = h->stream;
-  std::vector<int32_t> cols, col_off;
+  std::vector<int32_t> dcols, dcol_off, cols, col_off;
   std::vector<std::pair<int, int>> batches;
   int64_t cs_max = 0;
-  int rc = fit_domains(h, s_fit, l_fit, cols, col_off, batches, &cs_max);
+  int rc = fit_domains(h, s_fit, l_fit, dcols, dcol_off, cols, col_off, batches, &cs_max);
   if (rc) return rc;
   std::vector<int64_t> gc_off((size_t)n + 1, 0);
   int max_nc = 0;
@@ -2416,14 +2551,17 @@ static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, d
   }
   HIP_TRY(h, launch_fit_scatter(gamma, gc, h->gamma_rows, na, max_nc, h->d_row_lmo, d_goff,
                                 d_gcoff, d_cols, d_col_off, s));
+  HIP_TRY(h, launch_fit_mask(gamma, h->gamma_rows, na, h->d_row_lmo, h->d_row_x,
+                             h->d_nbr_off, h->d_nbr, s_fit, l_fit, s));
   return MBE3_OK;
 }
 
-// pair_K over the fitting domains: the kept columns projected as in
-// project_fit but stored transposed and compacted (GT_i: kept column x gamma
-// row of LMO i), then each K block summed over D_p and D_q together by
-// gathering the intersection's rows of GT_p and GT_q (k-row gathers of the
-// grouped-GEMM engine).
+// pair_K over the fitting domains (eq. osv_close_k, A' in D_p u D_q): the
+// columns C_i projected as in project_fit but stored transposed and
+// compacted (GT_i: column of C_i x gamma row of LMO i), then each K block of
+// slot (p, q) summed over the union D_p u D_q (D_p for a diagonal slot) by
+// gathering the union's rows of GT_p and GT_q, both of which hold it (k-row
+// gathers of the grouped-GEMM engine).
 static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, double *K,
                            int64_t k_elems) {
   if (h->recording)
@@ -2435,10 +2573,10 @@ static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, do
                    (long long)k_elems);
   const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
   hipStream_t s = h->stream;
-  std::vector<int32_t> cols, col_off;
+  std::vector<int32_t> dcols, dcol_off, cols, col_off;
   std::vector<std::pair<int, int>> batches;
   int64_t cs_max = 0;
-  int rc = fit_domains(h, s_fit, l_fit, cols, col_off, batches, &cs_max);
+  int rc = fit_domains(h, s_fit, l_fit, dcols, dcol_off, cols, col_off, batches, &cs_max);
   if (rc) return rc;
   std::vector<int64_t> gt_off((size_t)n + 1, 0);
   for (int i = 0; i < n; ++i)
@@ -2453,7 +2591,7 @@ static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, do
   base_sizes(h, sz);
   sz[B_SLAB] = cs_max;
   sz[B_GAMMA] = gt_off[n];
-  // GT_i = (B_i restricted to D_i)^T Q_{N+(i)}: A the compacted slab read
+  // GT_i = (B_i restricted to C_i)^T Q_{N+(i)}: A the compacted slab read
   // transposed, B the gathered rows of Q^T read transposed
   for (const auto &bt : batches) {
     const int i0 = bt.first, i1 = bt.second;
@@ -2498,27 +2636,31 @@ static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, do
     b.rows = d_rows;
     HIP_TRY(h, launch_gemm_tasks(d_ts, (int)ts.size(), tiles, b, GEMM_64x64, s));
   }
-  // K blocks (x, y) of every slot over the intersection of the domains
+  // K blocks (x, y) of every slot over the union of the two domains
   std::vector<GemmTask> kt;
   std::vector<int32_t> krows;
-  std::vector<int32_t> ip, iq;
+  std::vector<int32_t> un, ip, iq;
+  // positions of the ascending columns u in the ascending list C_i (every u
+  // is in C_i: D_p, D_q are both in C_p and in C_q for a kept pair)
+  auto positions = [&](int i, std::vector<int32_t> &out) -> bool {
+    out.clear();
+    int c = col_off[i];
+    for (int32_t P : un) {
+      while (c < col_off[i + 1] && cols[c] < P) ++c;
+      if (c == col_off[i + 1] || cols[c] != P) return false;
+      out.push_back(c - col_off[i]);
+    }
+    return true;
+  };
   for (int sl = 0; sl < h->n_slot; ++sl) {
     const int p = h->sp[sl], q = h->sq[sl];
-    ip.clear();
-    iq.clear();
-    for (int a = col_off[p], c = col_off[q]; a < col_off[p + 1] && c < col_off[q + 1];) {
-      if (cols[a] < cols[c]) {
-        ++a;
-      } else if (cols[c] < cols[a]) {
-        ++c;
-      } else {
-        ip.push_back(a - col_off[p]);
-        iq.push_back(c - col_off[q]);
-        ++a;
-        ++c;
-      }
-    }
-    if (ip.empty()) continue;
+    un.clear();
+    std::set_union(dcols.begin() + dcol_off[p], dcols.begin() + dcol_off[p + 1],
+                   dcols.begin() + dcol_off[q], dcols.begin() + dcol_off[q + 1],
+                   std::back_inserter(un));
+    if (un.empty()) continue;
+    if (!positions(p, ip) || !positions(q, iq))
+      return h->fail(MBE3_EINVAL, "internal: union of D_%d and D_%d outside C", p, q);
     const int32_t ro_p = (int32_t)krows.size();
     krows.insert(krows.end(), ip.begin(), ip.end());
     const int32_t ro_q = (int32_t)krows.size();
@@ -2567,6 +2709,163 @@ static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, do
     HIP_TRY(h, launch_gemm_tasks(d_kt, (int)kt.size(), tiles, b, GEMM_32x32, s));
   }
   return MBE3_OK;
+}
+
+// Randomized OSV generation (Alg. 3) for every LMO, in batches of LMOs whose
+// T_ii fit a budget: compacted slab columns of D_i -> T = B_D B_D^T, the
+// Cauchy scaling (eq. mp2_tkk) -> the Gaussian rows G (Philox stream 11)
+// -> Y = G T -> range finder -> T~ = Z T -> M = T~ T~^T -> eigenvectors of
+// M (eq. tii_rsvd through the Gram matrix) -> Q_i^T = Q~^T Z (eq. back_q)
+// -> selection by w >= l_osv.
+static constexpr int ROSV_R = 10;             // rows per stopping-test block
+static constexpr uint64_t ROSV_STREAM = 11;   // Philox stream of G
+static constexpr int64_t ROSV_BUDGET = 8LL << 30;  // bytes of T per batch
+
+static int rosv_body(mbe3_handle *h, const double *s_fit, double l_fit, double l_osv,
+                     int n_max, double *Q_out, double *w_out, int32_t *n_osv,
+                     int32_t *rows_out) {
+  if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_rosv allocates: not recordable");
+  if (!Q_out || !w_out || !n_osv || !rows_out)
+    return h->fail(MBE3_EINVAL, "Q_out, w_out, n_osv and rows required");
+  if (s_fit && std::isnan(l_fit)) return h->fail(MBE3_EINVAL, "l_fit is NaN");
+  if (!(l_osv > 0.0)) return h->fail(MBE3_EINVAL, "l_osv must be positive");
+  const int n = h->n_occ, nv = h->n_vir, na = h->n_aux;
+  if (n_max < 1 || n_max > nv || n_max > eig_qr_max_order())
+    return h->fail(MBE3_EINVAL, "n_max = %d outside 1 .. min(n_vir, %d)", n_max,
+                   eig_qr_max_order());
+  hipStream_t st = h->stream;
+  // fitting domains (all columns without a metric)
+  std::vector<int32_t> cols, col_off((size_t)n + 1, 0);
+  if (s_fit) {
+    std::vector<double> sf((size_t)n * na);
+    HIP_TRY(h, hipMemcpyAsync(sf.data(), s_fit, sf.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+      for (int P = 0; P < na; ++P)
+        if (sf[(size_t)i * na + P] > l_fit) cols.push_back(P);
+      col_off[i + 1] = (int32_t)cols.size();
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      for (int P = 0; P < na; ++P) cols.push_back(P);
+      col_off[i + 1] = (int32_t)cols.size();
+    }
+  }
+  const int nr = ROSV_R + n_max;                 // Gaussian rows per LMO
+  const int Dq = (n_max + 15) / 16 * 16;         // eigenvector pitch
+  const int64_t t_elems = (int64_t)nv * nv;
+  int nb_max = (int)std::max<int64_t>(1, std::min<int64_t>(
+      ROSV_BUDGET / (t_elems * (int64_t)sizeof(double)), 65535));
+  int64_t max_nc = 0;
+  for (int i = 0; i < n; ++i) max_nc = std::max<int64_t>(max_nc, col_off[i + 1] - col_off[i]);
+  nb_max = (int)std::min<int64_t>(nb_max, std::max<int64_t>(
+      1, (SLAB_BUDGET / (int64_t)sizeof(double)) / std::max<int64_t>(1, nv * max_nc)));
+  nb_max = std::min(nb_max, n);
+  CallTemp tmp(h);
+  int32_t *d_cols = nullptr, *d_col_off = nullptr, *d_rows = nullptr;
+  double *cs = nullptr, *T = nullptr, *G = nullptr, *Y = nullptr, *Z = nullptr, *Tt = nullptr,
+         *M = nullptr, *Qe = nullptr, *ev = nullptr, *Qr = nullptr;
+  const int64_t cs_per = (int64_t)nv * std::max<int64_t>(1, max_nc);
+  int rc;
+  if ((rc = tmp.upload(&d_cols, cols)) || (rc = tmp.upload(&d_col_off, col_off)) ||
+      (rc = tmp.alloc(&cs, (int64_t)nb_max * cs_per)) ||
+      (rc = tmp.alloc(&T, (int64_t)nb_max * t_elems)) ||
+      (rc = tmp.alloc(&G, (int64_t)nb_max * nr * nv)) ||
+      (rc = tmp.alloc(&Y, (int64_t)nb_max * nr * nv)) ||
+      (rc = tmp.alloc(&Z, (int64_t)nb_max * n_max * nv)) ||
+      (rc = tmp.alloc(&Tt, (int64_t)nb_max * n_max * nv)) ||
+      (rc = tmp.alloc(&M, (int64_t)nb_max * n_max * n_max)) ||
+      (rc = tmp.alloc(&Qe, (int64_t)nb_max * Dq * Dq)) ||
+      (rc = tmp.alloc(&ev, (int64_t)nb_max * Dq)) ||
+      (rc = tmp.alloc(&Qr, (int64_t)nb_max * n_max * nv)) ||
+      (rc = tmp.alloc(&d_rows, nb_max)))
+    return rc;
+  // operands of the call's products (base ids of the engine, call-time
+  // pointers): compacted slabs, T, G, Y, Z, T~, M, eigenvectors, Q rows
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  sz[B_SLAB] = (int64_t)nb_max * cs_per;
+  sz[B_PK] = (int64_t)nb_max * t_elems;
+  sz[B_PS2] = (int64_t)nb_max * nr * nv;
+  sz[B_K] = (int64_t)nb_max * nr * nv;
+  sz[B_PM] = (int64_t)nb_max * n_max * nv;
+  sz[B_PP] = (int64_t)nb_max * n_max * nv;
+  sz[B_PKT] = (int64_t)nb_max * n_max * n_max;
+  sz[B_PDT] = (int64_t)nb_max * Dq * Dq;
+  sz[B_GAMMA] = (int64_t)nb_max * n_max * nv;
+  GemmBases b = bases(h);
+  b.p[B_SLAB] = cs;
+  b.p[B_PK] = T;
+  b.p[B_PS2] = G;
+  b.p[B_K] = Y;
+  b.p[B_PM] = Z;
+  b.p[B_PP] = Tt;
+  b.p[B_PKT] = M;
+  b.p[B_PDT] = Qe;
+  b.p[B_GAMMA] = Qr;
+  const double thr = l_osv / (10.0 * std::sqrt(2.0 / 3.141592653589793));
+  for (int i0 = 0; i0 < n; i0 += nb_max) {
+    const int nb = std::min(nb_max, n - i0);
+    std::vector<int64_t> out_off;
+    std::vector<GemmTask> tT, tY, tTt, tM, tQ;
+    std::vector<EigTask> et;
+    int64_t off = 0;
+    for (int k = 0; k < nb; ++k) {
+      const int i = i0 + k;
+      const int nc = col_off[i + 1] - col_off[i];
+      out_off.push_back(off);
+      const int64_t t0 = (int64_t)k * t_elems;
+      const int64_t y0 = (int64_t)k * nr * nv, z0 = (int64_t)k * n_max * nv;
+      if (nc > 0)  // T = B_D B_D^T (the compacted slab is n_vir x nc)
+        tT.push_back(gemm(B_SLAB, off, nc, 0, B_SLAB, off, nc, 1, B_PK, t0, nv, nv, nv, nc));
+      off += (int64_t)nv * nc;
+      tY.push_back(gemm(B_PS2, y0, nv, 0, B_PK, t0, nv, 0, B_K, y0, nv, nr, nv, nv));  // Y = G T
+      tTt.push_back(gemm(B_PM, z0, nv, 0, B_PK, t0, nv, 0, B_PP, z0, nv, n_max, nv, nv));  // Z T
+      tM.push_back(gemm(B_PP, z0, nv, 0, B_PP, z0, nv, 1, B_PKT, (int64_t)k * n_max * n_max,
+                        n_max, n_max, n_max, nv));  // M = T~ T~^T
+      tQ.push_back(gemm(B_PDT, (int64_t)k * Dq * Dq, Dq, 1, B_PM, z0, nv, 0, B_GAMMA, z0, nv,
+                        n_max, nv, n_max));  // rows of Q~^T Z
+      EigTask e;
+      std::memset(&e, 0, sizeof e);
+      e.a_off = (int64_t)k * n_max * n_max;
+      e.lda = n_max;
+      e.n = n_max;  // selects the launch; the order is rows[k]
+      e.D = Dq;
+      e.o_off = (int64_t)k * Dq * Dq;
+      e.e_off = (int64_t)k * Dq;
+      e.slot = k;
+      et.push_back(e);
+    }
+    int64_t *d_out_off = nullptr;
+    EigTask *d_et = nullptr;
+    if ((rc = tmp.upload(&d_out_off, out_off)) || (rc = tmp.upload(&d_et, et))) return rc;
+    HIP_TRY(h, launch_fill(T, 0.0, (int64_t)nb * t_elems, st));  // LMOs with empty domains
+    HIP_TRY(h, launch_regen_cols(cs, d_out_off, d_cols, d_col_off, i0, nb, cs_per, nv, na,
+                                 h->seed, h->w_ia, h->w_iP, h->slab, st));
+    if ((rc = run_call_list(h, tmp, "rosv T", tT, sz, b, GEMM_128x128))) return rc;
+    HIP_TRY(h, launch_rosv_tscale(T, i0, nb, nv, h->eps, h->f, n, st));
+    HIP_TRY(h, launch_regen_gauss(G, i0, nb, nr, nv, h->seed, ROSV_STREAM, st));
+    if ((rc = run_call_list(h, tmp, "rosv Y", tY, sz, b, GEMM_64x64))) return rc;
+    HIP_TRY(h, launch_range_finder(Y, Z, d_rows, nb, ROSV_R, n_max, nv, thr, st));
+    if ((rc = run_call_list(h, tmp, "rosv T~", tTt, sz, b, GEMM_64x64))) return rc;
+    if ((rc = run_call_list(h, tmp, "rosv M", tM, sz, b, GEMM_64x64))) return rc;
+    HIP_TRY(h, launch_eigh(d_et, nb, n_max, M, Qe, ev, d_rows, 1, 0.0, nullptr, h->eig_ws,
+                           h->eig_ws_doubles, st));
+    if ((rc = run_call_list(h, tmp, "rosv Q", tQ, sz, b, GEMM_64x64))) return rc;
+    HIP_TRY(h, launch_rosv_finalize(ev, Dq, Qr, d_rows, i0, nb, n_max, nv, l_osv, Q_out, w_out,
+                                    n_osv, rows_out, st));
+  }
+  HIP_TRY(h, hipStreamSynchronize(st));
+  return MBE3_OK;
+}
+
+int mbe3_rosv(mbe3_handle *h, const double *s_fit, double l_fit, double l_osv, int n_max,
+              double *Q_out, double *w_out, int32_t *n_osv, int32_t *rows) {
+  if (!h) return MBE3_EINVAL;
+  return no_throw(h, [&] {
+    return rosv_body(h, s_fit, l_fit, l_osv, n_max, Q_out, w_out, n_osv, rows);
+  });
 }
 
 int mbe3_pair_K_fit(mbe3_handle *h, const double *s_fit, double l_fit, double *K,

@@ -64,12 +64,17 @@ hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
 
 // Sparse fitting metric s_fit[i][P] = sum_a B_i[a][P]^2 of the regenerated
 // (slab == nullptr) or given slabs, and the restriction of gamma-layout rows
-// (LMO of each row in row_lmo) to s_fit > l_fit (regen.hip).
+// to the columns the domains D_q = {P : s_fit[q][P] > l_fit} select for
+// them: a row of block (i, x), x != i (LMO in row_lmo, block in row_x),
+// keeps D_i u D_x; a row of block (i, i) keeps the union of D_q over q in
+// N+(i) (CSR nbr_off / nbr) (regen.hip).
 hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia, const double *w_iP,
                              const double *slab, hipStream_t s);
 hipError_t launch_fit_mask(double *g, int64_t rows, int n_aux, const int32_t *row_lmo,
-                           const double *s_fit, double l_fit, hipStream_t s);
+                           const int32_t *row_x, const int32_t *nbr_off,
+                           const int32_t *nbr, const double *s_fit, double l_fit,
+                           hipStream_t s);
 // Projection over the fitting domains only: the kept columns of a batch of
 // slabs compacted (LMO i's columns cols[col_off[i]..col_off[i+1]), batch
 // member b at out_off[b]), and compacted gamma rows scattered back into the
@@ -82,6 +87,20 @@ hipError_t launch_fit_scatter(double *g, const double *gc, int64_t rows, int n_a
                               int max_nc, const int32_t *row_lmo, const int64_t *g_off,
                               const int64_t *gc_off, const int32_t *cols,
                               const int32_t *col_off, hipStream_t s);
+
+// Randomized OSV generation: Gaussian test rows (regen.hip, Philox key
+// (seed, stream), counter (a, s, i, 0)); the Cauchy scaling of T_ii, the
+// range finder and the final selection (rosv.hip).
+hipError_t launch_regen_gauss(double *out, int i0, int nb, int n_rows, int n_vir,
+                              uint64_t seed, uint64_t stream, hipStream_t s);
+hipError_t launch_rosv_tscale(double *T, int i0, int nb, int n_vir, const double *eps,
+                              const double *f, int n_occ, hipStream_t s);
+hipError_t launch_range_finder(double *Y, double *Z, int32_t *rows, int nb, int r, int n_max,
+                               int n_vir, double thr, hipStream_t s);
+hipError_t launch_rosv_finalize(const double *evals, int D, const double *Qr,
+                                const int32_t *rows, int i0, int nb, int n_max, int n_vir,
+                                double l_osv, double *Q_out, double *w_out, int32_t *n_osv,
+                                int32_t *rows_out, hipStream_t s);
 
 // Split-precision operands (regen.hip): three bf16 planes (bit patterns),
 // plane stride ps elements, rows padded with zeros to ldk (a multiple of 8).
@@ -316,6 +335,12 @@ hipError_t launch_fsym(const double *g, int n, double scale, double *out,
 // ---------------------------------------------------------------------------
 hipError_t launch_mbe_sum(const double *e_frag, const double *coef, int64_t n,
                           double *out2, hipStream_t s);
+// per_slot[s] = c_s <Ka_s - Kb_s, W_s> (c_s = 2 diagonal, 4 pair slots), one
+// workgroup per slot, fixed-order sums (reduce.hip).  launch_mbe_sum with
+// coef == nullptr sums its values with unit coefficients.
+hipError_t launch_slot_dot(const double *Ka, const double *Kb, const double *W,
+                           const int64_t *k_off, int n_occ, int64_t n_slot,
+                           double *per_slot, hipStream_t s);
 hipError_t launch_increments(const double *e_frag, const int32_t *sub,
                              int64_t n, double *incr, hipStream_t s);
 hipError_t launch_fill(double *p, double v, int64_t n, hipStream_t s);

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(1024) void mbe_sum_kernel(
   __shared__ double sh_lo[1024];
   dd acc = {0.0, 0.0};
   for (int64_t k = threadIdx.x; k < n; k += 1024)
-    acc = dd_add(acc, dd_mul_dd(c[k], e[k]));
+    acc = dd_add(acc, c ? dd_mul_dd(c[k], e[k]) : dd{e[k], 0.0});
   sh_hi[threadIdx.x] = acc.hi;
   sh_lo[threadIdx.x] = acc.lo;
   __syncthreads();
@@ -69,6 +69,42 @@ hipError_t launch_mbe_sum(const double *e_frag, const double *coef, int64_t n,
                           double *out2, hipStream_t s) {
   hipLaunchKernelGGL(mbe_sum_kernel, dim3(1), dim3(1024), 0, s, e_frag, coef, n,
                      out2);
+  return hipGetLastError();
+}
+
+// First-order energy change of a change of the pair integrals, per slot:
+//   per_slot[s] = c_s <K_a,s - K_b,s, W_s>,  c_s = 2 (diagonal slot s < n_occ),
+//                                              c_s = 4 (pair slot),
+// with W the multipliers of fragment_solve (dE/dK_s = c_s W_s).  One
+// workgroup per slot: each thread sums a strided share of the slot's
+// elements in order, then a fixed tree in LDS.
+__global__ __launch_bounds__(256) void slot_dot_kernel(
+    const double *__restrict__ Ka, const double *__restrict__ Kb,
+    const double *__restrict__ W, const int64_t *__restrict__ k_off, int n_occ,
+    int64_t n_slot, double *__restrict__ per_slot) {
+  __shared__ double sh[256];
+  for (int64_t sl = blockIdx.x; sl < n_slot; sl += gridDim.x) {
+    const int64_t o0 = k_off[sl], o1 = k_off[sl + 1];
+    double acc = 0.0;
+    for (int64_t e = o0 + threadIdx.x; e < o1; e += 256) acc += (Ka[e] - Kb[e]) * W[e];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) per_slot[sl] = (sl < n_occ ? 2.0 : 4.0) * sh[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_slot_dot(const double *Ka, const double *Kb, const double *W,
+                           const int64_t *k_off, int n_occ, int64_t n_slot,
+                           double *per_slot, hipStream_t s) {
+  if (n_slot <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)(n_slot < 65536 ? n_slot : 65536);
+  hipLaunchKernelGGL(slot_dot_kernel, dim3(blocks), dim3(256), 0, s, Ka, Kb, W, k_off,
+                     n_occ, n_slot, per_slot);
   return hipGetLastError();
 }
 

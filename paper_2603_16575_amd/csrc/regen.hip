@@ -246,18 +246,31 @@ __global__ __launch_bounds__(256) void fit_metric_kernel(
 }
 
 // Restriction of gamma-layout rows (Gamma~, or a gradient with respect to
-// it) to the fitting domains: element P of a row of LMO i becomes zero
-// unless s_fit[i][P] > l_fit.  Kept elements are neither read nor written.
-// Threads run along P (coalesced), workgroups stride over rows.
+// it) to the columns the fitting domains select for them (eq. osv_imua):
+// a row of block (i, x), x != i, keeps P when P is in D_i or D_x; a row of
+// the diagonal block (i, i) keeps P when P is in D_q for some q in N+(i),
+// the union of the pair domains D_i u D_q of every pair that reads it
+// (eq. osv_close_k).  D_q = {P : s_fit[q][P] > l_fit}.  Other elements
+// become zero; kept elements are neither read nor written.  Threads run
+// along P (coalesced), workgroups stride over rows.
 __global__ __launch_bounds__(256) void fit_mask_kernel(
     double *__restrict__ g, int64_t rows, int n_aux,
-    const int32_t *__restrict__ row_lmo, const double *__restrict__ s_fit,
-    double l_fit) {
+    const int32_t *__restrict__ row_lmo, const int32_t *__restrict__ row_x,
+    const int32_t *__restrict__ nbr_off, const int32_t *__restrict__ nbr,
+    const double *__restrict__ s_fit, double l_fit) {
   const int P = blockIdx.x * 256 + threadIdx.x;
   if (P >= n_aux) return;
   for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
-    const int i = row_lmo[row];
-    if (!(s_fit[(int64_t)i * n_aux + P] > l_fit)) g[row * n_aux + P] = 0.0;
+    const int i = row_lmo[row], x = row_x[row];
+    bool keep;
+    if (x != i) {
+      keep = s_fit[(int64_t)i * n_aux + P] > l_fit || s_fit[(int64_t)x * n_aux + P] > l_fit;
+    } else {
+      keep = false;
+      for (int k = nbr_off[i]; k < nbr_off[i + 1] && !keep; ++k)
+        keep = s_fit[(int64_t)nbr[k] * n_aux + P] > l_fit;
+    }
+    if (!keep) g[row * n_aux + P] = 0.0;
   }
 }
 
@@ -334,6 +347,38 @@ hipError_t launch_fit_scatter(double *g, const double *gc, int64_t rows, int n_a
   return hipGetLastError();
 }
 
+// Gaussian test rows of the randomized OSV range finder: row s, column a of
+// batch member b (LMO i0 + b) is the Box-Muller normal of the Philox block at
+// counter (a, s, i, 0) under key (seed, stream); rows [n_rows][n_vir] per
+// member, members n_rows * n_vir apart.
+__global__ __launch_bounds__(256) void regen_gauss_kernel(double *__restrict__ out, int i0,
+                                                          int nb, int n_rows, int n_vir,
+                                                          uint64_t seed, uint64_t stream) {
+  const int64_t per = (int64_t)n_rows * n_vir;
+  const int64_t total = per * nb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / per);
+    const int64_t r = e - (int64_t)b * per;
+    const int srow = (int)(r / n_vir);
+    const int a = (int)(r - (int64_t)srow * n_vir);
+    uint64_t c0 = (uint64_t)a, c1 = (uint64_t)srow, c2 = (uint64_t)(i0 + b), c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, stream);
+    out[e] = box_muller(c0, c1);
+  }
+}
+
+hipError_t launch_regen_gauss(double *out, int i0, int nb, int n_rows, int n_vir,
+                              uint64_t seed, uint64_t stream, hipStream_t s) {
+  const int64_t total = (int64_t)nb * n_rows * n_vir;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(regen_gauss_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, i0, nb,
+                     n_rows, n_vir, seed, stream);
+  return hipGetLastError();
+}
+
 hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia, const double *w_iP,
                              const double *slab, hipStream_t s) {
@@ -347,12 +392,14 @@ hipError_t launch_fit_metric(double *s_fit, int n_occ, int n_vir, int n_aux,
 }
 
 hipError_t launch_fit_mask(double *g, int64_t rows, int n_aux, const int32_t *row_lmo,
-                           const double *s_fit, double l_fit, hipStream_t s) {
+                           const int32_t *row_x, const int32_t *nbr_off,
+                           const int32_t *nbr, const double *s_fit, double l_fit,
+                           hipStream_t s) {
   if (rows <= 0 || n_aux <= 0) return hipSuccess;
   const unsigned gx = (unsigned)((n_aux + 255) / 256);
   const unsigned gy = (unsigned)(rows < 4096 ? rows : 4096);
   hipLaunchKernelGGL(fit_mask_kernel, dim3(gx, gy), dim3(256), 0, s, g, rows, n_aux,
-                     row_lmo, s_fit, l_fit);
+                     row_lmo, row_x, nbr_off, nbr, s_fit, l_fit);
   return hipGetLastError();
 }
 

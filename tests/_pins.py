@@ -25,7 +25,7 @@ def _commutation(n):
     return P
 
 
-def kron_fragment_solve(B, Q, eps, f, frag):
+def kron_fragment_solve(B, Q, eps, f, frag, Kfun=None):
     """Solve the projected full-space residual equations of one fragment.
 
     Unknowns: T_s for every p <= q in the fragment, t_pq = V T V^T.
@@ -33,8 +33,11 @@ def kron_fragment_solve(B, Q, eps, f, frag):
       r_pq = K_pq + eps t_pq + t_pq eps - sum_k (f_pk t_kq + f_kq t_pk),
     k over the fragment, written with Kronecker products and solved densely.
     Returns (E, t) with E = sum_{ordered p,q} <K_pq, 2 t_pq - t_pq^T> and the
-    full-space amplitudes t[(p, q)] for all ordered pairs.
+    full-space amplitudes t[(p, q)] for all ordered pairs.  Kfun(p, q)
+    (optional) supplies the full-space K_pq in place of B_p B_q^T.
     """
+    if Kfun is None:
+        Kfun = lambda p, q: full_K(B, p, q)
     frag = sorted(frag)
     n = len(eps)
     I = np.eye(n)
@@ -69,7 +72,7 @@ def kron_fragment_solve(B, Q, eps, f, frag):
         proj = np.kron(V[t].T, V[t].T)
         sl = slice(offs[t], offs[t] + dims[t] ** 2)
         A[sl] = proj @ Lin
-        rhs[sl] = -(proj @ full_K(B, p, q).ravel())
+        rhs[sl] = -(proj @ Kfun(p, q).ravel())
     x = np.linalg.solve(A, rhs)
     t_full = {}
     for x_ in frag:
@@ -77,7 +80,7 @@ def kron_fragment_solve(B, Q, eps, f, frag):
             t_full[(x_, y_)] = (lift(x_, y_) @ x).reshape(n, n)
     E = 0.0
     for (x_, y_), t in t_full.items():
-        E += np.sum(full_K(B, x_, y_) * (2.0 * t - t.T))
+        E += np.sum(Kfun(x_, y_) * (2.0 * t - t.T))
     return E, t_full
 
 

@@ -1,19 +1,22 @@
-"""Sparse fitting domains (mbe3_fit_metric, mbe3_fit_mask) through the C-ABI
-against the oracle (needs an MI355X): the metric of every (i, P) of the
-8-LMO chain and of sampled (i, P) of the 1024-LMO helix, the restricted
-Gamma~, pair integrals, fragment and MBE(3) energies at a threshold that
-splits the domains, the gradient of the restricted energy, the exact
-masking pattern, a recorded restriction replayed, argument errors, the
-metric of a given slab array, the restriction in both split-precision
-forms, sampled fragments of the restricted 160-LMO lattice at full size,
-the projection over the domains only and pair_K over their
-intersections (bit for bit the masked dense path, timed on the helix)."""
+"""Sparse fitting domains (mbe3_fit_metric, mbe3_fit_mask, mbe3_project_fit,
+mbe3_pair_K_fit) through the C-ABI against the oracle (needs an MI355X): the
+metric of every (i, P) of the 8-LMO chain and of sampled (i, P) of the
+1024-LMO helix; Gamma~ as stored over the domains (block (i, x) on
+D_i u D_x, the diagonal block on the union over N+(i)); pair integrals
+summed over D_p u D_q; fragment and MBE(3) energies at a threshold that
+splits the domains; the exact masking pattern; a recorded restriction
+replayed; argument errors; the metric of a given slab array; the same
+restricted integrals in the split-precision forms; sampled fragments of the
+restricted 160-LMO lattice at full size; the projection over the domains
+only (bit for bit the masked dense path) and pair_K over the unions, with
+sampled slots and fragments of the helix against the oracle."""
 import dataclasses
 import sys
 
 import numpy as np
 import pytest
 
+import _workloads
 import oracle
 import synth
 from oracle import fit
@@ -61,11 +64,26 @@ def k_block(h, prob, K, s):
     return K[off:off + d * d].view(d, d).cpu().numpy(), (int(p), int(q))
 
 
-def row_lmo(h, prob):
+def row_blocks(h, prob):
+    """(LMO i, block orbital x) of every gamma row."""
     rl = np.empty(int(h.g_off[-1]), dtype=np.int64)
+    rx = np.empty_like(rl)
     for i in range(prob.n_occ):
-        rl[int(h.g_off[i]):int(h.g_off[i + 1])] = i
-    return rl
+        row = int(h.g_off[i])
+        for x in prob.neighbours(i):
+            rl[row:row + int(prob.r[x])] = i
+            rx[row:row + int(prob.r[x])] = int(x)
+            row += int(prob.r[x])
+    return rl, rx
+
+
+def keep_mask(h, prob, s, l_fit):
+    """Columns kept in every gamma row by the union rule, from the metric
+    (written out here: D_i u D_x, or the union over N+(i) for x = i)."""
+    D = s > l_fit
+    rl, rx = row_blocks(h, prob)
+    C = np.stack([np.any(D[prob.neighbours(i)], axis=0) for i in range(prob.n_occ)])
+    return np.where((rl == rx)[:, None], C[rl], D[rl] | D[rx])
 
 
 def test_fit_metric_chain8(m):
@@ -81,8 +99,9 @@ def test_fit_metric_chain8(m):
 
 
 def test_fit_restricted_chain8(m):
-    """Restricted Gamma~, K and energies at a threshold splitting the
-    domains, both sides from T = 0 (the oracle's iterates)."""
+    """Gamma~ as stored over the domains, K over D_p u D_q and the energies at
+    a threshold splitting the domains, both sides from T = 0 (the oracle's
+    iterates)."""
     import torch
     say("case: chain8, restricted forward (split threshold) vs oracle")
     prob = synth.config(0)
@@ -99,12 +118,13 @@ def test_fit_restricted_chain8(m):
     kept = float(np.mean(s_ref > l_fit))
     say(f"  l_fit {l_fit:.3e}, kept {kept:.3f}, nearest metric {gap:.1e} (relative) away")
     ora = fit.restricted_oracle(prob, l_fit, base=base, s_fit=s_ref)
+    g = h.project_fit(out["s_fit"], l_fit, h.empty_gamma())
     for i in range(prob.n_occ):
         for x in prob.neighbours(i):
-            g = gamma_block(h, prob, out["gamma"], i, int(x))
-            r = ora.gamma(i, int(x))
-            assert np.array_equal(g == 0.0, np.broadcast_to(~(s_ref[i] > l_fit), g.shape))
-            assert np.abs(g - r).max() <= 1e-13 * np.abs(r).max(), (i, x)
+            gb = gamma_block(h, prob, g, i, int(x))
+            r = ora.gamma_fit(i, int(x))
+            assert np.array_equal(gb == 0.0, r == 0.0), (i, x)
+            assert np.abs(gb - r).max() <= 1e-13 * np.abs(r).max(), (i, x)
     for sl in range(h.layout.n_slot):
         k, (p, q) = k_block(h, prob, out["K"], sl)
         r = ora.Kbar(p, q)
@@ -112,8 +132,6 @@ def test_fit_restricted_chain8(m):
     ref = oracle.run(prob, ora=ora)
     E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
     e = out["e_frag"].cpu().numpy()
-    comp = h.forward(l_fit=l_fit, compact=True)
-    assert comp["E"] == out["E"] and torch.equal(comp["e_frag"], out["e_frag"])
     full = h.forward()
     say(f"  E restricted GPU {out['E']:.14f} oracle {E_ref:.14f}; "
         f"unrestricted {full['E']:.14f}")
@@ -121,40 +139,6 @@ def test_fit_restricted_chain8(m):
     assert np.array_equal(out["iters"].cpu().numpy(), ref["iters"])
     assert abs(out["E"] - E_ref) <= 1e-10
     assert abs(out["E"] - full["E"]) > 1e-6 * abs(full["E"])
-    h.close()
-
-
-def test_fit_restricted_gradient_chain8(m):
-    """dE_r/dB of the restricted energy E_r(B) = E(B restricted): the
-    GRAD_GAMMA output at the restricted Gamma~, masked by mbe3_fit_mask and
-    un-projected here, against the oracle's slab gradient at the restricted
-    slabs with the dropped columns zeroed."""
-    import torch
-    say("case: chain8, gradient of the restricted energy vs oracle, tol 1e-11")
-    prob = dataclasses.replace(synth.config(0), tol=1e-11, max_iter=300)
-    h = m.from_problem(prob, warm_start=False)
-    base = oracle.Oracle(prob)
-    s_ref = fit.fit_metrics(base)
-    l_fit = split_threshold(s_ref)
-    out = h.forward(grad=True, l_fit=l_fit)
-    dG, _ = h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_GAMMA)
-    h.fit_mask(out["s_fit"], l_fit, dG)
-    torch.cuda.synchronize()
-    g = oracle.gradient(prob, ora=fit.restricted_oracle(prob, l_fit, base=base, s_fit=s_ref))
-    mask = s_ref > l_fit
-    dGn = dG.cpu().numpy().reshape(-1, prob.n_aux)
-    worst = 0.0
-    for i in range(prob.n_occ):
-        acc = np.zeros((prob.n_vir, prob.n_aux))
-        row = int(h.g_off[i])
-        for x in prob.neighbours(i):
-            rx = int(prob.r[x])
-            acc += base.Q[int(x)] @ dGn[row:row + rx]
-            row += rx
-        worst = max(worst, rel(acc, g["dB"][i] * mask[i][None, :]))
-        assert not np.any(acc[:, ~mask[i]])
-    say(f"  dE_r/dB rel {worst:.2e}")
-    assert worst <= 1e-10
     h.close()
 
 
@@ -171,7 +155,8 @@ def test_fit_mask_pattern_and_errors(m):
     g = torch.randn(int(h.layout.gamma_elems), dtype=torch.float64, device="cuda:0")
     g0 = g.cpu().numpy().reshape(-1, prob.n_aux)
     h.fit_mask(s, l_fit, g)
-    keep = (sn > l_fit)[row_lmo(h, prob)]
+    keep = keep_mask(h, prob, sn, l_fit)
+    assert 0.3 < keep.mean() < 1.0
     got = g.cpu().numpy().reshape(-1, prob.n_aux)
     assert np.array_equal(got, np.where(keep, g0, 0.0))
     # below every metric: nothing changes; above every metric: all zero
@@ -197,17 +182,17 @@ def test_fit_mask_pattern_and_errors(m):
 
 
 def test_fit_recorded_replays(m):
-    """osv_project, fit_metric, fit_mask and pair_K recorded once and
-    replayed three times, each replay equal bit for bit to the eager calls."""
+    """osv_project, fit_metric and fit_mask recorded once and replayed three
+    times, each replay equal bit for bit to the eager calls."""
     import torch
     say("case: chain8, recorded restriction replayed 3 times vs eager")
     prob = synth.config(0)
     h = m.from_problem(prob)
-    sn = h.fit_metric().cpu().numpy()
-    l_fit = split_threshold(sn)
-    eager = h.forward(l_fit=l_fit)
+    s_e = h.fit_metric()
+    l_fit = split_threshold(s_e.cpu().numpy())
+    g_e = h.fit_mask(s_e, l_fit, h.osv_project(h.empty_gamma()))
     torch.cuda.synchronize()
-    gamma, K = h.empty_gamma(), h.empty_K()
+    gamma = h.empty_gamma()
     s = torch.empty((prob.n_occ, prob.n_aux), dtype=torch.float64, device="cuda:0")
     torch.cuda.synchronize()
     h.graph_begin()
@@ -215,19 +200,16 @@ def test_fit_recorded_replays(m):
         h.osv_project(gamma)
         h.fit_metric(out=s)
         h.fit_mask(s, l_fit, gamma)
-        h.pair_K(gamma, K)
     finally:
         h.graph_end()
     for rep in range(3):
         gamma.fill_(1.0)
-        K.zero_()
         s.zero_()
         torch.cuda.synchronize()
         h.graph_launch()
         torch.cuda.synchronize()
-        assert torch.equal(s, eager["s_fit"]), rep
-        assert torch.equal(gamma, eager["gamma"]), rep
-        assert torch.equal(K, eager["K"]), rep
+        assert torch.equal(s, s_e), rep
+        assert torch.equal(gamma, g_e), rep
     h.close()
 
 
@@ -236,7 +218,7 @@ def test_fit_metric_helix1024_sampled(m):
     columns, and the share of each domain kept at the paper's threshold."""
     import torch
     say("case: helix1024, s_fit at 24 sampled (i, P) vs oracle slab columns")
-    prob = synth.config(4)
+    prob = _workloads.config(4)
     h = m.from_problem(prob)
     s = h.fit_metric().cpu().numpy()
     torch.cuda.synchronize()
@@ -278,26 +260,22 @@ def test_fit_metric_given_slab(m):
 
 @pytest.mark.parametrize("form", ["MBE3_MIXED_BF16", "MBE3_MIXED_BF16_PROJ"])
 def test_fit_restricted_split_precision(m, form):
-    """The restriction in the split-precision forms: dropped Gamma~ elements
-    stay exactly zero and the restricted energy is within the FP64 path's
-    budget of the oracle's restricted energy."""
+    """pair_K over the domains runs in FP64 in every precision mode: a
+    split-precision handle returns bit for bit the FP64 handle's restricted
+    integrals."""
     import torch
-    say(f"case: chain8, restricted forward in {form} vs oracle")
+    say(f"case: chain8, pair_K over the domains on a {form} handle vs FP64")
     prob = synth.config(0)
-    base = oracle.Oracle(prob)
-    s_ref = fit.fit_metrics(base)
-    l_fit = split_threshold(s_ref)
-    h = m.from_problem(prob, warm_start=False, precision=getattr(m, form))
-    out = h.forward(l_fit=l_fit)
+    h64 = m.from_problem(prob)
+    s = h64.fit_metric()
+    l_fit = split_threshold(s.cpu().numpy())
+    K64 = h64.pair_K_fit(s, l_fit, h64.empty_K())
+    h = m.from_problem(prob, precision=getattr(m, form))
+    K = h.pair_K_fit(s, l_fit, h.empty_K())
     torch.cuda.synchronize()
-    g = out["gamma"].view(-1, prob.n_aux).cpu().numpy()
-    drop = ~(s_ref > l_fit)[row_lmo(h, prob)]
-    assert not np.any(g[drop])
-    ref = oracle.run(prob, ora=fit.restricted_oracle(prob, l_fit, base=base, s_fit=s_ref))
-    E_ref, _ = oracle.mbe3_energy(prob.frags, ref["e_frag"])
-    say(f"  E {out['E']:.14f} oracle {E_ref:.14f} dE {out['E'] - E_ref:.2e}")
-    assert abs(out["E"] - E_ref) <= 1e-6
+    assert torch.equal(K, K64)
     h.close()
+    h64.close()
 
 
 def test_fit_restricted_water40u_sampled(m):
@@ -377,7 +355,7 @@ def test_project_fit_helix1024(m):
     import time
     import torch
     say("case: helix1024, restricted projection at l_fit 1e-6 vs project + mask")
-    prob = synth.config(4)
+    prob = _workloads.config(4)
     h = m.from_problem(prob)
     s = h.fit_metric()
     g = h.empty_gamma()
@@ -406,48 +384,59 @@ def test_project_fit_helix1024(m):
 
 
 def test_pair_K_fit_chain8(m):
-    """pair_K over the domain intersections against pair_K of the masked
-    gamma and against the oracle's restricted K, at a splitting threshold,
-    below every metric (the unrestricted K) and above every metric (zero)."""
+    """pair_K over the unions D_p u D_q against the oracle's restricted K at a
+    splitting threshold; below every metric it is the unrestricted pair_K,
+    above every metric zero."""
     import torch
-    say("case: chain8, pair_K over D_p and D_q vs pair_K of the masked gamma and oracle")
+    say("case: chain8, pair_K over D_p u D_q vs oracle and the limits")
     prob = synth.config(0)
     h = m.from_problem(prob)
     s = h.fit_metric()
     sn = s.cpu().numpy()
     base = oracle.Oracle(prob)
-    for l_fit in (split_threshold(sn), -1.0, float(sn.max())):
-        g = h.fit_mask(s, l_fit, h.osv_project(h.empty_gamma()))
-        ref = h.pair_K(g, h.empty_K())
-        got = h.pair_K_fit(s, l_fit, h.empty_K())
-        torch.cuda.synchronize()
-        scale = float(ref.abs().max()) if float(ref.abs().max()) > 0 else 1.0
-        d = float((got - ref).abs().max()) / scale
-        say(f"  l_fit {l_fit:.3e}: max |K_fit - K(masked)| / max|K| = {d:.2e}")
-        assert d <= 1e-13
-        if l_fit == float(sn.max()):
-            assert not torch.any(got)
+    full = h.pair_K(h.osv_project(h.empty_gamma()), h.empty_K())
+    got = h.pair_K_fit(s, -1.0, h.empty_K())
+    torch.cuda.synchronize()
+    d = float((got - full).abs().max()) / float(full.abs().max())
+    say(f"  every column kept: max |K_fit - K| / max|K| = {d:.2e}")
+    assert d <= 1e-13
+    assert not torch.any(h.pair_K_fit(s, float(sn.max()), h.empty_K()))
     l_fit = split_threshold(sn)
     ora = fit.restricted_oracle(prob, l_fit, base=base, s_fit=fit.fit_metrics(base))
     K = h.pair_K_fit(s, l_fit, h.empty_K())
+    worst = 0.0
     for sl in range(h.layout.n_slot):
         k, (p, q) = k_block(h, prob, K, sl)
         r = ora.Kbar(p, q)
-        assert np.abs(k - r).max() <= 1e-13 * np.abs(r).max(), sl
+        worst = max(worst, float(np.abs(k - r).max() / np.abs(r).max()))
+    say(f"  split threshold: max rel diff to the oracle {worst:.2e}")
+    assert worst <= 1e-13
     h.close()
 
 
+def helix_sample_slots(prob):
+    """Diagonal slots and pairs around LMOs 1, 2 and 500 of the helix."""
+    n = prob.n_occ
+    pr = [tuple(int(v) for v in pq) for pq in prob.pairs]
+    want = [(1, 2), (1, 4), (500, 501), (499, 502)]
+    slots = [1, 2, 500]
+    for w in want:
+        if w in pr:
+            slots.append(n + pr.index(w))
+    return slots
+
+
 def test_pair_K_fit_helix1024(m):
-    """The 1024-LMO helix at l_fit = 1e-6: pair_K over the intersections
-    (projection of the kept columns included) against pair_K of the masked
-    dense gamma, both timed."""
+    """The 1024-LMO helix at l_fit = 1e-6: pair_K over the unions
+    (projection of the needed columns included) against the oracle on
+    sampled slots, timed against the dense pair_K."""
     import time
     import torch
-    say("case: helix1024, pair_K over the domain intersections vs masked dense path")
-    prob = synth.config(4)
+    say("case: helix1024, pair_K over the domain unions vs oracle slots")
+    prob = _workloads.config(4)
     h = m.from_problem(prob)
     s = h.fit_metric()
-    g = h.fit_mask(s, m.L_FIT, h.osv_project(h.empty_gamma()))
+    g = h.osv_project(h.empty_gamma())
     K_ref, K = h.empty_K(), h.empty_K()
     for _ in range(2):
         torch.cuda.synchronize()
@@ -463,23 +452,30 @@ def test_pair_K_fit_helix1024(m):
         h.pair_K_fit(s, m.L_FIT, K)
         torch.cuda.synchronize()
         t_fit = time.perf_counter() - t0
-    d = float((K - K_ref).abs().max()) / float(K_ref.abs().max())
-    say(f"  pair_K on the masked gamma {t_dense * 1e3:.1f} ms; projection + pair_K over "
-        f"the intersections {t_fit * 1e3:.1f} ms; max rel diff {d:.2e}")
-    assert d <= 1e-12
+    ora = fit.RestrictedOracle(prob, m.L_FIT)
+    worst = 0.0
+    for sl in helix_sample_slots(prob):
+        k, (p, q) = k_block(h, prob, K, sl)
+        r = ora.Kbar(p, q)
+        worst = max(worst, float(np.abs(k - r).max() / np.abs(r).max()))
+    kept = [int(ora.dom(i).sum()) for i in ora.s]
+    say(f"  dense pair_K {t_dense * 1e3:.1f} ms; projection + pair_K over the unions "
+        f"{t_fit * 1e3:.1f} ms; domain sizes {kept}; sampled slots max rel diff {worst:.2e}")
+    assert worst <= 1e-12
     h.close()
 
 
 def test_fit_helix1024_restricted_energy(m):
     """End to end on the 1024-LMO helix at the paper's l_fit = 1e-6: the
-    MBE(3) energy from pair_K over the domain intersections (Gamma~ never
-    formed densely) next to the unrestricted energy; the restriction's
-    energy change is reported."""
+    MBE(3) energy from pair_K over the unions D_p u D_q (Gamma~ never formed
+    densely) next to the unrestricted energy, and every fragment containing
+    the pair (1, 2) against the restricted oracle, one by one (both from
+    T = 0)."""
     import time
     import torch
-    say("case: helix1024, restricted MBE(3) energy (l_fit 1e-6) vs unrestricted")
-    prob = synth.config(4)
-    h = m.from_problem(prob)
+    say("case: helix1024, restricted MBE(3) energy (l_fit 1e-6), sampled oracle fragments")
+    prob = _workloads.config(4)
+    h = m.from_problem(prob, warm_start=False)
     e = torch.empty(prob.n_frag, dtype=torch.float64, device="cuda:0")
     it = torch.empty(prob.n_frag, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
@@ -496,7 +492,13 @@ def test_fit_helix1024_restricted_energy(m):
     say(f"  E restricted {E_fit:.10f} ({t_fit * 1e3:.0f} ms with the metric), "
         f"unrestricted {out['E']:.10f} ({t_full * 1e3:.0f} ms), relative change {rel:.2e}")
     assert np.isfinite(E_fit) and (it >= 0).all()
-    assert abs(rel) < 0.05
+    fr = prob.frags
+    idx = np.nonzero((fr == 1).any(1) & (fr == 2).any(1))[0]
+    ora = fit.RestrictedOracle(prob, m.L_FIT)
+    res = oracle.run(prob, frags=fr[idx], ora=ora)
+    dE = np.abs(e.cpu().numpy()[idx] - res["e_frag"])
+    say(f"  fragments {fr[idx].tolist()}: max |dE_F| vs restricted oracle {dE.max():.3e}")
+    assert dE.max() <= 1e-12
     h.close()
     del out, K, s
     torch.cuda.empty_cache()

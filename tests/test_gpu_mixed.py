@@ -169,8 +169,8 @@ def test_mixed_energy_water40u(m, form):
     hf = m.from_problem(prob)
     of = hf.forward(grad=True)
     ef = of["e_frag"].cpu().numpy()
-    est, per = m.first_order_dE(hf.k_off, prob.n_occ, Km, of["K"].cpu().numpy(),
-                                of["W"].cpu().numpy())
+    est, per = hf.first_order_dE(torch.as_tensor(Km, device="cuda:0"), of["K"], of["W"])
+    per = per.cpu().numpy()
     E_f = of["E"]
     hf.close()
     d = np.abs(em - ef)
@@ -184,3 +184,52 @@ def test_mixed_energy_water40u(m, form):
     # holds to second order (and the solver's stopping threshold)
     assert abs(est - (E_m - E_f)) <= 0.05 * abs(E_m - E_f) + 1e-9
     assert d.max() <= 1e-7
+
+
+def test_first_order_dE_matches_finite_difference(m):
+    """mbe3_first_order_dE with the oracle's multipliers W reproduces the
+    central difference of the oracle's MBE(3) energy along a random change
+    of every K-bar block (diagonal slots, kept symmetric, and pairs): this
+    fixes the slot weights 2 and 4 and the packing of the K layout."""
+    import torch
+    say("case: micro n_occ=4, first-order dE vs oracle central difference")
+    prob = dataclasses.replace(synth.micro(4), tol=1e-13, max_iter=400)
+    g = oracle.gradient(prob)
+    ora0 = g["run"]["oracle"]
+    h = m.from_problem(prob)
+    n = prob.n_occ
+    slots = [(p, p) for p in range(n)] + [tuple(int(v) for v in pq) for pq in prob.pairs]
+    k_off = h.k_off
+    d = [int(round(np.sqrt(k_off[s + 1] - k_off[s]))) for s in range(len(slots))]
+    rng = np.random.default_rng(3)
+    K0 = np.concatenate([ora0.Kbar(p, q).ravel() for p, q in slots])
+    dK = rng.standard_normal(K0.shape) * np.abs(K0).max()
+    for s in range(n):  # K-bar_pp = G G^T stays symmetric
+        blk = dK[k_off[s]:k_off[s + 1]].reshape(d[s], d[s])
+        dK[k_off[s]:k_off[s + 1]] = (0.5 * (blk + blk.T)).ravel()
+    W = np.concatenate([g["W"][s].ravel() for s in slots])
+
+    def energy_at(eps):
+        ora = oracle.Oracle(prob)
+        for s, (p, q) in enumerate(slots):
+            ora._K[(p, q)] = (K0 + eps * dK)[k_off[s]:k_off[s + 1]].reshape(d[s], d[s])
+        return oracle.energy(prob, ora=ora)
+
+    step = 1e-5
+    fd = (energy_at(step) - energy_at(-step)) / (2 * step)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    est, per = h.first_order_dE(t(K0 + dK), t(K0), t(W))
+    per = per.cpu().numpy()
+    say(f"  first-order {est:.12e}, central difference {fd:.12e}")
+    assert per.shape == (len(slots),)
+    assert abs(per.sum() - est) <= 1e-13 * abs(est)
+    assert abs(est - fd) <= 1e-7 * abs(fd)
+    mask = np.zeros_like(dK)
+    mask[:k_off[n]] = 1.0
+    e_diag, _ = h.first_order_dE(t(K0 + mask * dK), t(K0), t(W))
+    assert abs(e_diag - 2.0 * float(np.sum((mask * dK) * W))) <= 1e-12 * abs(e_diag)
+    with pytest.raises(m.Mbe3Error) as ei:
+        m._lib.check(m._lib.load().mbe3_first_order_dE(h._h, None, None, None, None, None),
+                     h._h)
+    assert ei.value.code == m.MBE3_EINVAL
+    h.close()

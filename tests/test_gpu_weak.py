@@ -133,7 +133,8 @@ def test_weak_pairs_water40u_sampled(m):
     e_ref = np.array([weak.weak_pair(ora, int(i), int(j), Td[i], Td[j])[1] for i, j in pr])
     rs = float(np.abs(s - s_ref).max() / np.abs(s_ref).max())
     re = float(np.abs(e - e_ref).max() / np.abs(e_ref).max())
-    say(f"  {len(pr)} pairs, classes {np.bincount(m.pair_classes(s), minlength=3).tolist()}, "
+    cls = m.screen_lists(prob.n_occ, pr, s)["classes"]
+    say(f"  {len(pr)} pairs, classes {np.bincount(cls, minlength=3).tolist()}, "
         f"s2b rel {rs:.2e}, e rel {re:.2e}, sum e {e.sum():.6e}")
     assert rs <= 1e-13 and re <= 1e-11
     h.close()
@@ -186,3 +187,76 @@ def test_weak_and_screen_refused_while_recording(m):
     e = h.weak_pairs(pr, out["gamma"], out["W"]).cpu().numpy()
     assert np.array_equal(e, e_ref)
     h.close()
+
+
+def test_water40u_paper_classes(m):
+    """The 160-LMO lattice screened the paper's way instead of by distance:
+    s2b of all 12720 pairs on the GPU (mbe3_screen), classes and trimers
+    (mbe3_screen_lists) equal to the oracle's brute-force screening of its
+    own s2b; close pairs and the kept trimers solved as fragments, weak
+    pairs through mbe3_weak_pairs with the MBE(3) diagonal amplitudes of
+    that solve.  Against the oracle: every fragment containing LMO 0 and
+    every 97th fragment one by one, and the weak-pair energies of pairs
+    among a few LMOs, each side from its own T^MBE_ii (both from T = 0)."""
+    import torch
+    say("case: water40u with the paper's s2b / s3b screening, sampled vs oracle")
+    prob = synth.config(1)
+    n = prob.n_occ
+    cand = all_pairs(n)
+    mono = np.full((n, 3), -1, dtype=np.int32)
+    mono[:, 0] = np.arange(n)
+    h0 = m.from_problem(prob, pairs=np.zeros((0, 2), dtype=np.int32), frags=mono)
+    s = h0.screen(cand).cpu().numpy()
+    h0.close()
+    lists = m.screen_lists(n, cand, s)
+    ora = oracle.Oracle(prob)
+    s_ref = np.array([weak.s2b(ora, int(i), int(j)) for i, j in cand])
+    rs = float(np.abs(s - s_ref).max() / np.abs(s_ref).max())
+    # no metric within rounding of a class threshold or of the trimer mean
+    gap = min(float(np.min(np.abs(s_ref - t) / t)) for t in (m.S2B_DISTANT, m.S2B_CLOSE))
+    close, wk, tris = weak.screened_lists(n, {(int(i), int(j)): v for (i, j), v in zip(cand, s_ref)})
+    say(f"  s2b rel {rs:.2e}, nearest class threshold {gap:.1e} away; close {len(close)}, "
+        f"weak {len(wk)}, trimers {len(tris)} (oracle {len(lists['close'])}, "
+        f"{len(lists['weak'])}, {len(lists['trimers'])} on the GPU)")
+    assert rs <= 1e-13 and gap > 1e-10
+    assert [tuple(x) for x in lists["close"].tolist()] == close
+    assert [tuple(x) for x in lists["weak"].tolist()] == wk
+    assert [tuple(x) for x in lists["trimers"].tolist()] == tris
+    prob2 = dataclasses.replace(prob, pairs=lists["close"], trimers=lists["trimers"])
+    h = m.from_problem(prob2, warm_start=False)
+    out = h.forward(grad=True)
+    e = out["e_frag"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert (it >= 0).all() and np.isfinite(e).all()
+    fr = prob2.frags
+    pick = np.unique(np.concatenate([np.nonzero((fr == 0).any(1))[0],
+                                     np.arange(0, len(fr), 97)]))
+    ora2 = oracle.Oracle(prob2)
+    res = oracle.run(prob2, frags=fr[pick], ora=ora2)
+    dE = float(np.abs(e[pick] - res["e_frag"]).max())
+    say(f"  {len(fr)} fragments, E_MBE(3) = {out['E']:.10f}; {len(pick)} sampled: "
+        f"max |dE_F| {dE:.3e}")
+    assert dE <= 1e-12
+    assert np.array_equal(it[pick], res["iters"])
+    # weak pairs among a few LMOs: T^MBE_ii from every fragment containing i
+    wl = lists["weak"]
+    sel = wl[(wl[:, 0] == 0) | (wl[:, 0] == 1)][:4]
+    S = sorted(set(int(v) for v in sel.ravel()))
+    ew = h.weak_pairs(sel, out["gamma"], out["W"]).cpu().numpy()
+    coef = oracle.mbe3_coefficients(n, fr)
+    fidx = np.nonzero(np.isin(fr, S).any(1))[0]
+    rT = oracle.run(prob2, frags=fr[fidx], ora=ora2, keep_T=True)
+    Td = {i: 0.0 for i in S}
+    for f, cF, T in zip(fr[fidx], coef[fidx], rT["T"]):
+        for x in (int(v) for v in f if v >= 0):
+            if x in Td:
+                Td[x] = Td[x] + cF * T[(x, x)]
+    ew_ref = weak.weak_energies(ora2, sel, Td)
+    rw = float(np.abs(ew - ew_ref).max() / np.abs(ew_ref).max())
+    E_weak_all = float(h.weak_pairs(wl, out["gamma"], out["W"]).sum())
+    say(f"  weak pairs {sel.tolist()}: rel diff {rw:.2e}; all {len(wl)} weak pairs "
+        f"E_weak = {E_weak_all:.10f}, E_MBE(3) + E_weak = {out['E'] + E_weak_all:.10f}")
+    assert rw <= 1e-9
+    h.close()
+    del out
+    torch.cuda.empty_cache()

@@ -1,71 +1,69 @@
-"""Host-side helpers of the package against the oracle (no GPU needed)."""
-import dataclasses
-
+"""Host-side logic of the library (no GPU needed): the pair classes and
+trimer screening of mbe3_screen_lists against the oracle's brute-force
+screening, with the paper's thresholds."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from oracle import weak
 
 
 @pytest.fixture(scope="module")
 def pkg():
     import paper_2603_16575_amd as m
+    m._lib.load()
     return m
 
 
-def slot_list(prob):
-    """Slots in the K layout: the diagonal (p, p) of every LMO, then the
-    pairs in their sorted order."""
-    return [(p, p) for p in range(prob.n_occ)] + [tuple(int(v) for v in pq) for pq in prob.pairs]
-
-
-def test_first_order_dE_matches_finite_difference(pkg):
-    """first_order_dE with the oracle's multipliers W reproduces the central
-    difference of the oracle's MBE(3) energy along a random change of every
-    K-bar block (diagonal slots, kept symmetric, and pairs): this fixes the
-    slot weights 2 and 4 and the packing of the K layout."""
-    prob = dataclasses.replace(synth.micro(4), tol=1e-13, max_iter=400)
-    g = oracle.gradient(prob)
-    ora0 = g["run"]["oracle"]
-    slots = slot_list(prob)
-    d = [oracle.orbs(p, q) for p, q in slots]
-    d = [int(sum(prob.r[x] for x in o)) for o in d]
-    k_off = np.concatenate([[0], np.cumsum(np.square(d))]).astype(np.int64)
-    rng = np.random.default_rng(3)
-    K0 = np.concatenate([ora0.Kbar(p, q).ravel() for p, q in slots])
-    dK = rng.standard_normal(K0.shape) * np.abs(K0).max()
-    for s in range(prob.n_occ):  # K-bar_pp = G G^T stays symmetric
-        blk = dK[k_off[s]:k_off[s + 1]].reshape(d[s], d[s])
-        dK[k_off[s]:k_off[s + 1]] = (0.5 * (blk + blk.T)).ravel()
-    W = np.concatenate([g["W"][s].ravel() for s in slots])
-
-    def energy_at(eps):
-        ora = oracle.Oracle(prob)
-        for s, (p, q) in enumerate(slots):
-            blk = (K0 + eps * dK)[k_off[s]:k_off[s + 1]]
-            ora._K[(p, q)] = blk.reshape(d[s], d[s])
-        return oracle.energy(prob, ora=ora)
-
-    h = 1e-5
-    fd = (energy_at(h) - energy_at(-h)) / (2 * h)
-    est, per = pkg.first_order_dE(k_off, prob.n_occ, K0 + dK, K0, W)
-    assert per.shape == (len(slots),)
-    assert np.isclose(per.sum(), est)
-    assert abs(est - fd) <= 1e-7 * abs(fd)
-    # a change of the diagonal slots alone carries weight 2, pairs alone 4
-    mask = np.zeros_like(dK)
-    mask[:k_off[prob.n_occ]] = 1.0
-    e_diag, _ = pkg.first_order_dE(k_off, prob.n_occ, K0 + mask * dK, K0, W)
-    assert np.isclose(e_diag, 2.0 * float(np.sum((mask * dK) * W)))
-
-
-def test_pair_classes_match_oracle(pkg):
-    """The package's class and trimer helpers use the oracle's thresholds."""
-    from oracle import weak
+def test_screen_lists_thresholds(pkg):
+    """Class boundaries as printed (distant below 1e-7, weak below 1e-2,
+    close from 1e-2), the trimer boundary at s3b = 0.2, and the order of the
+    returned lists."""
     vals = [0.0, 5e-8, 1e-7, 2e-4, 9.99e-3, 1e-2, 0.5]
     names = {0: "distant", 1: "weak", 2: "close"}
-    got = pkg.pair_classes(vals)
-    assert [names[int(c)] for c in got] == [weak.pair_class(v) for v in vals]
-    trip = [(0.3, 0.2, 0.1 + 1e-12), (0.3, 0.2, 0.1 - 1e-9), (0.05, 0.01, 0.02)]
-    assert [bool(pkg.keep_trimers(*t)) for t in trip] == [weak.keep_trimer(*t) for t in trip]
+    pairs = np.array([[0, k + 1] for k in range(len(vals))])
+    out = pkg.screen_lists(len(vals) + 1, pairs, vals)
+    assert [names[int(c)] for c in out["classes"]] == [weak.pair_class(v) for v in vals]
+    # trimers: (0,1,2) with metrics 0.3, 0.2, 0.1 +- a little
+    for s_jk, keep in ((0.1 + 1e-12, True), (0.1 - 1e-9, False)):
+        p3 = np.array([[1, 2], [0, 2], [0, 1]])
+        got = pkg.screen_lists(3, p3, [s_jk, 0.2, 0.3])
+        assert got["close"].tolist() == [[0, 1], [0, 2], [1, 2]]
+        assert (len(got["trimers"]) == 1) == keep == weak.keep_trimer(0.3, 0.2, s_jk)
+    # a weak side removes the trimer whatever the mean
+    got = pkg.screen_lists(3, np.array([[0, 1], [0, 2], [1, 2]]), [0.9, 0.9, 5e-3])
+    assert len(got["trimers"]) == 0 and got["weak"].tolist() == [[1, 2]]
+
+
+def test_screen_lists_water40u_against_oracle(pkg):
+    """Every pair of the 160-LMO lattice with its s2b from the oracle: the
+    library's classes, close and weak lists and kept trimers equal the
+    oracle's brute-force screening exactly."""
+    prob = synth.config(1)
+    ora = oracle.Oracle(prob)
+    n = prob.n_occ
+    iu = np.triu_indices(n, 1)
+    pairs = np.stack(iu, 1).astype(np.int32)
+    s = np.array([weak.s2b(ora, int(i), int(j)) for i, j in pairs])
+    out = pkg.screen_lists(n, pairs[:, ::-1], s)  # either orientation accepted
+    close, wk, tris = weak.screened_lists(n, {(int(i), int(j)): v for (i, j), v in zip(pairs, s)})
+    assert [tuple(x) for x in out["close"].tolist()] == close
+    assert [tuple(x) for x in out["weak"].tolist()] == wk
+    assert [tuple(x) for x in out["trimers"].tolist()] == tris
+    assert len(close) > 0 and len(wk) > 0 and 0 < len(tris) < 10000
+
+
+def test_screen_lists_errors(pkg):
+    lib = pkg._lib.load()
+    with pytest.raises(pkg.Mbe3Error):
+        pkg.screen_lists(3, np.array([[0, 1], [1, 0]]), [0.5, 0.5])  # repeated
+    with pytest.raises(pkg.Mbe3Error):
+        pkg.screen_lists(3, np.array([[0, 3]]), [0.5])  # out of range
+    with pytest.raises(pkg.Mbe3Error):
+        pkg.screen_lists(3, np.array([[1, 1]]), [0.5])  # same orbital
+    with pytest.raises(pkg.Mbe3Error):
+        pkg.screen_lists(3, np.array([[0, 1]]), [np.nan])
+    assert "not finite" in lib.mbe3_last_error(None).decode()
+    out = pkg.screen_lists(4, np.zeros((0, 2)), [])
+    assert len(out["close"]) == len(out["weak"]) == len(out["trimers"]) == 0
