@@ -275,9 +275,11 @@ def recorded_run(m, prob, args, dev, grad, label, steps=None, warmup=None, **kw)
     e_eager = e.clone()
     log(f"bench: {label} eager step E={E_eager:.12f} ({t_first:.1f} s with planning)")
     t0 = time.perf_counter()
-    report = h.autotune(reps=2, dB=grad, gamma=gamma, K=K)
+    tuned = None
+    if not args.no_autotune:
+        report = h.autotune(reps=2, dB=grad, gamma=gamma, K=K)
+        tuned = tune_choices(report)
     t_tune = time.perf_counter() - t0
-    tuned = tune_choices(report)
     log(f"bench: {label} autotune {t_tune:.1f} s")
     E_t = step()
     torch.cuda.synchronize()
@@ -326,13 +328,15 @@ def phase_report(prob, h, res, grad, iters):
     n_aux, n_vir = prob.n_aux, prob.n_vir
     d2 = np.diff(h.k_off).astype(np.float64)   # d_s^2 per slot
     pair_d = prob.r[prob.pairs].sum(1) if len(prob.pairs) else np.zeros(1, np.int64)
-    wide = int((pair_d.max() + 15) // 16 * 16) > 96  # some chunk on the wide solver
+    # some chunk on the global-workspace solver (padded pair dimension above
+    # the LDS-resident solver's 128)
+    wide = int((pair_d.max() + 15) // 16 * 16) > 128
     sum_diag, sum_pair = float(d2[:prob.n_occ].sum()), float(d2[prob.n_occ:].sum())
     work = {
         "regen": ("alu", float(prob.n_occ) * n_vir * n_aux),
         "project": ("mfma", 2.0 * n_vir * n_aux * float(h.layout.gamma_rows)),
         "pair_K": ("mfma", 2.0 * n_aux * (sum_diag + sum_pair)),
-        # with gradients the LDS-resident solver (pair dimensions up to 96)
+        # with gradients the LDS-resident solver (pair dimensions up to 128)
         # runs its gradient pass as its own launch, timed in "grad" with the
         # multiplier and dE/df reductions; the wide one inside "solve"
         "solve": ("mfma", solve_flops(prob, iters, grad=grad and wide)),
@@ -535,6 +539,9 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the split-precision (bf16) comparison runs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes (counter runs: the "
+                         "solver's counters do not depend on them)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device copy (a reference kernel "
                          "of known traffic for counter calibration)")

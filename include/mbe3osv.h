@@ -100,6 +100,7 @@ extern "C" {
 /* Output selector of mbe3_backward. */
 #define MBE3_GRAD_SLAB 0  /* dE/d(ia|P), [n_occ][n_vir][n_aux]               */
 #define MBE3_GRAD_GAMMA 1 /* dE/dG, osv_project's layout                     */
+#define MBE3_GRAD_PROBE 2 /* <dE/dB, Delta> and <dE/dB, B>, no dense dE/dB  */
 
 typedef struct mbe3_handle mbe3_handle;
 
@@ -240,18 +241,42 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
  *   layout (fragment_solve's multipliers, or any d_s x d_s blocks G_s / 4
  *   for pairs and G_s / 2 for diagonal slots to back-propagate dE/dK = G).
  * mode MBE3_GRAD_SLAB: out = dE dE/dB, device [n_occ][n_vir][n_aux];
- *   MBE3_GRAD_GAMMA: out = dE dE/dG (G_{i,x} = Q_x^T B_i), gamma layout.
+ *   MBE3_GRAD_GAMMA: out = dE dE/dG (G_{i,x} = Q_x^T B_i), gamma layout;
+ *   MBE3_GRAD_PROBE: directional derivatives without the dense dE/dB (at
+ *   1024 LMOs it would take hundreds of GB): the probe direction
+ *     Delta_i[a][P] = w_ia w_iP z'(i, a, P),
+ *   z' the Box-Muller normal of the Philox4x64-10 block at counter
+ *   (P, a, i, 0) under key (seed, 10) (the slab's own generator with key
+ *   word 1 = 10 instead of 0), is regenerated and projected into out
+ *   (gamma layout, workspace, must not alias gamma; receives Q_x^T Delta_i),
+ *   and probe[0] = dE <dE/dB, Delta> = <dE dE/dG, Q^T Delta>,
+ *   probe[1] = dE <dE/dB, B> (the Euler sum below).  Needs an FP64 handle
+ *   with regenerated slabs and a host probe[2]; synchronises the stream.
  *   out_elems: doubles available at out.
  * dEdF: device [n_occ][n_occ] or NULL: dE (g + g^T) / 2 from the last
  *   fragment_solve that received W (MBE3_EINVAL if there was none).
- * probe: host double or NULL: receives <out_G, G> with out_G = dE dE/dG
- *   (summed in double-double).  E is homogeneous of degree 4 in the slabs,
+ * probe: host double or NULL (modes 0, 1): receives <out_G, G> with
+ *   out_G = dE dE/dG (summed in double-double).  E is homogeneous of
+ *   degree 4 in the slabs,
  *   so at exact convergence this is 4 E dE; the difference is of the order
  *   of the residual left at tol.  Synchronises the stream.
  */
 int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
                   const double *W, int mode, double *out, int64_t out_elems,
                   double *dEdF, double *probe);
+
+/*
+ * mbe3_set_slab_shift -- from the next call on, osv_project regenerates the
+ * shifted slabs B + t Delta (Delta the probe direction of MBE3_GRAD_PROBE),
+ * so that a central difference (E(t) - E(-t)) / 2t of the whole forward
+ * checks probe[0] along the same direction.  t = 0 restores B bit for bit.
+ * While t != 0 the other calls that regenerate slabs (mbe3_fit_metric,
+ * mbe3_project_fit, mbe3_pair_K_fit, mbe3_rosv) return MBE3_EINVAL.
+ * Needs an FP64 handle with regenerated slabs (MBE3_EINVAL otherwise, and
+ * for a non-finite t or while recording); releases a recorded graph, whose
+ * launches carry the old shift.  Synchronises the stream.
+ */
+int mbe3_set_slab_shift(mbe3_handle *h, double t);
 
 /*
  * mbe3_energy -- E = sum_i E_i + sum_ij dE_ij + sum_ijk dE_ijk with
@@ -330,6 +355,39 @@ int mbe3_screen_lists(int32_t n_occ, const int32_t *pairs, int64_t n, const doub
                       double t_distant, double t_close, double t_trimer, int8_t *cls,
                       int32_t *close_pairs, int64_t *n_close, int32_t *weak_pairs,
                       int64_t *n_weak, int32_t *trimers, int64_t tri_cap, int64_t *n_tri);
+
+/*
+ * Occupied-orbital localization (section on occupied orbital localization,
+ * Alg. 2, eq. loc_theta): Pipek-Mezey with Jacobi sweeps on Loewdin charges.
+ * No handle.  From symmetrically orthonormalized MO coefficients
+ * C~ (device [n_ao][n_occ], orthonormal columns) and the atom of every AO
+ * (host ao_off[n_atom + 1]: AOs of atom A are ao_off[A] .. ao_off[A+1]-1,
+ * ao_off[0] = 0, ao_off[n_atom] = n_ao):
+ *   P^A_ij = sum_{alpha in A} C~_{alpha i} C~_{alpha j},
+ * then sweeps over the pairs i < j in order:
+ *   a_ij = sum_A (P^A_ij)^2 - (P^A_ii - P^A_jj)^2 / 4,
+ *   b_ij = sum_A P^A_ij (P^A_ii - P^A_jj),
+ *   4 theta = atan2(b_ij, -a_ij)  (the maximizer of sum_{i,A} (P^A_ii)^2
+ *                                  over the pair rotation),
+ * and, when |sin theta| >= 1e-10, the increment
+ * sqrt(a^2 + b^2)(1 - cos 4 theta) is added to the sweep's sum and the
+ * columns i, j of U and both orbital indices of every P^A are rotated
+ * (i' = cos i + sin j, j' = cos j - sin i).  Sweeps repeat while the last
+ * sweep's sum exceeds l_loc (the paper's 1e-3), at most max_sweeps.
+ * Outputs: P device [n_occ][n_occ][n_atom] (element (i, j, A) at
+ * (i n_occ + j) n_atom + A): the charges of the localized orbitals; U device
+ * [n_occ][n_occ] row-major: the localized orbitals are C~ U; dL and
+ * rotations host [max_sweeps] (nullable): each sweep's sum and rotation
+ * count; *sweeps (host) the sweeps run.  One workgroup runs the sweeps (the
+ * pairs are sequential: each rotation changes what the next pair reads).
+ * Allocates two small device buffers per call and synchronises `stream`.
+ * MBE3_EINVAL for bad sizes or offsets (message from mbe3_last_error(NULL)),
+ * MBE3_ENOCONV when max_sweeps end above l_loc (outputs valid),
+ * MBE3_ENONFINITE for a non-finite increment.
+ */
+int mbe3_pm_localize(const double *C, const int32_t *ao_off, int32_t n_ao, int32_t n_occ,
+                     int32_t n_atom, double l_loc, int32_t max_sweeps, double *P, double *U,
+                     double *dL, int32_t *rotations, int32_t *sweeps, void *stream);
 
 /*
  * Weak pairs (the weak-pair part of Algorithm 7): energies of pairs left

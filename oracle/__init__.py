@@ -28,11 +28,12 @@ OSV rotations, homogeneity and the Euler identity, and central finite
 differences.
 """
 from .mbe3 import (Oracle, gradient, energy, fragment_gradient,
-                   mbe3_coefficients, mbe3_energy, orbs, run, slab, swap_blocks)
+                   mbe3_coefficients, mbe3_energy, orbs, probe_direction, run, slab,
+                   swap_blocks)
 from .philox import box_muller, philox4x64_10
 from . import fit, weak
 
 __all__ = ["Oracle", "gradient", "energy", "fragment_gradient",
            "mbe3_coefficients", "mbe3_energy",
-           "orbs", "run", "slab", "swap_blocks", "box_muller",
+           "orbs", "probe_direction", "run", "slab", "swap_blocks", "box_muller",
            "philox4x64_10", "fit", "weak"]

@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import math
 import os
+from collections import OrderedDict
 from typing import Dict, Iterable, Optional, Sequence, Tuple
 
 import numpy as np
@@ -30,6 +31,7 @@ import numpy as np
 from .philox import box_muller, philox4x64_10
 
 STREAM_SLAB = 0
+STREAM_PROBE = 10
 
 
 # --------------------------------------------------------------------------
@@ -49,17 +51,29 @@ def slab(prob, i: int, cols=None, impl: str = "c") -> np.ndarray:
     The two agree bit for bit on the Philox words and to 4 ulp on the slab
     (pinned in the test-suite).
     """
+    return _weighted_normals(prob, i, STREAM_SLAB, cols, impl)
+
+
+def probe_direction(prob, i: int, cols=None, impl: str = "c") -> np.ndarray:
+    """Delta_i[a,P] = z'(seed,i,a,P) * w_ia[i,a] * w_iP[i,P]: the direction
+    along which the gradient is probed, the slab's own definition with key
+    (seed, 10) in place of (seed, 0), so that it has the slab's scale and
+    its normals are independent of the slab's."""
+    return _weighted_normals(prob, i, STREAM_PROBE, cols, impl)
+
+
+def _weighted_normals(prob, i, stream, cols, impl):
     nv = prob.n_vir
     P = np.arange(prob.n_aux) if cols is None else np.asarray(cols)
     if impl == "c":
         from . import _clib
-        return _clib.normal_slab((prob.seed, STREAM_SLAB), i, nv, P,
+        return _clib.normal_slab((prob.seed, stream), i, nv, P,
                                  prob.w_ia[i], prob.w_iP[i])
     ctr = np.zeros((nv, len(P), 4), dtype=np.uint64)
     ctr[..., 0] = P.astype(np.uint64)[None, :]
     ctr[..., 1] = np.arange(nv, dtype=np.uint64)[:, None]
     ctr[..., 2] = np.uint64(i)
-    w = philox4x64_10(ctr, (prob.seed, STREAM_SLAB))
+    w = philox4x64_10(ctr, (prob.seed, stream))
     z = box_muller(w[..., 0], w[..., 1])
     return (z * prob.w_ia[i][:, None]) * prob.w_iP[i][P][None, :]
 
@@ -81,21 +95,50 @@ def swap_blocks(M: np.ndarray, ra: int, rb: int) -> np.ndarray:
     return out
 
 
+class _Bounded(OrderedDict):
+    """A dict that forgets its least recently used entries beyond ``cap``
+    (None: unbounded).  Only memory changes: a forgotten value is computed
+    again, by the same arithmetic, when asked for."""
+
+    def __init__(self, cap=None, init=None):
+        super().__init__(init or {})
+        self.cap = cap
+
+    def __getitem__(self, k):
+        v = super().__getitem__(k)
+        self.move_to_end(k)
+        return v
+
+    def __setitem__(self, k, v):
+        super().__setitem__(k, v)
+        self.move_to_end(k)
+        if self.cap is not None:
+            while len(self) > self.cap:
+                super().__delitem__(next(iter(self)))
+
+
 class Oracle:
     """All intermediates of the hot path for one Problem.
 
     ``slabs``: optional explicit {i: B_i} replacing the regenerated slabs
-    (used for derivative checks along a perturbed slab).
+    (used for derivative checks along a perturbed slab).  ``max_slabs`` /
+    ``max_gammas`` (optional) bound how many regenerated slabs and projected
+    blocks stay cached (for workloads whose slabs do not fit in host
+    memory); explicit slabs are always kept.
     """
 
-    def __init__(self, prob, slabs: Optional[Dict[int, np.ndarray]] = None):
+    def __init__(self, prob, slabs: Optional[Dict[int, np.ndarray]] = None,
+                 max_slabs: Optional[int] = None, max_gammas: Optional[int] = None):
         self.prob = prob
         self.f = np.asarray(prob.f_occ, dtype=np.float64)
         self.eps = np.asarray(prob.eps_vir, dtype=np.float64)
         self.Q = prob.Q
         self.r = [int(x) for x in prob.r]
-        self._slabs = dict(slabs) if slabs is not None else {}
-        self._gamma: Dict[Tuple[int, int], np.ndarray] = {}
+        if slabs is not None:
+            self._slabs = dict(slabs)
+        else:
+            self._slabs = _Bounded(max_slabs)
+        self._gamma = _Bounded(max_gammas)
         self._S: Dict[Tuple[int, int], np.ndarray] = {}
         self._F: Dict[Tuple[int, int], np.ndarray] = {}
         self._K: Dict[Tuple[int, int], np.ndarray] = {}

@@ -14,16 +14,16 @@ import numpy as np
 
 from . import _lib
 from ._lib import (MBE3_EHIP, MBE3_EINVAL, MBE3_ENOCONV, MBE3_ENOMEM,
-                   MBE3_ENONFINITE, MBE3_FP64, MBE3_GRAD_GAMMA, MBE3_GRAD_SLAB,
-                   MBE3_MIXED_BF16, MBE3_MIXED_BF16_PROJ, MBE3_OK, Mbe3Error)
+                   MBE3_ENONFINITE, MBE3_FP64, MBE3_GRAD_GAMMA, MBE3_GRAD_PROBE,
+                   MBE3_GRAD_SLAB, MBE3_MIXED_BF16, MBE3_MIXED_BF16_PROJ, MBE3_OK, Mbe3Error)
 
 __all__ = ["Mbe3", "Mbe3Error", "osv_project", "pair_K", "fragment_solve",
            "mbe3_energy", "mbe3_backward", "mbe3_pair_basis", "energy_fn",
            "MBE3_OK", "MBE3_EINVAL", "MBE3_ENOMEM", "MBE3_EHIP",
            "MBE3_ENOCONV", "MBE3_ENONFINITE", "MBE3_GRAD_SLAB",
-           "MBE3_GRAD_GAMMA", "MBE3_FP64", "MBE3_MIXED_BF16",
+           "MBE3_GRAD_GAMMA", "MBE3_GRAD_PROBE", "MBE3_FP64", "MBE3_MIXED_BF16",
            "MBE3_MIXED_BF16_PROJ", "L_FIT", "screen_lists",
-           "S2B_DISTANT", "S2B_CLOSE", "S3B_KEEP"]
+           "S2B_DISTANT", "S2B_CLOSE", "S3B_KEEP", "pm_localize", "L_LOC"]
 
 
 def _f64(t):
@@ -156,19 +156,29 @@ class Mbe3:
         """dE * dE/d(slab) (mode MBE3_GRAD_SLAB, [n_occ, n_vir, n_aux]) or
         dE * dE/dGamma (MBE3_GRAD_GAMMA, gamma layout) into ``out``, and
         dE * dE/df_occ into ``dEdF`` when given.  Returns (out, probe) with
-        probe = <dE dE/dGamma, Gamma> (host float) if requested."""
+        probe = <dE dE/dGamma, Gamma> (host float) if requested.  Mode
+        MBE3_GRAD_PROBE: ``out`` (gamma layout) receives the projected probe
+        direction and probe = (dE <dE/dB, Delta>, dE <dE/dB, B>)."""
         import torch
         if out is None:
             shape = ((self.n_occ, self.n_vir, self.n_aux) if mode == MBE3_GRAD_SLAB
                      else (int(self.layout.gamma_elems),))
             out = torch.empty(shape, dtype=torch.float64, device=self.device)
-        pr = np.zeros(1, dtype=np.float64)
+        if mode == MBE3_GRAD_PROBE:
+            probe = True
+        pr = np.zeros(2, dtype=np.float64)
         _lib.check(_lib.load().mbe3_backward(
             self._h, float(dE), _lib.ptr(_f64(gamma)), _lib.ptr(_f64(W)),
             int(mode), _lib.ptr(_f64(out)), out.numel(),
             _lib.ptr(None if dEdF is None else _f64(dEdF)),
             _lib.ptr(pr) if probe else None), self._h)
+        if mode == MBE3_GRAD_PROBE:
+            return out, (float(pr[0]), float(pr[1]))
         return out, (float(pr[0]) if probe else None)
+
+    def set_slab_shift(self, t):
+        """osv_project regenerates B + t Delta from the next call on."""
+        _lib.check(_lib.load().mbe3_set_slab_shift(self._h, float(t)), self._h)
 
     def mbe3_pair_basis(self):
         import torch
@@ -430,6 +440,37 @@ def energy_fn(h, slab, f_occ):
 
 # sparse fitting threshold of the paper's sparsity table (eq. sparse_fit_metric)
 L_FIT = 1e-6
+
+
+L_LOC = 1e-3  # the paper's localization threshold
+
+
+def pm_localize(C, ao_off, l_loc=L_LOC, max_sweeps=100, stream=None, check=True):
+    """Pipek-Mezey localization with Jacobi sweeps (mbe3_pm_localize) of the
+    orthonormalized MO coefficients C (float64 CUDA tensor [n_ao, n_occ])
+    with the AOs of atom A at ao_off[A] .. ao_off[A+1]-1 (host ints).
+    Returns dict(U [n_occ, n_occ], P [n_occ, n_occ, n_atom] (device), dL
+    and rotations per sweep, sweeps, status)."""
+    import torch
+    lib = _lib.load()
+    C = _f64(C)
+    off = np.ascontiguousarray(ao_off, dtype=np.int32)
+    n_ao, n_occ = int(C.shape[0]), int(C.shape[1])
+    n_atom = len(off) - 1
+    P = torch.empty((n_occ, n_occ, n_atom), dtype=torch.float64, device=C.device)
+    U = torch.empty((n_occ, n_occ), dtype=torch.float64, device=C.device)
+    dL = np.zeros(max(int(max_sweeps), 1), dtype=np.float64)
+    rot = np.zeros(max(int(max_sweeps), 1), dtype=np.int32)
+    ns = np.zeros(1, dtype=np.int32)
+    if stream is None:
+        stream = torch.cuda.current_stream(C.device)
+    rc = lib.mbe3_pm_localize(_lib.ptr(C), _lib.ptr(off), n_ao, n_occ, n_atom, float(l_loc),
+                              int(max_sweeps), _lib.ptr(P), _lib.ptr(U), _lib.ptr(dL),
+                              _lib.ptr(rot), _lib.ptr(ns), ctypes.c_void_p(stream.cuda_stream))
+    if check:
+        _lib.check(rc, None)
+    k = int(ns[0])
+    return dict(U=U, P=P, dL=dL[:k].copy(), rotations=rot[:k].copy(), sweeps=k, status=rc)
 
 
 S2B_DISTANT, S2B_CLOSE, S3B_KEEP = 1e-7, 1e-2, 0.2  # the paper's thresholds

@@ -24,6 +24,7 @@ MBE3_MIXED_BF16 = 1
 MBE3_MIXED_BF16_PROJ = 2
 MBE3_GRAD_SLAB = 0
 MBE3_GRAD_GAMMA = 1
+MBE3_GRAD_PROBE = 2
 
 EXPORTS = [
     "mbe3_create", "mbe3_destroy", "mbe3_last_error", "mbe3_get_layout",
@@ -34,7 +35,8 @@ EXPORTS = [
     "mbe3_graph_launch", "mbe3_autotune", "mbe3_set_gemm_shape",
     "mbe3_tune_report", "mbe3_screen", "mbe3_weak_pairs", "mbe3_fit_metric",
     "mbe3_fit_mask", "mbe3_project_fit", "mbe3_pair_K_fit", "mbe3_first_order_dE",
-    "mbe3_screen_lists", "mbe3_rosv",
+    "mbe3_screen_lists", "mbe3_rosv", "mbe3_pm_localize",
+    "mbe3_set_slab_shift",
 ]
 GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128", "96x96"]
 PHASES = ["regen", "project", "pair_K", "bases", "pairs", "cross", "solve",
@@ -112,6 +114,9 @@ def load():
         "mbe3_project_fit": [vp, vp, ctypes.c_double, vp, i64],
         "mbe3_pair_K_fit": [vp, vp, ctypes.c_double, vp, i64],
         "mbe3_first_order_dE": [vp, vp, vp, vp, vp, vp],
+        "mbe3_set_slab_shift": [vp, ctypes.c_double],
+        "mbe3_pm_localize": [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp],
         "mbe3_rosv": [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp],
         "mbe3_screen_lists": [ctypes.c_int32, vp, i64, vp, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, vp, vp, vp, vp, vp, vp, i64, vp],

@@ -86,6 +86,7 @@ struct mbe3_handle {
   std::vector<int64_t> q_off;
   const double *Q = nullptr, *eps = nullptr, *f = nullptr;
   const double *w_ia = nullptr, *w_iP = nullptr, *slab = nullptr;
+  double slab_shift = 0.0;  // osv_project regenerates B + slab_shift * Delta
   uint64_t seed = 0;
   std::vector<std::array<int, 2>> pairs;
   std::vector<std::array<int, 3>> frags;
@@ -854,13 +855,34 @@ int build_plans(mbe3_handle *h) {
     const int nf = h->frags[m][2] >= 0 ? 3 : (h->frags[m][1] >= 0 ? 2 : 1);
     cost[m] = c * c * c * (nf == 3 ? 18 : (nf == 2 ? 4 : 1));
   }
+  // the largest padded pair dimension among a fragment's slots: it picks the
+  // solver kernel and its register / LDS layout for the whole chunk
+  std::vector<int> fdim(h->frags.size());
+  for (size_t m = 0; m < h->frags.size(); ++m) {
+    const auto &o = h->frags[m];
+    int d = 16;
+    for (int a = 0; a < 3; ++a) {
+      if (o[a] < 0) continue;
+      d = std::max(d, h->sD[o[a]]);
+      for (int b = a + 1; b < 3; ++b)
+        if (o[b] >= 0) d = std::max(d, h->sD[slot_of(h, o[a], o[b])]);
+    }
+    fdim[m] = d;
+  }
+  // solver class of a fragment: the four-wave instances take every fragment
+  // up to 80-wide pair domains (one chunk's instance is sized by its widest
+  // fragment); each width above that has its own eight-wave instance, so
+  // one class per width
+  auto fclass = [&](int m) { return fdim[m] <= 80 ? 0 : fdim[m]; };
   std::vector<int> order(h->frags.size());
   for (size_t m = 0; m < order.size(); ++m) order[m] = (int)m;
-  // heavy first; with warm starts every monomer and dimer comes before the
-  // trimers (their solutions seed the trimers' pairs)
+  // with warm starts every monomer and dimer comes before the trimers (their
+  // solutions seed the trimers' pairs); then by class, widest first, so
+  // that each chunk holds one class; heavy first inside a class
   auto is_tri = [&](int m) { return h->frags[m][2] >= 0; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     if (h->warm_start && is_tri(a) != is_tri(b)) return !is_tri(a);
+    if (fclass(a) != fclass(b)) return fclass(a) > fclass(b);
     return cost[a] > cost[b];
   });
 
@@ -919,8 +941,9 @@ int build_plans(mbe3_handle *h) {
           need += (dt * ds + dt * Ds + 2 * Dt * Ds) * 8;
         }
     }
-    const bool phase_change = h->warm_start && nf == 3 && !cur.frag_ids.empty() &&
-                              !is_tri(cur.frag_ids.back());
+    const bool phase_change = !cur.frag_ids.empty() &&
+                              ((h->warm_start && nf == 3 && !is_tri(cur.frag_ids.back())) ||
+                               fclass(m) != fclass(cur.frag_ids.back()));
     if (!cur.frag_ids.empty() &&
         ((ca_total + cm_total + st1_total) * 8 + need > CHUNK_BUDGET || phase_change)) {
       if ((rc = flush())) return rc;
@@ -1677,9 +1700,9 @@ int build_grad_plans(mbe3_handle *h) {
   if ((rc = dev_alloc(h, &h->ga, h->ga_total))) return rc;
   if ((rc = dev_alloc(h, &h->dg, h->gamma_rows * na))) return rc;
   if ((rc = dev_alloc(h, &h->dot_part, 2LL * dot_partials()))) return rc;
-  if ((rc = dev_alloc(h, &h->d_probe, 1))) return rc;
+  if ((rc = dev_alloc(h, &h->d_probe, 2))) return rc;
   if (!h->dry)
-    HIP_TRY(h, hipHostMalloc((void **)&h->h_probe, sizeof(double)));
+    HIP_TRY(h, hipHostMalloc((void **)&h->h_probe, 2 * sizeof(double)));
   h->grad_planned = true;
   return MBE3_OK;
 }
@@ -1937,6 +1960,67 @@ int mbe3_screen_lists(int32_t n_occ, const int32_t *pairs, int64_t n, const doub
   return MBE3_OK;
 }
 
+// Pipek-Mezey localization with Jacobi sweeps (Alg. 2): no handle; errors
+// through mbe3_last_error(NULL).
+int mbe3_pm_localize(const double *C, const int32_t *ao_off, int32_t n_ao, int32_t n_occ,
+                     int32_t n_atom, double l_loc, int32_t max_sweeps, double *P, double *U,
+                     double *dL, int32_t *rotations, int32_t *sweeps, void *stream) {
+  auto fail = [](int code, const char *msg) {
+    g_create_error = msg;
+    return code;
+  };
+  if (!C || !ao_off || !P || !U || !sweeps)
+    return fail(MBE3_EINVAL, "mbe3_pm_localize: C, ao_off, P, U and sweeps are required");
+  if (n_ao < 1 || n_occ < 1 || n_atom < 1 || max_sweeps < 1 || std::isnan(l_loc))
+    return fail(MBE3_EINVAL, "mbe3_pm_localize: sizes and max_sweeps must be positive");
+  if (ao_off[0] != 0 || ao_off[n_atom] != n_ao)
+    return fail(MBE3_EINVAL, "mbe3_pm_localize: ao_off must run from 0 to n_ao");
+  for (int A = 0; A < n_atom; ++A)
+    if (ao_off[A + 1] < ao_off[A])
+      return fail(MBE3_EINVAL, "mbe3_pm_localize: ao_off must not decrease");
+  hipStream_t st = (hipStream_t)stream;
+  int32_t *d_off = nullptr;
+  double *d_rec = nullptr;
+  auto release = [&] {
+    if (d_off) (void)hipFree(d_off);
+    if (d_rec) (void)hipFree(d_rec);
+  };
+  std::vector<double> rec((size_t)2 * max_sweeps + 1, 0.0);
+  hipError_t e = hipMalloc((void **)&d_off, sizeof(int32_t) * ((size_t)n_atom + 1));
+  if (e == hipSuccess) e = hipMalloc((void **)&d_rec, sizeof(double) * rec.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(MBE3_ENOMEM, "mbe3_pm_localize: device allocation failed");
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_off, ao_off, sizeof(int32_t) * ((size_t)n_atom + 1),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_pm_charges(C, d_off, n_occ, n_atom, P, st);
+  if (e == hipSuccess) e = launch_pm_jacobi(P, U, n_occ, n_atom, l_loc, max_sweeps, d_rec, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rec.data(), d_rec, sizeof(double) * rec.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  release();
+  if (e != hipSuccess) {
+    static thread_local char buf[256];
+    snprintf(buf, sizeof buf, "mbe3_pm_localize: %s", hipGetErrorString(e));
+    return fail(MBE3_EHIP, buf);
+  }
+  const int ns = (int)rec[2 * (size_t)max_sweeps];
+  *sweeps = ns;
+  for (int k = 0; k < ns; ++k) {
+    if (dL) dL[k] = rec[2 * (size_t)k];
+    if (rotations) rotations[k] = (int32_t)rec[2 * (size_t)k + 1];
+  }
+  if (ns > 0 && !std::isfinite(rec[2 * (size_t)(ns - 1)]))
+    return fail(MBE3_ENONFINITE, "mbe3_pm_localize: non-finite increment");
+  if (ns > 0 && rec[2 * (size_t)(ns - 1)] > l_loc)
+    return fail(MBE3_ENOCONV, "mbe3_pm_localize: max_sweeps reached above l_loc");
+  g_create_error = "ok";
+  return MBE3_OK;
+}
+
 int mbe3_destroy(mbe3_handle *h) {
   if (!h) return MBE3_EINVAL;
   if (h->recording) {
@@ -2019,7 +2103,7 @@ int osv_project(mbe3_handle *h, double *gamma, int64_t gamma_elems) {
     if (!h->slab) {
       PhaseScope ps_(h, MBE3_PHASE_REGEN);
       HIP_TRY(h, launch_regen_slab(h->slab_buf, i0, i1 - i0, h->n_vir, h->n_aux,
-                                   h->seed, h->w_ia, h->w_iP, s));
+                                   h->seed, h->w_ia, h->w_iP, 1.0, h->slab_shift, s));
     }
     PhaseScope ps_(h, MBE3_PHASE_PROJECT);
     HIP_TRY(h, launch_list(h, h->L_proj[k], b, s));
@@ -2104,17 +2188,23 @@ int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
     // layout; the scratch stride is the handle's (sized for the largest)
     a.dmax = c.dmax;
     if (c.dmax <= SOLVE_LDS_DMAX) {
-      // persistent grid: as many workgroups as fit on the 256 CUs at once
-      const int per_cu = (int)std::max<size_t>(
-          1, std::min<size_t>(4, (160 * 1024) / (solve_lds_bytes(c.dmax) + 2048)));
+      // persistent grid: as many workgroups as are resident on the 256 CUs
+      // at once (registers and LDS of the instance), so that no workgroup
+      // starts after others have finished their share
+      int per_cu = 0, per_cu_g = 0;
+      HIP_TRY(h, solve_blocks_per_cu(a, W ? 1 : 0, &per_cu));
+      per_cu = std::max(1, per_cu);
       const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu);
       {
         PhaseScope ps_(h, MBE3_PHASE_SOLVE);
         HIP_TRY(h, launch_solve(a, nwg, s));
       }
       if (W) {  // dE/df contractions and Y~ at the converged amplitudes
+        HIP_TRY(h, solve_blocks_per_cu(a, 2, &per_cu_g));
+        per_cu_g = std::max(1, per_cu_g);
+        const int nwg_g = std::min(std::min(SOLVE_WG, c.n_frag), 256 * per_cu_g);
         PhaseScope ps_(h, MBE3_PHASE_GRAD);
-        HIP_TRY(h, launch_solve_grad(a, nwg, s));
+        HIP_TRY(h, launch_solve_grad(a, nwg_g, s));
       }
     } else {
       const int nwg = std::min(std::min(SOLVE_WG, c.n_frag), 256);
@@ -2153,7 +2243,7 @@ int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
                   double *dEdF, double *probe) {
   if (!h) return MBE3_EINVAL;
   if (!gamma || !W || !out) return h->fail(MBE3_EINVAL, "gamma, W and out required");
-  if (mode != MBE3_GRAD_SLAB && mode != MBE3_GRAD_GAMMA)
+  if (mode != MBE3_GRAD_SLAB && mode != MBE3_GRAD_GAMMA && mode != MBE3_GRAD_PROBE)
     return h->fail(MBE3_EINVAL, "unknown gradient mode %d", mode);
   if (!std::isfinite(dE)) return h->fail(MBE3_EINVAL, "dE is not finite");
   const int64_t na = h->n_aux;
@@ -2164,12 +2254,19 @@ int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
                    (long long)out_elems);
   if (dEdF && !(h->recording ? h->rec_grad : h->grad_ready))
     return h->fail(MBE3_EINVAL, "dE/df needs a preceding successful fragment_solve with W");
+  if (mode == MBE3_GRAD_PROBE) {
+    if (!probe) return h->fail(MBE3_EINVAL, "MBE3_GRAD_PROBE needs probe[2]");
+    if (h->precision != MBE3_FP64 || h->slab)
+      return h->fail(MBE3_EINVAL, "MBE3_GRAD_PROBE needs an FP64 handle with regenerated slabs");
+    if (out == gamma) return h->fail(MBE3_EINVAL, "MBE3_GRAD_PROBE: out must not be gamma");
+  }
   if (probe && h->recording)
     return h->fail(MBE3_EINVAL, "the probe is read on the host: not available while recording");
   int rc = no_throw(h, [&] { return build_grad_plans(h); });
   if (rc) return rc;
   hipStream_t s = h->stream;
   double *dgam = mode == MBE3_GRAD_GAMMA ? out : h->dg;
+  const int64_t gel = h->gamma_rows * na;
   {
     PhaseScope ps_(h, MBE3_PHASE_BACKWARD);
     GemmBases b = bases(h);
@@ -2183,16 +2280,54 @@ int mbe3_backward(mbe3_handle *h, double dE, const double *gamma,
     if (mode == MBE3_GRAD_SLAB)
       HIP_TRY(h, launch_list(h, h->L_up, b, s));
     if (dEdF) HIP_TRY(h, launch_fsym(h->graw, h->n_occ, dE, dEdF, s));
-    if (probe)
-      HIP_TRY(h, launch_dot(dgam, gamma, h->gamma_rows * na, 1.0, h->dot_part,
-                            h->d_probe, s));
+  }
+  if (mode == MBE3_GRAD_PROBE) {
+    // <dE/dB, Delta> = sum_{i,x} <dE/dG_{i,x}, Q_x^T Delta_i>: Delta is
+    // regenerated and projected into out with osv_project's own lists
+    GemmBases b = bases(h);
+    b.p[B_GAMMA] = out;
+    for (size_t k = 0; k < h->proj_batches.size(); ++k) {
+      const int i0 = h->proj_batches[k].first, i1 = h->proj_batches[k].second;
+      {
+        PhaseScope ps_(h, MBE3_PHASE_REGEN);
+        HIP_TRY(h, launch_regen_slab(h->slab_buf, i0, i1 - i0, h->n_vir, h->n_aux, h->seed,
+                                     h->w_ia, h->w_iP, 0.0, 1.0, s));
+      }
+      PhaseScope ps_(h, MBE3_PHASE_BACKWARD);
+      HIP_TRY(h, launch_list(h, h->L_proj[k], b, s));
+    }
+    PhaseScope ps_(h, MBE3_PHASE_BACKWARD);
+    HIP_TRY(h, launch_dot(dgam, out, gel, 1.0, h->dot_part, h->d_probe, s));
+    HIP_TRY(h, launch_dot(dgam, gamma, gel, 1.0, h->dot_part, h->d_probe + 1, s));
+    HIP_TRY(h, hipMemcpyAsync(h->h_probe, h->d_probe, 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    probe[0] = h->h_probe[0];
+    probe[1] = h->h_probe[1];
+    return MBE3_OK;
   }
   if (probe) {
+    {
+      PhaseScope ps_(h, MBE3_PHASE_BACKWARD);
+      HIP_TRY(h, launch_dot(dgam, gamma, gel, 1.0, h->dot_part, h->d_probe, s));
+    }
     HIP_TRY(h, hipMemcpyAsync(h->h_probe, h->d_probe, sizeof(double),
                               hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     *probe = *h->h_probe;
   }
+  return MBE3_OK;
+}
+
+int mbe3_set_slab_shift(mbe3_handle *h, double t) {
+  if (!h) return MBE3_EINVAL;
+  if (!std::isfinite(t)) return h->fail(MBE3_EINVAL, "shift is not finite");
+  if (h->recording) return h->fail(MBE3_EINVAL, "the shift cannot change while recording");
+  if (t != 0.0 && (h->precision != MBE3_FP64 || h->slab))
+    return h->fail(MBE3_EINVAL, "a slab shift needs an FP64 handle with regenerated slabs");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  release_graph(h);  // its regeneration launches carry the old shift
+  h->slab_shift = t;
   return MBE3_OK;
 }
 
@@ -2392,6 +2527,8 @@ static int weak_body(mbe3_handle *h, const int32_t *pairs, int64_t n, const doub
 
 int mbe3_fit_metric(mbe3_handle *h, double *s_fit) {
   if (!h) return MBE3_EINVAL;
+  if (h->slab_shift != 0.0)
+    return h->fail(MBE3_EINVAL, "a slab shift is set: only osv_project regenerates B + t Delta");
   if (!s_fit) return h->fail(MBE3_EINVAL, "s_fit required");
   PhaseScope ps_(h, MBE3_PHASE_REGEN);
   HIP_TRY(h, launch_fit_metric(s_fit, h->n_occ, h->n_vir, h->n_aux, h->seed, h->w_ia,
@@ -2473,6 +2610,8 @@ static int fit_domains(mbe3_handle *h, const double *s_fit, double l_fit,
 // kernel (eq. osv_imua).
 static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, double *gamma,
                             int64_t gamma_elems) {
+  if (h->slab_shift != 0.0)
+    return h->fail(MBE3_EINVAL, "a slab shift is set: only osv_project regenerates B + t Delta");
   if (h->recording)
     return h->fail(MBE3_EINVAL, "mbe3_project_fit allocates: not recordable");
   if (!s_fit || !gamma) return h->fail(MBE3_EINVAL, "s_fit and gamma required");
@@ -2564,6 +2703,8 @@ static int project_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, d
 // gathers of the grouped-GEMM engine).
 static int pair_k_fit_body(mbe3_handle *h, const double *s_fit, double l_fit, double *K,
                            int64_t k_elems) {
+  if (h->slab_shift != 0.0)
+    return h->fail(MBE3_EINVAL, "a slab shift is set: only osv_project regenerates B + t Delta");
   if (h->recording)
     return h->fail(MBE3_EINVAL, "mbe3_pair_K_fit allocates: not recordable");
   if (!s_fit || !K) return h->fail(MBE3_EINVAL, "s_fit and K required");
@@ -2724,6 +2865,8 @@ static constexpr int64_t ROSV_BUDGET = 8LL << 30;  // bytes of T per batch
 static int rosv_body(mbe3_handle *h, const double *s_fit, double l_fit, double l_osv,
                      int n_max, double *Q_out, double *w_out, int32_t *n_osv,
                      int32_t *rows_out) {
+  if (h->slab_shift != 0.0)
+    return h->fail(MBE3_EINVAL, "a slab shift is set: only osv_project regenerates B + t Delta");
   if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_rosv allocates: not recordable");
   if (!Q_out || !w_out || !n_osv || !rows_out)
     return h->fail(MBE3_EINVAL, "Q_out, w_out, n_osv and rows required");

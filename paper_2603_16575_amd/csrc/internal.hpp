@@ -58,9 +58,14 @@ hipError_t launch_gemm_tasks(const GemmTask *d_tasks, int n_tasks,
 // ---------------------------------------------------------------------------
 // Slab regeneration (regen.hip)
 // ---------------------------------------------------------------------------
+// Philox key word 1 of the gradient probe direction Delta (key word 1 of the
+// slab itself is 0).
+constexpr uint64_t PROBE_STREAM = 10;
+// out[b][a][P] = w_ia w_iP (cb z_0 + cd z_10) for i = i0 + b: the slab
+// (cb = 1, cd = 0), the probe direction (0, 1) or B + t Delta (1, t).
 hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia,
-                             const double *w_iP, hipStream_t s);
+                             const double *w_iP, double cb, double cd, hipStream_t s);
 
 // Sparse fitting metric s_fit[i][P] = sum_a B_i[a][P]^2 of the regenerated
 // (slab == nullptr) or given slabs, and the restriction of gamma-layout rows
@@ -101,6 +106,15 @@ hipError_t launch_rosv_finalize(const double *evals, int D, const double *Qr,
                                 const int32_t *rows, int i0, int nb, int n_max, int n_vir,
                                 double l_osv, double *Q_out, double *w_out, int32_t *n_osv,
                                 int32_t *rows_out, hipStream_t s);
+
+// Pipek-Mezey localization (loc.hip): Loewdin charges P[(i n + j) na + A]
+// from orthonormalized MO coefficients C [n_ao][n] with the AOs of atom A at
+// ao_off[A] .. ao_off[A+1]-1 (device), and the Jacobi sweeps of one
+// workgroup (rec: 2 doubles per sweep, then the sweep count).
+hipError_t launch_pm_charges(const double *C, const int32_t *ao_off, int n, int na, double *P,
+                             hipStream_t s);
+hipError_t launch_pm_jacobi(double *P, double *U, int n, int na, double l_loc, int max_sweeps,
+                            double *rec, hipStream_t s);
 
 // Split-precision operands (regen.hip): three bf16 planes (bit patterns),
 // plane stride ps elements, rows padded with zeros to ldk (a multiple of 8).
@@ -276,7 +290,10 @@ hipError_t launch_solve_grad(const SolveArgs &a, int n_wg, hipStream_t s);
 // (which must hold 4 ny + 2 dmax^2 doubles, as solve_scratch_doubles gives).
 hipError_t launch_solve_wide(const SolveArgs &a, int n_wg, hipStream_t s);
 size_t solve_wide_lds_bytes(int dmax);
-constexpr int SOLVE_LDS_DMAX = 96;  // largest dmax of the LDS-resident solver
+constexpr int SOLVE_LDS_DMAX = 128;  // largest dmax of the LDS-resident solver
+// Resident workgroups per CU of the solver instance a chunk with a.dmax
+// runs (mode 0 solve, 1 solve and store, 2 gradient pass).
+hipError_t solve_blocks_per_cu(const SolveArgs &a, int mode, int *per_cu);
 int64_t solve_scratch_doubles(int ny_max, int dmax);
 size_t solve_lds_bytes(int dmax);
 

@@ -34,10 +34,16 @@ __device__ __forceinline__ double box_muller(uint64_t w0, uint64_t w1) {
   return sqrt(-2.0 * log(u1)) * cos((2.0 * M_PI) * u2);
 }
 
+// Element (a, P) of LMO i: w_ia w_iP (cb z_0 + cd z_10), z_s the normal of
+// the Philox block at counter (P, a, i, 0) under key (seed, s).  cb = 1,
+// cd = 0 gives the slab B itself (bit for bit w_ia w_iP z_0); cb = 0, cd = 1
+// the gradient probe direction Delta (stream 10); cb = 1, cd = t the shifted
+// slab B + t Delta of a finite-difference check.  cb and cd are uniform over
+// the launch, so the skipped draw is a uniform branch.
 __global__ __launch_bounds__(256) void regen_slab_kernel(
     double *__restrict__ out, int i0, int nb, int n_vir, int n_aux,
     uint64_t seed, const double *__restrict__ w_ia,
-    const double *__restrict__ w_iP) {
+    const double *__restrict__ w_iP, double cb, double cd) {
   const int64_t per = (int64_t)n_vir * n_aux;
   const int64_t total = per * nb;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -47,9 +53,18 @@ __global__ __launch_bounds__(256) void regen_slab_kernel(
     const int a = (int)(r / n_aux);
     const int P = (int)(r - (int64_t)a * n_aux);
     const int i = i0 + b;
-    uint64_t c0 = (uint64_t)P, c1 = (uint64_t)a, c2 = (uint64_t)i, c3 = 0;
-    philox4x64_10(c0, c1, c2, c3, seed, 0ull);
-    const double z = box_muller(c0, c1);
+    double z = 0.0;
+    if (cb != 0.0) {
+      uint64_t c0 = (uint64_t)P, c1 = (uint64_t)a, c2 = (uint64_t)i, c3 = 0;
+      philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+      z = box_muller(c0, c1);
+      if (cb != 1.0) z *= cb;
+    }
+    if (cd != 0.0) {
+      uint64_t c0 = (uint64_t)P, c1 = (uint64_t)a, c2 = (uint64_t)i, c3 = 0;
+      philox4x64_10(c0, c1, c2, c3, seed, (uint64_t)PROBE_STREAM);
+      z += cd * box_muller(c0, c1);
+    }
     out[e] = (z * w_ia[(int64_t)i * n_vir + a]) * w_iP[(int64_t)i * n_aux + P];
   }
 }
@@ -199,13 +214,13 @@ hipError_t launch_split_rows_fixed(const double *x, int64_t rows, int cols, int6
 
 hipError_t launch_regen_slab(double *out, int i0, int nb, int n_vir, int n_aux,
                              uint64_t seed, const double *w_ia,
-                             const double *w_iP, hipStream_t s) {
+                             const double *w_iP, double cb, double cd, hipStream_t s) {
   const int64_t total = (int64_t)n_vir * n_aux * nb;
   if (total <= 0) return hipSuccess;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(regen_slab_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                     out, i0, nb, n_vir, n_aux, seed, w_ia, w_iP);
+                     out, i0, nb, n_vir, n_aux, seed, w_ia, w_iP, cb, cd);
   return hipGetLastError();
 }
 

@@ -31,7 +31,9 @@
 // of Y^T (16 rows of it) is read as 16-column strips of Y's rows and
 // transposed on its way into LDS, and the residual reads Y^T elements
 // straight from Y, so each sweep writes its amplitudes once, coalesced.  LDS per workgroup is
-// D_max^2 + 32 D_max doubles, so two fragments share a CU.  A diagonal pair's
+// D_max^2 + 32 D_max doubles (16 D_max at D_max = 128, one Y buffer): two
+// fragments share a CU up to 80-wide domains (four waves each), one above
+// (eight waves, each owning one row block).  A diagonal pair's
 // mirror terms f S~ Y S~^T and its transpose are formed once and symmetrised
 // through LDS.
 // Sweep 0 has T = 0, so R~ = K~ needs no product.  All pair blocks are zero
@@ -63,12 +65,34 @@ struct SlotLds {
   int32_t D, ysub, sym, wgt;
 };
 
-// Workgroup sum in a fixed order (wave shuffles, then the four waves).
+// Sum / max of the per-wave partials r[0 .. N) as a fixed tree: the first
+// half (the largest power of two below N) and the rest, recursively.
+template <int N>
+__device__ __forceinline__ double wave_tree_sum(const double *r) {
+  if constexpr (N == 1) {
+    return r[0];
+  } else {
+    constexpr int H = N > 4 ? 4 : (N > 2 ? 2 : 1);
+    return wave_tree_sum<H>(r) + wave_tree_sum<N - H>(r + H);
+  }
+}
+template <int N>
+__device__ __forceinline__ double wave_tree_max(const double *r) {
+  if constexpr (N == 1) {
+    return r[0];
+  } else {
+    constexpr int H = N > 4 ? 4 : (N > 2 ? 2 : 1);
+    return fmax(wave_tree_max<H>(r), wave_tree_max<N - H>(r + H));
+  }
+}
+
+// Workgroup sum in a fixed order (wave shuffles, then the waves' tree).
+template <int NW>
 __device__ __forceinline__ double wg_sum(double v, double *red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  const double s = wave_tree_sum<NW>(red);
   __syncthreads();
   return s;
 }
@@ -89,8 +113,8 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
       {                                                                        \
         d2 *s_ = reinterpret_cast<d2 *>(Sl + 16 * mp * Dt);                    \
         d2 *y_ = reinterpret_cast<d2 *>(yb);                                   \
-        _Pragma("unroll") for (int u = 0; u < MAXNT; ++u) {                    \
-          const int e = tid + 256 * u;                                         \
+        _Pragma("unroll") for (int u = 0; u < PFN; ++u) {                      \
+          const int e = tid + NTH * u;                                         \
           if (e < p_n1) {                                                      \
             s_[e] = pf[u];                                                     \
           } else if (e - p_n1 < p_n2) {                                        \
@@ -114,7 +138,7 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
       _Pragma("unroll") for (int mm = 0; mm < 4; ++mm) {                       \
         const int ml = 4 * mm + lq;                                            \
         _Pragma("unroll") for (int rb = 0; rb < MAXRB; ++rb) {                 \
-          const int ib = wave + 4 * rb;                                        \
+          const int ib = wave + NW * rb;                                       \
           if (ib < nT) {                                                       \
             const double bv = STp[ml * Dt + ib * 16 + l16];                    \
             _Pragma("unroll") for (int kb = 0; kb < MAXNT; ++kb)               \
@@ -123,13 +147,15 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
           }                                                                    \
         }                                                                      \
       }                                                                        \
+      /* one Y buffer: the next panel's store waits for these reads */        \
+      if (!DBY) __syncthreads();                                               \
     }                                                                          \
     _Pragma("unroll") for (int kp = 0; kp < MAXNT; ++kp) {                     \
       if (kp < nS) {                                                           \
         _Pragma("unroll") for (int v = 0; v < 4; ++v) {                        \
           const double *brow = Sl + (kp * 16 + 4 * v + lq) * Dt + l16;         \
           _Pragma("unroll") for (int rb = 0; rb < MAXRB; ++rb) {               \
-            const int ib = wave + 4 * rb;                                      \
+            const int ib = wave + NW * rb;                                     \
             if (ib < nT) {                                                     \
               const double av = (COEF) * W[rb][kp][v];                         \
               _Pragma("unroll") for (int jb = 0; jb < MAXNT; ++jb)             \
@@ -150,13 +176,16 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
 // store then receives Y~ = 2Y - Y^T for the multipliers.  Fragments that did
 // not converge (iters < 0) are skipped.  Keeping the pass out of the solving
 // launch keeps its registers out of the iterations.
-template <int MAXNT, int MODE>
-__global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
+template <int MAXNT, int MODE, int NW>
+__global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(SolveArgs a) {
   constexpr bool ST = MODE == 1, GP = MODE == 2;
   extern __shared__ double lds[];
-  constexpr int MAXRB = (MAXNT + 3) / 4;  // row blocks per wave
-  __shared__ double red_d[8];
-  __shared__ int red_i[8];
+  constexpr int NTH = 64 * NW;                   // threads per workgroup
+  constexpr int MAXRB = (MAXNT + NW - 1) / NW;   // row blocks per wave
+  constexpr int PFN = (4 * MAXNT + NW - 1) / NW;  // panel slots per thread
+  constexpr bool DBY = MAXNT <= 7;               // two Y panel buffers
+  __shared__ double red_d[2 * NW];
+  __shared__ int red_i[NW];
   __shared__ TermLds tc[MAX_FRAG_TERMS];
   __shared__ SlotLds sc[6];
   const int tid = threadIdx.x;
@@ -168,13 +197,13 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
   // Y^(T) rows stream through two 16-row buffers.
   double *const Sl = lds;
   double *const yb0 = lds + (int64_t)a.dmax * a.dmax;
-  double *const yb1 = yb0 + 16 * a.dmax;
+  double *const yb1 = DBY ? yb0 + 16 * a.dmax : yb0;
 
   double *scr = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
   const int64_t ny_cap = (a.scratch_stride - 2LL * a.dmax * a.dmax) / 4;
   double *const Y0 = scr;  // two buffers of ny_cap (current, next)
 
-  d2 pf[MAXNT];  // next panel: S~ rows then Y^(T) rows
+  d2 pf[PFN];  // next panel: S~ rows then Y^(T) rows
 
   for (int fi = blockIdx.x; fi < a.n_frag; fi += gridDim.x) {
     const FragDesc *__restrict__ fdp = a.frags + fi;
@@ -225,7 +254,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         double *wy = Y0 + ny_cap + sc[tl].ysub;
         double *yd = Y0 + 2 * ny_cap + sc[tl].ysub;
         double part = 0.0;
-        for (int e = tid; e < D * D; e += 256) {
+        for (int e = tid; e < D * D; e += NTH) {
           const int i = e / D, j = e - i * D;
           const double yv = y[e], yt = y[(int64_t)j * D + i];
           const double ytil = 2.0 * yv - yt;
@@ -233,7 +262,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           if (sy) yd[e] = ytil;
           part += ytil * yv;
         }
-        const double tot = wg_sum(part, red_d);  // also orders the wy writes
+        const double tot = wg_sum<NW>(part, red_d);  // also orders the wy writes
         if (tid == 0) a.gdiag[6 * fi + tl] = tot;
       }
       hasY = true;
@@ -270,8 +299,8 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
     p_n1 = 8 * dt_;                                                            \
     p_n2 = 8 * ds_;                                                            \
     p_tr = tm_.trans != 0;                                                     \
-    _Pragma("unroll") for (int u = 0; u < MAXNT; ++u) {                        \
-      const int e = tid + 256 * u;                                             \
+    _Pragma("unroll") for (int u = 0; u < PFN; ++u) {                          \
+      const int e = tid + NTH * u;                                             \
       if (e < p_n1) {                                                          \
         pf[u] = st_[e];                                                        \
       } else if (e - p_n1 < p_n2) {                                            \
@@ -312,7 +341,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
               double part = 0.0;
 #pragma unroll
               for (int rb = 0; rb < MAXRB; ++rb) {
-                const int ib = wave + 4 * rb;
+                const int ib = wave + NW * rb;
 #pragma unroll
                 for (int jb = 0; jb < MAXNT; ++jb) {
                   if (ib < nT && jb < nT) {
@@ -325,7 +354,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
                   acc[rb][jb] = d4{0.0, 0.0, 0.0, 0.0};
                 }
               }
-              const double tot = wg_sum(part, red_d);
+              const double tot = wg_sum<NW>(part, red_d);
               if (tid == 0) a.gterm[ti] = tot;
             }
           }
@@ -337,7 +366,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           __syncthreads();  // S~ of the last term is no longer read
 #pragma unroll
           for (int rb = 0; rb < MAXRB; ++rb) {
-            const int ib = wave + 4 * rb;
+            const int ib = wave + NW * rb;
             if (ib < nT) {
 #pragma unroll
               for (int jb = 0; jb < MAXNT; ++jb)
@@ -361,7 +390,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
         const double w = (double)sl.wgt;
 #pragma unroll
         for (int rb = 0; rb < MAXRB; ++rb) {
-          const int ib = wave + 4 * rb;
+          const int ib = wave + NW * rb;
           if (ib < nT) {
 #pragma unroll
             for (int jb = 0; jb < MAXNT; ++jb) {
@@ -398,7 +427,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           const int D = sc[tl].D;
           const double *src = Y0 + (sc[tl].sym ? 2 : 1) * ny_cap + sc[tl].ysub;
           double *o = a.yfin + fdp->yout + sc[tl].ysub;
-          for (int e = tid; e < D * D; e += 256) o[e] = src[e];
+          for (int e = tid; e < D * D; e += NTH) o[e] = src[e];
         }
         __syncthreads();  // the scratch is read; the next fragment refills it
         break;
@@ -411,13 +440,15 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
       }
       if (lane == 0) {
         red_d[wave] = mres;
-        red_d[4 + wave] = epart;
+        red_d[NW + wave] = epart;
         red_i[wave] = bad;
       }
       __syncthreads();  // also orders this sweep's Y writes before the next
-      const double M = fmax(fmax(red_d[0], red_d[1]), fmax(red_d[2], red_d[3]));
-      const double E = (red_d[4] + red_d[5]) + (red_d[6] + red_d[7]);
-      const int B = red_i[0] | red_i[1] | red_i[2] | red_i[3];
+      const double M = wave_tree_max<NW>(red_d);
+      const double E = wave_tree_sum<NW>(red_d + NW);
+      int B = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) B |= red_i[w2];
       __syncthreads();
       const bool conv = M < a.tol;
       if (conv || B || it >= a.max_iter) {
@@ -434,7 +465,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
           // residual), so every trimer starts from defined values
           const SlotLds sl = sc[fdp->warm_out];
           const double *src = ysrc(fdp->warm_out);
-          for (int e = tid; e < sl.D * sl.D; e += 256)
+          for (int e = tid; e < sl.D * sl.D; e += NTH)
             a.warm[sl.kt_off + e] = hasY && !B ? src[e] : 0.0;
         }
         if (ST && conv && !B) {
@@ -444,7 +475,7 @@ __global__ __launch_bounds__(256, 2) void solve_kernel(SolveArgs a) {
             const int D = sc[tl].D;
             const double *src = ysrc(tl);
             double *dst = a.yfin + fdp->yout + sc[tl].ysub;
-            for (int e = tid; e < D * D; e += 256) dst[e] = hasY ? src[e] : 0.0;
+            for (int e = tid; e < D * D; e += NTH) dst[e] = hasY ? src[e] : 0.0;
           }
         }
         __syncthreads();  // the scratch is read; the next fragment refills it
@@ -464,43 +495,69 @@ int64_t solve_scratch_doubles(int ny_max, int dmax) {
   return 4LL * ny_max + 2LL * dmax * dmax;
 }
 
+// Waves per workgroup of the instance for chunks whose widest pair domain
+// has NT 16-row blocks: four up to 80-wide domains (two workgroups share a
+// CU), eight from 96 on, where the resident S~ block leaves room for one
+// workgroup per CU.  Measured on the 512- and 160-LMO lattices against one
+// wave per row block of the widest targets (five to eight waves): balanced
+// rows but fewer waves to hide the panel loads, 3% and 20% slower.
+template <int NT>
+constexpr int solve_waves() { return NT <= 5 ? 4 : 8; }
+
+// LDS of one workgroup: the resident S~ block and two 16-row Y panel
+// buffers, one for the 128-wide instance (two would not leave room).
 size_t solve_lds_bytes(int dmax) {
-  return (size_t)(dmax * dmax + 32 * dmax) * sizeof(double);
+  const int ybuf = dmax <= 112 ? 32 : 16;
+  return (size_t)(dmax * dmax + ybuf * dmax) * sizeof(double);
 }
 
-template <int NT, int MODE>
-static hipError_t launch_nt_g(const SolveArgs &a, int n_wg, hipStream_t s) {
+template <int NT, int MODE, int NW>
+static hipError_t launch_nt_g(const SolveArgs &a, int n_wg, hipStream_t s, int *per_cu) {
   const size_t smem = solve_lds_bytes(a.dmax);
-  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT, MODE>,
+  hipError_t e = hipFuncSetAttribute((const void *)solve_kernel<NT, MODE, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((solve_kernel<NT, MODE>), dim3(n_wg), dim3(256), smem, s, a);
+  if (per_cu)  // resident workgroups per CU for this instance
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, (const void *)solve_kernel<NT, MODE, NW>, 64 * NW, smem);
+  hipLaunchKernelGGL((solve_kernel<NT, MODE, NW>), dim3(n_wg), dim3(64 * NW), smem, s, a);
   return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t launch_mode(const SolveArgs &a, int n_wg, hipStream_t s) {
-  if (a.n_frag <= 0) return hipSuccess;
+static hipError_t launch_mode(const SolveArgs &a, int n_wg, hipStream_t s, int *per_cu) {
+  if (!per_cu && a.n_frag <= 0) return hipSuccess;
   if (solve_lds_bytes(a.dmax) > 150 * 1024) return hipErrorInvalidValue;
   switch (a.dmax / 16) {
     case 1:
-    case 2: return launch_nt_g<2, MODE>(a, n_wg, s);
-    case 3: return launch_nt_g<3, MODE>(a, n_wg, s);
-    case 4: return launch_nt_g<4, MODE>(a, n_wg, s);
-    case 5: return launch_nt_g<5, MODE>(a, n_wg, s);
-    case 6: return launch_nt_g<6, MODE>(a, n_wg, s);
+    case 2: return launch_nt_g<2, MODE, solve_waves<2>()>(a, n_wg, s, per_cu);
+    case 3: return launch_nt_g<3, MODE, solve_waves<3>()>(a, n_wg, s, per_cu);
+    case 4: return launch_nt_g<4, MODE, solve_waves<4>()>(a, n_wg, s, per_cu);
+    case 5: return launch_nt_g<5, MODE, solve_waves<5>()>(a, n_wg, s, per_cu);
+    case 6: return launch_nt_g<6, MODE, solve_waves<6>()>(a, n_wg, s, per_cu);
+    case 7: return launch_nt_g<7, MODE, solve_waves<7>()>(a, n_wg, s, per_cu);
+    case 8: return launch_nt_g<8, MODE, solve_waves<8>()>(a, n_wg, s, per_cu);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_solve(const SolveArgs &a, int n_wg, hipStream_t s) {
-  return a.yfin ? launch_mode<1>(a, n_wg, s) : launch_mode<0>(a, n_wg, s);
+  return a.yfin ? launch_mode<1>(a, n_wg, s, nullptr) : launch_mode<0>(a, n_wg, s, nullptr);
 }
 
 hipError_t launch_solve_grad(const SolveArgs &a, int n_wg, hipStream_t s) {
   if (!a.yfin || !a.gterm || !a.gdiag) return hipErrorInvalidValue;
-  return launch_mode<2>(a, n_wg, s);
+  return launch_mode<2>(a, n_wg, s, nullptr);
+}
+
+hipError_t solve_blocks_per_cu(const SolveArgs &a, int mode, int *per_cu) {
+  *per_cu = 0;
+  switch (mode) {
+    case 0: return launch_mode<0>(a, 0, nullptr, per_cu);
+    case 1: return launch_mode<1>(a, 0, nullptr, per_cu);
+    default: return launch_mode<2>(a, 0, nullptr, per_cu);
+  }
 }
 
 }  // namespace mbe3

@@ -73,6 +73,23 @@ def check_vs_oracle(m, prob, tol_rel):
     assert worst_f <= tol_rel
     assert probe == probe_g
     assert abs(probe - euler) <= tol_rel * abs(euler)
+    # probe mode: <dE/dB, Delta> against the oracle's dense gradient, the
+    # Euler sum bit for bit that of the other modes, and out = Q^T Delta
+    dD, (pr_d, pr_e) = h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_PROBE)
+    D = [oracle.probe_direction(prob, i) for i in range(prob.n_occ)]
+    dirn = sum(float(np.sum(D[i] * g["dB"][i])) for i in range(prob.n_occ))
+    scale = sum(float(np.sum(np.abs(D[i] * g["dB"][i]))) for i in range(prob.n_occ))
+    say(f"probe mode: <dE/dB, Delta> {pr_d:.15e} oracle {dirn:.15e} (sum |.| {scale:.3e})")
+    assert pr_e == probe
+    assert abs(pr_d - dirn) <= tol_rel * scale
+    oD = oracle.Oracle(prob, slabs={i: D[i] for i in range(prob.n_occ)})
+    dDn = dD.cpu().numpy().reshape(-1, prob.n_aux)
+    for i in range(prob.n_occ):
+        row = int(h.g_off[i])
+        for x in prob.neighbours(i):
+            rx = int(prob.r[x])
+            assert rel(dDn[row:row + rx], oD.gamma(i, int(x))) <= 1e-13
+            row += rx
     # un-projection of the GAMMA output reproduces the SLAB output
     dGn = dG.cpu().numpy().reshape(-1, prob.n_aux)
     for i in range(prob.n_occ):
@@ -98,6 +115,61 @@ def test_backward_micro_strong(m, n_occ):
     say(f"case: micro n_occ={n_occ} strong coupling backward vs oracle.gradient")
     prob = dataclasses.replace(strong(synth.micro(n_occ)), tol=1e-12, max_iter=300)
     check_vs_oracle(m, prob, 1e-10)
+
+
+def richardson_fd(h, t):
+    """(8 (E(t) - E(-t)) - (E(2t) - E(-2t))) / 12 t of the GPU forward along
+    the probe direction (slabs regenerated as B + s Delta)."""
+    E = {}
+    for k in (1, -1, 2, -2):
+        h.set_slab_shift(k * t)
+        E[k] = h.forward()["E"]
+    h.set_slab_shift(0.0)
+    return (8.0 * (E[1] - E[-1]) - (E[2] - E[-2])) / (12.0 * t)
+
+
+def test_probe_mode_fd_chain8(m):
+    """The probe mode's <dE/dB, Delta> against a fourth-order central
+    difference of the GPU energy along Delta (t = 1e-4 on slabs of the same
+    scale: truncation ~t^4, rounding ~1e-15 E / t); shift 0 gives the
+    unshifted energy back bit for bit."""
+    say("case: chain8 probe mode vs GPU central difference along Delta, tol 1e-12")
+    prob = dataclasses.replace(synth.config(0), tol=1e-12, max_iter=400)
+    h = m.from_problem(prob)
+    E_ref = h.forward()["E"]
+    out = h.forward(grad=True)
+    _, (pr_d, pr_e) = h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_PROBE)
+    fd = richardson_fd(h, 1e-4)
+    E0 = h.forward()["E"]
+    say(f"probe {pr_d:.12e} fd {fd:.12e} rel {abs(fd - pr_d) / abs(pr_d):.2e}")
+    assert E0 == E_ref
+    assert abs(fd - pr_d) <= 1e-8 * abs(pr_d)
+    assert abs(pr_e - 4.0 * out["E"]) <= 1e-9 * abs(out["E"])
+    h.close()
+
+
+def test_probe_mode_errors(m):
+    import torch
+    say("case: micro n_occ=3 probe mode and slab shift argument errors")
+    prob = synth.micro(3)
+    h = m.from_problem(prob)
+    out = h.forward(grad=True)
+    with pytest.raises(m.Mbe3Error):  # out aliasing gamma
+        h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_PROBE, out=out["gamma"])
+    with pytest.raises(m.Mbe3Error):
+        h.set_slab_shift(float("nan"))
+    h.set_slab_shift(1e-3)
+    s_fit = torch.empty((prob.n_occ, prob.n_aux), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(m.Mbe3Error):  # only osv_project takes the shift
+        h.fit_metric(s_fit)
+    h.set_slab_shift(0.0)
+    h.fit_metric(s_fit)
+    h.close()
+    hs = m.from_problem(prob, precision=m.MBE3_MIXED_BF16)
+    with pytest.raises(m.Mbe3Error):
+        hs.set_slab_shift(1e-3)
+    hs.set_slab_shift(0.0)
+    hs.close()
 
 
 def test_euler_identity_tight(m):

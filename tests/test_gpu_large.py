@@ -75,6 +75,43 @@ def test_large_pairs_energy_vs_oracle(m):
     h.close()
 
 
+def mid_micro():
+    """4 LMOs with 50-64 OSVs each: pair dimensions 100-128 (the eight-wave
+    LDS solver), diagonal 50-64."""
+    p = synth.micro(4, n_vir=192, n_aux=48, r=(50, 64))
+    return dataclasses.replace(strong(p), tol=1e-11, max_iter=300)
+
+
+def test_mid_pairs_energy_and_gradient_vs_oracle(m):
+    """Pair dimensions 100-128 (padded 112 / 128): energies, update counts
+    and the gradient (solve, store and gradient-pass instances) against the
+    oracle."""
+    import torch
+    say("case: micro n_occ=4, r 50-64 (D 112-128), strong coupling, vs oracle")
+    prob = mid_micro()
+    d = prob.r[prob.pairs[:, 0]] + prob.r[prob.pairs[:, 1]]
+    say(f"pair dims {sorted(set(int(x) for x in d))}")
+    assert 96 < d.max() <= 128
+    h = m.from_problem(prob, warm_start=False)
+    out = h.forward()
+    ref = oracle.run(prob)
+    e = out["e_frag"].cpu().numpy()
+    say(f"max |dE_F| = {np.abs(e - ref['e_frag']).max():.3e}")
+    assert np.abs(e - ref["e_frag"]).max() <= 1e-12
+    assert np.array_equal(out["iters"].cpu().numpy(), ref["iters"])
+    out = h.forward(grad=True)
+    dF = torch.empty((prob.n_occ, prob.n_occ), dtype=torch.float64, device="cuda:0")
+    dB, _ = h.mbe3_backward(out["gamma"], out["W"], dEdF=dF)
+    g = oracle.gradient(prob)
+    dBn = dB.cpu().numpy()
+    rb = max(float(np.abs(dBn[i] - g["dB"][i]).max() / np.abs(g["dB"][i]).max())
+             for i in range(prob.n_occ))
+    rf = float(np.abs(dF.cpu().numpy() - g["df"]).max() / np.abs(g["df"]).max())
+    say(f"dB rel {rb:.2e}, df rel {rf:.2e}")
+    assert rb <= 1e-10 and rf <= 1e-10
+    h.close()
+
+
 def test_large_pairs_backward_vs_oracle(m):
     import torch
     say("case: micro n_occ=4, r 56-80, backward vs oracle.gradient")
@@ -231,7 +268,9 @@ def test_helix1024_forward_and_gradient(m):
     every fragment converged and finite; projected blocks of the two LMOs
     with the most OSVs against the oracle on a subset of auxiliary columns;
     the gradient in the compressed (Gamma) layout, since a dense dE/d(ia|P)
-    would take 412 GB: Euler probe <dE/dGamma, Gamma> = 4 E, and dE/df_xy
+    would take 412 GB: Euler probe <dE/dGamma, Gamma> = 4 E, the probe
+    mode's <dE/dB, Delta> against a central difference of the GPU energy
+    along the regenerated direction Delta, and dE/df_xy
     against a central difference of the GPU energy (h = 1e-4: the difference
     E(+h) - E(-h) is ~6e-9 Eh against ~1e-14 Eh of rounding in E)."""
     import torch
@@ -262,10 +301,26 @@ def test_helix1024_forward_and_gradient(m):
                                 dEdF=dF, probe=True)
     say(f"helix1024: probe / 4E - 1 = {probe / (4 * E) - 1:.3e}")
     assert abs(probe / (4.0 * E) - 1.0) <= 1e-4
+    # directional derivative along the probe direction Delta (dG as the
+    # workspace for Q^T Delta), against a fourth-order central difference of
+    # the GPU energy with the slabs regenerated as B + s Delta
+    _, (pr_d, pr_e) = h.mbe3_backward(out["gamma"], out["W"], mode=m.MBE3_GRAD_PROBE,
+                                      out=dG)
+    assert pr_e == probe
     x, y = (int(v) for v in prob.pairs[len(prob.pairs) // 2])
     an = 2.0 * float(dF[x, y])
     del out, dG
     torch.cuda.empty_cache()
+    t = 1e-4
+    Ed = {}
+    for k in (1, -1, 2, -2):
+        h.set_slab_shift(k * t)
+        Ed[k] = h.forward()["E"]
+    h.set_slab_shift(0.0)
+    fd_d = (8.0 * (Ed[1] - Ed[-1]) - (Ed[2] - Ed[-2])) / (12.0 * t)
+    say(f"helix1024: <dE/dB, Delta> probe {pr_d:.10e} fd {fd_d:.10e} "
+        f"rel {abs(fd_d - pr_d) / abs(pr_d):.2e}")
+    assert abs(fd_d - pr_d) <= 1e-6 * abs(pr_d)
     step = 1e-4
     Es = []
     for sgn in (+1, -1):
