@@ -159,7 +159,9 @@ typedef struct mbe3_layout {
 
 /* Create a handle for problem *p on `stream` (hipStream_t).  Validates the
    lists (MBE3_EINVAL), builds the execution plans and allocates the
-   workspace (MBE3_ENOMEM).  *h is NULL on failure. */
+   workspace (MBE3_ENOMEM).  *h is NULL on failure.  The handle belongs to
+   the device current at this call: its workspace is allocated there,
+   `stream` must be that device's, and later calls on h expect it current. */
 int mbe3_create(mbe3_handle **h, const mbe3_problem *p, void *stream);
 /* Release the handle and its workspace (after finishing its stream). */
 int mbe3_destroy(mbe3_handle *h);
@@ -355,6 +357,26 @@ int mbe3_screen_lists(int32_t n_occ, const int32_t *pairs, int64_t n, const doub
                       double t_distant, double t_close, double t_trimer, int8_t *cls,
                       int32_t *close_pairs, int64_t *n_close, int32_t *weak_pairs,
                       int64_t *n_weak, int32_t *trimers, int64_t tri_cap, int64_t *n_tri);
+
+/*
+ * mbe3_screen without any allocation, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc / hipFree, tight
+ * serving loops, harnesses that forbid allocation): the same s2b values as
+ * mbe3_screen, bit for bit (same kernels, same order), with the task table,
+ * the pair table and the overlap blocks S_(i,j) held in a fixed scratch
+ * array of mbe3_screen_noalloc_max_bytes() bytes (64 MiB) inside the
+ * library, one per GPU, kept until the process ends.  A call needs about
+ * 8 sum_k r_i r_j bytes plus 200 bytes per pair; more than the array holds
+ * is refused with MBE3_EINVAL (split the pairs over several calls).  The
+ * host tables are copied on the handle's stream and the call synchronises
+ * it.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind; nothing in it needs to start at zero.  Calls that
+ * overlap on one GPU (another handle, another host thread) race.
+ * pairs: host [n][2] (two distinct LMOs each).  s2b: device [n].
+ * MBE3_EINVAL as mbe3_screen, or while recording.
+ */
+int mbe3_screen_noalloc(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b);
+int64_t mbe3_screen_noalloc_max_bytes(void);
 
 /*
  * Occupied-orbital localization (section on occupied orbital localization,

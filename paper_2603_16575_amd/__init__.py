@@ -200,6 +200,17 @@ class Mbe3:
                                            _lib.ptr(out)), self._h)
         return out
 
+    def screen_noalloc(self, pairs, out=None):
+        """screen() through mbe3_screen_noalloc (no device allocation in the
+        library; the caller passes the output tensor or one is made here)."""
+        import torch
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        if out is None:
+            out = torch.empty(len(pr), dtype=torch.float64, device=self.device)
+        _lib.check(_lib.load().mbe3_screen_noalloc(self._h, _lib.ptr(pr), len(pr),
+                                                   _lib.ptr(out)), self._h)
+        return out
+
     def weak_pairs(self, pairs, gamma, W):
         """Energies of weak pairs (host int array [n, 2], i < j) from
         osv_project's gamma and fragment_solve's multipliers W (their

@@ -35,7 +35,7 @@ EXPORTS = [
     "mbe3_graph_launch", "mbe3_autotune", "mbe3_set_gemm_shape",
     "mbe3_tune_report", "mbe3_screen", "mbe3_weak_pairs", "mbe3_fit_metric",
     "mbe3_fit_mask", "mbe3_project_fit", "mbe3_pair_K_fit", "mbe3_first_order_dE",
-    "mbe3_screen_lists", "mbe3_rosv", "mbe3_pm_localize",
+    "mbe3_screen_lists", "mbe3_screen_noalloc", "mbe3_rosv", "mbe3_pm_localize",
     "mbe3_set_slab_shift",
 ]
 GEMM_SHAPES = ["64x64", "128x128", "32x32", "32x128", "64x128", "96x96"]
@@ -114,6 +114,7 @@ def load():
         "mbe3_project_fit": [vp, vp, ctypes.c_double, vp, i64],
         "mbe3_pair_K_fit": [vp, vp, ctypes.c_double, vp, i64],
         "mbe3_first_order_dE": [vp, vp, vp, vp, vp, vp],
+        "mbe3_screen_noalloc": [vp, vp, i64, vp],
         "mbe3_set_slab_shift": [vp, ctypes.c_double],
         "mbe3_pm_localize": [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp],
@@ -129,6 +130,8 @@ def load():
     lib.mbe3_last_error.restype = ctypes.c_char_p
     lib.mbe3_tune_report.argtypes = [vp]
     lib.mbe3_tune_report.restype = ctypes.c_char_p
+    lib.mbe3_screen_noalloc_max_bytes.argtypes = []
+    lib.mbe3_screen_noalloc_max_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -135,6 +136,7 @@ struct mbe3_handle {
   double *d_coef = nullptr;
   int32_t *d_sub = nullptr;
   double *d_e3 = nullptr;
+  unsigned char *noalloc_scratch = nullptr;  // this device's copy of `scratch`
   double *h_e3 = nullptr;
   int32_t *d_rows = nullptr;
   SlotInfo *d_slots = nullptr;
@@ -1830,6 +1832,93 @@ static int no_throw(mbe3_handle *h, F &&f) {
 
 extern "C" {
 
+// ---- scratch of the allocation-free entry point (mbe3_screen_noalloc) ----
+// A fixed device array in the library's code object: every GPU the library
+// runs on holds its own copy until the process ends.  In host code the
+// array's name is not a device address; each device's address comes from
+// hipGetSymbolAddress (with that device current), once, and only that
+// address is ever handed to kernels or copies.
+static constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;  // 64 MiB
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static constexpr int SCRATCH_MAX_DEV = 64;
+static unsigned char *g_scratch_dev[SCRATCH_MAX_DEV];
+
+static int scratch_init(mbe3_handle *h) {
+  int dev = 0;
+  HIP_TRY(h, hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV)
+    return h->fail(MBE3_EINVAL, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    HIP_TRY(h, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = (unsigned char *)p;
+  }
+  h->noalloc_scratch = g_scratch_dev[dev];
+  return MBE3_OK;
+}
+
+static int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// mbe3_screen with every buffer (task table, pair table, overlap blocks) in
+// the device's scratch array instead of per-call allocations.
+static int screen_noalloc_body(mbe3_handle *h, const int32_t *pairs, int64_t n,
+                               double *s2b) {
+  if (h->recording) return h->fail(MBE3_EINVAL, "mbe3_screen_noalloc synchronises: not recordable");
+  if (!h->noalloc_scratch) return h->fail(MBE3_EINVAL, "scratch not initialised on this handle");
+  if (n < 0 || (n > 0 && (!pairs || !s2b)))
+    return h->fail(MBE3_EINVAL, "pairs and s2b required for n > 0");
+  if (n == 0) return MBE3_OK;
+  std::vector<WeakPair> wp;
+  std::vector<int64_t> p_off;
+  int64_t ko, to, po;
+  int rc = weak_layout(h, pairs, n, false, wp, &ko, &to, &po, p_off);
+  if (rc) return rc;
+  const int nv = h->n_vir;
+  std::vector<GemmTask> ts;
+  for (const WeakPair &w : wp)  // S_(i,j) = Q_i^T Q_j (rows of the packed Q)
+    ts.push_back(gemm(B_Q, h->q_off[w.i] * nv, nv, 0, B_Q, h->q_off[w.j] * nv, nv, 1,
+                      B_PS2, w.k_off, w.rj, w.ri, w.rj, nv));
+  const int64_t tiles = finish_tasks(ts, GEMM_32x32);
+  int64_t sz[B_COUNT];
+  base_sizes(h, sz);
+  sz[B_PS2] = ko;
+  if ((rc = check_gemm_list(h, "screen S (no alloc)", ts, sz, std::vector<int32_t>(),
+                            GEMM_32x32)))
+    return rc;
+  const int64_t off_wp = align256((int64_t)(ts.size() * sizeof(GemmTask)));
+  const int64_t off_s = align256(off_wp + n * (int64_t)sizeof(WeakPair));
+  const int64_t need = off_s + ko * (int64_t)sizeof(double);
+  if (need > (int64_t)SCRATCH_BYTES)
+    return h->fail(MBE3_EINVAL,
+                   "mbe3_screen_noalloc: %lld pairs need %lld bytes of scratch, the "
+                   "library holds %lld; pass fewer pairs per call",
+                   (long long)n, (long long)need, (long long)SCRATCH_BYTES);
+  hipStream_t st = h->stream;
+  GemmTask *d_ts = (GemmTask *)h->noalloc_scratch;
+  WeakPair *d_wp = (WeakPair *)(h->noalloc_scratch + off_wp);
+  double *S = (double *)(h->noalloc_scratch + off_s);
+  HIP_TRY(h, hipMemcpyAsync(d_ts, ts.data(), ts.size() * sizeof(GemmTask),
+                            hipMemcpyHostToDevice, st));
+  HIP_TRY(h, hipMemcpyAsync(d_wp, wp.data(), wp.size() * sizeof(WeakPair),
+                            hipMemcpyHostToDevice, st));
+  GemmBases b = bases(h);
+  b.p[B_PS2] = S;
+  HIP_TRY(h, launch_gemm_tasks(d_ts, (int)ts.size(), tiles, b, GEMM_32x32, st));
+  HIP_TRY(h, launch_s2b(d_wp, (int)n, S, s2b, st));
+  // the host tables stay alive until the copies have run
+  HIP_TRY(h, hipStreamSynchronize(st));
+  return MBE3_OK;
+}
+
+int mbe3_screen_noalloc(mbe3_handle *h, const int32_t *pairs, int64_t n, double *s2b) {
+  if (!h) return MBE3_EINVAL;
+  return no_throw(h, [&] { return screen_noalloc_body(h, pairs, n, s2b); });
+}
+
+int64_t mbe3_screen_noalloc_max_bytes(void) { return (int64_t)SCRATCH_BYTES; }
+
 int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
   if (!out) return MBE3_EINVAL;
   *out = nullptr;
@@ -1842,6 +1931,7 @@ int mbe3_create(mbe3_handle **out, const mbe3_problem *p, void *stream) {
     if (!r) r = build_plans(h);
     if (!r) r = alloc_workspace(h);
     if (!r) r = validate_plans(h);
+    if (!r) r = scratch_init(h);
     return r;
   });
   if (rc) {
