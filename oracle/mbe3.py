@@ -381,6 +381,16 @@ def _warm_T0(f, warm):
     return {(p, q): warm[(p, q)] for a, p in enumerate(o) for q in o[a:]}
 
 
+def _one_blas_thread():
+    """Pool workers each run one BLAS thread (the pool is the parallelism;
+    a BLAS pool per worker would oversubscribe the cores)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
 def _solve_chunk(args):
     frags, tol, max_iter, keep_T = args
     ora = _POOL_ORACLE
@@ -417,7 +427,7 @@ def _solve_list(ora, frags, tol, max_iter, keep_T, workers, warm):
     _POOL_ORACLE, _POOL_WARM = ora, warm
     chunks = np.array_split(np.arange(len(frags)), workers * 8)
     ctx = mp.get_context("fork")
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(workers, initializer=_one_blas_thread) as pool:
         parts = pool.map(_solve_chunk,
                          [(frags[c], tol, max_iter, keep_T) for c in chunks])
     _POOL_ORACLE, _POOL_WARM = None, None

@@ -127,6 +127,9 @@ struct mbe3_handle {
   int32_t *sflag = nullptr;  // per slot: overlap not safely positive definite
   double *eig_ws = nullptr;  // eigensolver workspace for orders beyond LDS
   int64_t eig_ws_doubles = 0;
+  double *cws = nullptr;     // records of the split Fock step (chase)
+  int64_t cws_doubles = 0;
+  int32_t *eig_meta = nullptr, *eig_redo = nullptr;
   double *at = nullptr, *mt = nullptr, *st0 = nullptr;
   double *ca = nullptr, *cm = nullptr, *st1 = nullptr;
   double *scratch = nullptr;
@@ -770,9 +773,14 @@ int build_plans(mbe3_handle *h) {
       EigTask a;
       a.a_off = h->k_off[s]; a.lda = d; a.n = d; a.D = D; a.slot = (int)s;
       a.o_off = h->x_off[s]; a.e_off = h->et_off[s];
+      a.w_off = -1;
       e0.push_back(a);
       EigTask b = a;
       b.a_off = h->kt_off[s]; b.lda = D; b.o_off = h->kt_off[s];
+      if (d <= eig_split_max_order()) {  // the Fock step's chase record
+        b.w_off = h->cws_doubles;
+        h->cws_doubles += eig_chase_ws_doubles(D);
+      }
       e1.push_back(b);
       // M1 = F X0 (d x D) -> tmp (x layout)
       m1.push_back(gemm(B_PF, h->k_off[s], d, 0, B_X0, h->x_off[s], D, 0, B_TMP,
@@ -1148,6 +1156,9 @@ int alloc_workspace(mbe3_handle *h) {
   if ((rc = dev_alloc(h, &h->ev0, h->et_off[h->n_slot]))) return rc;
   if ((rc = dev_alloc(h, &h->rank, h->n_slot))) return rc;
   if ((rc = dev_alloc(h, &h->sflag, h->n_slot))) return rc;
+  if ((rc = dev_alloc(h, &h->cws, h->cws_doubles))) return rc;
+  if ((rc = dev_alloc(h, &h->eig_meta, 4 * h->n_slot))) return rc;
+  if ((rc = dev_alloc(h, &h->eig_redo, h->n_slot))) return rc;
   if (h->warm_start && (rc = dev_alloc(h, &h->warm, h->kt_off[h->n_slot]))) return rc;
   {
     const int md = max_d(h), nl = eig_lds_max_order();
@@ -1228,9 +1239,9 @@ int prepare_bases(mbe3_handle *h) {
                            h->eig_ws_doubles, s));
   HIP_TRY(h, launch_list(h, h->L_m1, b, s));
   HIP_TRY(h, launch_list(h, h->L_fp, b, s));
-  HIP_TRY(h, launch_eigh(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
-                           h->rank, 1, h->tau_S, nullptr, h->eig_ws,
-                           h->eig_ws_doubles, s));
+  HIP_TRY(h, launch_eigh_split(h->d_eig1, (int)h->n_slot, md, h->fp, h->zb, h->et,
+                                 h->rank, h->cws, h->eig_meta, h->eig_redo, h->eig_ws,
+                                 h->eig_ws_doubles, s));
   HIP_TRY(h, launch_list(h, h->L_x, b, s));
   if (!h->recording) h->bases_done = true;  // replays do not set it
   return MBE3_OK;
@@ -1440,6 +1451,9 @@ int validate_plans(mbe3_handle *h) {
         if (t.lda < t.D || t.a_off + (int64_t)(t.D - 1) * t.lda + t.D - 1 >= sz[B_FP])
           return bad("eigen (F input)", k);
         if (t.o_off + (int64_t)t.D * t.D > sz[B_Z]) return bad("eigen (Z output)", k);
+        if (t.n <= eig_split_max_order() &&
+            (t.w_off < 0 || t.w_off + eig_chase_ws_doubles(t.D) > h->cws_doubles))
+          return bad("eigen (chase record)", k);
       }
     }
   }
@@ -3068,6 +3082,7 @@ static int rosv_body(mbe3_handle *h, const double *s_fit, double l_fit, double l
       e.o_off = (int64_t)k * Dq * Dq;
       e.e_off = (int64_t)k * Dq;
       e.slot = k;
+      e.w_off = -1;
       et.push_back(e);
     }
     int64_t *d_out_off = nullptr;

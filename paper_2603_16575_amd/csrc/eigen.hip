@@ -668,6 +668,403 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fock step (mode 1) in three launches.  In the fused kernel above the
+// implicit QR steps take most of the time: the Givens chase is a serial
+// chain of dependent FP64 operations, and while it runs the matrix Q holds
+// the LDS, so above order ~90 one chase runs per CU.  Split:
+//   house:  the Householder reduction and Q exactly as above (one wave per
+//           matrix, in LDS); Q goes to the output block (pitch D), d and e
+//           to the task's record;
+//   chase:  the same implicit QR steps on d and e alone (2 KB of LDS per
+//           wave, so chases fill the CU up to the wave limit), every step's
+//           sweep bounds (l, m) and rotations (c, s) appended to the record;
+//   apply:  Q back into LDS and the recorded rotations applied to its rows
+//           in order with the fused kernel's arithmetic (column k + 2
+//           loaded one rotation ahead, columns k, k + 1 carried in
+//           registers), then the fused kernel's ordering and outputs.
+// Record of a task (doubles at cws + w_off): d [D], e [D], sweep bounds
+// [SC(D)] (two int32 each), rotations [2 RC(D)].  Typical solves need about
+// 2n sweeps and 1.1 n^2 rotations; a task that would pass SC or RC is
+// marked in redo[] and solved by the fused kernel afterwards.
+// ---------------------------------------------------------------------------
+static constexpr int SPLIT_MAX_ORDER = 128;
+static __host__ __device__ inline int64_t chase_sc(int D) { return 4LL * D + 8; }
+static __host__ __device__ inline int64_t chase_rc(int D) { return 2LL * D * D; }
+
+int eig_split_max_order() { return SPLIT_MAX_ORDER; }
+int64_t eig_chase_ws_doubles(int D) { return 2LL * D + chase_sc(D) + 2 * chase_rc(D); }
+
+// The reduction and Q of tridiag_qr_kernel with four waves per matrix (the
+// LDS matrix allows one per CU): rows and columns spread over 256 threads,
+// the two wave sums of a step become workgroup sums.
+__global__ __launch_bounds__(256) void tridiag_house_kernel(
+    const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
+    double *__restrict__ out, const int32_t *__restrict__ rank, double *__restrict__ cws,
+    int n_lo, int n_hi) {
+  extern __shared__ double sm[];
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+    const EigTask t = tasks[ti];
+    const int n = rank[t.slot];
+    // tasks without a record (order above the split path's) run fused
+    if (t.w_off < 0 || n < n_lo || n > n_hi) continue;
+    const int D = t.D;
+    const int ld = qr_pitch(n);
+    double *const M = sm;
+    double *const dd = M + (size_t)n * ld;
+    double *const ee = dd + n;
+    double *const vv = ee + n;
+    double *const ww = vv + n;
+    double *const taus = ww + n;
+
+    for (int e = tid; e < n * n; e += 256) {
+      const int r = e / n, c = e - r * n;
+      M[r * ld + c] = in[t.a_off + (int64_t)r * t.lda + c];
+    }
+    __syncthreads();
+    // ---- Householder reduction (the steps of tridiag_qr_kernel) ----
+    for (int k = 0; k + 2 < n; ++k) {
+      double sig = 0.0;
+      for (int i = k + 2 + tid; i < n; i += 256) {
+        const double x = M[i * ld + k];
+        sig += x * x;
+      }
+      sig = block_sum(sig, red);
+      const double alpha = M[(k + 1) * ld + k];
+      double tk = 0.0, beta = alpha;
+      if (sig > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sig);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tk = (beta - alpha) / beta;
+        const double sc = 1.0 / (alpha - beta);
+        for (int i = k + 2 + tid; i < n; i += 256) {
+          const double v = M[i * ld + k] * sc;
+          M[i * ld + k] = v;
+          vv[i] = v;
+        }
+        if (tid == 0) vv[k + 1] = 1.0;
+      }
+      if (tid == 0) {
+        ee[k] = beta;
+        taus[k] = tk;
+        dd[k] = M[k * ld + k];
+      }
+      __syncthreads();
+      if (tk != 0.0) {
+        double pv = 0.0;
+        double pj = 0.0;
+        const int i = k + 1 + tid;
+        if (i < n) {
+          const double *row = M + i * ld;
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          int c = k + 1;
+          for (; c + 3 < n; c += 4) {
+            a0 += row[c] * vv[c];
+            a1 += row[c + 1] * vv[c + 1];
+            a2 += row[c + 2] * vv[c + 2];
+            a3 += row[c + 3] * vv[c + 3];
+          }
+          for (; c < n; ++c) a0 += row[c] * vv[c];
+          pj = tk * ((a0 + a1) + (a2 + a3));
+          pv = pj * vv[i];
+        }
+        const double kk = 0.5 * tk * block_sum(pv, red);
+        if (i < n) ww[i] = pj - kk * vv[i];
+        __syncthreads();
+        if (i < n) {
+          const double vi = vv[i], wi = ww[i];
+          double *row = M + i * ld;
+#pragma unroll 4
+          for (int c = k + 1; c < n; ++c) row[c] -= vi * ww[c] + wi * vv[c];
+        }
+        __syncthreads();
+      }
+    }
+    if (tid == 0 && n >= 1) {
+      if (n >= 2) {
+        dd[n - 2] = M[(n - 2) * ld + n - 2];
+        ee[n - 2] = M[(n - 1) * ld + n - 2];
+      }
+      dd[n - 1] = M[(n - 1) * ld + n - 1];
+      ee[n - 1] = 0.0;
+    }
+    __syncthreads();
+    // ---- Q in place, last reflector first ----
+    if (n >= 2) {
+      if (tid < 4) {
+        const int r = n - 2 + (tid >> 1), c = n - 2 + (tid & 1);
+        M[r * ld + c] = r == c ? 1.0 : 0.0;
+      }
+    } else if (n == 1 && tid == 0) {
+      M[0] = 1.0;
+    }
+    __syncthreads();
+    for (int k = n - 3; k >= 0; --k) {
+      for (int c = k + 2 + tid; c < n; c += 256) {
+        M[(k + 1) * ld + c] = 0.0;
+        M[c * ld + k + 1] = 0.0;
+      }
+      if (tid == 0) M[(k + 1) * ld + k + 1] = 1.0;
+      __syncthreads();
+      const double tk = taus[k];
+      if (tk != 0.0) {
+        for (int c = k + 1 + tid; c < n; c += 256) {  // one column per thread
+          double u0 = M[(k + 1) * ld + c], u1 = 0.0, u2 = 0.0, u3 = 0.0;
+          int i = k + 2;
+          for (; i + 3 < n; i += 4) {
+            u0 += M[i * ld + k] * M[i * ld + c];
+            u1 += M[(i + 1) * ld + k] * M[(i + 1) * ld + c];
+            u2 += M[(i + 2) * ld + k] * M[(i + 2) * ld + c];
+            u3 += M[(i + 3) * ld + k] * M[(i + 3) * ld + c];
+          }
+          for (; i < n; ++i) u0 += M[i * ld + k] * M[i * ld + c];
+          const double u = tk * ((u0 + u1) + (u2 + u3));
+          M[(k + 1) * ld + c] -= u;
+#pragma unroll 4
+          for (int i2 = k + 2; i2 < n; ++i2) M[i2 * ld + c] -= M[i2 * ld + k] * u;
+        }
+        __syncthreads();
+      }
+    }
+    if (n >= 2) {
+      for (int c = 1 + tid; c < n; c += 256) {
+        M[c] = 0.0;
+        M[c * ld] = 0.0;
+      }
+      if (tid == 0) M[0] = 1.0;
+    }
+    __syncthreads();
+    // ---- Q to the output block, d and e to the record ----
+    for (int e = tid; e < n * n; e += 256) {
+      const int r = e / n, c = e - r * n;
+      out[t.o_off + (int64_t)r * D + c] = M[r * ld + c];
+    }
+    double *const rec = cws + t.w_off;
+    for (int i = tid; i < n; i += 256) {
+      rec[i] = dd[i];
+      rec[D + i] = ee[i];
+    }
+    __syncthreads();  // the workspace is reused by the next task
+  }
+}
+
+__global__ __launch_bounds__(64) void tridiag_chase_kernel(
+    const EigTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ rank,
+    double *__restrict__ cws, int32_t *__restrict__ meta, int n_lo, int n_hi) {
+  __shared__ double dd[SPLIT_MAX_ORDER + 1], ee[SPLIT_MAX_ORDER + 1];
+  constexpr int RPL = (SPLIT_MAX_ORDER + 63) / 64;
+  const int lane = threadIdx.x;
+  for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+    const EigTask t = tasks[ti];
+    const int n = rank[t.slot];
+    // tasks without a record (order above the split path's) run fused
+    if (t.w_off < 0 || n < n_lo || n > n_hi) continue;
+    const int D = t.D;
+    double *const rec = cws + t.w_off;
+    int32_t *const bounds = reinterpret_cast<int32_t *>(rec + 2 * D);
+    double *const rot = rec + 2 * D + chase_sc(D);
+    const int64_t cap_s = chase_sc(D), cap_r = chase_rc(D);
+    for (int i = lane; i < n; i += 64) {
+      dd[i] = rec[i];
+      ee[i] = rec[D + i];
+    }
+    __syncthreads();
+    // ---- the implicit QR steps of tridiag_qr_kernel on d and e alone ----
+    constexpr double EPS = 2.220446049250313e-16;
+    int m = n - 1;
+    int steps = 0;
+    const int max_steps = 30 * n + 30;
+    int64_t ns = 0, nr = 0;
+    int ovf = 0;
+    while (m > 0 && steps < max_steps) {
+      int l = 0;
+#pragma unroll
+      for (int j = RPL - 1; j >= 0; --j) {
+        const int k = lane + 64 * j;
+        const bool neg =
+            k < m && fabs(ee[k]) <= EPS * (fabs(dd[k]) + fabs(dd[k + 1]));
+        const unsigned long long b = __ballot(neg);
+        if (l == 0 && b != 0ULL) l = 64 * j + 64 - __clzll((long long)b);
+      }
+      if (l == m) {
+        --m;
+        continue;
+      }
+      ++steps;
+      if (ns >= cap_s || nr + (m - l) > cap_r) {  // the record is full
+        ovf = 1;
+        break;
+      }
+      if (lane == 0) {
+        bounds[2 * ns] = l;
+        bounds[2 * ns + 1] = m;
+      }
+      ++ns;
+      const double dm1 = dd[m - 1], dm = dd[m], b = ee[m - 1];
+      const double del = 0.5 * (dm1 - dm);
+      const double hyp = sqrt(del * del + b * b);
+      const double mu = dm - b * b / (del + (del >= 0.0 ? hyp : -hyp));
+      double dk = dd[l], ek = ee[l];
+      double dk1 = dd[l + 1];
+      double ek1 = l + 1 < m ? ee[l + 1] : 0.0;
+      double x = dk - mu, z = ek;
+      for (int k = l; k < m; ++k) {
+        const double dk2 = k + 2 <= m ? dd[k + 2] : 0.0;
+        const double ek2 = k + 2 < m ? ee[k + 2] : 0.0;
+        double c = 1.0, s = 0.0, r = x;
+        const double hh = x * x + z * z;
+        if (hh > 0.0) {
+          const double ir = rsqrt_nr(hh);
+          r = hh * ir;
+          c = x * ir;
+          s = -z * ir;
+        }
+        if (k > l) ee[k - 1] = r;
+        const double cs = c * s, c2 = c * c, s2 = s * s;
+        const double nd0 = c2 * dk - 2.0 * cs * ek + s2 * dk1;
+        const double nd1 = s2 * dk + 2.0 * cs * ek + c2 * dk1;
+        const double ne = cs * (dk - dk1) + (c2 - s2) * ek;
+        dd[k] = nd0;
+        if (lane == 0) {
+          rot[2 * nr] = c;
+          rot[2 * nr + 1] = s;
+        }
+        ++nr;
+        if (k + 1 < m) {
+          z = -s * ek1;
+          ek = c * ek1;
+          x = ne;
+          dk = nd1;
+          dk1 = dk2;
+          ek1 = ek2;
+        } else {
+          dd[k + 1] = nd1;
+          ee[k] = ne;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) rec[i] = dd[i];  // the eigenvalues, unsorted
+    if (lane == 0) {
+      int32_t *mt = meta + 4 * (int64_t)ti;
+      mt[0] = (int32_t)ns;
+      mt[1] = (int32_t)nr;
+      mt[2] = (!ovf && m > 0) ? 1 : 0;  // did not converge
+      mt[3] = ovf;
+    }
+    __syncthreads();  // dd and ee are reused by the next task
+  }
+}
+
+// LDS of the apply launch: Q (n x pitch), d, the rotation stage and perm.
+static size_t apply_smem(int n, int stage) {
+  return sizeof(double) * ((size_t)n * qr_pitch(n) + (size_t)n + 2 * (size_t)stage) +
+         sizeof(int) * ((size_t)n + 1);
+}
+
+// Four waves per matrix: the rotations act on the rows of Q independently,
+// so row i belongs to lane i % RW of wave i / RW (RW = ceil(n_hi / 4) rows
+// per wave), and the four SIMDs of the CU each carry a quarter of the rows
+// through the whole record (the LDS matrix allows one matrix per CU).  The
+// waves meet only at the stage refills.
+__global__ __launch_bounds__(256) void tridiag_apply_kernel(
+    const EigTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ rank,
+    const double *__restrict__ cws, const int32_t *__restrict__ meta,
+    double *__restrict__ out, double *__restrict__ evals, int32_t *__restrict__ redo,
+    int stage, int n_lo, int n_hi) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x;
+  const int rw = (n_hi + 3) / 4;  // rows per wave
+  const int lane = tid & 63, wave = tid >> 6;
+  const int my_row = lane < rw ? wave * rw + lane : -1;
+  for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+    const EigTask t = tasks[ti];
+    const int n = rank[t.slot];
+    // tasks without a record (order above the split path's) run fused
+    if (t.w_off < 0 || n < n_lo || n > n_hi) continue;
+    const int32_t *mt = meta + 4 * (int64_t)ti;
+    const int ns = mt[0];
+    const int64_t nr = mt[1];
+    const bool failed = mt[2] != 0;
+    const int ovf = mt[3];
+    if (tid == 0) redo[t.slot] = ovf;
+    if (ovf) continue;  // the fused kernel solves it
+    const int D = t.D;
+    const int ld = qr_pitch(n);
+    double *const M = sm;
+    double *const dd = M + (size_t)n * ld;
+    double *const st = dd + n;
+    int *const perm = reinterpret_cast<int *>(st + 2 * stage);
+    const double *const rec = cws + t.w_off;
+    const int32_t *const bounds = reinterpret_cast<const int32_t *>(rec + 2 * D);
+    const double *const rot = rec + 2 * D + chase_sc(D);
+    for (int e = tid; e < n * n; e += 256) {
+      const int r = e / n, c = e - r * n;
+      M[r * ld + c] = out[t.o_off + (int64_t)r * D + c];
+    }
+    for (int i = tid; i < n; i += 256) dd[i] = rec[i];
+    __syncthreads();
+    // ---- the recorded rotations, in order, on this thread's row ----
+    const int i = my_row < n ? my_row : -1;
+    double *const Mi = M + (i >= 0 ? i : 0) * ld;
+    int64_t j0 = 0, j1 = 0;  // rotations [j0, j1) are staged
+    int64_t j = 0;
+    double cx = 0.0, sx = 0.0;  // rotation j, read from the stage one step ahead
+    for (int h = 0; h < ns; ++h) {
+      const int l = bounds[2 * h], m = bounds[2 * h + 1];
+      double qc = i >= 0 ? Mi[l] : 0.0;
+      double qn = i >= 0 ? Mi[l + 1] : 0.0;
+      for (int k = l; k < m; ++k, ++j) {
+        if (j == j1) {  // next stage of the record (uniform branch)
+          __syncthreads();
+          j0 = j;
+          const int64_t cnt = nr - j0 < stage ? nr - j0 : stage;
+          j1 = j0 + cnt;
+          for (int64_t e = tid; e < 2 * cnt; e += 256) st[e] = rot[2 * j0 + e];
+          __syncthreads();
+          cx = st[0];
+          sx = st[1];
+        }
+        const double c = cx, s = sx;
+        if (j + 1 < j1) {
+          cx = st[2 * (j + 1 - j0)];
+          sx = st[2 * (j + 1 - j0) + 1];
+        }
+        const double qnn = (k + 2 <= m && i >= 0) ? Mi[k + 2] : 0.0;
+        const double q0 = qc, q1 = qn;
+        if (i >= 0) Mi[k] = c * q0 - s * q1;
+        qc = s * q0 + c * q1;
+        qn = qnn;
+      }
+      if (i >= 0) Mi[m] = qc;
+    }
+    __syncthreads();
+    // ---- ascending order (ties by index) and the mode-1 outputs ----
+    for (int r0 = tid; r0 < n; r0 += 256) {
+      const double li = dd[r0];
+      int r = 0;
+      for (int q = 0; q < n; ++q) {
+        const double lj = dd[q];
+        r += (lj < li) || (lj == li && q < r0);
+      }
+      perm[r] = r0;
+    }
+    __syncthreads();
+    const double nanv = __builtin_nan("");
+    for (int e = tid; e < D * D; e += 256) {
+      const int r = e / D, c = e - r * D;
+      double v = 0.0;
+      if (r < n && c < n) v = M[r * ld + perm[c]];
+      out[t.o_off + (int64_t)r * D + c] = v;
+    }
+    for (int c = tid; c < D; c += 256)
+      evals[t.e_off + c] = c < n ? (failed ? nanv : dd[perm[c]]) : EV_SENTINEL;
+    __syncthreads();  // the workspace is reused by the next task
+  }
+}
+
 static size_t cholesky_smem(int n) { return sizeof(double) * (size_t)2 * n * (n + 1); }
 
 static size_t jacobi_smem(int n) {
@@ -769,6 +1166,78 @@ hipError_t launch_eigh(const EigTask *d_tasks, int n_tasks, int max_n,
   const int grid = (int)std::min<int64_t>(n_tasks, gws_doubles / stride);
   hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), 0, s, d_tasks, n_tasks, in, out,
                      evals, rank, mode, tau, only_flagged, nq + 1, max_n, gws, stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_eigh_split(const EigTask *d_tasks, int n_tasks, int max_n,
+                             const double *in, double *out, double *evals,
+                             int32_t *rank, double *cws, int32_t *meta, int32_t *redo,
+                             double *gws, int64_t gws_doubles, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  if (!cws || !meta || !redo) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  const int top = std::min(max_n, SPLIT_MAX_ORDER);
+  for (int lo = 1; lo <= top && e == hipSuccess; lo += 64) {
+    const int hi = std::min(top, lo + 63);
+    // the split launches select tasks by their order rank[slot] (order 0,
+    // an empty basis, in the first range); the fused fallback by t.n, the
+    // range whose LDS it reserved: each task's redo flag is written by the
+    // apply launch of its order's range, before the fallback of t.n's
+    const int rlo = lo == 1 ? 0 : lo;
+    const size_t hs = qr_smem(hi);
+    // 512 staged rotations (8 KB) keep the record's reads off the chain;
+    // more would only take LDS from other workgroups
+    int stage = (int)std::min<int64_t>(512, ((int64_t)EIG_LDS - (int64_t)apply_smem(hi, 0)) / 16);
+    stage = stage / 64 * 64;
+    if (stage < 64) return hipErrorInvalidValue;
+    const size_t as = apply_smem(hi, stage);
+    if (hi <= 64) {
+      e = hipFuncSetAttribute((const void *)tridiag_house_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)hs);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)tridiag_apply_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)as);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(tridiag_house_kernel, dim3(n_tasks), dim3(256), hs, s, d_tasks,
+                         n_tasks, in, out, rank, cws, rlo, hi);
+      hipLaunchKernelGGL(tridiag_chase_kernel, dim3(n_tasks), dim3(64), 0, s, d_tasks,
+                         n_tasks, rank, cws, meta, rlo, hi);
+      hipLaunchKernelGGL(tridiag_apply_kernel, dim3(n_tasks), dim3(256), as, s, d_tasks,
+                         n_tasks, rank, cws, meta, out, evals, redo, stage, rlo, hi);
+      e = hipGetLastError();
+      if (e == hipSuccess)  // records that overflowed: the fused kernel
+        e = launch_qr<1>(d_tasks, n_tasks, lo, hi, in, out, evals, rank, 1, 0.0, redo, s);
+    } else {
+      e = hipFuncSetAttribute((const void *)tridiag_house_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)hs);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)tridiag_apply_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)as);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(tridiag_house_kernel, dim3(n_tasks), dim3(256), hs, s, d_tasks,
+                         n_tasks, in, out, rank, cws, rlo, hi);
+      hipLaunchKernelGGL(tridiag_chase_kernel, dim3(n_tasks), dim3(64), 0, s, d_tasks,
+                         n_tasks, rank, cws, meta, rlo, hi);
+      hipLaunchKernelGGL(tridiag_apply_kernel, dim3(n_tasks), dim3(256), as, s, d_tasks,
+                         n_tasks, rank, cws, meta, out, evals, redo, stage, rlo, hi);
+      e = hipGetLastError();
+      if (e == hipSuccess)
+        e = launch_qr<2>(d_tasks, n_tasks, lo, hi, in, out, evals, rank, 1, 0.0, redo, s);
+    }
+  }
+  if (e != hipSuccess || max_n <= SPLIT_MAX_ORDER) return e;
+  // orders above the split path: the fused kernel, then cyclic Jacobi
+  const int nq = eig_qr_max_order();
+  for (int lo = SPLIT_MAX_ORDER + 1; lo <= std::min(max_n, nq) && e == hipSuccess; lo += 64) {
+    const int hi = std::min(std::min(max_n, nq), lo + 63);
+    e = launch_qr<3>(d_tasks, n_tasks, lo, hi, in, out, evals, rank, 1, 0.0, nullptr, s);
+  }
+  if (e != hipSuccess || max_n <= nq) return e;
+  const int64_t stride = eig_workspace_doubles(max_n);
+  if (!gws || gws_doubles < stride) return hipErrorInvalidValue;
+  const int grid = (int)std::min<int64_t>(n_tasks, gws_doubles / stride);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), 0, s, d_tasks, n_tasks, in, out,
+                     evals, rank, 1, 0.0, nullptr, nq + 1, max_n, gws, stride);
   return hipGetLastError();
 }
 

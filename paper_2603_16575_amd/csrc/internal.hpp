@@ -190,6 +190,8 @@ struct EigTask {
   int32_t lda;
   int32_t D;        // padded column count of the outputs
   int32_t slot;     // slot id (rank array index)
+  int64_t w_off;    // split Fock step: the task's record in the chase
+                    // workspace (eig_chase_ws_doubles(D) doubles), or -1
 };
 // mode 0: overlap step.  Writes X0 = U_keep s^-1/2 (kept eigenvalues > tau,
 //         ascending), zero columns up to D, rank[slot] = kept count;
@@ -206,6 +208,20 @@ hipError_t launch_eigh(const EigTask *d_tasks, int n_tasks, int max_n,
                        int mode, double tau, const int32_t *only_flagged, double *gws,
                        int64_t gws_doubles, hipStream_t s);
 int eig_qr_max_order();
+// Split Fock step (mode 1 only) for orders up to eig_split_max_order():
+// Householder reduction and Q per wave in LDS, then the implicit QR steps
+// on (d, e) alone with every sweep's bounds and rotations recorded in the
+// task's workspace record (ws + w_off, eig_chase_ws_doubles(D) doubles),
+// then the rotations replayed onto Q and the outputs of launch_eigh's
+// mode 1.  meta: device [n_tasks][4] int32 scratch; redo: device [n_slot]
+// int32, set for tasks whose record overflowed (they are then solved by the
+// fused kernel in the same call).  Larger orders as in launch_eigh.
+int eig_split_max_order();
+int64_t eig_chase_ws_doubles(int D);
+hipError_t launch_eigh_split(const EigTask *d_tasks, int n_tasks, int max_n,
+                             const double *in, double *out, double *evals,
+                             int32_t *rank, double *cws, int32_t *meta, int32_t *redo,
+                             double *gws, int64_t gws_doubles, hipStream_t s);
 // Overlap step by Cholesky (X0 = L^-T, full rank).  Slots whose pivots drop
 // to <= tau get flag[slot] = 1 and are redone by launch_eigh(mode 0,
 // only_flagged = flag).

@@ -111,3 +111,29 @@ def test_identity_osv_canonical_mp2(m):
         assert np.allclose(Xs.T @ S @ Xs, np.eye(rank[s]), atol=1e-12)
         assert np.allclose(Xs.T @ F @ Xs, np.diag(es), atol=1e-12)
     h.close()
+
+
+def test_create_enomem_then_usable(m):
+    """A problem whose single-LMO slab buffer (20000 x 2e6 doubles, 320 GB)
+    exceeds the device: mbe3_create returns MBE3_ENOMEM with the size in the
+    message, frees what it had allocated, and the device takes the next
+    handle normally."""
+    import torch
+    say("case: mbe3_create beyond device memory (320 GB slab buffer) -> MBE3_ENOMEM")
+    nv, na = 20000, 2000000
+    dev = "cuda:0"
+    Q = torch.ones((nv, 1), dtype=torch.float64, device=dev) / np.sqrt(nv)
+    eps = torch.linspace(0.5, 3.0, nv, dtype=torch.float64, device=dev)
+    f = torch.full((1, 1), -0.5, dtype=torch.float64, device=dev)
+    w_ia = torch.ones((1, nv), dtype=torch.float64, device=dev)
+    w_iP = torch.ones((1, na), dtype=torch.float64, device=dev)
+    free0, _ = torch.cuda.mem_get_info()
+    with pytest.raises(m.Mbe3Error) as ex:
+        m.Mbe3(r=[1], Q=Q, eps_vir=eps, f_occ=f, pairs=np.zeros((0, 2)),
+               frags=[[0, -1, -1]], w_ia=w_ia, w_iP=w_iP)
+    say(f"  {ex.value}")
+    assert ex.value.code == m.MBE3_ENOMEM and "bytes" in str(ex.value)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (64 << 20)  # the partial workspace was released
+    forward_backward_vs_oracle(m, synth.micro(3))

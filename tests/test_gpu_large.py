@@ -1,8 +1,11 @@
-"""Pair domains beyond 96 (the global-workspace eigensolver and the streamed
-solver): a small oracle-checked problem with D up to 160, and the large
-configurations 2 (D <= 128, 470k fragments) and 4 (D <= 160) on the GPU with
-sampled checks (needs an MI355X)."""
+"""Wide pair domains (the eight-wave LDS solver up to 128, the streamed
+solver and the global-workspace eigensolver above): a small oracle-checked
+problem with D up to 160, and the large configurations 2 (D <= 128, 470k
+fragments) and 4 (D <= 160) on the GPU with sampled checks (needs an
+MI355X)."""
 import dataclasses
+import json
+import os
 import sys
 
 import numpy as np
@@ -153,7 +156,10 @@ def test_water128u_sampled(m):
     """water128u (512 LMOs, n_vir 2432, n_aux 7040, D up to 128, 470k
     fragments) in full on the GPU: every fragment converged and finite, and
     the fragments of one trimer with a 128-wide pair (with its dimers and
-    monomers) against the oracle, one by one; its projected blocks too."""
+    monomers) against the oracle, one by one; its projected blocks too; and
+    the stored oracle sample of 5915 fragments (every 97th and every one
+    containing LMO 0) with their update counts, and sampled K-bar elements
+    of eight slots."""
     import torch
     say("case: water128u full forward, sampled oracle trimer")
     prob = synth.config(2)
@@ -183,6 +189,33 @@ def test_water128u_sampled(m):
     dE = np.abs(e[idx] - res["e_frag"])
     say(f"sampled fragments: max |dE_F| = {dE.max():.3e}")
     assert dE.max() <= 1e-12
+    # the stored oracle sample (tests/golden/make_golden_water128u.py, oracle
+    # only): every 97th fragment and every fragment containing LMO 0, from
+    # T = 0, with their update counts, and 16 seeded elements and the norm
+    # of eight K-bar slots
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "water128u_sample_oracle.json")))
+    assert g["n_frag"] == prob.n_frag and g["converged"]
+    sidx = np.asarray(g["sample_index"])
+    ref_e = np.array([float(v) for v in g["e_frag"]])
+    d_e = np.abs(e[sidx] - ref_e)
+    same_it = it[sidx] == np.asarray(g["iters"])
+    say(f"golden sample: {len(sidx)} fragments, max |dE_F| = {d_e.max():.3e}, "
+        f"update counts equal {int(same_it.sum())}/{len(sidx)}, "
+        f"sum dE = {float(np.sum(e[sidx]) - np.sum(ref_e)):.3e}")
+    assert d_e.max() <= 1e-12
+    assert same_it.all()
+    slot = {(int(a), int(b)): prob.n_occ + k for k, (a, b) in enumerate(prob.pairs)}
+    for ks in g["k_slots"]:
+        p_, q_ = ks["p"], ks["q"]
+        sidx_k = p_ if p_ == q_ else slot[(p_, q_)]
+        blk = out["K"][int(h.k_off[sidx_k]):int(h.k_off[sidx_k + 1])].cpu().numpy()
+        assert blk.size == ks["d"] ** 2
+        fro = float(ks["frobenius"])
+        got = blk[np.asarray(ks["flat_index"])]
+        want = np.array([float(v) for v in ks["values"]])
+        assert np.abs(got - want).max() <= 1e-13 * fro, (p_, q_)
+        assert abs(float(np.linalg.norm(blk)) - fro) <= 1e-13 * fro, (p_, q_)
     h.close()
     del out
     torch.cuda.empty_cache()
