@@ -690,10 +690,39 @@ __global__ __launch_bounds__(64) void tridiag_qr_kernel(
 // ---------------------------------------------------------------------------
 static constexpr int SPLIT_MAX_ORDER = 128;
 static __host__ __device__ inline int64_t chase_sc(int D) { return 4LL * D + 8; }
-static __host__ __device__ inline int64_t chase_rc(int D) { return 2LL * D * D; }
+// rotations: about 1.1 n^2 plus up to 30 identity rotations per sweep that
+// pad it to whole blocks of 16 columns
+static __host__ __device__ inline int64_t chase_rc(int D) { return 2LL * D * D + 16 * chase_sc(D); }
 
 int eig_split_max_order() { return SPLIT_MAX_ORDER; }
 int64_t eig_chase_ws_doubles(int D) { return 2LL * D + chase_sc(D) + 2 * chase_rc(D); }
+
+// rows x cols of a row-major global matrix (pitch gld) into LDS (pitch ld):
+// rows over the four waves, columns over the lanes, eight loads of a wave
+// in flight before their LDS stores (a load per iteration would wait out
+// the memory latency every time).
+__device__ __forceinline__ void copy_in_rows(double *M, int ld, const double *__restrict__ g,
+                                             int64_t gld, int rows, int cols, int wv, int ln) {
+  const int per_row = (cols + 63) / 64;
+  const int total = ((rows - wv + 3) / 4) * per_row;  // this wave's (row, block) items
+  for (int b = 0; b < total; b += 8) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int it = b + u;
+      const int r = wv + 4 * (it / per_row), c = ln + 64 * (it % per_row);
+      const bool ok = it < total && c < cols;
+      const double y = g[ok ? (int64_t)r * gld + c : 0];  // index kept inside the matrix
+      x[u] = ok ? y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int it = b + u;
+      const int r = wv + 4 * (it / per_row), c = ln + 64 * (it % per_row);
+      if (it < total && c < cols) M[r * ld + c] = x[u];
+    }
+  }
+}
 
 // The reduction and Q of tridiag_qr_kernel with four waves per matrix (the
 // LDS matrix allows one per CU): rows and columns spread over 256 threads,
@@ -719,10 +748,10 @@ __global__ __launch_bounds__(256) void tridiag_house_kernel(
     double *const ww = vv + n;
     double *const taus = ww + n;
 
-    for (int e = tid; e < n * n; e += 256) {
-      const int r = e / n, c = e - r * n;
-      M[r * ld + c] = in[t.a_off + (int64_t)r * t.lda + c];
-    }
+    // rows over the four waves, columns over the lanes: coalesced, no
+    // division, the loads of a row's column blocks in flight together
+    const int wv = tid >> 6, ln = tid & 63;
+    copy_in_rows(M, ld, in + t.a_off, t.lda, n, n, wv, ln);
     __syncthreads();
     // ---- Householder reduction (the steps of tridiag_qr_kernel) ----
     for (int k = 0; k + 2 < n; ++k) {
@@ -837,10 +866,8 @@ __global__ __launch_bounds__(256) void tridiag_house_kernel(
     }
     __syncthreads();
     // ---- Q to the output block, d and e to the record ----
-    for (int e = tid; e < n * n; e += 256) {
-      const int r = e / n, c = e - r * n;
-      out[t.o_off + (int64_t)r * D + c] = M[r * ld + c];
-    }
+    for (int r = wv; r < n; r += 4)
+      for (int c = ln; c < n; c += 64) out[t.o_off + (int64_t)r * D + c] = M[r * ld + c];
     double *const rec = cws + t.w_off;
     for (int i = tid; i < n; i += 256) {
       rec[i] = dd[i];
@@ -893,15 +920,27 @@ __global__ __launch_bounds__(64) void tridiag_chase_kernel(
         continue;
       }
       ++steps;
-      if (ns >= cap_s || nr + (m - l) > cap_r) {  // the record is full
+      // the sweep's record covers columns bl .. bm - 1 (whole 16-blocks):
+      // identity rotations before l and from m on
+      const int bl = l & ~15, bm = ((m - 1) | 15) + 1;
+      if (ns >= cap_s || nr + (bm - bl) > cap_r) {  // the record is full
         ovf = 1;
         break;
       }
       if (lane == 0) {
         bounds[2 * ns] = l;
         bounds[2 * ns + 1] = m;
+        for (int k = bl; k < l; ++k) {
+          rot[2 * (nr + k - bl)] = 1.0;
+          rot[2 * (nr + k - bl) + 1] = 0.0;
+        }
+        for (int k = m; k < bm; ++k) {
+          rot[2 * (nr + k - bl)] = 1.0;
+          rot[2 * (nr + k - bl) + 1] = 0.0;
+        }
       }
       ++ns;
+      nr += l - bl;  // the sweep's own rotations follow its leading pad
       const double dm1 = dd[m - 1], dm = dd[m], b = ee[m - 1];
       const double del = 0.5 * (dm1 - dm);
       const double hyp = sqrt(del * del + b * b);
@@ -944,6 +983,7 @@ __global__ __launch_bounds__(64) void tridiag_chase_kernel(
           ee[k] = ne;
         }
       }
+      nr += ((m - 1) | 15) + 1 - m;  // the trailing pad
     }
     __syncthreads();
     for (int i = lane; i < n; i += 64) rec[i] = dd[i];  // the eigenvalues, unsorted
@@ -958,10 +998,11 @@ __global__ __launch_bounds__(64) void tridiag_chase_kernel(
   }
 }
 
-// LDS of the apply launch: Q (n x pitch), d, the rotation stage and perm.
+// LDS of the apply launch: Q (n x pitch), d, the rotation stage, perm and
+// the sweep bounds of the largest record.
 static size_t apply_smem(int n, int stage) {
   return sizeof(double) * ((size_t)n * qr_pitch(n) + (size_t)n + 2 * (size_t)stage) +
-         sizeof(int) * ((size_t)n + 1);
+         sizeof(int) * ((size_t)n + 1 + 2 * (size_t)chase_sc(SPLIT_MAX_ORDER));
 }
 
 // Four waves per matrix: the rotations act on the rows of Q independently,
@@ -997,48 +1038,88 @@ __global__ __launch_bounds__(256) void tridiag_apply_kernel(
     double *const dd = M + (size_t)n * ld;
     double *const st = dd + n;
     int *const perm = reinterpret_cast<int *>(st + 2 * stage);
+    int *const bnd = perm + n + 1;  // the sweep bounds, staged once per task
     const double *const rec = cws + t.w_off;
     const int32_t *const bounds = reinterpret_cast<const int32_t *>(rec + 2 * D);
     const double *const rot = rec + 2 * D + chase_sc(D);
-    for (int e = tid; e < n * n; e += 256) {
-      const int r = e / n, c = e - r * n;
-      M[r * ld + c] = out[t.o_off + (int64_t)r * D + c];
-    }
+    copy_in_rows(M, ld, out + t.o_off, D, n, n, wave, lane);
     for (int i = tid; i < n; i += 256) dd[i] = rec[i];
+    for (int e = tid; e < 2 * ns; e += 256) bnd[e] = bounds[e];
     __syncthreads();
     // ---- the recorded rotations, in order, on this thread's row ----
+    // A sweep (l, m) rotates columns (k, k + 1) for k = l .. m - 1 in turn;
+    // its record covers the whole 16-column blocks from bl = 16 floor(l/16)
+    // to bm = 16 ceil(m/16), identity rotations (c = 1, s = 0, which leave
+    // both values exactly as they are) outside [l, m).  Each block: the
+    // row's 16 values and the 16 rotations come in at once, the rotations
+    // run in registers (v[q] is column bl + 16 b + q, v[16] the next
+    // block's first, carried).
     const int i = my_row < n ? my_row : -1;
     double *const Mi = M + (i >= 0 ? i : 0) * ld;
     int64_t j0 = 0, j1 = 0;  // rotations [j0, j1) are staged
-    int64_t j = 0;
-    double cx = 0.0, sx = 0.0;  // rotation j, read from the stage one step ahead
+    int64_t j = 0;           // first rotation of the sweep's record
     for (int h = 0; h < ns; ++h) {
-      const int l = bounds[2 * h], m = bounds[2 * h + 1];
-      double qc = i >= 0 ? Mi[l] : 0.0;
-      double qn = i >= 0 ? Mi[l + 1] : 0.0;
-      for (int k = l; k < m; ++k, ++j) {
-        if (j == j1) {  // next stage of the record (uniform branch)
-          __syncthreads();
-          j0 = j;
-          const int64_t cnt = nr - j0 < stage ? nr - j0 : stage;
-          j1 = j0 + cnt;
-          for (int64_t e = tid; e < 2 * cnt; e += 256) st[e] = rot[2 * j0 + e];
-          __syncthreads();
-          cx = st[0];
-          sx = st[1];
+      const int l = bnd[2 * h], m = bnd[2 * h + 1];
+      const int bl = l & ~15, bm = ((m - 1) | 15) + 1;
+      if (j + (bm - bl) > j1) {  // the sweep's record into the stage (uniform)
+        __syncthreads();
+        j0 = j;
+        const int64_t cnt = nr - j0 < stage ? nr - j0 : stage;
+        j1 = j0 + cnt;
+        {
+          double x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {  // 2 * stage <= 1024 = 4 * 256
+            const int64_t e = tid + 256 * u;
+            const double y = rot[2 * j0 + (e < 2 * cnt ? e : 0)];  // index kept inside the record
+            x[u] = e < 2 * cnt ? y : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t e = tid + 256 * u;
+            if (e < 2 * cnt) st[e] = x[u];
+          }
         }
-        const double c = cx, s = sx;
-        if (j + 1 < j1) {
-          cx = st[2 * (j + 1 - j0)];
-          sx = st[2 * (j + 1 - j0) + 1];
-        }
-        const double qnn = (k + 2 <= m && i >= 0) ? Mi[k + 2] : 0.0;
-        const double q0 = qc, q1 = qn;
-        if (i >= 0) Mi[k] = c * q0 - s * q1;
-        qc = s * q0 + c * q1;
-        qn = qnn;
+        __syncthreads();
       }
-      if (i >= 0) Mi[m] = qc;
+      const double *sr = st + 2 * (j - j0);  // rotation of column bl + 16 b + q at sr[2 (16 b + q)]
+      double v[17];
+      v[0] = (i >= 0) ? Mi[bl] : 0.0;
+      for (int c0 = bl; c0 < bm; c0 += 16, sr += 32) {
+        const bool inner = c0 + 16 < n;  // the block and its carry inside the row (uniform)
+        if (inner) {
+#pragma unroll
+          for (int q = 1; q <= 16; ++q) v[q] = Mi[c0 + q];
+        } else {
+          // the row's last block: reads clamped into the row, columns past
+          // it held at zero
+#pragma unroll
+          for (int q = 1; q <= 16; ++q) {
+            const double x = Mi[c0 + q < n ? c0 + q : n - 1];
+            v[q] = c0 + q < n ? x : 0.0;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const double c = sr[2 * q], s = sr[2 * q + 1];
+          const double q0 = v[q], q1 = v[q + 1];
+          v[q] = c * q0 - s * q1;
+          v[q + 1] = s * q0 + c * q1;
+        }
+        if (i >= 0) {
+          if (inner) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) Mi[c0 + q] = v[q];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+              if (c0 + q < n) Mi[c0 + q] = v[q];
+          }
+        }
+        v[0] = v[16];
+      }
+      if (i >= 0 && bm < n) Mi[bm] = v[0];
+      j += bm - bl;
     }
     __syncthreads();
     // ---- ascending order (ties by index) and the mode-1 outputs ----
@@ -1053,12 +1134,12 @@ __global__ __launch_bounds__(256) void tridiag_apply_kernel(
     }
     __syncthreads();
     const double nanv = __builtin_nan("");
-    for (int e = tid; e < D * D; e += 256) {
-      const int r = e / D, c = e - r * D;
-      double v = 0.0;
-      if (r < n && c < n) v = M[r * ld + perm[c]];
-      out[t.o_off + (int64_t)r * D + c] = v;
-    }
+    for (int r = wave; r < D; r += 4)
+      for (int c = lane; c < D; c += 64) {
+        double v = 0.0;
+        if (r < n && c < n) v = M[r * ld + perm[c]];
+        out[t.o_off + (int64_t)r * D + c] = v;
+      }
     for (int c = tid; c < D; c += 256)
       evals[t.e_off + c] = c < n ? (failed ? nanv : dd[perm[c]]) : EV_SENTINEL;
     __syncthreads();  // the workspace is reused by the next task
