@@ -49,6 +49,20 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Global-memory view of a pointer whose address space the compiler cannot
+// see (one read back from LDS): loads through it are global loads, counted
+// by vmcnt alone.  Through a generic pointer they would be flat loads, which
+// also count in lgkmcnt, so every wait for an LDS access would wait for the
+// prefetched panel as well.
+typedef __attribute__((address_space(1))) const d2 gd2;
+__device__ __forceinline__ const gd2 *as_global(const double *p) {
+  return (const gd2 *)(p);
+}
+
+// s_waitcnt immediate of vmcnt(0) alone (gfx9 encoding: expcnt and lgkmcnt
+// at their maxima)
+constexpr int WAIT_VMCNT0 = 0x0F70;
+
 // A fragment's terms and slots as the workgroup reads them, staged in LDS at
 // the start of each fragment: every panel step and residual block then reads
 // its descriptors from LDS instead of chasing term -> slot -> dimension
@@ -110,6 +124,10 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
     __syncthreads(); /* the previous term's S~ is no longer read */            \
     for (int mp = 0; mp < nS; ++mp) {                                          \
       double *const yb = (mp & 1) ? yb1 : yb0;                                 \
+      /* the panel in pf has landed; waiting here explicitly leaves no load   \
+         outstanding on any path, so the next panel's loads issue back to     \
+         back instead of each waiting for the one before */                  \
+      __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);                                 \
       {                                                                        \
         d2 *s_ = reinterpret_cast<d2 *>(Sl + 16 * mp * Dt);                    \
         d2 *y_ = reinterpret_cast<d2 *>(yb);                                   \
@@ -291,22 +309,24 @@ __global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(Solv
     const TermLds &tm_ = tc[p_ti - f_tb];                                      \
     const int dt_ = tm_.dt;                                                    \
     const int ds_ = tm_.ds;                                                    \
-    const d2 *st_ = reinterpret_cast<const d2 *>(tm_.st + (int64_t)16 * p_m * dt_); \
+    const gd2 *st_ = as_global(tm_.st + (int64_t)16 * p_m * dt_);              \
     /* rows 16m.. of Y, or (transposed source) columns 16m.. of every row */  \
     const double *ys_ = ysrc(tm_.src);                                         \
-    const d2 *y_ = reinterpret_cast<const d2 *>(                               \
-        tm_.trans ? ys_ + 16 * p_m : ys_ + (int64_t)16 * p_m * ds_);           \
+    const gd2 *y_ = as_global(tm_.trans ? ys_ + 16 * p_m : ys_ + (int64_t)16 * p_m * ds_); \
     p_n1 = 8 * dt_;                                                            \
     p_n2 = 8 * ds_;                                                            \
     p_tr = tm_.trans != 0;                                                     \
+    /* one unconditional load per slot from a selected address: no two      \
+       loads of a step write the same registers, so none waits for another */\
     _Pragma("unroll") for (int u = 0; u < PFN; ++u) {                          \
       const int e = tid + NTH * u;                                             \
-      if (e < p_n1) {                                                          \
-        pf[u] = st_[e];                                                        \
-      } else if (e - p_n1 < p_n2) {                                            \
-        const int q_ = e - p_n1;                                               \
-        pf[u] = p_tr ? y_[(q_ >> 3) * (ds_ >> 1) + (q_ & 7)] : y_[q_];         \
-      }                                                                        \
+      const int q_ = e - p_n1;                                                 \
+      /* slots past the panel load its first element (never stored) */       \
+      const gd2 *src_ = e < p_n1 ? st_ + e                                     \
+                        : q_ >= p_n2 ? st_                                     \
+                        : p_tr ? y_ + (q_ >> 3) * (ds_ >> 1) + (q_ & 7)        \
+                        : y_ + q_;                                             \
+      pf[u] = *src_;                                                           \
     }                                                                          \
   } while (0)
 #define MBE3_ADVANCE()                                                         \
