@@ -304,18 +304,28 @@ __global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(Solv
       int p_ti = f_tb, p_m = 0;  // step held in pf
       int p_n1 = 0, p_n2 = 0;
       bool p_tr = false;  // the Y part of pf is a strip of Y columns
+      // descriptors of term c_ti (the one the prefetch is in), read from LDS
+      // once per term rather than once per panel
+      int c_ti = -1, c_dt = 0, c_ds = 16;
+      bool c_tr = false;
+      const double *c_st = nullptr, *c_ys = nullptr;
 #define MBE3_LOAD_PANEL()                                                      \
   do {                                                                         \
-    const TermLds &tm_ = tc[p_ti - f_tb];                                      \
-    const int dt_ = tm_.dt;                                                    \
-    const int ds_ = tm_.ds;                                                    \
-    const gd2 *st_ = as_global(tm_.st + (int64_t)16 * p_m * dt_);              \
+    if (p_ti != c_ti) { /* a new term: its descriptors, once */                \
+      const TermLds &tm_ = tc[p_ti - f_tb];                                    \
+      c_dt = __builtin_amdgcn_readfirstlane(tm_.dt);                           \
+      c_ds = __builtin_amdgcn_readfirstlane(tm_.ds);                           \
+      c_tr = __builtin_amdgcn_readfirstlane(tm_.trans) != 0;                   \
+      c_st = tm_.st;                                                           \
+      c_ys = ysrc(tm_.src);                                                    \
+      c_ti = p_ti;                                                             \
+    }                                                                          \
+    const gd2 *st_ = as_global(c_st + (int64_t)16 * p_m * c_dt);               \
     /* rows 16m.. of Y, or (transposed source) columns 16m.. of every row */  \
-    const double *ys_ = ysrc(tm_.src);                                         \
-    const gd2 *y_ = as_global(tm_.trans ? ys_ + 16 * p_m : ys_ + (int64_t)16 * p_m * ds_); \
-    p_n1 = 8 * dt_;                                                            \
-    p_n2 = 8 * ds_;                                                            \
-    p_tr = tm_.trans != 0;                                                     \
+    const gd2 *y_ = as_global(c_tr ? c_ys + 16 * p_m : c_ys + (int64_t)16 * p_m * c_ds); \
+    p_n1 = 8 * c_dt;                                                           \
+    p_n2 = 8 * c_ds;                                                           \
+    p_tr = c_tr;                                                               \
     /* one unconditional load per slot from a selected address: no two      \
        loads of a step write the same registers, so none waits for another */\
     _Pragma("unroll") for (int u = 0; u < PFN; ++u) {                          \
@@ -324,15 +334,14 @@ __global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(Solv
       /* slots past the panel load its first element (never stored) */       \
       const gd2 *src_ = e < p_n1 ? st_ + e                                     \
                         : q_ >= p_n2 ? st_                                     \
-                        : p_tr ? y_ + (q_ >> 3) * (ds_ >> 1) + (q_ & 7)        \
+                        : p_tr ? y_ + (q_ >> 3) * (c_ds >> 1) + (q_ & 7)       \
                         : y_ + q_;                                             \
       pf[u] = *src_;                                                           \
     }                                                                          \
   } while (0)
 #define MBE3_ADVANCE()                                                         \
   do {                                                                         \
-    const int ds_ = tc[p_ti - f_tb].ds;                                        \
-    if (++p_m >= (ds_ >> 4)) { p_m = 0; ++p_ti; }                              \
+    if (++p_m >= (c_ds >> 4)) { p_m = 0; ++p_ti; }                             \
   } while (0)
 
       if (hasY && f_tb < f_te) MBE3_LOAD_PANEL();
