@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(Solv
   __shared__ SlotLds sc[6];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
   const int l16 = lane & 15;
   const int lq = lane >> 4;
   // LDS: the term's whole S~ (D_s x D_t) stays resident for both passes; the
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(Solv
 
       for (int tl = 0; tl < f_nt; ++tl) {
         const SlotLds sl = sc[tl];
-        const int Dt = sl.D;
+        const int Dt = __builtin_amdgcn_readfirstlane(sl.D);
         const int nT = Dt >> 4;
         d4 acc[MAXRB][MAXNT];
 #pragma unroll
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(64 * NW, MAXNT <= 5 ? 2 : 1) void solve_kernel(Solv
           for (int ti = f_tb; ti < f_te; ++ti) {
             if (tc[ti - f_tb].target != tl) continue;
             const double coef = tc[ti - f_tb].coef;
-            const int Ds = tc[ti - f_tb].ds;
+            const int Ds = __builtin_amdgcn_readfirstlane(tc[ti - f_tb].ds);
             const int nS = Ds >> 4;
             MBE3_TERM_PRODUCTS(coef);
             if (GP) {
