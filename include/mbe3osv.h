@@ -26,7 +26,12 @@
  *     the handle's device; "host" pointers are ordinary host memory.
  *   - All floating point data is IEEE double, row-major.
  *   - Every call is ordered on the handle's stream (hipStream_t passed as
- *     void*; NULL = the default stream).  Only mbe3_energy synchronises.
+ *     void*; NULL = the default stream).  In the forward path mbe3_energy
+ *     (which returns the sum) and fragment_solve (which returns the
+ *     fragments' convergence status) synchronise the stream when called
+ *     directly; inside a recording neither does, and mbe3_graph_launch
+ *     checks the status after each replay.  Other calls that synchronise
+ *     say so below.
  *   - Every call returns an int status (MBE3_*).  On failure,
  *     mbe3_last_error() describes the cause.  No C++ exception crosses the
  *     ABI.  The library allocates its own device workspace (at create and
@@ -219,9 +224,10 @@ int pair_K(mbe3_handle *h, const double *gamma, double *K, int64_t k_elems);
  * E = sum_F c_F e_frag[F]) at the converged amplitudes, and the handle
  * records dE/df_occ for mbe3_backward.  The first call with W plans and
  * allocates the gradient workspace (about one Y block per fragment and
- * chunk, one gamma-sized buffer).  Returns MBE3_ENOCONV / MBE3_ENONFINITE
- * after the stream finished if any fragment failed (other fragments are
- * valid; W is then not).
+ * chunk, one gamma-sized buffer).  Called directly it synchronises the
+ * stream and returns MBE3_ENOCONV / MBE3_ENONFINITE if any fragment failed
+ * (other fragments are valid; W is then not); while recording it returns at
+ * once and mbe3_graph_launch reports the status of each replay.
  */
 int fragment_solve(mbe3_handle *h, const double *K, double *e_frag,
                    int32_t *iters, double *W);
