@@ -46,8 +46,9 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
     int32_t *__restrict__ rank, int mode, double tau,
     const int32_t *__restrict__ only_flagged, int n_lo, int n_hi, double *gws,
     int64_t gstride) {
-  extern __shared__ double sm_dyn[];
-  double *const sm = gws ? gws + (int64_t)blockIdx.x * gstride : sm_dyn;
+  // launched only for orders above the LDS limit, always on the global
+  // workspace (a pointer known to be global: global, not flat, accesses)
+  double *const sm = gws + (int64_t)blockIdx.x * gstride;
   for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
   const EigTask t = tasks[ti];
   if (t.n < n_lo || t.n > n_hi) continue;  // the other launch's task
@@ -227,14 +228,17 @@ __global__ __launch_bounds__(256) void jacobi_kernel(
 // every eigenvalue of S above tau (the rank canonical orthogonalisation
 // keeps is then n as well).  A pivot <= tau or a larger norm sets
 // flag[slot] and leaves the slot to the canonical-orthogonalisation launch
-// that follows.
+// that follows.  GWS: the matrices live in a global-memory slice per
+// workgroup (orders above the LDS limit); otherwise in LDS, through a pointer
+// the compiler knows to be LDS (ds instructions, not flat ones).
+template <bool GWS>
 __global__ __launch_bounds__(256) void cholesky_kernel(
     const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
     double *__restrict__ out, double *__restrict__ evals,
     int32_t *__restrict__ rank, int32_t *__restrict__ flag, double tau, int n_lo,
     int n_hi, double *gws, int64_t gstride) {
   extern __shared__ double sm_dyn[];
-  double *const sm = gws ? gws + (int64_t)blockIdx.x * gstride : sm_dyn;
+  double *const sm = GWS ? gws + (int64_t)blockIdx.x * gstride : sm_dyn;
   __shared__ int failed;
   __shared__ double wsum[4];  // per-wave partial sums (256 threads)
   for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
@@ -1192,13 +1196,19 @@ hipError_t launch_cholesky(const EigTask *d_tasks, int n_tasks, int max_n,
   return two_launches(n_tasks, max_n, cholesky_smem, gws, gws_doubles,
                       [&](int grid, int lo, int hi, double *ws, int64_t stride,
                           size_t smem) -> hipError_t {
+                        if (ws) {
+                          hipLaunchKernelGGL(cholesky_kernel<true>, dim3(grid), dim3(256), 0,
+                                             s, d_tasks, n_tasks, in, out, evals, rank,
+                                             flag, tau, lo, hi, ws, stride);
+                          return hipGetLastError();
+                        }
                         hipError_t e = hipFuncSetAttribute(
-                            (const void *)cholesky_kernel,
+                            (const void *)cholesky_kernel<false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
                         if (e != hipSuccess) return e;
-                        hipLaunchKernelGGL(cholesky_kernel, dim3(grid), dim3(256), smem,
-                                           s, d_tasks, n_tasks, in, out, evals, rank,
-                                           flag, tau, lo, hi, ws, stride);
+                        hipLaunchKernelGGL(cholesky_kernel<false>, dim3(grid), dim3(256),
+                                           smem, s, d_tasks, n_tasks, in, out, evals,
+                                           rank, flag, tau, lo, hi, ws, stride);
                         return hipGetLastError();
                       });
 }
