@@ -244,27 +244,30 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
   for (int ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
   const EigTask t = tasks[ti];
   if (t.n < n_lo || t.n > n_hi) continue;  // the other launch's task
-  const int n = t.n, D = t.D, ld = n + 1;
-  double *L = sm;             // n x ld, lower triangle
-  double *Li = sm + n * ld;   // n x ld, L^{-1} (lower triangle)
+  const int n = t.n, D = t.D;
+  // L and L^{-1} as packed lower triangles (row i starts at i (i + 1) / 2),
+  // so that orders up to 142 fit 160 KB of LDS
+  auto P = [](int i, int j) { return i * (i + 1) / 2 + j; };
+  double *L = sm;                       // n (n + 1) / 2
+  double *Li = sm + n * (n + 1) / 2;    // n (n + 1) / 2
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < n * n; e += nt) {
     const int r = e / n, c = e - r * n;
-    L[r * ld + c] = c <= r ? in[t.a_off + (int64_t)r * t.lda + c] : 0.0;
+    if (c <= r) L[P(r, c)] = in[t.a_off + (int64_t)r * t.lda + c];
   }
   if (tid == 0) failed = 0;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const double piv = L[k * ld + k];
+    const double piv = L[P(k, k)];
     if (!(piv > tau)) {  // uniform: every thread reads the same value
       if (tid == 0) failed = 1;
       break;
     }
     const double lkk = sqrt(piv);
     const double inv = 1.0 / lkk;
-    for (int i = k + 1 + tid; i < n; i += nt) L[i * ld + k] *= inv;
+    for (int i = k + 1 + tid; i < n; i += nt) L[P(i, k)] *= inv;
     __syncthreads();
-    if (tid == 0) L[k * ld + k] = lkk;
+    if (tid == 0) L[P(k, k)] = lkk;
     const int m = n - k - 1;  // trailing order
     const int ntri = m * (m + 1) / 2;
     for (int e = tid; e < ntri; e += nt) {
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
       while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
       const int jj = e - ii * (ii + 1) / 2;  // jj <= ii
       const int i = k + 1 + ii, j = k + 1 + jj;
-      L[i * ld + j] -= L[i * ld + k] * L[j * ld + k];
+      L[P(i, j)] -= L[P(i, k)] * L[P(j, k)];
     }
     __syncthreads();
   }
@@ -287,12 +290,11 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
   // squares of the column as it goes
   double ssq = 0.0;
   for (int c = tid; c < n; c += nt) {
-    for (int i = 0; i < c; ++i) Li[i * ld + c] = 0.0;
     for (int i = c; i < n; ++i) {
       double acc = (i == c) ? 1.0 : 0.0;
-      for (int m2 = c; m2 < i; ++m2) acc -= L[i * ld + m2] * Li[m2 * ld + c];
-      const double v = acc / L[i * ld + i];
-      Li[i * ld + c] = v;
+      for (int m2 = c; m2 < i; ++m2) acc -= L[P(i, m2)] * Li[P(m2, c)];
+      const double v = acc / L[P(i, i)];
+      Li[P(i, c)] = v;
       ssq += v * v;
     }
   }
@@ -316,10 +318,10 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
     __syncthreads();
     continue;
   }
-  // X0 = L^{-T}: X0[r][c] = Li[c][r]
+  // X0 = L^{-T}: X0[r][c] = Li[c][r], zero above the diagonal of Li
   for (int e = tid; e < n * D; e += nt) {
     const int r = e / D, c = e - r * D;
-    out[t.o_off + (int64_t)r * D + c] = c < n ? Li[c * ld + r] : 0.0;
+    out[t.o_off + (int64_t)r * D + c] = (c < n && c >= r) ? Li[P(c, r)] : 0.0;
   }
   for (int c = tid; c < D; c += nt) evals[t.e_off + c] = c < n ? 1.0 : EV_SENTINEL;
   if (tid == 0) {
@@ -1150,7 +1152,7 @@ __global__ __launch_bounds__(256) void tridiag_apply_kernel(
   }
 }
 
-static size_t cholesky_smem(int n) { return sizeof(double) * (size_t)2 * n * (n + 1); }
+static size_t cholesky_smem(int n) { return sizeof(double) * (size_t)n * (n + 1); }
 
 static size_t jacobi_smem(int n) {
   const int ld = n + 1, nh = (n + 1) / 2;
