@@ -731,8 +731,10 @@ __device__ __forceinline__ void copy_in_rows(double *M, int ld, const double *__
 }
 
 // The reduction and Q of tridiag_qr_kernel with four waves per matrix (the
-// LDS matrix allows one per CU): rows and columns spread over 256 threads,
-// the two wave sums of a step become workgroup sums.
+// LDS matrix allows one per CU): each row of the trailing block (reduction)
+// and each column (Q) goes to a pair of adjacent lanes that split it by
+// parity (orders up to 128), the two wave sums of a step become workgroup
+// sums.
 __global__ __launch_bounds__(256) void tridiag_house_kernel(
     const EigTask *__restrict__ tasks, int n_tasks, const double *__restrict__ in,
     double *__restrict__ out, const int32_t *__restrict__ rank, double *__restrict__ cws,
@@ -788,31 +790,38 @@ __global__ __launch_bounds__(256) void tridiag_house_kernel(
       }
       __syncthreads();
       if (tk != 0.0) {
+        // two adjacent lanes per row (orders up to 128 on 256 threads), each
+        // taking the columns of one parity; the halves meet by a lane swap,
+        // even columns first
         double pv = 0.0;
         double pj = 0.0;
-        const int i = k + 1 + tid;
+        const int h = tid & 1;
+        const int i = k + 1 + (tid >> 1);
+        double part = 0.0;
         if (i < n) {
           const double *row = M + i * ld;
-          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-          int c = k + 1;
-          for (; c + 3 < n; c += 4) {
+          double a0 = 0.0, a1 = 0.0;
+          int c = k + 1 + h;
+          for (; c + 2 < n; c += 4) {
             a0 += row[c] * vv[c];
-            a1 += row[c + 1] * vv[c + 1];
-            a2 += row[c + 2] * vv[c + 2];
-            a3 += row[c + 3] * vv[c + 3];
+            a1 += row[c + 2] * vv[c + 2];
           }
-          for (; c < n; ++c) a0 += row[c] * vv[c];
-          pj = tk * ((a0 + a1) + (a2 + a3));
-          pv = pj * vv[i];
+          for (; c < n; c += 2) a0 += row[c] * vv[c];
+          part = a0 + a1;
+        }
+        const double other = __shfl_xor(part, 1);
+        if (i < n) {
+          pj = tk * (h == 0 ? part + other : other + part);
+          if (h == 0) pv = pj * vv[i];
         }
         const double kk = 0.5 * tk * block_sum(pv, red);
-        if (i < n) ww[i] = pj - kk * vv[i];
+        if (i < n && h == 0) ww[i] = pj - kk * vv[i];
         __syncthreads();
         if (i < n) {
           const double vi = vv[i], wi = ww[i];
           double *row = M + i * ld;
 #pragma unroll 4
-          for (int c = k + 1; c < n; ++c) row[c] -= vi * ww[c] + wi * vv[c];
+          for (int c = k + 1 + h; c < n; c += 2) row[c] -= vi * ww[c] + wi * vv[c];
         }
         __syncthreads();
       }
@@ -845,20 +854,24 @@ __global__ __launch_bounds__(256) void tridiag_house_kernel(
       __syncthreads();
       const double tk = taus[k];
       if (tk != 0.0) {
-        for (int c = k + 1 + tid; c < n; c += 256) {  // one column per thread
-          double u0 = M[(k + 1) * ld + c], u1 = 0.0, u2 = 0.0, u3 = 0.0;
-          int i = k + 2;
-          for (; i + 3 < n; i += 4) {
+        // two adjacent lanes per column, each taking the rows of one parity
+        // (both lanes of a pair run the same columns, so the swap partner is
+        // always active)
+        const int h = tid & 1;
+        for (int c = k + 1 + (tid >> 1); c < n; c += 128) {
+          double u0 = h == 0 ? M[(k + 1) * ld + c] : 0.0, u1 = 0.0;
+          int i = k + 2 + h;
+          for (; i + 2 < n; i += 4) {
             u0 += M[i * ld + k] * M[i * ld + c];
-            u1 += M[(i + 1) * ld + k] * M[(i + 1) * ld + c];
-            u2 += M[(i + 2) * ld + k] * M[(i + 2) * ld + c];
-            u3 += M[(i + 3) * ld + k] * M[(i + 3) * ld + c];
+            u1 += M[(i + 2) * ld + k] * M[(i + 2) * ld + c];
           }
-          for (; i < n; ++i) u0 += M[i * ld + k] * M[i * ld + c];
-          const double u = tk * ((u0 + u1) + (u2 + u3));
-          M[(k + 1) * ld + c] -= u;
+          for (; i < n; i += 2) u0 += M[i * ld + k] * M[i * ld + c];
+          const double part = u0 + u1;
+          const double other = __shfl_xor(part, 1);
+          const double u = tk * (h == 0 ? part + other : other + part);
+          if (h == 0) M[(k + 1) * ld + c] -= u;
 #pragma unroll 4
-          for (int i2 = k + 2; i2 < n; ++i2) M[i2 * ld + c] -= M[i2 * ld + k] * u;
+          for (int i2 = k + 2 + h; i2 < n; i2 += 2) M[i2 * ld + c] -= M[i2 * ld + k] * u;
         }
         __syncthreads();
       }
