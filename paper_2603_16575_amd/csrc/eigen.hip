@@ -268,15 +268,18 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
     for (int i = k + 1 + tid; i < n; i += nt) L[P(i, k)] *= inv;
     __syncthreads();
     if (tid == 0) L[P(k, k)] = lkk;
+    // trailing update of the lower triangle: the 256 threads as a 16 x 16
+    // grid striding over its rows and columns (no triangular index to
+    // invert per element)
     const int m = n - k - 1;  // trailing order
-    const int ntri = m * (m + 1) / 2;
-    for (int e = tid; e < ntri; e += nt) {
-      int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while (ii * (ii + 1) / 2 > e) --ii;
-      while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      const int jj = e - ii * (ii + 1) / 2;  // jj <= ii
-      const int i = k + 1 + ii, j = k + 1 + jj;
-      L[P(i, j)] -= L[P(i, k)] * L[P(j, k)];
+    const int ty = tid >> 4, tx = tid & 15;
+    for (int ii = ty; ii < m; ii += 16) {
+      const int i = k + 1 + ii;
+      const double lik = L[P(i, k)];
+      for (int jj = tx; jj <= ii; jj += 16) {
+        const int j = k + 1 + jj;
+        L[P(i, j)] -= lik * L[P(j, k)];
+      }
     }
     __syncthreads();
   }
