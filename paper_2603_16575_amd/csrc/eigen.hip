@@ -289,16 +289,26 @@ __global__ __launch_bounds__(256) void cholesky_kernel(
     __syncthreads();
     continue;
   }
-  // L^{-1}: thread c solves L x = e_c for column c (rows >= c), summing the
-  // squares of the column as it goes
+  // L^{-1}: four adjacent lanes solve L x = e_c for column c (rows >= c),
+  // each summing the terms m2 = its lane (mod 4) of every row's dot product
+  // (the long columns no longer hold one lane for the whole solve); the lane
+  // that will read row i's value again is the one that stores it, and it
+  // adds its square
   double ssq = 0.0;
-  for (int c = tid; c < n; c += nt) {
-    for (int i = c; i < n; ++i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int m2 = c; m2 < i; ++m2) acc -= L[P(i, m2)] * Li[P(m2, c)];
-      const double v = acc / L[P(i, i)];
-      Li[P(i, c)] = v;
-      ssq += v * v;
+  {
+    const int sub = tid & 3;
+    for (int c = tid >> 2; c < n; c += nt >> 2) {
+      for (int i = c; i < n; ++i) {
+        double part = 0.0;
+        for (int m2 = c + sub; m2 < i; m2 += 4) part += L[P(i, m2)] * Li[P(m2, c)];
+        part += __shfl_xor(part, 1, 64);
+        part += __shfl_xor(part, 2, 64);
+        const double v = (((i == c) ? 1.0 : 0.0) - part) / L[P(i, i)];
+        if (sub == (i & 3)) {
+          Li[P(i, c)] = v;
+          ssq += v * v;
+        }
+      }
     }
   }
   // Positive pivots do not bound the smallest eigenvalue of S; the trace of
